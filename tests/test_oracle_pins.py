@@ -1,0 +1,331 @@
+"""Pins of the FP64 oracle against facts the paper and the mathematics fix.
+
+None of these checks re-types the oracle's own formula: each compares it with a
+library routine, a brute-force evaluation of a definition, a closed form, a
+hand-derived example or an invariant the paper proves.
+"""
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def tiny_problem(seed, P=2, K=3, W=5, T=40, rho=0.08, noise=0.1):
+    X, D, Zt = synth.generate(P, K, W, T, rho, noise, seed)
+    return X.astype(np.float64), D.astype(np.float64), Zt
+
+
+# ---------------------------------------------------------------- primitives
+
+def test_soft_threshold_hand_values():
+    # Sh(u, lambda) = sign(u) max(|u| - lambda, 0)  (Sec. 2.1)
+    assert oracle.soft_threshold(3.0, 1.0) == 2.0
+    assert oracle.soft_threshold(-3.0, 1.0) == -2.0
+    assert oracle.soft_threshold(-0.5, 1.0) == 0.0
+    assert oracle.soft_threshold(1.0, 1.0) == 0.0
+    assert oracle.soft_threshold(0.25, 0.0) == 0.25
+
+
+def test_s_table_matches_numpy_correlate():
+    # S_{k,l}[d] = sum_tau <D_k[tau], D_l[tau+d]> via numpy.correlate ('full').
+    _, D, _ = tiny_problem(1, P=3, K=4, W=7)
+    K, P, W = D.shape
+    S = oracle.s_table(D)
+    for k in range(K):
+        for l in range(K):
+            ref = sum(np.correlate(D[l, p], D[k, p], mode="full") for p in range(P))
+            np.testing.assert_allclose(S[k, l], ref, rtol=0, atol=1e-14)
+    # symmetry S_{k,l}[d] = S_{l,k}[-d] and S_{k,k}[0] = |D_k|^2
+    np.testing.assert_allclose(S, np.transpose(S, (1, 0, 2))[:, :, ::-1], atol=1e-15)
+    np.testing.assert_allclose(np.diagonal(S[:, :, W - 1]), oracle.norms(D), atol=1e-15)
+
+
+def test_correlate_matches_numpy():
+    X, D, _ = tiny_problem(2, P=3, K=4, W=6, T=50)
+    K, P, W = D.shape
+    B = oracle.correlate(D, X)
+    for k in range(K):
+        ref = sum(np.correlate(X[p], D[k, p], mode="valid") for p in range(P))
+        np.testing.assert_allclose(B[k], ref, rtol=0, atol=1e-13)
+
+
+def test_reconstruct_matches_numpy_convolve():
+    X, D, Zt = tiny_problem(3, P=2, K=3, W=5, T=30, rho=0.3)
+    K, P, W = D.shape
+    T = X.shape[1]
+    R = oracle.reconstruct(D, Zt, T)
+    ref = np.zeros((P, T))
+    for k in range(K):
+        for p in range(P):
+            ref[p] += np.convolve(Zt[k], D[k, p], mode="full")
+    np.testing.assert_allclose(R, ref, rtol=0, atol=1e-12)
+
+
+def _beta_by_definition(X, D, Z):
+    """beta_k[t]: correlate D_k with X - sum_{k'} Z_{k'} * D_{k'} where Z_k[t] alone
+    is replaced by 0 (the replacement operator Phi_t of Sec. 2)."""
+    K, P, W = D.shape
+    T = X.shape[1]
+    L = T - W + 1
+    out = np.zeros((K, L))
+    for k in range(K):
+        for t in range(L):
+            Zm = Z.copy()
+            Zm[k, t] = 0.0
+            R = X.copy()
+            for kk in range(K):
+                for p in range(P):
+                    R[p] -= np.convolve(Zm[kk], D[kk, p], mode="full")
+            out[k, t] = sum(np.dot(D[k, p], R[p, t:t + W]) for p in range(P))
+    return out
+
+
+def test_beta_matches_definition_with_replacement_operator():
+    X, D, Zt = tiny_problem(4, P=2, K=2, W=4, T=20, rho=0.3)
+    np.testing.assert_allclose(oracle.beta(X, D, Zt), _beta_by_definition(X, D, Zt),
+                               rtol=0, atol=1e-12)
+
+
+# ------------------------------------------------------------ solver checks
+
+def _greedy_brute_force(X, D, lam, eps, n_steps):
+    """Algorithm 1 with beta recomputed from its definition at every step."""
+    K, P, W = D.shape
+    L = X.shape[1] - W + 1
+    n2 = np.sum(D * D, axis=(1, 2))
+    Z = np.zeros((K, L))
+    steps = []
+    for _ in range(n_steps):
+        B = _beta_by_definition(X, D, Z)
+        Zp = np.sign(B) * np.maximum(np.abs(B) - lam, 0.0) / n2[:, None]
+        dz = np.abs(Zp - Z)
+        # argmax with ties to the smallest t, then the smallest k
+        flat = np.argmax(dz.T.reshape(-1))
+        t0, k0 = divmod(int(flat), K)
+        if dz[k0, t0] < eps:
+            break
+        steps.append((k0, t0, Zp[k0, t0]))
+        Z[k0, t0] = Zp[k0, t0]
+    return Z, steps
+
+
+@pytest.mark.parametrize("seed", [0, 5])
+def test_single_segment_is_greedy_cd(seed):
+    # M = 1: the locally greedy rule is the greedy rule of Algorithm 1; the
+    # incremental beta of eq. (3) must reproduce the from-scratch trajectory.
+    X, D, _ = tiny_problem(seed, P=2, K=2, W=4, T=24, rho=0.15)
+    lam = 0.1 * oracle.lambda_max(X, D)
+    n = 25
+    Zb, steps = _greedy_brute_force(X, D, lam, 1e-9, n)
+    for sched in (oracle.SCHED_EVENODD, oracle.SCHED_SEQUENCE):
+        Z, st, tr = oracle.lgcd(X, D, lam, 1e-9, 1, schedule=sched,
+                                seq=[0] if sched == oracle.SCHED_SEQUENCE else None,
+                                max_steps=len(steps), trace_cap=n)
+        assert len(tr) == len(steps)
+        for rec, (k0, t0, zn) in zip(tr, steps):
+            assert (rec["k0"], rec["t0"]) == (k0, t0)
+            assert abs(rec["z_new"] - zn) <= 1e-10 * max(1.0, abs(zn))
+        np.testing.assert_allclose(Z, Zb, atol=1e-10)
+
+
+def test_prop_a1_cost_change_matches_objective():
+    # Prop. A.1: per-update decrease equals E(Z) - E(Z') computed directly.
+    X, D, _ = tiny_problem(6, P=2, K=3, W=5, T=60)
+    lam = 0.1 * oracle.lambda_max(X, D)
+    Zprev = np.zeros((3, 56))
+    Eprev = oracle.objective(X, D, Zprev, lam)
+    _, _, tr = oracle.lgcd(X, D, lam, 1e-8, 3, trace_cap=10)
+    for j in range(1, 8):
+        Z, _, _ = oracle.lgcd(X, D, lam, 1e-8, 3, max_steps=j)
+        E = oracle.objective(X, D, Z, lam)
+        assert abs((Eprev - E) - tr[j - 1]["dE"]) <= 1e-10 * max(1.0, abs(Eprev))
+        Eprev = E
+
+
+def test_monotone_decrease_and_lemma_a1_bound():
+    # Convergence proof of Theorem 1: each sequential update decreases E;
+    # Lemma A.1: the decrease is at least |D_k|^2 delta^2 / 2.
+    X, D, _ = synth.workload(synth.SMALL, 2)
+    lam = 0.1 * oracle.lambda_max(X, D)
+    Z, st, tr = oracle.lgcd(X, D, lam, 1e-6, 4, cap=8, trace_cap=10**5)
+    assert st["converged"] == 1
+    n2 = oracle.norms(D)
+    delta = tr["z_new"] - tr["z_old"]
+    assert np.all(tr["dE"] > 0)
+    assert np.all(tr["dE"] - 0.5 * n2[tr["k0"]] * delta ** 2 >= -1e-9 * np.maximum(1, tr["dE"]))
+    E0 = oracle.objective(X, D, np.zeros_like(Z), lam)
+    E1 = oracle.objective(X, D, Z, lam)
+    assert abs((E0 - E1) - st["dE_sum"]) <= 1e-9 * E0
+
+
+def test_lambda_at_or_above_lambda_max_gives_zero():
+    X, D, _ = tiny_problem(7)
+    lmax = oracle.lambda_max(X, D)
+    Z, st, _ = oracle.lgcd(X, D, lmax * (1 + 1e-12), 1e-8, 2)
+    assert st["n_updates"] == 0 and st["converged"] == 1
+    assert not Z.any()
+    Z, st, _ = oracle.lgcd(X, D, lmax * 0.99, 1e-8, 2)
+    assert st["n_updates"] >= 1
+
+
+def test_orthonormal_atoms_of_length_one_closed_form():
+    # W = 1 and orthonormal atoms (P = K): the problem separates over t and
+    # k and z_k[t] = Sh(<D_k, X[t]>, lambda).
+    rng = np.random.default_rng(0)
+    P = K = 4
+    Q, _ = np.linalg.qr(rng.standard_normal((P, P)))
+    D = Q.T[:, :, None].copy()           # D_k[p, 0] = Q[p, k]
+    X = 3.0 * rng.standard_normal((P, 30))
+    lam = 1.5
+    Z, st, _ = oracle.lgcd(X, D, lam, 1e-12, 1)
+    ref = Q.T @ X
+    ref = np.sign(ref) * np.maximum(np.abs(ref) - lam, 0.0)
+    np.testing.assert_allclose(Z, ref, atol=1e-12)
+    assert st["n_updates"] == np.count_nonzero(ref)
+
+
+def test_single_coordinate_closed_form():
+    # T = W (L = 1), K = 1: z = Sh(<D, X>, lambda) / |D|^2 (eq. (pb_coord)).
+    rng = np.random.default_rng(1)
+    D = rng.standard_normal((1, 3, 6))
+    X = rng.standard_normal((3, 6)) * 4
+    lam = 0.7
+    Z, _, _ = oracle.lgcd(X, D, lam, 1e-14, 1)
+    u = float(np.sum(D[0] * X))
+    ref = np.sign(u) * max(abs(u) - lam, 0.0) / float(np.sum(D * D))
+    assert abs(Z[0, 0] - ref) <= 1e-14
+
+
+def _read_golden():
+    rows = []
+    with open(os.path.join(GOLDEN, "two_coordinate_lasso.txt")) as f:
+        for line in f:
+            if not line.strip() or line.startswith("#"):
+                continue
+            name, x, z, g = [s.split() for s in line.split("|")]
+            rows.append((name[0], [Fraction(v) for v in x], [Fraction(v) for v in z],
+                         [Fraction(v) for v in g]))
+    return rows
+
+
+@pytest.mark.parametrize("row", _read_golden(), ids=lambda r: r[0])
+def test_golden_two_coordinate_lasso(row):
+    _, x, z, _ = row
+    D = np.array([[[0.6, 0.8]]])
+    X = np.array([[float(v) for v in x]])
+    for M, sched in ((1, oracle.SCHED_EVENODD), (2, oracle.SCHED_SEQUENCE)):
+        Z, st, _ = oracle.lgcd(X, D, 0.5, 1e-14, M, schedule=sched,
+                               seq=[0, 1] if sched == oracle.SCHED_SEQUENCE else None)
+        assert st["converged"] == 1
+        np.testing.assert_allclose(Z[0], [float(v) for v in z], atol=1e-12)
+
+
+def _toeplitz_design(D, T):
+    """Explicit Lasso design A in R^{PT x KL}: column (k, t) is D_k placed at t."""
+    K, P, W = D.shape
+    L = T - W + 1
+    A = np.zeros((P * T, K * L))
+    for k in range(K):
+        for t in range(L):
+            col = np.zeros((P, T))
+            col[:, t:t + W] = D[k]
+            A[:, k * L + t] = col.reshape(-1)
+    return A
+
+
+def _fista(A, x, lam, n_iter=20000, tol=1e-14):
+    Lip = np.linalg.norm(A, 2) ** 2
+    z = np.zeros(A.shape[1])
+    y = z.copy()
+    s = 1.0
+    for _ in range(n_iter):
+        u = y - A.T @ (A @ y - x) / Lip
+        zn = np.sign(u) * np.maximum(np.abs(u) - lam / Lip, 0.0)
+        sn = (1 + np.sqrt(1 + 4 * s * s)) / 2
+        y = zn + (s - 1) / sn * (zn - z)
+        if np.max(np.abs(zn - z)) < tol:
+            z = zn
+            break
+        z, s = zn, sn
+    return z
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_tiny_brute_force_explicit_toeplitz_lasso(seed):
+    # Problem (2) is a Lasso with a banded Toeplitz design (Sec. 2.1); solve it
+    # independently with FISTA on the explicit matrix.
+    X, D, _ = tiny_problem(seed, P=2, K=3, W=6, T=48, rho=0.1)
+    lam = 0.2 * oracle.lambda_max(X, D)
+    A = _toeplitz_design(D, X.shape[1])
+    zf = _fista(A, X.reshape(-1), lam).reshape(D.shape[0], -1)
+    Z, st, _ = oracle.lgcd(X, D, lam, 1e-12, 3)
+    assert st["converged"] == 1
+    np.testing.assert_allclose(Z, zf, atol=1e-8)
+    Ef = 0.5 * np.sum((X.reshape(-1) - A @ zf.reshape(-1)) ** 2) + lam * np.abs(zf).sum()
+    assert abs(oracle.objective(X, D, Z, lam) - Ef) <= 1e-10 * Ef
+
+
+def test_kkt_conditions_at_solution():
+    # Coordinate-wise optimality (Theorem A.1) in terms of
+    # g = beta - |D_k|^2 Z: |g - lambda sign z| <= |D|^2 eps on the support,
+    # |g| <= lambda + |D|^2 eps elsewhere.
+    X, D, _ = synth.workload(synth.SMALL, 1)
+    lam = 0.1 * oracle.lambda_max(X, D)
+    eps = 1e-6
+    Z, st, _ = oracle.lgcd(X, D, lam, eps, 4, cap=16)
+    n2 = oracle.norms(D)[:, None]
+    g = oracle.beta(X, D, Z) - n2 * Z
+    on = Z != 0
+    assert np.all(np.abs(g[on] - lam * np.sign(Z[on])) <= (n2 * eps * np.ones_like(Z))[on] * (1 + 1e-9))
+    assert np.all(np.abs(g[~on]) <= lam + (n2 * eps * np.ones_like(Z))[~on])
+    assert oracle.max_dz(X, D, Z, lam)[0] < eps
+
+
+def test_schedules_reach_the_same_solution():
+    # Theorem 1: every schedule converges to the same minimiser; eps-solutions
+    # of different schedules agree to the accuracy eps allows.
+    X, D, _ = synth.workload(synth.SMALL, 3)
+    lam = 0.1 * oracle.lambda_max(X, D)
+    ref, _, _ = oracle.lgcd(X, D, lam, 1e-11, 1)
+    Eref = oracle.objective(X, D, ref, lam)
+    runs = [
+        oracle.lgcd(X, D, lam, 1e-6, 4)[0],
+        oracle.lgcd(X, D, lam, 1e-6, 4, cap=1)[0],
+        oracle.lgcd(X, D, lam, 1e-6, 16, cap=8)[0],
+        oracle.lgcd(X, D, lam, 1e-6, 4, schedule=oracle.SCHED_SEQUENCE,
+                    seq=synth.segment_sequence(4, 50000, 9))[0],
+        oracle.lgcd(X, D, lam, 1e-6, 8, schedule=oracle.SCHED_SEQUENCE,
+                    seq=np.arange(8))[0],
+    ]
+    for Z in runs:
+        assert np.max(np.abs(Z - ref)) <= 1e-4
+        assert abs(oracle.objective(X, D, Z, lam) - Eref) <= 1e-9 * Eref
+
+
+def test_h1_coherence_of_generated_dictionaries():
+    # H1: |S_{k0,k1}[d]| / (|D_k0| |D_k1|) < 1 away from (k0 = k1, d = 0).
+    for w in (synth.SMALL, synth.PAPER):
+        _, D, _ = synth.generate(w.P, w.K, w.W, 4 * w.W, w.rho, w.sigma_noise, 0)
+        D = D.astype(np.float64)
+        S = oracle.s_table(D)
+        nrm = np.sqrt(oracle.norms(D))
+        C = S / (nrm[:, None, None] * nrm[None, :, None])
+        K, W = D.shape[0], D.shape[2]
+        C[np.arange(K), np.arange(K), W - 1] = 0.0
+        assert np.max(np.abs(C)) < 1.0
+
+
+def test_bad_arguments_rejected():
+    X, D, _ = tiny_problem(0)
+    with pytest.raises(ValueError):
+        oracle.lgcd(X, D, 0.0, 1e-6, 1)
+    with pytest.raises(ValueError):
+        oracle.lgcd(X, D, 1.0, 0.0, 1)
+    with pytest.raises(ValueError):        # segments shorter than 2W
+        oracle.lgcd(X, D, 1.0, 1e-6, 8)
