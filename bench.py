@@ -1,0 +1,175 @@
+"""Benchmark: time-to-eps and coordinate updates/s of LGCD on one MI355X.
+
+A step is one complete solve of the paper-shaped workload (P=7, K=25, W=200,
+T=150,000, Bernoulli(0.007) x N(0, 10^2) activations, noise sigma 0.1,
+lambda = 0.1 lambda_max, eps = 1e-6, float descent with double-precision
+stop test) with X already resident in HBM: beta init, lambda_max, the even/odd
+descent phases and the final double-precision check, through the C ABI.
+
+Prints one JSON line.  value = coordinate updates per second over the timed
+steps (whole job); ms_per_step = time-to-eps of one solve.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+PEAK_HBM_GBS = 8000.0
+KERNEL_SRC = os.path.join(ROOT, "paper_1705_10087_amd", "csrc", "kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "lgcd_phase_paper_shaped_traffic.json")
+
+
+def algorithmic_bytes_per_update(K, W, elem=4):
+    """S slice read + window of g read + written: 3 * K * (2W - 1) elements."""
+    return 3 * elem * K * (2 * W - 1)
+
+
+def kernel_sha():
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per LGCD launch from the committed rocprofv3 counter runs, or
+    None when they are missing or were taken on a different kernel source."""
+    try:
+        rec = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_src_sha") != kernel_sha():
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(X, D, lam, eps, M, cap):
+    import oracle
+    t0 = time.perf_counter()
+    Z, st, _ = oracle.lgcd(X.astype(np.float64), D.astype(np.float64), lam, eps, M, cap=cap)
+    dt = time.perf_counter() - t0
+    return {"value": st["n_updates"] / dt, "unit": "coord updates/s", "cores": 1,
+            "kind": "oracle", "time_to_eps_s": dt, "n_updates": int(st["n_updates"]),
+            "sample": f"one full solve of the same workload by the FP64 C oracle, even/odd "
+                      f"schedule, M={M}, update cap {cap}, single thread"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--cap", type=int, default=16, help="updates per segment per phase")
+    ap.add_argument("--n-seg", type=int, default=0, help="0 = library default (L // 2W)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-sweep", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU; --gpus "
+                                   f"{args.gpus} is not supported (multi-GPU sharding is "
+                                   "a design only)"}))
+        sys.exit(2)
+
+    import torch
+    import synth
+    import paper_1705_10087_amd as d
+
+    w = synth.PAPER
+    X, D, _ = synth.workload(w, args.seed)
+    K, P, W = D.shape
+    T = X.shape[1]
+    L = T - W + 1
+    dev = torch.device("cuda:0")
+    Xd = torch.from_numpy(X).to(dev)
+    Zd = torch.empty((K, L), dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    print(f"[bench] workload {w.name}; steps={args.steps} warmup={args.warmup}",
+          file=sys.stderr, flush=True)
+
+    with d.Context(update_cap=args.cap) as c:
+        c.set_dictionary(D)
+        for i in range(args.warmup):
+            _, st, _ = c.solve_device(Xd, -w.lam_rel, w.eps, args.n_seg, Zd, stream)
+        torch.cuda.synchronize()
+        stats = []
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            _, st, _ = c.solve_device(Xd, -w.lam_rel, w.eps, args.n_seg, Zd, stream)
+            stats.append(st)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        print(f"[bench] timed {args.steps} solves in {wall:.3f} s", file=sys.stderr, flush=True)
+
+    with d.Context(update_cap=args.cap, timing=1) as c:
+        c.set_dictionary(D)
+        _, tst, _ = c.solve_device(Xd, -w.lam_rel, w.eps, args.n_seg, Zd, stream)
+        torch.cuda.synchronize()
+
+    n_upd = sum(s["n_updates"] for s in stats)
+    ms_per_step = 1e3 * wall / args.steps
+    bpu = algorithmic_bytes_per_update(K, W)
+    launches = tst["n_phase_launches"]
+    kern_ms = tst["t_lgcd_kernel_ms"]
+    achieved = (tst["n_updates"] * bpu / launches) / (kern_ms / launches * 1e-3) / 1e9
+    traffic = measured_traffic()
+    s0 = stats[-1]
+    out = {
+        "metric": "time-to-eps (s) & coord updates/s on 1 MI355X; p50/p99 solve latency "
+                  "(served)",
+        "value": n_upd / wall,
+        "unit": "coord updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "time_to_eps_s": ms_per_step / 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "P": P, "K": K, "W": W, "T": T, "rho": w.rho,
+                   "sigma_noise": w.sigma_noise, "lambda": "0.1*lambda_max",
+                   "eps": w.eps, "n_seg": s0["n_seg"], "seg_len": s0["seg_len"],
+                   "update_cap": args.cap, "precision": "FP32 descent, FP64 stop test",
+                   "schedule": "even/odd", "seed": args.seed},
+        "solve": {"n_updates": s0["n_updates"], "n_phases": s0["n_phases"],
+                  "n_phase_launches": s0["n_phase_launches"], "n_refresh": s0["n_refresh"],
+                  "nnz": s0["nnz"], "objective": s0["objective"], "max_dz": s0["max_dz"],
+                  "converged": s0["converged"], "t_init_ms": s0["t_init_ms"],
+                  "t_cd_ms": s0["t_cd_ms"], "t_verify_ms": s0["t_verify_ms"]},
+        "roofline": {"kernel": "k_lgcd_phase", "bound": "hbm", "achieved": achieved,
+                     "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
+                     "traffic": traffic,
+                     "bytes_per_update": bpu,
+                     "updates_per_launch": tst["n_updates"] / launches,
+                     "avg_launch_us": 1e3 * kern_ms / launches,
+                     "launches": launches, "kernel_ms": kern_ms},
+    }
+    if not args.no_sweep:
+        sweep = []
+        with d.Context(update_cap=args.cap) as c:
+            c.set_dictionary(D)
+            for M in (8, 16, 32, 64, 128, 256, 374, 512):
+                try:
+                    t1 = time.perf_counter()
+                    _, st, _ = c.solve_device(Xd, -w.lam_rel, w.eps, M, Zd, stream)
+                    torch.cuda.synchronize()
+                    sweep.append({"n_seg": M, "time_to_eps_s": time.perf_counter() - t1,
+                                  "n_updates": st["n_updates"], "n_phases": st["n_phases"]})
+                except d.DicodError as e:
+                    sweep.append({"n_seg": M, "error": str(e)[:120]})
+        out["segment_sweep"] = sweep
+    if not args.no_cpu_baseline:
+        lam = s0["lambda"]
+        out["cpu_baseline"] = cpu_baseline(X, D, lam, w.eps, s0["n_seg"], args.cap)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

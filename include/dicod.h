@@ -1,0 +1,231 @@
+/*
+ * dicod.h -- C ABI of the MI355X (gfx950) library for convolutional sparse
+ * coding by locally greedy convolutional coordinate descent (LGCD).
+ *
+ * The problem (Moreau, Oudre & Vayatis, ICML 2018, Sec. 2.1, eq. (2)):
+ *
+ *     min_Z  E(Z) = 1/2 || X - sum_k Z_k * D_k ||_2^2 + lambda sum_k ||Z_k||_1
+ *
+ * with a signal X of P channels and length T, K atoms D_k of P channels and
+ * length W, and activations Z_k of length L = T - W + 1 (eq. (1)).  The
+ * solver runs the locally greedy coordinate descent of Algorithm 3 over M
+ * time segments (Sec. 2.2, the DICOD segments C_m): each segment picks the
+ * coordinate with the largest |Delta Z| (eq. (pb_coord)) inside itself and
+ * applies the beta update of eq. (3).  Segments of one parity run at the same
+ * time, one GPU workgroup each, then the other parity (even/odd schedule);
+ * an update whose window reaches a neighbouring segment writes the
+ * neighbour's state directly, which plays the part of the paper's boundary
+ * messages (Algorithm 2).  The run stops when every coordinate has
+ * |Delta Z| < eps (Sec. 2.1, last paragraph), checked in double precision.
+ *
+ * Conventions for every entry point:
+ *   - All arrays are dense, row-major (C order), and caller-owned.  The
+ *     library never keeps a caller pointer after a call returns.
+ *   - X is [P][T] (channel-major); D is [K][P][W]; Z is [K][L].
+ *   - Host pointers are plain CPU memory.  "_device" entry points take HIP
+ *     device pointers on the context's device instead.
+ *   - Return value: DICOD_OK (0) on success, DICOD_PENDING (1) from
+ *     dicod_poll while a request runs, a negative DICOD_E* code on error.
+ *     dicod_last_error() then describes the failure.  No C++ exception
+ *     crosses this interface.
+ *   - lambda > 0 is absolute.  lambda < 0 is relative: the library uses
+ *     |lambda| * lambda_max with lambda_max = max_{k,t} |(D^T X)_k[t]|, the
+ *     smallest value for which Z = 0 is optimal.  lambda == 0 or non-finite
+ *     is rejected (the paper requires lambda > 0).
+ *   - A context is used by one host thread at a time, except dicod_submit /
+ *     dicod_poll, which are internally synchronised.
+ */
+#ifndef DICOD_H
+#define DICOD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return codes ---------------------------------------------------- */
+#define DICOD_OK 0
+#define DICOD_PENDING 1
+#define DICOD_EINVAL (-1)   /* bad argument (message says which)            */
+#define DICOD_ENOMEM (-2)   /* device memory or HBM budget exhausted        */
+#define DICOD_EDEVICE (-3)  /* HIP runtime error                            */
+#define DICOD_ENOTCONV (-4) /* max_phases reached; Z holds the last iterate */
+#define DICOD_ENOREQ (-5)   /* unknown request id                           */
+#define DICOD_ENOTSUP (-6)  /* shape outside what the kernels support       */
+
+/* ---- precision policies ---------------------------------------------- */
+/* FP64: beta/g, S and Z in double throughout the descent.
+ * FP32: beta init and the final check in double; the descent keeps g in
+ *       float (Z in double) and is refreshed from a double recompute until
+ *       the double-precision stop test holds.
+ * MIXED: as FP32, but beta init uses split-bf16 MFMA with fp32 accumulation
+ *       (three products hi*hi + hi*lo + lo*hi); lambda_max is made exact by
+ *       recomputing the near-maximal entries in double.                    */
+#define DICOD_PREC_FP64 0
+#define DICOD_PREC_FP32 1
+#define DICOD_PREC_MIXED 2
+
+/* ---- schedules --------------------------------------------------------- */
+#define DICOD_SCHED_EVENODD 0
+
+typedef struct dicod_ctx dicod_ctx;
+
+typedef struct {
+    int device;              /* HIP device ordinal                                  */
+    int precision;           /* DICOD_PREC_*                                        */
+    int schedule;            /* DICOD_SCHED_*                                       */
+    int update_cap;          /* max updates per segment per phase; 0 = no cap        */
+    int64_t max_phases;      /* watchdog: phases before DICOD_ENOTCONV              */
+    int max_refresh;         /* double-precision verify-and-resume rounds (FP32)    */
+    int phases_per_poll;     /* phases launched between convergence polls (>= 1)    */
+    double inner_eps_factor; /* descent stops at eps * factor before the FP64 test  */
+    size_t hbm_budget_bytes; /* serving admission budget; 0 = 80% of free memory    */
+    int max_inflight;        /* serving: max signals on the device at once          */
+    int timing;              /* 1 = time every LGCD kernel launch with HIP events    */
+    int64_t trace_capacity;  /* update records kept for dicod_get_trace (0 = none)  */
+} dicod_config;
+
+typedef struct {
+    int64_t n_updates;        /* coordinate updates applied                         */
+    int64_t n_phases;         /* even/odd phases until the stop test held           */
+    int64_t n_phase_launches; /* LGCD kernel launches (>= n_phases)                 */
+    int64_t n_segment_runs;   /* segment runs that made at least one update         */
+    int64_t nnz;              /* non-zeros of the returned Z                        */
+    int n_seg;                /* segments M                                         */
+    int seg_len;              /* floor(L / M)                                       */
+    int converged;            /* 1 if max |Delta Z| < eps held in double            */
+    int n_refresh;            /* verify rounds that failed and refreshed g          */
+    double lambda;            /* lambda used                                        */
+    double lambda_max;        /* max |D^T X| (0 if lambda was absolute and unused)   */
+    double eps;
+    double objective;         /* E(Z), eq. (2), in double                            */
+    double max_dz;            /* max over all coordinates of |Delta Z|, in double    */
+    double kkt_on;            /* max |g - lambda sign z| / |D_k|^2 over the support  */
+    double kkt_off;           /* max (|g| - lambda)_+ / |D_k|^2 off the support       */
+    double max_abs_z;
+    double t_init_ms;         /* dictionary-independent setup + beta init            */
+    double t_cd_ms;           /* descent phases (wall time of the phase loop)       */
+    double t_verify_ms;       /* double-precision checks and refreshes              */
+    double t_total_ms;        /* whole call                                         */
+    double t_lgcd_kernel_ms;  /* sum of LGCD kernel durations (timing = 1)          */
+} dicod_stats;
+
+/* One record per applied update (dicod_get_trace); 32 bytes. */
+typedef struct {
+    int32_t phase;    /* even/odd phase index                 */
+    int32_t seg;      /* global segment index                 */
+    int32_t k0;       /* atom                                 */
+    int32_t n_local;  /* update index within the segment run  */
+    int64_t t0;       /* position within the signal           */
+    double delta;     /* applied change of Z_{k0}[t0]         */
+} dicod_trace_rec;
+
+/* Fills *cfg with the defaults: device 0, FP32, even/odd, update_cap 16,
+ * max_phases 1e6, max_refresh 8, phases_per_poll 16, inner_eps_factor 0.5,
+ * timing 0, no trace.  Returns DICOD_OK, or DICOD_EINVAL if cfg is NULL. */
+int dicod_config_init(dicod_config *cfg);
+
+/* Creates a context on cfg->device (cfg NULL = defaults) with its own HIP
+ * stream.  *out receives the context (NULL on failure).  Errors: EINVAL
+ * (bad config), EDEVICE (no such device / HIP failure). */
+int dicod_init(dicod_ctx **out, const dicod_config *cfg);
+
+/* Releases every device buffer, the stream and the context.  NULL is a no-op. */
+void dicod_finalize(dicod_ctx *ctx);
+
+/* Message of the last error on this context ("" if none); valid until the
+ * next call on the context.  ctx NULL gives the message of the last failed
+ * dicod_init on this thread. */
+const char *dicod_last_error(const dicod_ctx *ctx);
+
+/* Makes D (host, float [K][P][W]) the resident dictionary: copies it to the
+ * device and computes, in double on MFMA, the correlation table
+ * S_{k,l}[d] = sum_tau <D_k[tau], D_l[tau + d]> for |d| < W (eq. (3)) and the
+ * norms |D_k|^2 (eq. (pb_coord)).  Errors: EINVAL (NULL, K/P/W <= 0,
+ * non-finite entry, an atom of zero norm), ENOTSUP (K > 32 or P > 16),
+ * ENOMEM, EDEVICE. */
+int dicod_set_dictionary(dicod_ctx *ctx, const float *D, int K, int P, int W);
+
+/* Solves problem (2) for one signal with host buffers.
+ *   X      host float [P][T], T >= W
+ *   D      host float [K][P][W]; NULL = use the resident dictionary (then K, W
+ *          must match it); non-NULL replaces the resident dictionary
+ *   lambda see conventions above; eps > 0 is the stop threshold on |Delta Z|
+ *   n_seg  number of segments M; 0 = chosen by the library.  M > 1 requires
+ *          floor(L / M) >= 2W so that segments of one parity never touch the
+ *          same coordinates (Sec. 2.2: an update changes beta on 2W - 1
+ *          positions)
+ *   Z_out  host double [K][L], written on DICOD_OK and DICOD_ENOTCONV
+ *   st     optional statistics
+ * Errors: EINVAL, ENOTSUP (segment too long for the on-chip kernel), ENOMEM,
+ * EDEVICE, ENOTCONV. */
+int dicod_solve(dicod_ctx *ctx, const float *X, int P, int64_t T, const float *D,
+                int K, int W, double lambda, double eps, int n_seg, double *Z_out,
+                dicod_stats *st);
+
+/* As dicod_solve with the resident dictionary and device buffers:
+ *   X_dev device float [P][T]; Z_dev device double [K][L] (written).
+ *   stream: hipStream_t to order the work after (NULL = the context's own
+ *   stream); the call returns after the result is complete. */
+int dicod_solve_device(dicod_ctx *ctx, const float *X_dev, int64_t T, double lambda,
+                       double eps, int n_seg, double *Z_dev, dicod_stats *st,
+                       void *stream);
+
+/* Solves n_sig independent signals of different lengths against the resident
+ * dictionary in one set of launches: their segments are packed into the same
+ * even/odd phases (batching).
+ *   X_dev   device float, signal i is [P][T[i]] starting at element x_off[i]
+ *   T, x_off, z_off: host int64 arrays of n_sig entries
+ *   lambda  host double[n_sig] (each with the sign convention above)
+ *   n_seg   host int[n_sig] (0 = chosen per signal) or NULL (all chosen)
+ *   Z_dev   device double, signal i is [K][T[i]-W+1] starting at z_off[i]
+ *   st      optional host array of n_sig stats
+ * Errors as dicod_solve; EINVAL names the offending signal. */
+int dicod_solve_batch_device(dicod_ctx *ctx, int n_sig, const float *X_dev,
+                             const int64_t *T, const int64_t *x_off,
+                             const double *lambda, double eps, const int *n_seg,
+                             double *Z_dev, const int64_t *z_off, dicod_stats *st,
+                             void *stream);
+
+/* Correlation with the resident dictionary, out[k][t] = sum_{p,tau}
+ * D_k[p][tau] X[p][t + tau] for t < L (beta at Z = 0, Algorithm 1 init),
+ * computed on MFMA with the given precision (DICOD_PREC_FP64: double MFMA;
+ * DICOD_PREC_MIXED: split-bf16 MFMA with fp32 accumulation).  X host float
+ * [P][T]; out host double [K][L].  Errors: EINVAL, ENOMEM, EDEVICE. */
+int dicod_correlate(dicod_ctx *ctx, const float *X, int64_t T, int precision,
+                    double *out);
+
+/* Copies the resident correlation table to host double [K][K][2W-1] in the
+ * device layout S[l][k][d + W - 1] = S_{k,l}[d] (the slice a change of atom
+ * l applies, eq. (3)), and the norms to host double [K] (either may be NULL).
+ * Errors: EINVAL (no dictionary). */
+int dicod_get_s_table(dicod_ctx *ctx, double *S_out, double *norms_out);
+
+/* Copies up to cap update records of the last solve (in the order they were
+ * recorded; segments of one phase interleave) into out and the number
+ * available into *n.  Requires trace_capacity > 0 in the config. */
+int dicod_get_trace(dicod_ctx *ctx, dicod_trace_rec *out, int64_t cap, int64_t *n);
+
+/* ---- serving: continuous batching of encode requests ------------------- */
+/* Enqueues one signal (host float [P][T], copied before return) against the
+ * resident dictionary; a scheduler thread admits requests while the HBM
+ * budget and the in-flight limit allow, packs their segments into the
+ * running even/odd phases, and retires each one when its own stop test holds
+ * (requests that arrive while others run join the next phase).
+ * *req_id receives the request id.  Errors: EINVAL, ENOMEM (request larger
+ * than the whole budget), EDEVICE. */
+int dicod_submit(dicod_ctx *ctx, const float *X, int64_t T, double lambda,
+                 double eps, int n_seg, uint64_t *req_id);
+
+/* Non-blocking.  Returns DICOD_PENDING while the request runs; on completion
+ * writes Z (host double [K][L]) and st (optional), forgets the request and
+ * returns DICOD_OK (or the request's error code).  Unknown id: ENOREQ. */
+int dicod_poll(dicod_ctx *ctx, uint64_t req_id, double *Z_out, dicod_stats *st);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DICOD_H */

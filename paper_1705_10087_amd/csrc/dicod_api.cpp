@@ -1,0 +1,889 @@
+// Host runtime and C ABI (include/dicod.h) of the gfx950 LGCD library.
+//
+// Each solve follows Algorithm 3 of Moreau, Oudre & Vayatis (ICML 2018) over
+// M time segments (Sec. 2.2):
+//   1. beta at Z = 0 (Algorithm 1 init) on MFMA, in double;
+//   2. lambda = |lambda| * max |beta| when lambda is relative;
+//   3. even/odd phases of segment runs (kernels.hip: k_lgcd_phase) until two
+//      consecutive phases apply no update;
+//   4. a double-precision check of max |Delta Z| over all coordinates (the
+//      stop test of Sec. 2.1); in the FP32 policy a failed check refreshes g
+//      from the double recompute and resumes step 3.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <climits>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "dicod_internal.h"
+#include "dicod_serve.h"
+
+using namespace dicod;
+
+namespace {
+
+thread_local std::string g_init_error;
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t n = 0;
+    ~DevBuf() { release(); }
+    void release()
+    {
+        if (p)
+            (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+    template <typename T>
+    T* as() const { return static_cast<T*>(p); }
+};
+
+hipError_t ensure(DevBuf& b, size_t bytes)
+{
+    if (bytes == 0)
+        bytes = 16;
+    if (b.n >= bytes)
+        return hipSuccess;
+    b.release();
+    hipError_t e = hipMalloc(&b.p, bytes);
+    if (e == hipSuccess)
+        b.n = bytes;
+    else
+        b.p = nullptr;
+    return e;
+}
+
+struct Workspace {
+    DevBuf X, Zout;                       // staging for the host-pointer API
+    DevBuf beta0, g;                      // [K][L] per signal
+    DevBuf sig, segs, list0, list1;
+    DevBuf tilesL, tilesT, tilesA;
+    DevBuf dirty, phase_upd, sig_upd, sig_last, counters;
+    DevBuf part_r2, part6, results, lmax, done;
+    DevBuf trace;
+};
+
+}  // namespace
+
+struct dicod_ctx {
+    dicod_config cfg;
+    hipStream_t stream = nullptr;
+    std::string err;
+    // resident dictionary
+    bool has_dict = false;
+    int K = 0, P = 0, W = 0;
+    DevBuf D64, S64, S32, n2_64, inv64, n2_32, inv32;
+    Workspace ws;
+    unsigned long long* h_upd = nullptr;  // pinned copy of per-phase counts
+    size_t h_upd_cap = 0;
+    std::vector<hipEvent_t> ev_pool;
+    int64_t last_trace_n = 0;
+    dicod::Server* server = nullptr;
+};
+
+namespace {
+
+int fail(dicod_ctx* ctx, int code, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (ctx)
+        ctx->err = buf;
+    else
+        g_init_error = buf;
+    return code;
+}
+
+#define HIPCHECK(ctx, expr)                                                          \
+    do {                                                                             \
+        hipError_t _e = (expr);                                                      \
+        if (_e != hipSuccess)                                                        \
+            return fail((ctx), _e == hipErrorOutOfMemory ? DICOD_ENOMEM : DICOD_EDEVICE, \
+                        "%s: %s", #expr, hipGetErrorString(_e));                     \
+    } while (0)
+
+int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+double elapsed_ms(hipEvent_t a, hipEvent_t b)
+{
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, a, b) != hipSuccess)
+        return 0.0;
+    return (double)ms;
+}
+
+double now_ms()
+{
+    using namespace std::chrono;
+    return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+// Segment count M chosen by the library: the largest M with floor(L/M) >= 2W,
+// close to the paper's optimum M* ~ T / (2W) (Corollary 1).
+int auto_segments(int64_t L, int W)
+{
+    const int64_t M = L / (2 * (int64_t)W);
+    return M < 1 ? 1 : (int)std::min<int64_t>(M, INT32_MAX);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// config, init, finalize, errors
+// ---------------------------------------------------------------------------
+extern "C" int dicod_config_init(dicod_config* cfg)
+{
+    if (!cfg)
+        return DICOD_EINVAL;
+    std::memset(cfg, 0, sizeof *cfg);
+    cfg->device = 0;
+    cfg->precision = DICOD_PREC_FP32;
+    cfg->schedule = DICOD_SCHED_EVENODD;
+    cfg->update_cap = 16;
+    cfg->max_phases = 1000000;
+    cfg->max_refresh = 8;
+    cfg->phases_per_poll = 16;
+    cfg->inner_eps_factor = 0.5;
+    cfg->hbm_budget_bytes = 0;
+    cfg->max_inflight = 64;
+    cfg->timing = 0;
+    cfg->trace_capacity = 0;
+    return DICOD_OK;
+}
+
+extern "C" int dicod_init(dicod_ctx** out, const dicod_config* cfg)
+{
+    if (!out)
+        return fail(nullptr, DICOD_EINVAL, "dicod_init: out is NULL");
+    *out = nullptr;
+    dicod_config c;
+    if (cfg)
+        c = *cfg;
+    else
+        dicod_config_init(&c);
+    if (c.precision < DICOD_PREC_FP64 || c.precision > DICOD_PREC_MIXED)
+        return fail(nullptr, DICOD_EINVAL, "dicod_init: unknown precision %d", c.precision);
+    if (c.schedule != DICOD_SCHED_EVENODD)
+        return fail(nullptr, DICOD_EINVAL, "dicod_init: unknown schedule %d", c.schedule);
+    if (c.update_cap < 0 || c.max_phases < 2 || c.max_refresh < 0 ||
+        c.phases_per_poll < 1 || !(c.inner_eps_factor > 0.0 && c.inner_eps_factor <= 1.0) ||
+        c.trace_capacity < 0 || c.max_inflight < 1)
+        return fail(nullptr, DICOD_EINVAL, "dicod_init: invalid configuration field");
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0)
+        return fail(nullptr, DICOD_EDEVICE, "dicod_init: no HIP device visible");
+    if (c.device < 0 || c.device >= ndev)
+        return fail(nullptr, DICOD_EINVAL, "dicod_init: device %d out of range (%d devices)",
+                    c.device, ndev);
+    if (hipSetDevice(c.device) != hipSuccess)
+        return fail(nullptr, DICOD_EDEVICE, "dicod_init: hipSetDevice(%d) failed", c.device);
+    dicod_ctx* ctx = new (std::nothrow) dicod_ctx();
+    if (!ctx)
+        return fail(nullptr, DICOD_ENOMEM, "dicod_init: out of host memory");
+    ctx->cfg = c;
+    if (hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess) {
+        delete ctx;
+        return fail(nullptr, DICOD_EDEVICE, "dicod_init: hipStreamCreate failed");
+    }
+    *out = ctx;
+    return DICOD_OK;
+}
+
+extern "C" void dicod_finalize(dicod_ctx* ctx)
+{
+    if (!ctx)
+        return;
+    (void)hipSetDevice(ctx->cfg.device);
+    if (ctx->server) {
+        dicod::server_destroy(ctx->server);
+        ctx->server = nullptr;
+    }
+    if (ctx->stream)
+        (void)hipStreamSynchronize(ctx->stream);
+    for (hipEvent_t e : ctx->ev_pool)
+        (void)hipEventDestroy(e);
+    if (ctx->h_upd)
+        (void)hipHostFree(ctx->h_upd);
+    if (ctx->stream)
+        (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+}
+
+extern "C" const char* dicod_last_error(const dicod_ctx* ctx)
+{
+    return ctx ? ctx->err.c_str() : g_init_error.c_str();
+}
+
+// ---------------------------------------------------------------------------
+// dictionary
+// ---------------------------------------------------------------------------
+extern "C" int dicod_set_dictionary(dicod_ctx* ctx, const float* D, int K, int P, int W)
+{
+    if (!ctx)
+        return DICOD_EINVAL;
+    ctx->err.clear();
+    if (!D)
+        return fail(ctx, DICOD_EINVAL, "dicod_set_dictionary: D is NULL");
+    if (K <= 0 || P <= 0 || W <= 0)
+        return fail(ctx, DICOD_EINVAL, "dicod_set_dictionary: K=%d P=%d W=%d must be > 0",
+                    K, P, W);
+    if (P > kMaxP)
+        return fail(ctx, DICOD_ENOTSUP, "dicod_set_dictionary: P=%d > %d channels", P, kMaxP);
+    if ((int64_t)K * P * W > (int64_t)1 << 28)
+        return fail(ctx, DICOD_ENOTSUP, "dicod_set_dictionary: dictionary too large");
+    const size_t n = (size_t)K * P * W;
+    std::vector<double> d64(n);
+    for (size_t i = 0; i < n; ++i) {
+        if (!std::isfinite(D[i]))
+            return fail(ctx, DICOD_EINVAL, "dicod_set_dictionary: D[%zu] is not finite", i);
+        d64[i] = (double)D[i];
+    }
+    for (int k = 0; k < K; ++k) {
+        double s = 0.0;
+        for (size_t i = 0; i < (size_t)P * W; ++i)
+            s += d64[(size_t)k * P * W + i] * d64[(size_t)k * P * W + i];
+        if (!(s > 0.0))
+            return fail(ctx, DICOD_EINVAL, "dicod_set_dictionary: atom %d has zero norm", k);
+    }
+    HIPCHECK(ctx, hipSetDevice(ctx->cfg.device));
+    hipStream_t s = ctx->stream;
+    const int nd = 2 * W - 1;
+    const int Tp = 3 * W - 2;  // padded atom: W - 1 zeros, the atom, W - 1 zeros
+    std::vector<double> pad((size_t)K * P * Tp, 0.0);
+    for (int k = 0; k < K; ++k)
+        for (int p = 0; p < P; ++p)
+            for (int t = 0; t < W; ++t)
+                pad[((size_t)k * P + p) * Tp + (W - 1) + t] = d64[((size_t)k * P + p) * W + t];
+    std::vector<SigDesc> sd(K);
+    std::vector<int64_t> pref(K + 1, 0);
+    for (int k = 0; k < K; ++k) {
+        sd[k].x_off = (int64_t)k * P * Tp;
+        sd[k].z_off = (int64_t)k * K * nd;
+        sd[k].T = Tp;
+        sd[k].L = nd;
+        sd[k].seg_base = 0;
+        sd[k].M = 1;
+        sd[k].lam = 0.0;
+        pref[k + 1] = pref[k] + ceil_div(nd, kTile);
+    }
+    DevBuf dpad, dsig, dpref;
+    HIPCHECK(ctx, ensure(ctx->D64, n * sizeof(double)));
+    HIPCHECK(ctx, ensure(ctx->S64, (size_t)K * K * nd * sizeof(double)));
+    HIPCHECK(ctx, ensure(ctx->S32, (size_t)K * K * nd * sizeof(float)));
+    HIPCHECK(ctx, ensure(ctx->n2_64, K * sizeof(double)));
+    HIPCHECK(ctx, ensure(ctx->inv64, K * sizeof(double)));
+    HIPCHECK(ctx, ensure(ctx->n2_32, K * sizeof(float)));
+    HIPCHECK(ctx, ensure(ctx->inv32, K * sizeof(float)));
+    HIPCHECK(ctx, ensure(dpad, pad.size() * sizeof(double)));
+    HIPCHECK(ctx, ensure(dsig, sd.size() * sizeof(SigDesc)));
+    HIPCHECK(ctx, ensure(dpref, pref.size() * sizeof(int64_t)));
+    HIPCHECK(ctx, hipMemcpyAsync(ctx->D64.p, d64.data(), n * sizeof(double),
+                                 hipMemcpyHostToDevice, s));
+    HIPCHECK(ctx, hipMemcpyAsync(dpad.p, pad.data(), pad.size() * sizeof(double),
+                                 hipMemcpyHostToDevice, s));
+    HIPCHECK(ctx, hipMemcpyAsync(dsig.p, sd.data(), sd.size() * sizeof(SigDesc),
+                                 hipMemcpyHostToDevice, s));
+    HIPCHECK(ctx, hipMemcpyAsync(dpref.p, pref.data(), pref.size() * sizeof(int64_t),
+                                 hipMemcpyHostToDevice, s));
+    // S_{k,l}[d] as the correlation of every atom with every zero-padded atom.
+    HIPCHECK(ctx, launch_corr_f64_x64(ctx->D64.as<double>(), K, P, W, dpad.as<double>(),
+                                      dsig.as<SigDesc>(), dpref.as<int64_t>(), K,
+                                      pref[K], ctx->S64.as<double>(), s));
+    HIPCHECK(ctx, launch_dict_finish(ctx->S64.as<double>(), K, W, ctx->S32.as<float>(),
+                                     ctx->n2_64.as<double>(), ctx->inv64.as<double>(),
+                                     ctx->n2_32.as<float>(), ctx->inv32.as<float>(), s));
+    HIPCHECK(ctx, hipStreamSynchronize(s));
+    ctx->K = K;
+    ctx->P = P;
+    ctx->W = W;
+    ctx->has_dict = true;
+    return DICOD_OK;
+}
+
+extern "C" int dicod_get_s_table(dicod_ctx* ctx, double* S_out, double* norms_out)
+{
+    if (!ctx)
+        return DICOD_EINVAL;
+    if (!ctx->has_dict)
+        return fail(ctx, DICOD_EINVAL, "dicod_get_s_table: no resident dictionary");
+    HIPCHECK(ctx, hipSetDevice(ctx->cfg.device));
+    const size_t nS = (size_t)ctx->K * ctx->K * (2 * ctx->W - 1);
+    if (S_out)
+        HIPCHECK(ctx, hipMemcpy(S_out, ctx->S64.p, nS * sizeof(double), hipMemcpyDeviceToHost));
+    if (norms_out)
+        HIPCHECK(ctx, hipMemcpy(norms_out, ctx->n2_64.p, ctx->K * sizeof(double),
+                                hipMemcpyDeviceToHost));
+    return DICOD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// the solver
+// ---------------------------------------------------------------------------
+namespace {
+
+struct Plan {
+    std::vector<SigDesc> sig;
+    std::vector<SegDesc> segs;
+    std::vector<int32_t> list[2];
+    std::vector<int64_t> prefL, prefT, prefA;
+    int lm_max = 0, lext_max = 0;
+    size_t zext = 0;  // extent of the [K][L] arrays (elements)
+};
+
+int make_plan(dicod_ctx* ctx, int n_sig, const int64_t* T, const int64_t* x_off,
+              const double* lam, const int* n_seg, const int64_t* z_off, Plan& pl)
+{
+    const int K = ctx->K, W = ctx->W;
+    const bool fp64 = ctx->cfg.precision == DICOD_PREC_FP64;
+    pl.sig.resize(n_sig);
+    pl.prefL.assign(n_sig + 1, 0);
+    pl.prefT.assign(n_sig + 1, 0);
+    pl.prefA.assign(n_sig + 1, 0);
+    for (int i = 0; i < n_sig; ++i) {
+        if (T[i] < W)
+            return fail(ctx, DICOD_EINVAL, "signal %d: T=%lld < W=%d", i, (long long)T[i], W);
+        if (T[i] > (int64_t)INT32_MAX / 2)
+            return fail(ctx, DICOD_ENOTSUP, "signal %d: T=%lld too long", i, (long long)T[i]);
+        if (!std::isfinite(lam[i]) || lam[i] == 0.0)
+            return fail(ctx, DICOD_EINVAL, "signal %d: lambda must be finite and non-zero", i);
+        if (x_off[i] < 0 || z_off[i] < 0)
+            return fail(ctx, DICOD_EINVAL, "signal %d: negative offset", i);
+        const int64_t L = T[i] - W + 1;
+        int M = n_seg ? n_seg[i] : 0;
+        if (M < 0)
+            return fail(ctx, DICOD_EINVAL, "signal %d: n_seg=%d < 0", i, M);
+        if (M == 0)
+            M = auto_segments(L, W);
+        if (M > L)
+            return fail(ctx, DICOD_EINVAL, "signal %d: n_seg=%d > L=%lld", i, M, (long long)L);
+        if (M > 1 && L / M < 2 * (int64_t)W)
+            return fail(ctx, DICOD_EINVAL,
+                        "signal %d: n_seg=%d gives segments of %lld < 2W=%d coefficients", i,
+                        M, (long long)(L / M), 2 * W);
+        const int64_t lm = ceil_div(L, M);
+        int64_t lx = lm + 2 * (int64_t)(W - 1);
+        if (lx > L)
+            lx = L;
+        if (lgcd_lds_bytes(K, (int)lm, (int)lx, fp64) > kLdsBytes || lx > 4 * kPhaseThreads)
+            return fail(ctx, DICOD_ENOTSUP,
+                        "signal %d: segments of %lld coefficients do not fit the on-chip "
+                        "kernel (%zu bytes of LDS); use more segments", i, (long long)lm,
+                        lgcd_lds_bytes(K, (int)lm, (int)lx, fp64));
+        pl.lm_max = std::max(pl.lm_max, (int)lm);
+        pl.lext_max = std::max(pl.lext_max, (int)lx);
+        SigDesc& s = pl.sig[i];
+        s.x_off = x_off[i];
+        s.z_off = z_off[i];
+        s.T = T[i];
+        s.L = L;
+        s.seg_base = (int32_t)pl.segs.size();
+        s.M = M;
+        s.lam = lam[i];
+        for (int m = 0; m < M; ++m) {
+            SegDesc d;
+            d.z_off = z_off[i];
+            d.L = (int32_t)L;
+            d.b = (int32_t)(((__int128)m * L) / M);
+            d.e = (int32_t)(((__int128)(m + 1) * L) / M);
+            d.sig = i;
+            d.left = m > 0 ? s.seg_base + m - 1 : -1;
+            d.right = m < M - 1 ? s.seg_base + m + 1 : -1;
+            pl.list[m & 1].push_back(s.seg_base + m);
+            pl.segs.push_back(d);
+        }
+        pl.prefL[i + 1] = pl.prefL[i] + ceil_div(L, kTile);
+        pl.prefT[i + 1] = pl.prefT[i] + ceil_div(T[i], kTile);
+        pl.prefA[i + 1] = pl.prefA[i] + ceil_div((int64_t)K * L, 4096);
+        pl.zext = std::max(pl.zext, (size_t)(z_off[i] + (int64_t)K * L));
+    }
+    return DICOD_OK;
+}
+
+template <typename T>
+hipError_t upload(DevBuf& b, const std::vector<T>& v, hipStream_t s)
+{
+    hipError_t e = ensure(b, v.size() * sizeof(T));
+    if (e != hipSuccess || v.empty())
+        return e;
+    return hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s);
+}
+
+hipEvent_t pool_event(dicod_ctx* ctx, size_t i)
+{
+    while (ctx->ev_pool.size() <= i) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess)
+            return nullptr;
+        ctx->ev_pool.push_back(e);
+    }
+    return ctx->ev_pool[i];
+}
+
+}  // namespace
+
+namespace dicod {
+
+// Solves n_sig signals whose X and Z live on the device.  lam_in follows the
+// ABI sign convention.  st (optional) receives one entry per signal.
+int solve_device_batch(dicod_ctx* ctx, int n_sig, const float* dX, const int64_t* T,
+                       const int64_t* x_off, const double* lam_in, double eps,
+                       const int* n_seg, double* dZ, const int64_t* z_off,
+                       dicod_stats* st, hipStream_t s)
+{
+    const double t_call0 = now_ms();
+    if (!ctx->has_dict)
+        return fail(ctx, DICOD_EINVAL, "no resident dictionary (dicod_set_dictionary)");
+    if (n_sig <= 0 || !dX || !dZ || !T || !x_off || !lam_in || !z_off)
+        return fail(ctx, DICOD_EINVAL, "solve: NULL argument or n_sig <= 0");
+    if (!(eps > 0.0) || !std::isfinite(eps))
+        return fail(ctx, DICOD_EINVAL, "solve: eps must be finite and > 0");
+    if (ctx->cfg.precision == DICOD_PREC_MIXED)
+        return fail(ctx, DICOD_ENOTSUP, "solve: the MIXED policy is not available in this build");
+    const int K = ctx->K, P = ctx->P, W = ctx->W;
+    const bool fp64 = ctx->cfg.precision == DICOD_PREC_FP64;
+    const dicod_config& cfg = ctx->cfg;
+    Workspace& ws = ctx->ws;
+
+    Plan pl;
+    int rc = make_plan(ctx, n_sig, T, x_off, lam_in, n_seg, z_off, pl);
+    if (rc != DICOD_OK)
+        return rc;
+    const int n_seg_tot = (int)pl.segs.size();
+    const int64_t nL = pl.prefL[n_sig], nT = pl.prefT[n_sig], nA = pl.prefA[n_sig];
+    const int n_kblk = (K + kMaxK - 1) / kMaxK;
+    const int64_t max_ph = std::min<int64_t>(cfg.max_phases, (int64_t)1 << 22);
+
+    HIPCHECK(ctx, ensure(ws.beta0, pl.zext * sizeof(double)));
+    HIPCHECK(ctx, ensure(ws.g, pl.zext * (fp64 ? sizeof(double) : sizeof(float))));
+    HIPCHECK(ctx, ensure(ws.dirty, n_seg_tot * sizeof(uint32_t)));
+    HIPCHECK(ctx, ensure(ws.phase_upd, (size_t)(max_ph + 1) * sizeof(unsigned long long)));
+    HIPCHECK(ctx, ensure(ws.sig_upd, n_sig * sizeof(unsigned long long)));
+    HIPCHECK(ctx, ensure(ws.sig_last, n_sig * sizeof(int)));
+    HIPCHECK(ctx, ensure(ws.counters, sizeof(Counters)));
+    HIPCHECK(ctx, ensure(ws.part_r2, nT * sizeof(double)));
+    HIPCHECK(ctx, ensure(ws.part6, (size_t)nL * n_kblk * 6 * sizeof(double)));
+    HIPCHECK(ctx, ensure(ws.results, n_sig * sizeof(CheckResult)));
+    HIPCHECK(ctx, ensure(ws.lmax, n_sig * sizeof(unsigned long long)));
+    HIPCHECK(ctx, ensure(ws.done, n_sig * sizeof(uint32_t)));
+    if (cfg.trace_capacity > 0)
+        HIPCHECK(ctx, ensure(ws.trace, cfg.trace_capacity * sizeof(dicod_trace_rec)));
+    if ((size_t)(max_ph + 1) > ctx->h_upd_cap) {
+        if (ctx->h_upd)
+            (void)hipHostFree(ctx->h_upd);
+        ctx->h_upd = nullptr;
+        ctx->h_upd_cap = 0;
+        HIPCHECK(ctx, hipHostMalloc((void**)&ctx->h_upd,
+                                    (size_t)(max_ph + 1) * sizeof(unsigned long long),
+                                    hipHostMallocDefault));
+        ctx->h_upd_cap = (size_t)(max_ph + 1);
+    }
+    HIPCHECK(ctx, upload(ws.sig, pl.sig, s));
+    HIPCHECK(ctx, upload(ws.segs, pl.segs, s));
+    HIPCHECK(ctx, upload(ws.list0, pl.list[0], s));
+    HIPCHECK(ctx, upload(ws.list1, pl.list[1], s));
+    HIPCHECK(ctx, upload(ws.tilesL, pl.prefL, s));
+    HIPCHECK(ctx, upload(ws.tilesT, pl.prefT, s));
+    HIPCHECK(ctx, upload(ws.tilesA, pl.prefA, s));
+
+    hipEvent_t ev0 = pool_event(ctx, 0), ev1 = pool_event(ctx, 1);
+    hipEvent_t ev2 = pool_event(ctx, 2), ev3 = pool_event(ctx, 3);
+    if (!ev0 || !ev1 || !ev2 || !ev3)
+        return fail(ctx, DICOD_EDEVICE, "hipEventCreate failed");
+    HIPCHECK(ctx, hipEventRecord(ev0, s));
+
+    // ---- 1. beta at Z = 0 (double MFMA); g starts equal to it -------------
+    HIPCHECK(ctx, launch_corr_f64_x32(ctx->D64.as<double>(), K, P, W, dX, ws.sig.as<SigDesc>(),
+                                      ws.tilesL.as<int64_t>(), n_sig, nL, ws.beta0.as<double>(),
+                                      fp64 ? nullptr : ws.g.as<float>(),
+                                      fp64 ? ws.g.as<double>() : nullptr, s));
+    // ---- 2. lambda --------------------------------------------------------
+    std::vector<double> lmax(n_sig, 0.0);
+    bool any_rel = false;
+    for (int i = 0; i < n_sig; ++i)
+        any_rel |= lam_in[i] < 0.0;
+    if (any_rel) {
+        HIPCHECK(ctx, launch_fill_u64(ws.lmax.as<unsigned long long>(), 0ull, n_sig, s));
+        HIPCHECK(ctx, launch_absmax(ws.beta0.as<double>(), K, ws.sig.as<SigDesc>(),
+                                    ws.tilesA.as<int64_t>(), n_sig, nA,
+                                    ws.lmax.as<unsigned long long>(), s));
+        std::vector<unsigned long long> bits(n_sig);
+        HIPCHECK(ctx, hipMemcpyAsync(bits.data(), ws.lmax.p, n_sig * sizeof(unsigned long long),
+                                     hipMemcpyDeviceToHost, s));
+        HIPCHECK(ctx, hipStreamSynchronize(s));
+        for (int i = 0; i < n_sig; ++i) {
+            double v;
+            std::memcpy(&v, &bits[i], sizeof v);
+            lmax[i] = v;
+            if (lam_in[i] < 0.0) {
+                pl.sig[i].lam = -lam_in[i] * v;
+                if (!(pl.sig[i].lam > 0.0))
+                    pl.sig[i].lam = 1e-300;  // X orthogonal to every atom: Z = 0
+            }
+        }
+        HIPCHECK(ctx, upload(ws.sig, pl.sig, s));
+    }
+    // ---- 3. descent state -------------------------------------------------
+    for (int i = 0; i < n_sig; ++i)
+        HIPCHECK(ctx, launch_fill_f64(dZ + pl.sig[i].z_off, 0.0,
+                                      (size_t)K * pl.sig[i].L, s));
+    HIPCHECK(ctx, launch_fill_u32(ws.dirty.as<uint32_t>(), 1u, n_seg_tot, s));
+    HIPCHECK(ctx, launch_fill_u64(ws.phase_upd.as<unsigned long long>(), 0ull, max_ph + 1, s));
+    HIPCHECK(ctx, launch_fill_u64(ws.sig_upd.as<unsigned long long>(), 0ull, n_sig, s));
+    HIPCHECK(ctx, launch_fill_u32(ws.done.as<uint32_t>(), 0u, n_sig, s));
+    HIPCHECK(ctx, launch_fill_u32((uint32_t*)ws.sig_last.p, 0xffffffffu, n_sig, s));
+    HIPCHECK(ctx, launch_fill_u64((unsigned long long*)ws.counters.p, 0ull,
+                                  sizeof(Counters) / 8, s));
+    HIPCHECK(ctx, hipEventRecord(ev1, s));
+
+    PhaseArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.segs = ws.segs.as<SegDesc>();
+    a.g = ws.g.p;
+    a.Z = dZ;
+    a.S = fp64 ? ctx->S64.p : ctx->S32.p;
+    a.n2 = fp64 ? ctx->n2_64.p : ctx->n2_32.p;
+    a.inv_n2 = fp64 ? ctx->inv64.p : ctx->inv32.p;
+    a.sigs = ws.sig.as<SigDesc>();
+    a.K = K;
+    a.W = W;
+    // update_cap 0 means "run each segment to local convergence"; a finite
+    // bound still guarantees that every workgroup exits.
+    a.cap = cfg.update_cap > 0 ? cfg.update_cap : kRunUpdateBound;
+    a.eps_stop = fp64 ? eps : eps * cfg.inner_eps_factor;
+    a.dirty = ws.dirty.as<uint32_t>();
+    a.phase_upd = ws.phase_upd.as<unsigned long long>();
+    a.sig_upd = ws.sig_upd.as<unsigned long long>();
+    a.sig_last_upd = ws.sig_last.as<int>();
+    a.counters = ws.counters.as<Counters>();
+    a.trace = cfg.trace_capacity > 0 ? ws.trace.as<dicod_trace_rec>() : nullptr;
+    a.trace_cap = cfg.trace_capacity;
+    a.lm_max = pl.lm_max;
+    a.lext_max = pl.lext_max;
+
+    int64_t phase = 0, n_launch = 0, conv_phase = -1;
+    int n_refresh = 0;
+    bool accepted = false, out_of_phases = false;
+    double t_cd = 0.0, t_verify = 0.0, t_kernel = 0.0;
+    std::vector<CheckResult> res(n_sig);
+    std::vector<uint32_t> done(n_sig, 0u);
+
+    for (;;) {
+        // ---- 3. even/odd phases until two consecutive phases apply nothing
+        HIPCHECK(ctx, hipEventRecord(ev2, s));
+        const int64_t start = phase;
+        conv_phase = -1;
+        while (conv_phase < 0) {
+            if (phase >= max_ph) {
+                out_of_phases = true;
+                break;
+            }
+            // In float, rounding noise near the stop threshold can keep a few
+            // coordinates changing for ever; after a bounded number of phases
+            // the double-precision test decides instead.
+            if (!fp64 && phase - start >= kRoundPhaseLimit)
+                break;
+            const int64_t chunk = std::min<int64_t>(cfg.phases_per_poll, max_ph - phase);
+            size_t evi = 4;
+            for (int64_t c = 0; c < chunk; ++c, ++phase) {
+                const int par = (int)(phase & 1);
+                a.list = par ? ws.list1.as<int32_t>() : ws.list0.as<int32_t>();
+                a.n_list = (int)pl.list[par].size();
+                a.phase = (int)phase;
+                if (a.n_list == 0)
+                    continue;
+                hipEvent_t e0 = nullptr, e1 = nullptr;
+                if (cfg.timing) {
+                    e0 = pool_event(ctx, evi++);
+                    e1 = pool_event(ctx, evi++);
+                    if (!e0 || !e1)
+                        return fail(ctx, DICOD_EDEVICE, "hipEventCreate failed");
+                    HIPCHECK(ctx, hipEventRecord(e0, s));
+                }
+                size_t lds = 0;
+                hipError_t e = launch_lgcd_phase(a, fp64, &lds, s);
+                if (e != hipSuccess)
+                    return fail(ctx, DICOD_EDEVICE, "LGCD phase launch (%zu bytes LDS): %s",
+                                lds, hipGetErrorString(e));
+                ++n_launch;
+                if (cfg.timing)
+                    HIPCHECK(ctx, hipEventRecord(e1, s));
+            }
+            const int64_t from = std::max<int64_t>(start, phase - chunk - 1);
+            HIPCHECK(ctx, hipMemcpyAsync(ctx->h_upd + from, ws.phase_upd.as<unsigned long long>() + from,
+                                         (size_t)(phase - from) * sizeof(unsigned long long),
+                                         hipMemcpyDeviceToHost, s));
+            HIPCHECK(ctx, hipStreamSynchronize(s));
+            if (cfg.timing)
+                for (size_t i = 4; i < evi; i += 2)
+                    t_kernel += elapsed_ms(ctx->ev_pool[i], ctx->ev_pool[i + 1]);
+            for (int64_t p = std::max<int64_t>(start + 1, from + 1); p < phase; ++p)
+                if (ctx->h_upd[p] == 0 && ctx->h_upd[p - 1] == 0) {
+                    conv_phase = p;
+                    break;
+                }
+        }
+        HIPCHECK(ctx, hipEventRecord(ev3, s));
+        HIPCHECK(ctx, hipEventSynchronize(ev3));
+        t_cd += elapsed_ms(ev2, ev3);
+
+        // ---- 4. double-precision stop test (and refresh of g) --------------
+        HIPCHECK(ctx, hipEventRecord(ev2, s));
+        HIPCHECK(ctx, launch_resid(dX, ctx->D64.as<double>(), dZ, K, P, W, ws.sig.as<SigDesc>(),
+                                   ws.tilesT.as<int64_t>(), n_sig, nT, ws.part_r2.as<double>(), s));
+        HIPCHECK(ctx, launch_grad_check(ws.beta0.as<double>(), dZ, ctx->S64.as<double>(),
+                                        ctx->n2_64.as<double>(), K, W, ws.sig.as<SigDesc>(),
+                                        ws.tilesL.as<int64_t>(), n_sig, nL, a.eps_stop,
+                                        ws.done.as<uint32_t>(), ws.dirty.as<uint32_t>(),
+                                        ws.g.p, fp64,
+                                        ws.part6.as<double>(), s));
+        HIPCHECK(ctx, launch_check_reduce(ws.part_r2.as<double>(), ws.tilesT.as<int64_t>(),
+                                          ws.part6.as<double>(), ws.tilesL.as<int64_t>(), nL,
+                                          n_kblk, n_sig, ws.results.as<CheckResult>(), s));
+        HIPCHECK(ctx, hipMemcpyAsync(res.data(), ws.results.p, n_sig * sizeof(CheckResult),
+                                     hipMemcpyDeviceToHost, s));
+        HIPCHECK(ctx, hipEventRecord(ev3, s));
+        HIPCHECK(ctx, hipEventSynchronize(ev3));
+        t_verify += elapsed_ms(ev2, ev3);
+        accepted = true;
+        for (int i = 0; i < n_sig; ++i) {
+            done[i] = res[i].max_dz < eps ? 1u : 0u;
+            accepted &= done[i] != 0u;
+        }
+        if (accepted || out_of_phases || n_refresh >= cfg.max_refresh)
+            break;
+        // Signals that passed are frozen; the others had g refreshed and their
+        // offending segments marked dirty.  Resuming on an even phase keeps a
+        // signal's sequence of segment runs independent of its co-runners.
+        ++n_refresh;
+        HIPCHECK(ctx, upload(ws.done, done, s));
+        if (phase & 1)
+            ++phase;
+    }
+
+    std::vector<unsigned long long> supd(n_sig);
+    std::vector<int> slast(n_sig);
+    Counters cnt;
+    HIPCHECK(ctx, hipMemcpyAsync(supd.data(), ws.sig_upd.p, n_sig * sizeof(unsigned long long),
+                                 hipMemcpyDeviceToHost, s));
+    HIPCHECK(ctx, hipMemcpyAsync(slast.data(), ws.sig_last.p, n_sig * sizeof(int),
+                                 hipMemcpyDeviceToHost, s));
+    HIPCHECK(ctx, hipMemcpyAsync(&cnt, ws.counters.p, sizeof cnt, hipMemcpyDeviceToHost, s));
+    HIPCHECK(ctx, hipStreamSynchronize(s));
+    ctx->last_trace_n = (int64_t)cnt.trace_n;
+    const double t_init = elapsed_ms(ev0, ev1);
+    const double t_total = now_ms() - t_call0;
+    if (st) {
+        for (int i = 0; i < n_sig; ++i) {
+            dicod_stats& o = st[i];
+            std::memset(&o, 0, sizeof o);
+            o.n_updates = (int64_t)supd[i];
+            o.n_phases = n_sig == 1 ? (conv_phase >= 0 ? conv_phase + 1 : phase)
+                                    : std::min<int64_t>(phase, (int64_t)slast[i] + 3);
+            o.n_phase_launches = n_launch;
+            o.n_segment_runs = (int64_t)cnt.seg_runs;
+            o.nnz = (int64_t)res[i].nnz;
+            o.n_seg = pl.sig[i].M;
+            o.seg_len = (int)(pl.sig[i].L / pl.sig[i].M);
+            o.converged = res[i].max_dz < eps ? 1 : 0;
+            o.n_refresh = n_refresh;
+            o.lambda = pl.sig[i].lam;
+            o.lambda_max = lmax[i];
+            o.eps = eps;
+            o.objective = 0.5 * res[i].sum_r2 + pl.sig[i].lam * res[i].l1;
+            o.max_dz = res[i].max_dz;
+            o.kkt_on = res[i].kkt_on;
+            o.kkt_off = res[i].kkt_off;
+            o.max_abs_z = res[i].max_abs_z;
+            o.t_init_ms = t_init;
+            o.t_cd_ms = t_cd;
+            o.t_verify_ms = t_verify;
+            o.t_total_ms = t_total;
+            o.t_lgcd_kernel_ms = t_kernel;
+        }
+    }
+    if (!accepted)
+        return fail(ctx, DICOD_ENOTCONV,
+                    out_of_phases ? "max_phases reached before the stop test held"
+                                  : "double-precision stop test failed after max_refresh "
+                                    "refreshes");
+    return DICOD_OK;
+}
+
+}  // namespace dicod
+
+// ---------------------------------------------------------------------------
+// public solve entry points
+// ---------------------------------------------------------------------------
+extern "C" int dicod_solve_device(dicod_ctx* ctx, const float* X_dev, int64_t T,
+                                  double lambda, double eps, int n_seg, double* Z_dev,
+                                  dicod_stats* st, void* stream)
+{
+    if (!ctx)
+        return DICOD_EINVAL;
+    ctx->err.clear();
+    HIPCHECK(ctx, hipSetDevice(ctx->cfg.device));
+    const int64_t zero = 0;
+    return solve_device_batch(ctx, 1, X_dev, &T, &zero, &lambda, eps, &n_seg, Z_dev, &zero,
+                              st, stream ? (hipStream_t)stream : ctx->stream);
+}
+
+extern "C" int dicod_solve_batch_device(dicod_ctx* ctx, int n_sig, const float* X_dev,
+                                        const int64_t* T, const int64_t* x_off,
+                                        const double* lambda, double eps, const int* n_seg,
+                                        double* Z_dev, const int64_t* z_off,
+                                        dicod_stats* st, void* stream)
+{
+    if (!ctx)
+        return DICOD_EINVAL;
+    ctx->err.clear();
+    HIPCHECK(ctx, hipSetDevice(ctx->cfg.device));
+    return solve_device_batch(ctx, n_sig, X_dev, T, x_off, lambda, eps, n_seg, Z_dev, z_off,
+                              st, stream ? (hipStream_t)stream : ctx->stream);
+}
+
+extern "C" int dicod_solve(dicod_ctx* ctx, const float* X, int P, int64_t T, const float* D,
+                           int K, int W, double lambda, double eps, int n_seg, double* Z_out,
+                           dicod_stats* st)
+{
+    if (!ctx)
+        return DICOD_EINVAL;
+    ctx->err.clear();
+    if (!X || !Z_out)
+        return fail(ctx, DICOD_EINVAL, "dicod_solve: X or Z_out is NULL");
+    if (P <= 0 || K <= 0 || W <= 0)
+        return fail(ctx, DICOD_EINVAL, "dicod_solve: K=%d P=%d W=%d must be > 0", K, P, W);
+    if (T < W)
+        return fail(ctx, DICOD_EINVAL, "dicod_solve: T=%lld < W=%d", (long long)T, W);
+    if (D) {
+        int rc = dicod_set_dictionary(ctx, D, K, P, W);
+        if (rc != DICOD_OK)
+            return rc;
+    } else if (!ctx->has_dict || ctx->K != K || ctx->P != P || ctx->W != W) {
+        return fail(ctx, DICOD_EINVAL,
+                    "dicod_solve: D is NULL and the resident dictionary does not match");
+    }
+    const size_t nx = (size_t)P * T;
+    for (size_t i = 0; i < nx; ++i)
+        if (!std::isfinite(X[i]))
+            return fail(ctx, DICOD_EINVAL, "dicod_solve: X[%zu] is not finite", i);
+    HIPCHECK(ctx, hipSetDevice(ctx->cfg.device));
+    const int64_t L = T - W + 1;
+    const size_t nz = (size_t)K * L;
+    HIPCHECK(ctx, ensure(ctx->ws.X, nx * sizeof(float)));
+    HIPCHECK(ctx, ensure(ctx->ws.Zout, nz * sizeof(double)));
+    HIPCHECK(ctx, hipMemcpyAsync(ctx->ws.X.p, X, nx * sizeof(float), hipMemcpyHostToDevice,
+                                 ctx->stream));
+    const int64_t zero = 0;
+    int rc = solve_device_batch(ctx, 1, ctx->ws.X.as<float>(), &T, &zero, &lambda, eps, &n_seg,
+                                ctx->ws.Zout.as<double>(), &zero, st, ctx->stream);
+    if (rc == DICOD_OK || rc == DICOD_ENOTCONV) {
+        hipError_t e = hipMemcpy(Z_out, ctx->ws.Zout.p, nz * sizeof(double),
+                                 hipMemcpyDeviceToHost);
+        if (e != hipSuccess)
+            return fail(ctx, DICOD_EDEVICE, "copy of Z: %s", hipGetErrorString(e));
+    }
+    return rc;
+}
+
+extern "C" int dicod_correlate(dicod_ctx* ctx, const float* X, int64_t T, int precision,
+                               double* out)
+{
+    if (!ctx)
+        return DICOD_EINVAL;
+    ctx->err.clear();
+    if (!X || !out)
+        return fail(ctx, DICOD_EINVAL, "dicod_correlate: NULL argument");
+    if (!ctx->has_dict)
+        return fail(ctx, DICOD_EINVAL, "dicod_correlate: no resident dictionary");
+    const int K = ctx->K, P = ctx->P, W = ctx->W;
+    if (T < W)
+        return fail(ctx, DICOD_EINVAL, "dicod_correlate: T < W");
+    if (precision != DICOD_PREC_FP64)
+        return fail(ctx, DICOD_ENOTSUP, "dicod_correlate: precision %d not available", precision);
+    HIPCHECK(ctx, hipSetDevice(ctx->cfg.device));
+    hipStream_t s = ctx->stream;
+    const int64_t L = T - W + 1;
+    std::vector<SigDesc> sd(1);
+    sd[0].x_off = 0;
+    sd[0].z_off = 0;
+    sd[0].T = T;
+    sd[0].L = L;
+    sd[0].seg_base = 0;
+    sd[0].M = 1;
+    sd[0].lam = 0.0;
+    std::vector<int64_t> pref = {0, ceil_div(L, kTile)};
+    DevBuf dx, dout, dsig, dpref;
+    HIPCHECK(ctx, ensure(dx, (size_t)P * T * sizeof(float)));
+    HIPCHECK(ctx, ensure(dout, (size_t)K * L * sizeof(double)));
+    HIPCHECK(ctx, upload(dsig, sd, s));
+    HIPCHECK(ctx, upload(dpref, pref, s));
+    HIPCHECK(ctx, hipMemcpyAsync(dx.p, X, (size_t)P * T * sizeof(float), hipMemcpyHostToDevice, s));
+    HIPCHECK(ctx, launch_corr_f64_x32(ctx->D64.as<double>(), K, P, W, dx.as<float>(),
+                                      dsig.as<SigDesc>(), dpref.as<int64_t>(), 1, pref[1],
+                                      dout.as<double>(), nullptr, nullptr, s));
+    HIPCHECK(ctx, hipMemcpyAsync(out, dout.p, (size_t)K * L * sizeof(double),
+                                 hipMemcpyDeviceToHost, s));
+    HIPCHECK(ctx, hipStreamSynchronize(s));
+    return DICOD_OK;
+}
+
+extern "C" int dicod_get_trace(dicod_ctx* ctx, dicod_trace_rec* out, int64_t cap, int64_t* n)
+{
+    if (!ctx)
+        return DICOD_EINVAL;
+    if (!n || (cap > 0 && !out))
+        return fail(ctx, DICOD_EINVAL, "dicod_get_trace: NULL argument");
+    if (ctx->cfg.trace_capacity <= 0)
+        return fail(ctx, DICOD_EINVAL, "dicod_get_trace: trace_capacity is 0");
+    int64_t avail = std::min<int64_t>(ctx->last_trace_n, ctx->cfg.trace_capacity);
+    *n = avail;
+    int64_t cnt = std::min<int64_t>(avail, cap);
+    if (cnt > 0) {
+        HIPCHECK(ctx, hipSetDevice(ctx->cfg.device));
+        HIPCHECK(ctx, hipMemcpy(out, ctx->ws.trace.p, (size_t)cnt * sizeof(dicod_trace_rec),
+                                hipMemcpyDeviceToHost));
+    }
+    return DICOD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// serving (dicod_serve.cpp)
+// ---------------------------------------------------------------------------
+extern "C" int dicod_submit(dicod_ctx* ctx, const float* X, int64_t T, double lambda,
+                            double eps, int n_seg, uint64_t* req_id)
+{
+    if (!ctx)
+        return DICOD_EINVAL;
+    return dicod::server_submit(ctx, X, T, lambda, eps, n_seg, req_id);
+}
+
+extern "C" int dicod_poll(dicod_ctx* ctx, uint64_t req_id, double* Z_out, dicod_stats* st)
+{
+    if (!ctx)
+        return DICOD_EINVAL;
+    return dicod::server_poll(ctx, req_id, Z_out, st);
+}
+
+// Accessors used by the serving module.
+namespace dicod {
+dicod::Server*& ctx_server(dicod_ctx* ctx) { return ctx->server; }
+const dicod_config& ctx_config(const dicod_ctx* ctx) { return ctx->cfg; }
+int ctx_dims(const dicod_ctx* ctx, int* K, int* P, int* W)
+{
+    *K = ctx->K;
+    *P = ctx->P;
+    *W = ctx->W;
+    return ctx->has_dict ? 1 : 0;
+}
+int ctx_fail(dicod_ctx* ctx, int code, const char* msg) { return fail(ctx, code, "%s", msg); }
+}  // namespace dicod

@@ -1,0 +1,150 @@
+// Internal declarations shared by the host runtime (dicod_api.cpp) and the
+// gfx950 kernels (kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "dicod.h"
+
+namespace dicod {
+
+constexpr int kMaxK = 32;        // atoms handled by the verify kernels per pass
+constexpr int kMaxP = 16;        // channels handled by the residual kernel
+constexpr int kPhaseThreads = 512;
+constexpr int kTile = 256;       // positions per workgroup in the tiled kernels
+constexpr size_t kLdsBytes = 163840;  // LDS per workgroup on gfx950
+constexpr int kRunUpdateBound = 1 << 16;  // updates per segment run when uncapped
+constexpr int64_t kRoundPhaseLimit = 4096; // float descent phases between checks
+
+// One signal of a (possibly batched) solve.
+struct SigDesc {
+    int64_t x_off;    // element offset of X_i ([P][T] row-major)
+    int64_t z_off;    // element offset of the [K][L] arrays (g, Z, beta0)
+    int64_t T;        // samples
+    int64_t L;        // T - W + 1
+    int32_t seg_base; // global index of its first segment
+    int32_t M;        // number of segments
+    double lam;       // lambda used
+};
+
+// One time segment C_m of one signal.
+struct SegDesc {
+    int64_t z_off;  // element offset of the signal's [K][L] arrays
+    int32_t L;      // signal length in coefficients
+    int32_t b, e;   // segment covers t in [b, e)
+    int32_t sig;    // signal index
+    int32_t left;   // neighbour segment indices, -1 at the signal ends
+    int32_t right;
+};
+
+// Per-signal results of the double-precision check, reduced from partials.
+struct CheckResult {
+    double max_dz;
+    double kkt_on;
+    double kkt_off;
+    double l1;
+    double sum_r2;
+    double max_abs_z;
+    double nnz;
+    double pad;
+};
+
+// Device-side counters of one solve.
+struct Counters {
+    unsigned long long seg_runs;   // segment runs that made at least one update
+    unsigned long long trace_n;    // trace records requested
+};
+
+// ---- launchers (kernels.hip) ------------------------------------------------
+hipError_t launch_fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t s);
+hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, size_t n,
+                           hipStream_t s);
+hipError_t launch_fill_f64(double* p, double v, size_t n, hipStream_t s);
+
+// out[b][k][t] = sum_{p,tau} D[k][p][tau] Y_b[p][t + tau] in double on MFMA
+// (f64 16x16x4).  Signals/tiles are described by sig[] and tile_pref[].
+hipError_t launch_corr_f64_x32(const double* D, int K, int P, int W, const float* Y,
+                               const SigDesc* sig, const int64_t* tile_pref,
+                               int n_sig, int64_t n_tiles, double* out64,
+                               float* g32, double* g64, hipStream_t s);
+hipError_t launch_corr_f64_x64(const double* D, int K, int P, int W,
+                               const double* Y, const SigDesc* sig,
+                               const int64_t* tile_pref, int n_sig,
+                               int64_t n_tiles, double* out64, hipStream_t s);
+// Same contraction with split-bf16 MFMA (16x16x32 bf16, fp32 accumulation).
+hipError_t launch_corr_bf16x3(const float* Dhi_lo, int K, int P, int W,
+                              const float* Y, const SigDesc* sig,
+                              const int64_t* tile_pref, int n_sig, int64_t n_tiles,
+                              float* out32, hipStream_t s);
+
+// Dictionary finish: S32 = (float)S64, n2 = S64[k][k][W-1], inverses.
+hipError_t launch_dict_finish(const double* S64, int K, int W, float* S32,
+                              double* n2_64, double* inv_n2_64, float* n2_32,
+                              float* inv_n2_32, hipStream_t s);
+
+// Per-signal max |beta| as the bit pattern of a non-negative double.
+hipError_t launch_absmax(const double* beta, int K, const SigDesc* sig,
+                         const int64_t* tile_pref, int n_sig, int64_t n_tiles,
+                         unsigned long long* out_bits, hipStream_t s);
+
+// One even/odd phase of locally greedy CD over the segments in list[].
+struct PhaseArgs {
+    const SegDesc* segs;
+    const int32_t* list;
+    int n_list;
+    void* g;              // float or double state [K][L] per signal
+    double* Z;            // double [K][L] per signal
+    const void* S;        // [K][K][2W-1] in the state's type
+    const void* n2;       // [K]
+    const void* inv_n2;   // [K]
+    const SigDesc* sigs;
+    int K, W, cap;
+    double eps_stop;
+    int phase;
+    uint32_t* dirty;
+    unsigned long long* phase_upd;
+    unsigned long long* sig_upd;   // per-signal applied updates
+    int* sig_last_upd;
+    Counters* counters;
+    dicod_trace_rec* trace;
+    long long trace_cap;
+    int lm_max, lext_max;
+};
+hipError_t launch_lgcd_phase(const PhaseArgs& a, bool fp64, size_t* lds_bytes,
+                             hipStream_t s);
+size_t lgcd_lds_bytes(int K, int lm_max, int lext_max, bool fp64);
+
+// Double-precision check: residual energy per tile (partials).
+hipError_t launch_resid(const float* X, const double* D, const double* Z, int K,
+                        int P, int W, const SigDesc* sig, const int64_t* tile_pref,
+                        int n_sig, int64_t n_tiles, double* part_r2,
+                        hipStream_t s);
+// g = beta0 - S * Z, candidates in double, KKT partials, dirty flags for
+// segments holding a coordinate with |Delta Z| >= flag_eps, optional refresh
+// of the state g (float or double).
+hipError_t launch_grad_check(const double* beta0, const double* Z,
+                             const double* S64, const double* n2, int K, int W,
+                             const SigDesc* sig, const int64_t* tile_pref, int n_sig,
+                             int64_t n_tiles, double flag_eps, const uint32_t* sig_done,
+                             uint32_t* dirty, void* g_state, bool state_fp64,
+                             double* part6, hipStream_t s);
+hipError_t launch_check_reduce(const double* part_r2, const int64_t* tile_pref_T,
+                               const double* part6, const int64_t* tile_pref_L,
+                               int64_t n_tiles_L, int n_kblk, int n_sig,
+                               CheckResult* out, hipStream_t s);
+
+// MIXED precision: gather candidates with |beta| >= thr and recompute them in
+// double; per-signal max of the exact values.
+hipError_t launch_refine_absmax(const float* beta32, const double* D, const float* X,
+                                int K, int P, int W, const SigDesc* sig,
+                                const int64_t* tile_pref, int n_sig, int64_t n_tiles,
+                                const double* thr, unsigned long long* out_bits,
+                                hipStream_t s);
+hipError_t launch_absmax_f32(const float* beta, int K, const SigDesc* sig,
+                             const int64_t* tile_pref, int n_sig, int64_t n_tiles,
+                             unsigned long long* out_bits, hipStream_t s);
+hipError_t launch_split_bf16(const double* D, size_t n, float* hi_lo, hipStream_t s);
+
+}  // namespace dicod

@@ -1,0 +1,1006 @@
+// gfx950 kernels for locally greedy convolutional coordinate descent.
+//
+// Notation follows Moreau, Oudre & Vayatis (ICML 2018): X [P][T], atoms
+// D [K][P][W], activations Z [K][L] with L = T - W + 1, the auxiliary
+// variable beta of Sec. 2.1 and the correlation table S of eq. (3).
+//
+// The descent keeps g = beta - |D_k|^2 Z instead of beta (g is the
+// correlation of D_k with the full residual).  With g the update of eq. (3)
+// applies uniformly, including at the updated coordinate, and g stays of the
+// order of lambda near the solution, which keeps single precision usable.
+#include <hip/hip_runtime.h>
+
+#include <climits>
+#include <cstdint>
+#include <type_traits>
+#include <utility>
+
+#include "dicod_internal.h"
+
+namespace dicod {
+
+typedef double d4_t __attribute__((ext_vector_type(4)));
+
+// ---------------------------------------------------------------------------
+// small helpers
+// ---------------------------------------------------------------------------
+
+// Calls f(std::integral_constant<int, i>) for i = 0 .. N-1, so that register
+// arrays indexed by i are never indexed dynamically.
+template <typename F, int... Is>
+__device__ __forceinline__ void static_for_impl(F&& f, std::integer_sequence<int, Is...>)
+{
+    (f(std::integral_constant<int, Is>{}), ...);
+}
+template <int N, typename F>
+__device__ __forceinline__ void static_for(F&& f)
+{
+    static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
+
+// Largest i with pref[i] <= x (pref has n + 1 non-decreasing entries).
+__device__ __forceinline__ int find_sig(const int64_t* __restrict__ pref, int n,
+                                        int64_t x)
+{
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (pref[mid] <= x)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+template <typename T>
+__global__ void k_fill(T* __restrict__ p, T v, size_t n)
+{
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride)
+        p[i] = v;
+}
+
+template <typename T>
+static hipError_t fill(T* p, T v, size_t n, hipStream_t s)
+{
+    if (n == 0)
+        return hipSuccess;
+    size_t blocks = (n + 255) / 256;
+    if (blocks > 4096)
+        blocks = 4096;
+    hipLaunchKernelGGL(k_fill<T>, dim3((unsigned)blocks), dim3(256), 0, s, p, v, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t s)
+{
+    return fill<uint32_t>(p, v, n, s);
+}
+hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, size_t n,
+                           hipStream_t s)
+{
+    return fill<unsigned long long>(p, v, n, s);
+}
+hipError_t launch_fill_f64(double* p, double v, size_t n, hipStream_t s)
+{
+    return fill<double>(p, v, n, s);
+}
+
+// ---------------------------------------------------------------------------
+// Correlation out_k[t] = sum_{p,tau} D_k[p][tau] Y[p][t + tau] on f64 MFMA.
+//
+// Implicit im2col: the GEMM is [K x PW] . [PW x L]; a workgroup owns 256
+// output positions and 32 atoms, stages its Y window [P][256 + W - 1] in LDS
+// once and walks the reduction index r = p W + tau in chunks of 64, staging the
+// matching slice of D.  Each wave computes 32 atoms x 64 positions with
+// v_mfma_f64_16x16x4f64 (A = D slice, B = shifted Y rows).
+// ---------------------------------------------------------------------------
+constexpr int kCorrRC = 64;
+constexpr int kCorrDStride = kCorrRC + 1;  // odd stride: no LDS bank aliasing
+
+template <typename TY>
+__global__ void __launch_bounds__(256)
+k_corr_f64(const double* __restrict__ D, int K, int P, int W,
+           const TY* __restrict__ Y, const SigDesc* __restrict__ sig,
+           const int64_t* __restrict__ tile_pref, int n_sig,
+           double* __restrict__ out64, float* __restrict__ g32,
+           double* __restrict__ g64)
+{
+    extern __shared__ double lds[];
+    const int R = P * W;
+    const int ystride = kTile + W - 1;
+    double* Dc = lds;                          // [32][kCorrDStride]
+    double* Ys = lds + 32 * kCorrDStride;      // [P][ystride]
+
+    const int64_t tile = blockIdx.x;
+    const int si = find_sig(tile_pref, n_sig, tile);
+    const SigDesc sd = sig[si];
+    const int64_t t_a = (tile - tile_pref[si]) * kTile;
+    const int kbase = blockIdx.y * 32;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+
+    for (int i = tid; i < P * ystride; i += 256) {
+        int p = i / ystride;
+        int u = i - p * ystride;
+        int64_t t = t_a + u;
+        Ys[i] = t < sd.T ? (double)Y[sd.x_off + (int64_t)p * sd.T + t] : 0.0;
+    }
+
+    d4_t acc[2][4];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+            acc[a][b] = d4_t{0.0, 0.0, 0.0, 0.0};
+
+    const int arow = lane & 15;
+    const int kk = lane >> 4;
+    for (int r0 = 0; r0 < R; r0 += kCorrRC) {
+        __syncthreads();
+        for (int i = tid; i < 32 * kCorrRC; i += 256) {
+            int m = i / kCorrRC;
+            int rr = i - m * kCorrRC;
+            int k = kbase + m;
+            int r = r0 + rr;
+            Dc[m * kCorrDStride + rr] =
+                (k < K && r < R) ? D[(int64_t)k * R + r] : 0.0;
+        }
+        __syncthreads();
+        for (int ks = 0; ks < kCorrRC / 4; ++ks) {
+            if (r0 + ks * 4 >= R)
+                break;
+            const int rr = ks * 4 + kk;
+            const int r = r0 + rr;
+            const double a0 = Dc[arow * kCorrDStride + rr];
+            const double a1 = Dc[(16 + arow) * kCorrDStride + rr];
+            const bool valid = r < R;
+            const int p = valid ? r / W : 0;
+            const int tau = valid ? r - p * W : 0;
+            const double* yrow = Ys + p * ystride + wave * 64 + arow + tau;
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) {
+                const double bv = valid ? yrow[nt * 16] : 0.0;
+                acc[0][nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, bv, acc[0][nt], 0, 0, 0);
+                acc[1][nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, bv, acc[1][nt], 0, 0, 0);
+            }
+        }
+    }
+
+    // C[i][j] of a 16x16 f64 MFMA tile sits in lane (i % 4) * 16 + j, item i / 4
+    // (measured on gfx950; the f32/bf16 tiles use lane (i / 4) * 16 + j, item i % 4).
+#pragma unroll
+    for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int k = kbase + mi * 16 + kk + 4 * v;
+                const int64_t t = t_a + wave * 64 + nt * 16 + arow;
+                if (k < K && t < sd.L) {
+                    const double val = acc[mi][nt][v];
+                    const int64_t o = sd.z_off + (int64_t)k * sd.L + t;
+                    out64[o] = val;
+                    if (g32)
+                        g32[o] = (float)val;
+                    if (g64)
+                        g64[o] = val;
+                }
+            }
+}
+
+static size_t corr_lds(int P, int W)
+{
+    return sizeof(double) * (32 * kCorrDStride + (size_t)P * (kTile + W - 1));
+}
+
+hipError_t launch_corr_f64_x32(const double* D, int K, int P, int W, const float* Y,
+                               const SigDesc* sig, const int64_t* tile_pref,
+                               int n_sig, int64_t n_tiles, double* out64,
+                               float* g32, double* g64, hipStream_t s)
+{
+    size_t lds = corr_lds(P, W);
+    if (lds > kLdsBytes)
+        return hipErrorInvalidValue;
+    (void)hipFuncSetAttribute((const void*)k_corr_f64<float>,
+                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    dim3 grid((unsigned)n_tiles, (unsigned)((K + 31) / 32));
+    hipLaunchKernelGGL(k_corr_f64<float>, grid, dim3(256), lds, s, D, K, P, W, Y,
+                       sig, tile_pref, n_sig, out64, g32, g64);
+    return hipGetLastError();
+}
+
+hipError_t launch_corr_f64_x64(const double* D, int K, int P, int W,
+                               const double* Y, const SigDesc* sig,
+                               const int64_t* tile_pref, int n_sig,
+                               int64_t n_tiles, double* out64, hipStream_t s)
+{
+    size_t lds = corr_lds(P, W);
+    if (lds > kLdsBytes)
+        return hipErrorInvalidValue;
+    (void)hipFuncSetAttribute((const void*)k_corr_f64<double>,
+                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    dim3 grid((unsigned)n_tiles, (unsigned)((K + 31) / 32));
+    hipLaunchKernelGGL(k_corr_f64<double>, grid, dim3(256), lds, s, D, K, P, W, Y,
+                       sig, tile_pref, n_sig, out64, (float*)nullptr,
+                       (double*)nullptr);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Dictionary finish: float copy of S, norms |D_k|^2 = S_{k,k}[0] and inverses.
+// ---------------------------------------------------------------------------
+__global__ void k_dict_finish(const double* __restrict__ S64, int K, int W,
+                              float* __restrict__ S32, double* __restrict__ n2_64,
+                              double* __restrict__ inv64, float* __restrict__ n2_32,
+                              float* __restrict__ inv32)
+{
+    const int nd = 2 * W - 1;
+    const size_t n = (size_t)K * K * nd;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x)
+        S32[i] = (float)S64[i];
+    if (blockIdx.x == 0 && threadIdx.x < (unsigned)K) {
+        const int k = threadIdx.x;
+        const double v = S64[((size_t)k * K + k) * nd + (W - 1)];
+        n2_64[k] = v;
+        inv64[k] = 1.0 / v;
+        n2_32[k] = (float)v;
+        inv32[k] = (float)(1.0 / v);
+    }
+}
+
+hipError_t launch_dict_finish(const double* S64, int K, int W, float* S32,
+                              double* n2_64, double* inv_n2_64, float* n2_32,
+                              float* inv_n2_32, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_dict_finish, dim3(64), dim3(256), 0, s, S64, K, W, S32,
+                       n2_64, inv_n2_64, n2_32, inv_n2_32);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// lambda_max = max |beta| per signal (bit pattern of a non-negative double,
+// whose unsigned order is the numeric order).
+// ---------------------------------------------------------------------------
+constexpr int kAbsChunk = 4096;
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_absmax(const T* __restrict__ beta, int K, const SigDesc* __restrict__ sig,
+         const int64_t* __restrict__ tile_pref, int n_sig,
+         unsigned long long* __restrict__ out_bits)
+{
+    __shared__ double red[4];
+    const int64_t tile = blockIdx.x;
+    const int si = find_sig(tile_pref, n_sig, tile);
+    const SigDesc sd = sig[si];
+    const int64_t n = (int64_t)K * sd.L;
+    const int64_t i0 = (tile - tile_pref[si]) * kAbsChunk;
+    double m = 0.0;
+    for (int64_t i = i0 + threadIdx.x; i < n && i < i0 + kAbsChunk; i += 256)
+        m = fmax(m, fabs((double)beta[sd.z_off + i]));
+    for (int o = 32; o > 0; o >>= 1)
+        m = fmax(m, __shfl_xor(m, o));
+    if ((threadIdx.x & 63) == 0)
+        red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        m = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+        atomicMax(&out_bits[si], (unsigned long long)__double_as_longlong(m));
+    }
+}
+
+hipError_t launch_absmax(const double* beta, int K, const SigDesc* sig,
+                         const int64_t* tile_pref, int n_sig, int64_t n_tiles,
+                         unsigned long long* out_bits, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_absmax<double>, dim3((unsigned)n_tiles), dim3(256), 0, s,
+                       beta, K, sig, tile_pref, n_sig, out_bits);
+    return hipGetLastError();
+}
+
+hipError_t launch_absmax_f32(const float* beta, int K, const SigDesc* sig,
+                             const int64_t* tile_pref, int n_sig, int64_t n_tiles,
+                             unsigned long long* out_bits, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_absmax<float>, dim3((unsigned)n_tiles), dim3(256), 0, s,
+                       beta, K, sig, tile_pref, n_sig, out_bits);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// LGCD phase kernel: one workgroup runs the locally greedy descent of one
+// segment C_m (Algorithm 3 restricted to that segment) until its largest
+// |Delta Z| is below eps_stop or `cap` updates were applied.
+//
+// LDS holds g for the segment extended by W - 1 positions on each side (the
+// "interference zone" of Sec. 2.2) and a copy of Z for the segment.  Thread
+// tid owns the extended positions q = tid + i * 512, for all atoms; every LDS
+// entry is read and written only by its owner, so the window update of
+// eq. (3) needs no synchronisation.  The argmax is a block reduction of the
+// per-thread best (|Delta Z|, index t * K + k) keys; ties go to the smallest
+// t, then k.  Each update costs one barrier.
+//
+// Segments of one parity run in the same launch.  A run writes g back over
+// the part of the extended window it touched, i.e. into the idle neighbours'
+// positions: this is the even/odd form of the boundary messages of
+// Algorithm 2.  Segments are >= 2W long, so two runs of one launch never touch
+// the same entry.
+// ---------------------------------------------------------------------------
+struct Key {
+    unsigned long long v;  // bit pattern of |Delta Z| as a non-negative double
+    unsigned int i;        // j * K + k inside the segment
+};
+
+__device__ __forceinline__ bool better(const Key& a, const Key& b)
+{
+    return a.v > b.v || (a.v == b.v && a.i < b.i);
+}
+
+template <typename G>
+struct Slot {
+    Key key;
+    G d;
+};
+
+// Delta Z = Z' - Z in terms of g (eq. (pb_coord) with beta = g + |D|^2 z).
+template <typename G>
+__device__ __forceinline__ G coord_delta(G g, G z, G n2, G inv_n2, G lam, bool* zero)
+{
+    const G bb = g + n2 * z;
+    const G sg = bb > (G)0 ? (G)1 : (G)-1;
+    const bool zr = fabs(bb) <= lam;
+    *zero = zr;
+    return zr ? -z : (g - lam * sg) * inv_n2;
+}
+
+template <int NQ, typename G>
+__device__ __forceinline__ void block_argmax(const Key (&best)[NQ], const G (&dl)[NQ],
+                                             Slot<G>* __restrict__ slot, Key& out,
+                                             G& dout)
+{
+    constexpr int NW = kPhaseThreads / 64;
+    // value selects (not a branch over the struct) keep the arrays in registers
+    Key m = best[0];
+    G d = dl[0];
+    static_for<NQ>([&](auto ic) __attribute__((always_inline)) {
+        constexpr int i = decltype(ic)::value;
+        if (i > 0) {
+            const bool b = better(best[i], m);
+            m.v = b ? best[i].v : m.v;
+            m.i = b ? best[i].i : m.i;
+            d = b ? dl[i] : d;
+        }
+    });
+    Key w = m;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        Key x;
+        x.v = __shfl_xor(w.v, o);
+        x.i = __shfl_xor(w.i, o);
+        if (better(x, w))
+            w = x;
+    }
+    if (m.v == w.v && m.i == w.i) {
+        slot[threadIdx.x >> 6].key = w;
+        slot[threadIdx.x >> 6].d = d;
+    }
+    __syncthreads();
+    Key bb = slot[0].key;
+    G bd = slot[0].d;
+#pragma unroll
+    for (int wv = 1; wv < NW; ++wv) {
+        Key o = slot[wv].key;
+        if (better(o, bb)) {
+            bb = o;
+            bd = slot[wv].d;
+        }
+    }
+    out = bb;
+    dout = bd;
+}
+
+// Byte offset of the argmax slots after the g and Z arrays, 16-byte aligned.
+__host__ __device__ constexpr size_t slot_offset(size_t elem, int K, int lx, int lm)
+{
+    return ((elem * (size_t)K * ((size_t)lx + (size_t)lm)) + 15) & ~(size_t)15;
+}
+
+template <typename G, int KC, int NQ>
+__global__ void __launch_bounds__(kPhaseThreads)
+k_lgcd_phase(PhaseArgs a)
+{
+    constexpr int NT = kPhaseThreads;
+    constexpr int NW = NT / 64;
+    const int K = KC ? KC : a.K;
+    const int W = a.W;
+    const int nd = 2 * W - 1;
+    const int tid = threadIdx.x;
+
+    const int sid = a.list[blockIdx.x];
+    if (a.dirty[sid] == 0)
+        return;
+
+    extern __shared__ __align__(16) unsigned char smem[];
+    const SegDesc sd = a.segs[sid];
+    const int64_t L = sd.L;
+    const int b = sd.b;
+    const int Lm = sd.e - sd.b;
+    const int ext_lo = b - (W - 1) > 0 ? b - (W - 1) : 0;
+    const int ext_hi = sd.e + (W - 1) < sd.L ? sd.e + (W - 1) : sd.L;
+    const int Lext = ext_hi - ext_lo;
+    const int off = b - ext_lo;
+    const int lx = a.lext_max;
+    const int lm = a.lm_max;
+
+    G* g_l = reinterpret_cast<G*>(smem);
+    G* z_l = g_l + (size_t)K * lx;
+    Slot<G>* slots = reinterpret_cast<Slot<G>*>(
+        smem + slot_offset(sizeof(G), K, lx, lm));
+
+    G* __restrict__ gs = reinterpret_cast<G*>(a.g) + sd.z_off;
+    double* __restrict__ Zs = a.Z + sd.z_off;
+    const G* __restrict__ S = reinterpret_cast<const G*>(a.S);
+    const G* __restrict__ n2v = reinterpret_cast<const G*>(a.n2);
+    const G* __restrict__ inv2v = reinterpret_cast<const G*>(a.inv_n2);
+    const G lam = (G)a.sigs[sd.sig].lam;
+
+    for (int i = tid; i < K * Lext; i += NT) {
+        const int k = i / Lext;
+        const int q = i - k * Lext;
+        g_l[k * lx + q] = gs[(int64_t)k * L + ext_lo + q];
+    }
+    for (int i = tid; i < K * Lm; i += NT) {
+        const int k = i / Lm;
+        const int j = i - k * Lm;
+        z_l[k * lm + j] = (G)Zs[(int64_t)k * L + b + j];
+    }
+    __syncthreads();
+
+    const Key knull = {0ull, 0xffffffffu};
+    Key best[NQ];
+    G dl[NQ];
+    static_for<NQ>([&](auto ic) __attribute__((always_inline)) {
+        constexpr int i = decltype(ic)::value;
+        best[i] = knull;
+        dl[i] = (G)0;
+        const int q = tid + i * NT;
+        const int j = q - off;
+        if (q < Lext && j >= 0 && j < Lm) {
+            Key kbest = knull;
+            G dbest = (G)0;
+            for (int k = 0; k < K; ++k) {
+                bool zr;
+                const G d = coord_delta<G>(g_l[k * lx + q], z_l[k * lm + j], n2v[k],
+                                           inv2v[k], lam, &zr);
+                const Key kc = {(unsigned long long)__double_as_longlong(fabs((double)d)),
+                                (unsigned)(j * K + k)};
+                if (better(kc, kbest)) {
+                    kbest = kc;
+                    dbest = d;
+                }
+            }
+            best[i] = kbest;
+            dl[i] = dbest;
+        }
+    });
+
+    int it = 0;
+    Key kb;
+    G db;
+    block_argmax<NQ, G>(best, dl, slots + (it & 1) * NW, kb, db);
+    ++it;
+
+    int n = 0;
+    bool conv = false;
+    bool touch_l = false, touch_r = false;
+    int tlo = INT_MAX, thi = -1;
+    for (;;) {
+        const double v = __longlong_as_double((long long)kb.v);
+        if (v < a.eps_stop) {
+            conv = true;
+            break;
+        }
+        if (n == a.cap)
+            break;
+        const int j0 = (int)(kb.i / (unsigned)K);
+        const int k0 = (int)kb.i - j0 * K;
+        const int q0 = j0 + off;
+        const G delta = db;
+
+        if (tid == (q0 % NT)) {
+            // Owner of the updated position: new Z value (exactly 0 when the
+            // soft threshold is active), in LDS and in the double-precision Z.
+            const G zo = z_l[k0 * lm + j0];
+            bool zr;
+            (void)coord_delta<G>(g_l[k0 * lx + q0], zo, n2v[k0], inv2v[k0], lam, &zr);
+            const G zn = zr ? (G)0 : zo + delta;
+            z_l[k0 * lm + j0] = zn;
+            double* zp = Zs + (int64_t)k0 * L + b + j0;
+            if (sizeof(G) == sizeof(double)) {
+                *zp = (double)zn;
+            } else {
+                if (zr)
+                    *zp = 0.0;
+                else
+                    unsafeAtomicAdd(zp, (double)delta);  // single owner: deterministic
+            }
+            if (a.trace) {
+                const unsigned long long r = atomicAdd(&a.counters->trace_n, 1ull);
+                if ((long long)r < a.trace_cap) {
+                    dicod_trace_rec rec;
+                    rec.phase = a.phase;
+                    rec.seg = sid;
+                    rec.k0 = k0;
+                    rec.n_local = n;
+                    rec.t0 = (int64_t)b + j0;
+                    rec.delta = zr ? -(double)zo : (double)delta;
+                    a.trace[r] = rec;
+                }
+            }
+        }
+
+        const int wlo = q0 - (W - 1) > 0 ? q0 - (W - 1) : 0;
+        const int whi = q0 + (W - 1) < Lext - 1 ? q0 + (W - 1) : Lext - 1;
+        tlo = wlo < tlo ? wlo : tlo;
+        thi = whi > thi ? whi : thi;
+        if (q0 - (W - 1) < off && sd.left >= 0)
+            touch_l = true;
+        if (q0 + (W - 1) >= off + Lm && sd.right >= 0)
+            touch_r = true;
+
+        const G* __restrict__ Srow = S + (size_t)k0 * K * nd;
+        static_for<NQ>([&](auto ic) __attribute__((always_inline)) {
+            constexpr int i = decltype(ic)::value;
+            const int q = tid + i * NT;
+            if (q < wlo || q > whi)
+                return;
+            const int dj = q - q0 + (W - 1);
+            const int j = q - off;
+            if (j >= 0 && j < Lm) {
+                Key kbest = knull;
+                G dbest = (G)0;
+                for (int k = 0; k < K; ++k) {
+                    const G sv = Srow[k * nd + dj];
+                    const G gv = g_l[k * lx + q] - sv * delta;
+                    g_l[k * lx + q] = gv;
+                    bool zr;
+                    const G d = coord_delta<G>(gv, z_l[k * lm + j], n2v[k], inv2v[k],
+                                               lam, &zr);
+                    const Key kc = {
+                        (unsigned long long)__double_as_longlong(fabs((double)d)),
+                        (unsigned)(j * K + k)};
+                    if (better(kc, kbest)) {
+                        kbest = kc;
+                        dbest = d;
+                    }
+                }
+                best[i] = kbest;
+                dl[i] = dbest;
+            } else {
+                for (int k = 0; k < K; ++k)
+                    g_l[k * lx + q] -= Srow[k * nd + dj] * delta;
+            }
+        });
+        ++n;
+        block_argmax<NQ, G>(best, dl, slots + (it & 1) * NW, kb, db);
+        ++it;
+    }
+
+    if (n > 0) {
+        const int wdt = thi - tlo + 1;
+        for (int i = tid; i < K * wdt; i += NT) {
+            const int k = i / wdt;
+            const int q = tlo + (i - k * wdt);
+            gs[(int64_t)k * L + ext_lo + q] = g_l[k * lx + q];
+        }
+        if (tid == 0) {
+            atomicAdd(&a.phase_upd[a.phase], (unsigned long long)n);
+            atomicAdd(&a.sig_upd[sd.sig], (unsigned long long)n);
+            atomicMax(&a.sig_last_upd[sd.sig], a.phase);
+            atomicAdd(&a.counters->seg_runs, 1ull);
+        }
+    }
+    if (tid == 0) {
+        a.dirty[sid] = conv ? 0u : 1u;
+        if (touch_l)
+            a.dirty[sd.left] = 1u;
+        if (touch_r)
+            a.dirty[sd.right] = 1u;
+    }
+}
+
+size_t lgcd_lds_bytes(int K, int lm_max, int lext_max, bool fp64)
+{
+    const size_t e = fp64 ? sizeof(double) : sizeof(float);
+    const size_t slots = 2 * (kPhaseThreads / 64) *
+                         (fp64 ? sizeof(Slot<double>) : sizeof(Slot<float>));
+    return slot_offset(e, K, lext_max, lm_max) + slots;
+}
+
+template <typename G, int KC>
+static hipError_t launch_phase_k(const PhaseArgs& a, int nq, size_t lds, hipStream_t s)
+{
+    const void* fn;
+    switch (nq) {
+    case 1: fn = (const void*)k_lgcd_phase<G, KC, 1>; break;
+    case 2: fn = (const void*)k_lgcd_phase<G, KC, 2>; break;
+    case 3: fn = (const void*)k_lgcd_phase<G, KC, 3>; break;
+    case 4: fn = (const void*)k_lgcd_phase<G, KC, 4>; break;
+    default: return hipErrorInvalidValue;
+    }
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds);
+    if (e != hipSuccess)
+        return e;
+    dim3 grid((unsigned)a.n_list);
+    switch (nq) {
+    case 1: hipLaunchKernelGGL((k_lgcd_phase<G, KC, 1>), grid, dim3(kPhaseThreads), lds, s, a); break;
+    case 2: hipLaunchKernelGGL((k_lgcd_phase<G, KC, 2>), grid, dim3(kPhaseThreads), lds, s, a); break;
+    case 3: hipLaunchKernelGGL((k_lgcd_phase<G, KC, 3>), grid, dim3(kPhaseThreads), lds, s, a); break;
+    case 4: hipLaunchKernelGGL((k_lgcd_phase<G, KC, 4>), grid, dim3(kPhaseThreads), lds, s, a); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_lgcd_phase(const PhaseArgs& a, bool fp64, size_t* lds_bytes,
+                             hipStream_t s)
+{
+    if (a.n_list <= 0)
+        return hipSuccess;
+    const int nq = (a.lext_max + kPhaseThreads - 1) / kPhaseThreads;
+    if (nq < 1 || nq > 4)
+        return hipErrorInvalidValue;
+    const size_t lds = lgcd_lds_bytes(a.K, a.lm_max, a.lext_max, fp64);
+    if (lds_bytes)
+        *lds_bytes = lds;
+    if (lds > kLdsBytes)
+        return hipErrorInvalidValue;
+    if (fp64)
+        return a.K == 25 ? launch_phase_k<double, 25>(a, nq, lds, s)
+                         : launch_phase_k<double, 0>(a, nq, lds, s);
+    return a.K == 25 ? launch_phase_k<float, 25>(a, nq, lds, s)
+                     : launch_phase_k<float, 0>(a, nq, lds, s);
+}
+
+// ---------------------------------------------------------------------------
+// Double-precision check (final stop test and refresh).
+// ---------------------------------------------------------------------------
+
+// Deterministic stream compaction of the non-zeros of Z over a window
+// [s_lo, s_hi) x [0, K) into an LDS list, in (k, s) order.
+struct NzEnt {
+    int k;
+    int s;
+    double z;
+};
+constexpr int kNzCap = 2048;
+
+// Appends up to one round (256 candidates) starting at *pos; returns the
+// number of entries in the list afterwards.  All threads call it.
+__device__ __forceinline__ int nz_round(const double* __restrict__ Zs, int64_t L,
+                                        int s_lo, int ns, int64_t total, int64_t pos,
+                                        NzEnt* __restrict__ list, int cnt,
+                                        int* __restrict__ wcnt)
+{
+    const int tid = threadIdx.x;
+    const int64_t i = pos + tid;
+    double z = 0.0;
+    int k = 0, s = 0;
+    if (i < total) {
+        k = (int)(i / ns);
+        s = s_lo + (int)(i - (int64_t)k * ns);
+        z = Zs[(int64_t)k * L + s];
+    }
+    const bool f = z != 0.0;
+    const unsigned long long mask = __ballot(f);
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int pre = __popcll(mask & ((1ull << lane) - 1ull));
+    if (lane == 0)
+        wcnt[wave] = __popcll(mask);
+    __syncthreads();
+    int woff = 0;
+    for (int w = 0; w < wave; ++w)
+        woff += wcnt[w];
+    const int tot = wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3];
+    if (f) {
+        NzEnt e;
+        e.k = k;
+        e.s = s;
+        e.z = z;
+        list[cnt + woff + pre] = e;
+    }
+    __syncthreads();
+    return cnt + tot;
+}
+
+__device__ __forceinline__ double block_sum256(double v, double* red)
+{
+    for (int o = 32; o > 0; o >>= 1)
+        v += __shfl_xor(v, o);
+    if ((threadIdx.x & 63) == 0)
+        red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double r = (red[0] + red[1]) + (red[2] + red[3]);
+    __syncthreads();
+    return r;
+}
+
+__device__ __forceinline__ double block_max256(double v, double* red)
+{
+    for (int o = 32; o > 0; o >>= 1)
+        v = fmax(v, __shfl_xor(v, o));
+    if ((threadIdx.x & 63) == 0)
+        red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double r = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    __syncthreads();
+    return r;
+}
+
+// Residual energy: per tile of 256 samples, sum_p (X - sum_k Z_k * D_k)^2,
+// the convolution taken over the non-zeros of Z only (model eq. (1)).
+__global__ void __launch_bounds__(256)
+k_resid(const float* __restrict__ X, const double* __restrict__ D,
+        const double* __restrict__ Z, int K, int P, int W,
+        const SigDesc* __restrict__ sig, const int64_t* __restrict__ tile_pref,
+        int n_sig, double* __restrict__ part)
+{
+    __shared__ NzEnt list[kNzCap];
+    __shared__ int wcnt[4];
+    __shared__ double red[4];
+    const int64_t tile = blockIdx.x;
+    const int si = find_sig(tile_pref, n_sig, tile);
+    const SigDesc sd = sig[si];
+    const int64_t t_a = (tile - tile_pref[si]) * kTile;
+    const int64_t t = t_a + threadIdx.x;
+    const double* __restrict__ Zs = Z + sd.z_off;
+
+    double acc[kMaxP];
+#pragma unroll
+    for (int p = 0; p < kMaxP; ++p)
+        acc[p] = 0.0;
+    if (t < sd.T) {
+#pragma unroll
+        for (int p = 0; p < kMaxP; ++p)
+            if (p < P)
+                acc[p] = (double)X[sd.x_off + (int64_t)p * sd.T + t];
+    }
+    const int s_lo = t_a - (W - 1) > 0 ? (int)(t_a - (W - 1)) : 0;
+    const int s_hi = t_a + kTile < sd.L ? (int)(t_a + kTile) : (int)sd.L;
+    const int ns = s_hi > s_lo ? s_hi - s_lo : 0;
+    const int64_t total = (int64_t)K * ns;
+    int64_t pos = 0;
+    while (pos < total) {
+        int cnt = 0;
+        while (pos < total && cnt <= kNzCap - 256) {
+            cnt = nz_round(Zs, sd.L, s_lo, ns, total, pos, list, cnt, wcnt);
+            pos += 256;
+        }
+        for (int e = 0; e < cnt; ++e) {
+            const NzEnt ne = list[e];
+            const int64_t tau = t - ne.s;
+            if (tau >= 0 && tau < W) {
+                const double* __restrict__ drow = D + (int64_t)ne.k * P * W + tau;
+#pragma unroll
+                for (int p = 0; p < kMaxP; ++p)
+                    if (p < P)
+                        acc[p] -= ne.z * drow[(int64_t)p * W];
+            }
+        }
+        __syncthreads();
+    }
+    double e2 = 0.0;
+    if (t < sd.T) {
+#pragma unroll
+        for (int p = 0; p < kMaxP; ++p)
+            if (p < P)
+                e2 += acc[p] * acc[p];
+    }
+    e2 = block_sum256(e2, red);
+    if (threadIdx.x == 0)
+        part[tile] = e2;
+}
+
+hipError_t launch_resid(const float* X, const double* D, const double* Z, int K,
+                        int P, int W, const SigDesc* sig, const int64_t* tile_pref,
+                        int n_sig, int64_t n_tiles, double* part_r2, hipStream_t s)
+{
+    if (P > kMaxP)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_resid, dim3((unsigned)n_tiles), dim3(256), 0, s, X, D, Z, K,
+                       P, W, sig, tile_pref, n_sig, part_r2);
+    return hipGetLastError();
+}
+
+// g_k[t] = beta0_k[t] - sum_{l, s} S_{k,l}[t - s] Z_l[s] over the non-zeros
+// of Z (eq. (3) summed over all applied updates), then in double:
+// Delta Z = Sh(g + |D|^2 z, lambda)/|D|^2 - z and the optimality residuals.
+// part6 per tile: max|dz|, kkt_on, kkt_off, l1, max|z|, nnz.
+__global__ void __launch_bounds__(256)
+k_grad_check(const double* __restrict__ beta0, const double* __restrict__ Z,
+             const double* __restrict__ S64, const double* __restrict__ n2v, int K,
+             int W, const SigDesc* __restrict__ sig,
+             const int64_t* __restrict__ tile_pref, int n_sig, double flag_eps,
+             const uint32_t* __restrict__ sig_done, uint32_t* __restrict__ dirty,
+             float* __restrict__ g32, double* __restrict__ g64,
+             double* __restrict__ part6)
+{
+    __shared__ NzEnt list[kNzCap];
+    __shared__ int wcnt[4];
+    __shared__ double red[4];
+    const int nd = 2 * W - 1;
+    const int64_t tile = blockIdx.x;
+    const int si = find_sig(tile_pref, n_sig, tile);
+    const SigDesc sd = sig[si];
+    const int64_t t_a = (tile - tile_pref[si]) * kTile;
+    const int64_t t = t_a + threadIdx.x;
+    const bool act = t < sd.L;
+    const double* __restrict__ Zs = Z + sd.z_off;
+    const int kb = blockIdx.y * kMaxK;
+    const int kn = K - kb < kMaxK ? K - kb : kMaxK;
+    // accepted signals are only measured: no refresh, no new dirty segments
+    const bool frozen = sig_done && sig_done[si] != 0u;
+
+    double acc[kMaxK];
+#pragma unroll
+    for (int k = 0; k < kMaxK; ++k)
+        acc[k] = (act && k < kn) ? beta0[sd.z_off + (int64_t)(kb + k) * sd.L + t] : 0.0;
+
+    const int s_lo = t_a - (W - 1) > 0 ? (int)(t_a - (W - 1)) : 0;
+    const int s_hi = t_a + kTile + (W - 1) < sd.L ? (int)(t_a + kTile + (W - 1))
+                                                   : (int)sd.L;
+    const int ns = s_hi > s_lo ? s_hi - s_lo : 0;
+    const int64_t total = (int64_t)K * ns;
+    int64_t pos = 0;
+    while (pos < total) {
+        int cnt = 0;
+        while (pos < total && cnt <= kNzCap - 256) {
+            cnt = nz_round(Zs, sd.L, s_lo, ns, total, pos, list, cnt, wcnt);
+            pos += 256;
+        }
+        for (int e = 0; e < cnt; ++e) {
+            const NzEnt ne = list[e];
+            const int64_t dd = t - ne.s;
+            if (dd > -W && dd < W) {
+                // S[l][k][d + W - 1] = S_{k,l}[d]: the slice for atom l = ne.k
+                const double* __restrict__ srow =
+                    S64 + ((int64_t)ne.k * K + kb) * nd + (dd + W - 1);
+#pragma unroll
+                for (int k = 0; k < kMaxK; ++k)
+                    if (k < kn)
+                        acc[k] -= srow[(int64_t)k * nd] * ne.z;
+            }
+        }
+        __syncthreads();
+    }
+
+    double mdz = 0.0, kon = 0.0, koff = 0.0, l1 = 0.0, mz = 0.0, nnz = 0.0;
+    bool flag = false;
+    if (act) {
+        const double lam = sd.lam;
+#pragma unroll
+        for (int k = 0; k < kMaxK; ++k) {
+            if (k >= kn)
+                continue;
+            const int kk = kb + k;
+            const int64_t o = sd.z_off + (int64_t)kk * sd.L + t;
+            const double z = Zs[(int64_t)kk * sd.L + t];
+            const double n2 = n2v[kk];
+            const double g = acc[k];
+            const double bb = g + n2 * z;
+            const double ab = fabs(bb) - lam;
+            const double zp = ab > 0.0 ? (bb > 0.0 ? ab : -ab) / n2 : 0.0;
+            const double dz = fabs(zp - z);
+            mdz = fmax(mdz, dz);
+            if (dz >= flag_eps)
+                flag = true;
+            if (z != 0.0) {
+                kon = fmax(kon, fabs(g - (z > 0.0 ? lam : -lam)) / n2);
+                l1 += fabs(z);
+                mz = fmax(mz, fabs(z));
+                nnz += 1.0;
+            } else {
+                koff = fmax(koff, fmax(fabs(g) - lam, 0.0) / n2);
+            }
+            if (g32 && !frozen)
+                g32[o] = (float)g;
+            if (g64 && !frozen)
+                g64[o] = g;
+        }
+        if (flag && dirty && !frozen) {
+            // segment m holds t iff floor(m L / M) <= t < floor((m+1) L / M)
+            const int64_t m = ((t + 1) * (int64_t)sd.M - 1) / sd.L;
+            dirty[sd.seg_base + m] = 1u;
+        }
+    }
+    mdz = block_max256(mdz, red);
+    kon = block_max256(kon, red);
+    koff = block_max256(koff, red);
+    l1 = block_sum256(l1, red);
+    mz = block_max256(mz, red);
+    nnz = block_sum256(nnz, red);
+    if (threadIdx.x == 0) {
+        double* o = part6 + ((int64_t)blockIdx.y * gridDim.x + tile) * 6;
+        o[0] = mdz;
+        o[1] = kon;
+        o[2] = koff;
+        o[3] = l1;
+        o[4] = mz;
+        o[5] = nnz;
+    }
+}
+
+hipError_t launch_grad_check(const double* beta0, const double* Z, const double* S64,
+                             const double* n2, int K, int W, const SigDesc* sig,
+                             const int64_t* tile_pref, int n_sig, int64_t n_tiles,
+                             double flag_eps, const uint32_t* sig_done, uint32_t* dirty,
+                             void* g_state, bool state_fp64, double* part6, hipStream_t s)
+{
+    dim3 grid((unsigned)n_tiles, (unsigned)((K + kMaxK - 1) / kMaxK));
+    hipLaunchKernelGGL(k_grad_check, grid, dim3(256), 0, s, beta0, Z, S64, n2, K, W,
+                       sig, tile_pref, n_sig, flag_eps, sig_done, dirty,
+                       state_fp64 ? (float*)nullptr : (float*)g_state,
+                       state_fp64 ? (double*)g_state : (double*)nullptr, part6);
+    return hipGetLastError();
+}
+
+// One workgroup per signal reduces its tiles' partials in a fixed order.
+__global__ void __launch_bounds__(256)
+k_check_reduce(const double* __restrict__ part_r2, const int64_t* __restrict__ prefT,
+               const double* __restrict__ part6, const int64_t* __restrict__ prefL,
+               int64_t n_tiles_L, int n_kblk, CheckResult* __restrict__ out)
+{
+    __shared__ double red[4];
+    const int si = blockIdx.x;
+    double r2 = 0.0;
+    for (int64_t i = prefT[si] + threadIdx.x; i < prefT[si + 1]; i += 256)
+        r2 += part_r2[i];
+    double mdz = 0.0, kon = 0.0, koff = 0.0, l1 = 0.0, mz = 0.0, nnz = 0.0;
+    for (int kbk = 0; kbk < n_kblk; ++kbk)
+        for (int64_t i = prefL[si] + threadIdx.x; i < prefL[si + 1]; i += 256) {
+            const double* p = part6 + ((int64_t)kbk * n_tiles_L + i) * 6;
+            mdz = fmax(mdz, p[0]);
+            kon = fmax(kon, p[1]);
+            koff = fmax(koff, p[2]);
+            l1 += p[3];
+            mz = fmax(mz, p[4]);
+            nnz += p[5];
+        }
+    r2 = block_sum256(r2, red);
+    mdz = block_max256(mdz, red);
+    kon = block_max256(kon, red);
+    koff = block_max256(koff, red);
+    l1 = block_sum256(l1, red);
+    mz = block_max256(mz, red);
+    nnz = block_sum256(nnz, red);
+    if (threadIdx.x == 0) {
+        CheckResult c;
+        c.max_dz = mdz;
+        c.kkt_on = kon;
+        c.kkt_off = koff;
+        c.l1 = l1;
+        c.sum_r2 = r2;
+        c.max_abs_z = mz;
+        c.nnz = nnz;
+        c.pad = 0.0;
+        out[si] = c;
+    }
+}
+
+hipError_t launch_check_reduce(const double* part_r2, const int64_t* tile_pref_T,
+                                const double* part6, const int64_t* tile_pref_L,
+                                int64_t n_tiles_L, int n_kblk, int n_sig,
+                                CheckResult* out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_check_reduce, dim3((unsigned)n_sig), dim3(256), 0, s, part_r2,
+                       tile_pref_T, part6, tile_pref_L, n_tiles_L, n_kblk, out);
+    return hipGetLastError();
+}
+
+}  // namespace dicod

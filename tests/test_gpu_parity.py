@@ -1,0 +1,253 @@
+"""GPU parity: the HIP path, called through the C ABI, against the FP64 oracle.
+
+Tolerances (floating point; the stop threshold is eps = 1e-6):
+  * S table and beta at Z = 0 are double-precision MFMA contractions of the
+    same float inputs: |gpu - oracle| <= 1e-12 * max(1, scale).
+  * FP64 policy, even/odd schedule: the sequence of updates (phase, segment,
+    atom, position) equals the oracle's even/odd emulation; applied changes
+    agree to 1e-9 relative.
+  * FP32 policy: relative objective error <= 1e-6 and
+    max |z - z_oracle| <= 1e-4 max |z_oracle| (both eps-solutions), and the
+    returned Z passes the stop test max |Delta Z| < eps when the oracle
+    recomputes beta from scratch.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+EPS = 1e-6
+
+
+@pytest.fixture(scope="module")
+def dicod():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1705_10087_amd as d
+    return d
+
+
+def ctx_of(d, **cfg):
+    cfg.setdefault("max_phases", 50_000)      # bound the host loop of a broken run
+    return d.Context(**cfg)
+
+
+def small(seed):
+    return synth.workload(synth.SMALL, seed)
+
+
+def f64(a):
+    return np.asarray(a, dtype=np.float64)
+
+
+# ------------------------------------------------------------- a1: S table
+
+@pytest.mark.parametrize("K,P,W", [(5, 1, 32), (25, 7, 200), (3, 2, 5), (37, 3, 17)])
+def test_s_table_matches_oracle(dicod, K, P, W):
+    print(f"\ncase: S table K={K} P={P} W={W}", flush=True)
+    _, D, _ = synth.generate(P, K, W, 4 * W, 0.01, 0.1, seed=K + W)
+    with ctx_of(dicod) as c:
+        c.set_dictionary(D)
+        S_dev, n2 = c.s_table()
+    S_o = oracle.s_table(f64(D))               # S_o[k, l] = S_{k,l}
+    np.testing.assert_allclose(S_dev, S_o.transpose(1, 0, 2), rtol=0, atol=1e-13)
+    np.testing.assert_allclose(n2, oracle.norms(f64(D)), rtol=0, atol=1e-14)
+
+
+# ------------------------------------------------------------- a2: beta init
+
+@pytest.mark.parametrize("K,P,W,T", [(5, 1, 32, 4096), (37, 3, 17, 1013), (25, 7, 200, 150_000),
+                                     (2, 1, 1, 300), (4, 2, 9, 9)])
+def test_beta_init_matches_oracle(dicod, K, P, W, T):
+    print(f"\ncase: beta init K={K} P={P} W={W} T={T}", flush=True)
+    X, D, _ = synth.generate(P, K, W, T, 0.01, 0.1, seed=T)
+    with ctx_of(dicod) as c:
+        c.set_dictionary(D)
+        B = c.correlate(X)
+    Bo = oracle.correlate(f64(D), f64(X))
+    scale = max(1.0, float(np.abs(Bo).max()))
+    np.testing.assert_allclose(B, Bo, rtol=0, atol=1e-12 * scale)
+
+
+# ------------------------------------- a4-a9: FP64 trajectory = oracle even/odd
+
+def _sorted_gpu_trace(tr):
+    order = np.lexsort((tr["n_local"], tr["seg"], tr["phase"]))
+    return tr[order]
+
+
+def _sorted_oracle_trace(tr):
+    order = np.lexsort((tr["n_local"], tr["seg"], tr["phase"]))
+    return tr[order]
+
+
+@pytest.mark.parametrize("M,cap", [(4, 0), (4, 1), (4, 8), (1, 0), (63, 16)])
+@pytest.mark.parametrize("seed", [0, 1])
+def test_fp64_trajectory_matches_oracle(dicod, M, cap, seed):
+    print(f"\ncase: FP64 trajectory small seed={seed} M={M} cap={cap}", flush=True)
+    X, D, _ = small(seed)
+    lam = 0.1 * oracle.lambda_max(f64(X), f64(D))
+    Zo, so, tro = oracle.lgcd(f64(X), f64(D), lam, EPS, M, cap=cap, trace_cap=10**6)
+    with ctx_of(dicod, precision=dicod.DICOD_PREC_FP64, update_cap=cap,
+                trace_capacity=10**6) as c:
+        Z, st = c.solve(X, lam, EPS, n_seg=M, D=D)
+        tr = c.trace()
+    assert st["converged"] == 1 and so["converged"] == 1
+    assert st["n_updates"] == so["n_updates"] == len(tr)
+    assert st["n_phases"] == so["n_phases"]
+    a, b = _sorted_gpu_trace(tr), _sorted_oracle_trace(tro)
+    assert np.array_equal(a["phase"], b["phase"])
+    assert np.array_equal(a["seg"], b["seg"])
+    assert np.array_equal(a["k0"], b["k0"])
+    assert np.array_equal(a["t0"], b["t0"])
+    np.testing.assert_allclose(a["delta"], b["z_new"] - b["z_old"], rtol=1e-9, atol=1e-12)
+    np.testing.assert_allclose(Z, Zo, rtol=0, atol=1e-10)
+    assert np.array_equal(Z != 0, Zo != 0)
+    Eo = oracle.objective(f64(X), f64(D), Zo, lam)
+    assert abs(st["objective"] - Eo) <= 1e-10 * Eo
+
+
+# ------------------------------------------------ FP32 policy: eps-solutions
+
+def _check_solution(X, D, lam, Z, st, Zo):
+    Eo = oracle.objective(f64(X), f64(D), Zo, lam)
+    E = oracle.objective(f64(X), f64(D), Z, lam)
+    assert abs(E - Eo) <= 1e-6 * Eo, (E, Eo)
+    assert abs(st["objective"] - E) <= 1e-9 * E
+    assert np.max(np.abs(Z - Zo)) <= 1e-4 * np.max(np.abs(Zo))
+    assert st["converged"] == 1 and st["max_dz"] < EPS
+    mdz, _, _ = oracle.max_dz(f64(X), f64(D), Z, lam)
+    assert mdz < EPS * (1 + 1e-6), mdz
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+@pytest.mark.parametrize("M", [4, 0])
+def test_fp32_small_matches_oracle(dicod, seed, M):
+    print(f"\ncase: FP32 small seed={seed} M={M}", flush=True)
+    X, D, _ = small(seed)
+    lam = 0.1 * oracle.lambda_max(f64(X), f64(D))
+    Zo, so, _ = oracle.lgcd(f64(X), f64(D), lam, EPS, 4, cap=16)
+    with ctx_of(dicod) as c:
+        Z, st = c.solve(X, -0.1, EPS, n_seg=M, D=D)   # relative lambda
+    assert abs(st["lambda"] - lam) <= 1e-12 * lam
+    _check_solution(X, D, lam, Z, st, Zo)
+
+
+def test_paper_shaped_fp32_matches_oracle(dicod):
+    print("\ncase: FP32 paper-shaped P=7 K=25 W=200 T=150000 (auto segments)", flush=True)
+    X, D, _ = synth.workload(synth.PAPER, 0)
+    lam = 0.1 * oracle.lambda_max(f64(X), f64(D))
+    with ctx_of(dicod) as c:
+        Z, st = c.solve(X, -0.1, EPS, n_seg=0, D=D)
+    print(f"gpu: {st['n_updates']} updates, {st['n_phases']} phases, M={st['n_seg']}, "
+          f"refresh={st['n_refresh']}, cd={st['t_cd_ms']:.2f} ms", flush=True)
+    assert st["n_seg"] == 374
+    Zo, so, _ = oracle.lgcd(f64(X), f64(D), lam, EPS, 374, cap=16)
+    _check_solution(X, D, lam, Z, st, Zo)
+
+
+# ------------------------------------------------------------- edge cases
+
+def test_lambda_at_lambda_max_gives_zero(dicod):
+    X, D, _ = small(4)
+    with ctx_of(dicod) as c:
+        Z, st = c.solve(X, -1.0, EPS, n_seg=4, D=D)
+    assert st["n_updates"] == 0 and not Z.any() and st["converged"] == 1
+    assert st["objective"] == pytest.approx(0.5 * float(np.sum(f64(X) ** 2)), rel=1e-12)
+
+
+@pytest.mark.parametrize("prec", ["FP64", "FP32"])
+@pytest.mark.parametrize("K,P,W,T,M", [
+    (1, 1, 8, 8, 1),          # L = 1
+    (3, 2, 5, 200, 1),        # single segment, generic K
+    (3, 4, 5, 333, 7),        # ragged segments (L = 329 = 7 * 47)
+    (25, 7, 20, 5003, 13),    # K = 25 kernel, ragged tail
+    (40, 2, 6, 900, 5),       # K > 32: two atom blocks in the check kernels
+])
+def test_shapes_match_oracle(dicod, prec, K, P, W, T, M):
+    print(f"\ncase: shape {prec} K={K} P={P} W={W} T={T} M={M}", flush=True)
+    X, D, _ = synth.generate(P, K, W, T, 0.05, 0.1, seed=7 * T + K)
+    lam = 0.15 * oracle.lambda_max(f64(X), f64(D))
+    Zo, so, _ = oracle.lgcd(f64(X), f64(D), lam, 1e-10, M)
+    p = getattr(dicod, f"DICOD_PREC_{prec}")
+    with ctx_of(dicod, precision=p) as c:
+        Z, st = c.solve(X, lam, EPS, n_seg=M, D=D)
+    _check_solution(X, D, lam, Z, st, Zo)
+
+
+@pytest.mark.parametrize("bad", ["lam0", "lamnan", "eps0", "short_segments", "T_lt_W",
+                                 "nan_x", "zero_atom", "n_seg_gt_L"])
+def test_invalid_arguments_rejected(dicod, bad):
+    X, D, _ = small(0)
+    lam, eps, M = -0.1, EPS, 4
+    if bad == "lam0":
+        lam = 0.0
+    elif bad == "lamnan":
+        lam = float("nan")
+    elif bad == "eps0":
+        eps = 0.0
+    elif bad == "short_segments":
+        M = 64                       # 4065 / 64 < 2W = 64
+    elif bad == "T_lt_W":
+        X = X[:, :16]
+    elif bad == "nan_x":
+        X = X.copy()
+        X[0, 5] = np.nan
+    elif bad == "zero_atom":
+        D = D.copy()
+        D[2] = 0
+    elif bad == "n_seg_gt_L":
+        X = X[:, :40]
+        M = 20
+    with ctx_of(dicod) as c:
+        with pytest.raises(dicod.DicodError) as e:
+            c.solve(X, lam, eps, n_seg=M, D=D)
+        assert e.value.code == dicod.DICOD_EINVAL
+        assert dicod.dicod_last_error(c.h)
+
+
+# ------------------------------------------------- device API and batching
+
+def test_device_api_equals_host_api(dicod):
+    import torch
+    X, D, _ = small(5)
+    with ctx_of(dicod) as c:
+        Zh, sh = c.solve(X, -0.1, EPS, n_seg=4, D=D)
+        Xd = torch.from_numpy(X).cuda()
+        Zd, sd, _ = c.solve_device(Xd, -0.1, EPS, n_seg=4)
+        torch.cuda.synchronize()
+    assert np.array_equal(Zd.cpu().numpy(), Zh)
+    assert sd["n_updates"] == sh["n_updates"]
+
+
+def test_batch_equals_solo_bitwise(dicod):
+    import torch
+    P, K, W = 7, 25, 64
+    lens = [12_000, 3_001, 20_500, 9_999]
+    _, D, _ = synth.generate(P, K, W, 4 * W, 0.005, 0.1, seed=11)
+    sigs = [synth.generate(P, K, W, T, 0.005, 0.1, seed=100 + i, D=D)[0]
+            for i, T in enumerate(lens)]
+    Ls = [T - W + 1 for T in lens]
+    x_off = np.cumsum([0] + [P * T for T in lens[:-1]])
+    z_off = np.cumsum([0] + [K * L for L in Ls[:-1]])
+    with ctx_of(dicod) as c:
+        c.set_dictionary(D)
+        solo = []
+        for X in sigs:
+            Z, st, _ = c.solve_device(torch.from_numpy(X).cuda(), -0.1, EPS)
+            solo.append((Z.cpu().numpy(), st))
+        Xall = torch.from_numpy(np.concatenate([x.reshape(-1) for x in sigs])).cuda()
+        Zall = torch.zeros(int(sum(K * L for L in Ls)), dtype=torch.float64, device="cuda")
+        sts = c.solve_batch_device(Xall, lens, x_off, [-0.1] * len(lens), EPS, None, Zall,
+                                   z_off)
+        torch.cuda.synchronize()
+        Zall = Zall.cpu().numpy()
+    for i, (Zs, st) in enumerate(solo):
+        Zb = Zall[z_off[i]:z_off[i] + K * Ls[i]].reshape(K, Ls[i])
+        assert np.array_equal(Zb, Zs), f"signal {i} differs between batch and solo"
+        assert sts[i]["n_updates"] == st["n_updates"]
+        assert sts[i]["converged"] == 1
