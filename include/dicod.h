@@ -85,6 +85,10 @@ typedef struct {
     int max_inflight;        /* serving: max signals on the device at once          */
     int timing;              /* 1 = time every LGCD kernel launch with HIP events    */
     int64_t trace_capacity;  /* update records kept for dicod_get_trace (0 = none)  */
+    int state_in_lds;        /* 1 = keep a segment's state in LDS when it fits       */
+                             /* (else in HBM); 0 = always in HBM                     */
+    int fp64_polish_after;   /* FP32: after this many failed double-precision checks */
+                             /* the descent continues on a double state; 0 = never   */
 } dicod_config;
 
 typedef struct {
@@ -110,6 +114,10 @@ typedef struct {
     double t_verify_ms;       /* double-precision checks and refreshes              */
     double t_total_ms;        /* whole call                                         */
     double t_lgcd_kernel_ms;  /* sum of LGCD kernel durations (timing = 1)          */
+    int64_t round_updates[4]; /* updates of the first four descent rounds            */
+    int64_t round_phases[4];  /* phases of the first four descent rounds             */
+    int state_in_hbm;         /* 1 if segment state was kept in HBM, not LDS         */
+    int polished_fp64;        /* 1 if the descent finished on a double state         */
 } dicod_stats;
 
 /* One record per applied update (dicod_get_trace); 32 bytes. */
@@ -124,7 +132,8 @@ typedef struct {
 
 /* Fills *cfg with the defaults: device 0, FP32, even/odd, update_cap 16,
  * max_phases 1e6, max_refresh 8, phases_per_poll 16, inner_eps_factor 0.5,
- * timing 0, no trace.  Returns DICOD_OK, or DICOD_EINVAL if cfg is NULL. */
+ * timing 0, no trace, state_in_lds 1, fp64_polish_after 1.  Returns DICOD_OK,
+ * or DICOD_EINVAL if cfg is NULL. */
 int dicod_config_init(dicod_config *cfg);
 
 /* Creates a context on cfg->device (cfg NULL = defaults) with its own HIP

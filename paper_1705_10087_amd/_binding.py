@@ -52,6 +52,8 @@ class dicod_config(ctypes.Structure):
         ("max_inflight", ctypes.c_int),
         ("timing", ctypes.c_int),
         ("trace_capacity", ctypes.c_int64),
+        ("state_in_lds", ctypes.c_int),
+        ("fp64_polish_after", ctypes.c_int),
     ]
 
 
@@ -79,10 +81,17 @@ class dicod_stats(ctypes.Structure):
         ("t_verify_ms", ctypes.c_double),
         ("t_total_ms", ctypes.c_double),
         ("t_lgcd_kernel_ms", ctypes.c_double),
+        ("round_updates", ctypes.c_int64 * 4),
+        ("round_phases", ctypes.c_int64 * 4),
+        ("state_in_hbm", ctypes.c_int),
+        ("polished_fp64", ctypes.c_int),
     ]
 
     def to_dict(self):
-        d = {name: getattr(self, name) for name, _ in self._fields_}
+        d = {}
+        for name, _ in self._fields_:
+            v = getattr(self, name)
+            d[name] = list(v) if isinstance(v, ctypes.Array) else v
         d["lambda"] = d.pop("lambda_")
         return d
 

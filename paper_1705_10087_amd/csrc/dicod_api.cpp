@@ -62,7 +62,7 @@ hipError_t ensure(DevBuf& b, size_t bytes)
 
 struct Workspace {
     DevBuf X, Zout;                       // staging for the host-pointer API
-    DevBuf beta0, g;                      // [K][L] per signal
+    DevBuf beta0, g, g64;                 // [K][L] per signal (g64: double finish)
     DevBuf sig, segs, list0, list1;
     DevBuf tilesL, tilesT, tilesA;
     DevBuf dirty, phase_upd, sig_upd, sig_last, counters;
@@ -80,6 +80,7 @@ struct dicod_ctx {
     bool has_dict = false;
     int K = 0, P = 0, W = 0;
     DevBuf D64, S64, S32, n2_64, inv64, n2_32, inv32;
+    DevBuf St32, St64;  // phase-kernel layouts of S (float, double)
     Workspace ws;
     unsigned long long* h_upd = nullptr;  // pinned copy of per-phase counts
     size_t h_upd_cap = 0;
@@ -158,6 +159,8 @@ extern "C" int dicod_config_init(dicod_config* cfg)
     cfg->max_inflight = 64;
     cfg->timing = 0;
     cfg->trace_capacity = 0;
+    cfg->state_in_lds = 1;
+    cfg->fp64_polish_after = 1;
     return DICOD_OK;
 }
 
@@ -177,7 +180,7 @@ extern "C" int dicod_init(dicod_ctx** out, const dicod_config* cfg)
         return fail(nullptr, DICOD_EINVAL, "dicod_init: unknown schedule %d", c.schedule);
     if (c.update_cap < 0 || c.max_phases < 2 || c.max_refresh < 0 ||
         c.phases_per_poll < 1 || !(c.inner_eps_factor > 0.0 && c.inner_eps_factor <= 1.0) ||
-        c.trace_capacity < 0 || c.max_inflight < 1)
+        c.trace_capacity < 0 || c.max_inflight < 1 || c.fp64_polish_after < 0)
         return fail(nullptr, DICOD_EINVAL, "dicod_init: invalid configuration field");
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0)
@@ -302,6 +305,14 @@ extern "C" int dicod_set_dictionary(dicod_ctx* ctx, const float* D, int K, int P
     HIPCHECK(ctx, launch_dict_finish(ctx->S64.as<double>(), K, W, ctx->S32.as<float>(),
                                      ctx->n2_64.as<double>(), ctx->inv64.as<double>(),
                                      ctx->n2_32.as<float>(), ctx->inv32.as<float>(), s));
+    for (int f64 = 0; f64 < 2; ++f64) {
+        const int KP = lgcd_k_padded(K, f64 != 0);
+        if (KP < 0)
+            continue;  // the phase kernel reports ENOTSUP for this K
+        DevBuf& St = f64 ? ctx->St64 : ctx->St32;
+        HIPCHECK(ctx, ensure(St, (size_t)K * nd * KP * (f64 ? sizeof(double) : sizeof(float))));
+        HIPCHECK(ctx, launch_s_transpose(ctx->S64.as<double>(), K, W, f64 != 0, St.p, s));
+    }
     HIPCHECK(ctx, hipStreamSynchronize(s));
     ctx->K = K;
     ctx->P = P;
@@ -340,11 +351,26 @@ struct Plan {
     size_t zext = 0;  // extent of the [K][L] arrays (elements)
 };
 
+// Where a precision keeps the segment state during a phase: LDS when the
+// largest segment fits (and the configuration allows it), else HBM.  Returns
+// false when neither kernel can hold the segments.
+bool state_fits(const Plan& pl, int K, bool fp64, bool allow_lds, bool* in_lds)
+{
+    if (allow_lds && pl.lext_max <= 4 * kPhaseThreads &&
+        lgcd_lds_bytes(K, pl.lm_max, pl.lext_max, fp64) <= kLdsBytes) {
+        *in_lds = true;
+        return true;
+    }
+    *in_lds = false;
+    return lgcd_gm_lds_bytes(K, pl.lext_max, fp64) <= kLdsBytes;
+}
+
 int make_plan(dicod_ctx* ctx, int n_sig, const int64_t* T, const int64_t* x_off,
               const double* lam, const int* n_seg, const int64_t* z_off, Plan& pl)
 {
     const int K = ctx->K, W = ctx->W;
     const bool fp64 = ctx->cfg.precision == DICOD_PREC_FP64;
+    (void)K;
     pl.sig.resize(n_sig);
     pl.prefL.assign(n_sig + 1, 0);
     pl.prefT.assign(n_sig + 1, 0);
@@ -374,11 +400,10 @@ int make_plan(dicod_ctx* ctx, int n_sig, const int64_t* T, const int64_t* x_off,
         int64_t lx = lm + 2 * (int64_t)(W - 1);
         if (lx > L)
             lx = L;
-        if (lgcd_lds_bytes(K, (int)lm, (int)lx, fp64) > kLdsBytes || lx > 4 * kPhaseThreads)
+        if (lgcd_gm_lds_bytes(K, (int)lx, fp64) > kLdsBytes)
             return fail(ctx, DICOD_ENOTSUP,
-                        "signal %d: segments of %lld coefficients do not fit the on-chip "
-                        "kernel (%zu bytes of LDS); use more segments", i, (long long)lm,
-                        lgcd_lds_bytes(K, (int)lm, (int)lx, fp64));
+                        "signal %d: segments of %lld coefficients are too long even for the "
+                        "HBM-state kernel; use more segments", i, (long long)lm);
         pl.lm_max = std::max(pl.lm_max, (int)lm);
         pl.lext_max = std::max(pl.lext_max, (int)lx);
         SigDesc& s = pl.sig[i];
@@ -545,21 +570,25 @@ int solve_device_batch(dicod_ctx* ctx, int n_sig, const float* dX, const int64_t
                                   sizeof(Counters) / 8, s));
     HIPCHECK(ctx, hipEventRecord(ev1, s));
 
+    // Precision of the descent state: float (FP32 policy) until the double
+    // check has failed fp64_polish_after times, then double; always double in
+    // the FP64 policy.
+    bool cur64 = fp64;
+    bool in_lds = false;
+    if (!state_fits(pl, K, cur64, cfg.state_in_lds != 0, &in_lds))
+        return fail(ctx, DICOD_ENOTSUP, "segments do not fit any phase kernel");
+    bool polished = false, any_hbm = !in_lds;
+
     PhaseArgs a;
     std::memset(&a, 0, sizeof a);
     a.segs = ws.segs.as<SegDesc>();
-    a.g = ws.g.p;
     a.Z = dZ;
-    a.S = fp64 ? ctx->S64.p : ctx->S32.p;
-    a.n2 = fp64 ? ctx->n2_64.p : ctx->n2_32.p;
-    a.inv_n2 = fp64 ? ctx->inv64.p : ctx->inv32.p;
     a.sigs = ws.sig.as<SigDesc>();
     a.K = K;
     a.W = W;
     // update_cap 0 means "run each segment to local convergence"; a finite
     // bound still guarantees that every workgroup exits.
     a.cap = cfg.update_cap > 0 ? cfg.update_cap : kRunUpdateBound;
-    a.eps_stop = fp64 ? eps : eps * cfg.inner_eps_factor;
     a.dirty = ws.dirty.as<uint32_t>();
     a.phase_upd = ws.phase_upd.as<unsigned long long>();
     a.sig_upd = ws.sig_upd.as<unsigned long long>();
@@ -569,11 +598,20 @@ int solve_device_batch(dicod_ctx* ctx, int n_sig, const float* dX, const int64_t
     a.trace_cap = cfg.trace_capacity;
     a.lm_max = pl.lm_max;
     a.lext_max = pl.lext_max;
+    auto set_state = [&](bool use64, bool lds) {
+        a.g = use64 && !fp64 ? ws.g64.p : ws.g.p;
+        a.S = use64 ? (lds ? ctx->St64.p : ctx->S64.p) : (lds ? ctx->St32.p : ctx->S32.p);
+        a.n2 = use64 ? ctx->n2_64.p : ctx->n2_32.p;
+        a.inv_n2 = use64 ? ctx->inv64.p : ctx->inv32.p;
+        a.eps_stop = use64 ? eps : eps * cfg.inner_eps_factor;
+    };
+    set_state(cur64, in_lds);
 
     int64_t phase = 0, n_launch = 0, conv_phase = -1;
-    int n_refresh = 0;
+    int n_refresh = 0, round = 0;
     bool accepted = false, out_of_phases = false;
     double t_cd = 0.0, t_verify = 0.0, t_kernel = 0.0;
+    int64_t round_upd[4] = {0, 0, 0, 0}, round_ph[4] = {0, 0, 0, 0};
     std::vector<CheckResult> res(n_sig);
     std::vector<uint32_t> done(n_sig, 0u);
 
@@ -590,7 +628,7 @@ int solve_device_batch(dicod_ctx* ctx, int n_sig, const float* dX, const int64_t
             // In float, rounding noise near the stop threshold can keep a few
             // coordinates changing for ever; after a bounded number of phases
             // the double-precision test decides instead.
-            if (!fp64 && phase - start >= kRoundPhaseLimit)
+            if (!cur64 && phase - start >= kRoundPhaseLimit)
                 break;
             const int64_t chunk = std::min<int64_t>(cfg.phases_per_poll, max_ph - phase);
             size_t evi = 4;
@@ -610,10 +648,11 @@ int solve_device_batch(dicod_ctx* ctx, int n_sig, const float* dX, const int64_t
                     HIPCHECK(ctx, hipEventRecord(e0, s));
                 }
                 size_t lds = 0;
-                hipError_t e = launch_lgcd_phase(a, fp64, &lds, s);
+                hipError_t e = in_lds ? launch_lgcd_phase(a, cur64, &lds, s)
+                                      : launch_lgcd_phase_gm(a, cur64, &lds, s);
                 if (e != hipSuccess)
-                    return fail(ctx, DICOD_EDEVICE, "LGCD phase launch (%zu bytes LDS): %s",
-                                lds, hipGetErrorString(e));
+                    return fail(ctx, DICOD_EDEVICE, "LGCD phase launch (%s state, %zu bytes LDS): %s",
+                                in_lds ? "LDS" : "HBM", lds, hipGetErrorString(e));
                 ++n_launch;
                 if (cfg.timing)
                     HIPCHECK(ctx, hipEventRecord(e1, s));
@@ -635,17 +674,32 @@ int solve_device_batch(dicod_ctx* ctx, int n_sig, const float* dX, const int64_t
         HIPCHECK(ctx, hipEventRecord(ev3, s));
         HIPCHECK(ctx, hipEventSynchronize(ev3));
         t_cd += elapsed_ms(ev2, ev3);
+        if (round < 4) {
+            const int64_t last = conv_phase >= 0 ? conv_phase + 1 : phase;
+            round_ph[round] = last - start;
+            for (int64_t p = start; p < last; ++p)
+                round_upd[round] += (int64_t)ctx->h_upd[p];
+        }
+        ++round;
 
-        // ---- 4. double-precision stop test (and refresh of g) --------------
+        // ---- 4. double-precision stop test; refresh of the next round's g
+        const bool next64 = cur64 || (cfg.fp64_polish_after > 0 &&
+                                      n_refresh + 1 >= cfg.fp64_polish_after);
+        bool next_lds = in_lds;
+        if (next64 != cur64 && !state_fits(pl, K, true, cfg.state_in_lds != 0, &next_lds))
+            return fail(ctx, DICOD_ENOTSUP, "segments do not fit the double-state kernel");
+        if (next64 && !fp64)
+            HIPCHECK(ctx, ensure(ws.g64, pl.zext * sizeof(double)));
+        void* g_next = next64 && !fp64 ? ws.g64.p : ws.g.p;
+        const double flag_eps = next64 ? eps : eps * cfg.inner_eps_factor;
         HIPCHECK(ctx, hipEventRecord(ev2, s));
         HIPCHECK(ctx, launch_resid(dX, ctx->D64.as<double>(), dZ, K, P, W, ws.sig.as<SigDesc>(),
                                    ws.tilesT.as<int64_t>(), n_sig, nT, ws.part_r2.as<double>(), s));
         HIPCHECK(ctx, launch_grad_check(ws.beta0.as<double>(), dZ, ctx->S64.as<double>(),
                                         ctx->n2_64.as<double>(), K, W, ws.sig.as<SigDesc>(),
-                                        ws.tilesL.as<int64_t>(), n_sig, nL, a.eps_stop,
+                                        ws.tilesL.as<int64_t>(), n_sig, nL, flag_eps,
                                         ws.done.as<uint32_t>(), ws.dirty.as<uint32_t>(),
-                                        ws.g.p, fp64,
-                                        ws.part6.as<double>(), s));
+                                        g_next, next64, ws.part6.as<double>(), s));
         HIPCHECK(ctx, launch_check_reduce(ws.part_r2.as<double>(), ws.tilesT.as<int64_t>(),
                                           ws.part6.as<double>(), ws.tilesL.as<int64_t>(), nL,
                                           n_kblk, n_sig, ws.results.as<CheckResult>(), s));
@@ -665,6 +719,13 @@ int solve_device_batch(dicod_ctx* ctx, int n_sig, const float* dX, const int64_t
         // offending segments marked dirty.  Resuming on an even phase keeps a
         // signal's sequence of segment runs independent of its co-runners.
         ++n_refresh;
+        if (next64 != cur64) {
+            cur64 = true;
+            in_lds = next_lds;
+            polished = true;
+            any_hbm |= !in_lds;
+        }
+        set_state(cur64, in_lds);
         HIPCHECK(ctx, upload(ws.done, done, s));
         if (phase & 1)
             ++phase;
@@ -709,6 +770,12 @@ int solve_device_batch(dicod_ctx* ctx, int n_sig, const float* dX, const int64_t
             o.t_verify_ms = t_verify;
             o.t_total_ms = t_total;
             o.t_lgcd_kernel_ms = t_kernel;
+            for (int r = 0; r < 4; ++r) {
+                o.round_updates[r] = n_sig == 1 ? round_upd[r] : 0;
+                o.round_phases[r] = round_ph[r];
+            }
+            o.state_in_hbm = any_hbm ? 1 : 0;
+            o.polished_fp64 = polished ? 1 : 0;
         }
     }
     if (!accepted)

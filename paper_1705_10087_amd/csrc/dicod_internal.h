@@ -115,6 +115,17 @@ struct PhaseArgs {
 hipError_t launch_lgcd_phase(const PhaseArgs& a, bool fp64, size_t* lds_bytes,
                              hipStream_t s);
 size_t lgcd_lds_bytes(int K, int lm_max, int lext_max, bool fp64);
+// The same phase with g and Z kept in HBM (segments too long for LDS, or
+// double state at large K * W); S in the [l][k][d] layout.
+hipError_t launch_lgcd_phase_gm(const PhaseArgs& a, bool fp64, size_t* lds_bytes,
+                                hipStream_t s);
+size_t lgcd_gm_lds_bytes(int K, int lext_max, bool fp64);
+// Atoms per position in the phase kernel's layout (K padded), -1 if K is
+// beyond the instantiated sizes.
+int lgcd_k_padded(int K, bool fp64);
+// St[l][d][k] = S_{k,l}[d - W + 1] (k < K; 0 for padded atoms), float or double.
+hipError_t launch_s_transpose(const double* S64, int K, int W, bool fp64, void* St,
+                              hipStream_t s);
 
 // Double-precision check: residual energy per tile (partials).
 hipError_t launch_resid(const float* X, const double* D, const double* Z, int K,

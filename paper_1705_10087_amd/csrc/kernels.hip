@@ -318,12 +318,15 @@ hipError_t launch_absmax_f32(const float* beta, int K, const SigDesc* sig,
 // |Delta Z| is below eps_stop or `cap` updates were applied.
 //
 // LDS holds g for the segment extended by W - 1 positions on each side (the
-// "interference zone" of Sec. 2.2) and a copy of Z for the segment.  Thread
-// tid owns the extended positions q = tid + i * 512, for all atoms; every LDS
-// entry is read and written only by its owner, so the window update of
-// eq. (3) needs no synchronisation.  The argmax is a block reduction of the
-// per-thread best (|Delta Z|, index t * K + k) keys; ties go to the smallest
-// t, then k.  Each update costs one barrier.
+// "interference zone" of Sec. 2.2) and a copy of Z for the segment, both
+// position-major with the atoms of one position contiguous (padded to a
+// multiple of 16 bytes).  The correlation table is read in the matching
+// layout St[k0][d][k], so the eq. (3) update of one position is a few 16-byte
+// loads, one multiply-add per atom and 16-byte stores.  Thread tid owns the
+// extended positions q = tid + i * 512; every LDS entry is read and written
+// only by its owner, so the window update needs no synchronisation.  The
+// argmax is a block reduction of the per-position best (|Delta Z|, t * K + k)
+// keys; ties go to the smallest t, then k.  Each update costs one barrier.
 //
 // Segments of one parity run in the same launch.  A run writes g back over
 // the part of the extended window it touched, i.e. into the idle neighbours'
@@ -331,23 +334,111 @@ hipError_t launch_absmax_f32(const float* beta, int K, const SigDesc* sig,
 // Algorithm 2.  Segments are >= 2W long, so two runs of one launch never touch
 // the same entry.
 // ---------------------------------------------------------------------------
-struct Key {
-    unsigned long long v;  // bit pattern of |Delta Z| as a non-negative double
+
+template <typename G>
+struct Vec;
+template <>
+struct Vec<float> {
+    typedef float T __attribute__((ext_vector_type(4)));
+    static constexpr int N = 4;
+};
+template <>
+struct Vec<double> {
+    typedef double T __attribute__((ext_vector_type(2)));
+    static constexpr int N = 2;
+};
+
+// Argmax keys.  float state: one 64-bit word, |Delta Z| bits above the
+// complemented index, so a plain unsigned max picks the largest value and,
+// among equal values, the smallest index.  double state: value bits and index
+// in two words.
+struct Key64 {
+    unsigned long long v;  // bit pattern of |Delta Z| (non-negative double)
     unsigned int i;        // j * K + k inside the segment
 };
 
-__device__ __forceinline__ bool better(const Key& a, const Key& b)
-{
-    return a.v > b.v || (a.v == b.v && a.i < b.i);
-}
+template <typename G>
+struct KeyOps;
+
+template <>
+struct KeyOps<float> {
+    typedef unsigned long long T;
+    static __device__ __forceinline__ T null() { return 0ull; }
+    static __device__ __forceinline__ T make(float ad, unsigned idx)
+    {
+        return ((unsigned long long)__float_as_uint(ad) << 32) |
+               (unsigned long long)(0xffffffffu - idx);
+    }
+    static __device__ __forceinline__ bool better(T a, T b) { return a > b; }
+    static __device__ __forceinline__ double value(T a)
+    {
+        return (double)__uint_as_float((unsigned)(a >> 32));
+    }
+    static __device__ __forceinline__ unsigned index(T a)
+    {
+        return 0xffffffffu - (unsigned)(a & 0xffffffffull);
+    }
+    static __device__ __forceinline__ T wave_max(T a)
+    {
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const T b = __shfl_xor(a, o);
+            a = b > a ? b : a;
+        }
+        return a;
+    }
+    static __device__ __forceinline__ bool same(T a, T b) { return a == b; }
+    static __device__ __forceinline__ T select(bool c, T a, T b) { return c ? a : b; }
+};
+
+template <>
+struct KeyOps<double> {
+    typedef Key64 T;
+    static __device__ __forceinline__ T null() { return Key64{0ull, 0xffffffffu}; }
+    static __device__ __forceinline__ T make(double ad, unsigned idx)
+    {
+        return Key64{(unsigned long long)__double_as_longlong(ad), idx};
+    }
+    static __device__ __forceinline__ bool better(const T& a, const T& b)
+    {
+        return a.v > b.v || (a.v == b.v && a.i < b.i);
+    }
+    static __device__ __forceinline__ double value(const T& a)
+    {
+        return __longlong_as_double((long long)a.v);
+    }
+    static __device__ __forceinline__ unsigned index(const T& a) { return a.i; }
+    static __device__ __forceinline__ T wave_max(T a)
+    {
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            T b;
+            b.v = __shfl_xor(a.v, o);
+            b.i = __shfl_xor(a.i, o);
+            const bool t = better(b, a);
+            a.v = t ? b.v : a.v;
+            a.i = t ? b.i : a.i;
+        }
+        return a;
+    }
+    static __device__ __forceinline__ bool same(const T& a, const T& b)
+    {
+        return a.v == b.v && a.i == b.i;
+    }
+    static __device__ __forceinline__ T select(bool c, const T& a, const T& b)
+    {
+        return Key64{c ? a.v : b.v, c ? a.i : b.i};
+    }
+};
 
 template <typename G>
 struct Slot {
-    Key key;
+    typename KeyOps<G>::T key;
     G d;
 };
 
-// Delta Z = Z' - Z in terms of g (eq. (pb_coord) with beta = g + |D|^2 z).
+// Delta Z = Z' - Z in terms of g (eq. (pb_coord) with beta = g + |D|^2 z);
+// *zero tells that the soft threshold sends the coordinate to 0.
 template <typename G>
 __device__ __forceinline__ G coord_delta(G g, G z, G n2, G inv_n2, G lam, bool* zero)
 {
@@ -358,65 +449,116 @@ __device__ __forceinline__ G coord_delta(G g, G z, G n2, G inv_n2, G lam, bool* 
     return zr ? -z : (g - lam * sg) * inv_n2;
 }
 
-template <int NQ, typename G>
-__device__ __forceinline__ void block_argmax(const Key (&best)[NQ], const G (&dl)[NQ],
-                                             Slot<G>* __restrict__ slot, Key& out,
-                                             G& dout)
+// Block argmax over every thread's NQ position keys; returns the winner's key
+// and Delta Z in all threads.  One barrier; slots are double-buffered by the
+// caller.
+template <typename G, int NQ>
+__device__ __forceinline__ void block_argmax(const typename KeyOps<G>::T (&best)[NQ],
+                                             const G (&dl)[NQ], Slot<G>* __restrict__ slot,
+                                             typename KeyOps<G>::T& out, G& dout)
 {
+    typedef KeyOps<G> KO;
     constexpr int NW = kPhaseThreads / 64;
-    // value selects (not a branch over the struct) keep the arrays in registers
-    Key m = best[0];
+    typename KO::T m = best[0];
     G d = dl[0];
     static_for<NQ>([&](auto ic) __attribute__((always_inline)) {
         constexpr int i = decltype(ic)::value;
         if (i > 0) {
-            const bool b = better(best[i], m);
-            m.v = b ? best[i].v : m.v;
-            m.i = b ? best[i].i : m.i;
+            const bool b = KO::better(best[i], m);
+            m = KO::select(b, best[i], m);
             d = b ? dl[i] : d;
         }
     });
-    Key w = m;
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        Key x;
-        x.v = __shfl_xor(w.v, o);
-        x.i = __shfl_xor(w.i, o);
-        if (better(x, w))
-            w = x;
-    }
-    if (m.v == w.v && m.i == w.i) {
+    const typename KO::T w = KO::wave_max(m);
+    if (KO::same(m, w)) {
         slot[threadIdx.x >> 6].key = w;
         slot[threadIdx.x >> 6].d = d;
     }
     __syncthreads();
-    Key bb = slot[0].key;
+    typename KO::T bb = slot[0].key;
     G bd = slot[0].d;
 #pragma unroll
     for (int wv = 1; wv < NW; ++wv) {
-        Key o = slot[wv].key;
-        if (better(o, bb)) {
-            bb = o;
-            bd = slot[wv].d;
-        }
+        const typename KO::T o = slot[wv].key;
+        const bool b = KO::better(o, bb);
+        bb = KO::select(b, o, bb);
+        bd = b ? slot[wv].d : bd;
     }
     out = bb;
     dout = bd;
 }
 
-// Byte offset of the argmax slots after the g and Z arrays, 16-byte aligned.
-__host__ __device__ constexpr size_t slot_offset(size_t elem, int K, int lx, int lm)
+// One extended position: optional eq. (3) update g -= S delta (s_row != null)
+// and, for an own position (z_row != null), the best candidate over the atoms.
+// Padded atoms have g = z = S = 0 and |D|^2 = 1, so their candidate is 0.
+template <typename G, int KQ>
+__device__ __forceinline__ void visit(G* __restrict__ g_row, const G* __restrict__ z_row,
+                                      const G* __restrict__ s_row, G delta,
+                                      const G (&n2r)[KQ * Vec<G>::N],
+                                      const G (&invr)[KQ * Vec<G>::N], G lam,
+                                      unsigned idx_base, typename KeyOps<G>::T& key, G& dbest)
 {
-    return ((elem * (size_t)K * ((size_t)lx + (size_t)lm)) + 15) & ~(size_t)15;
+    typedef typename Vec<G>::T V;
+    constexpr int N = Vec<G>::N;
+    V sv[KQ], gv[KQ], zv[KQ];
+    if (s_row) {
+#pragma unroll
+        for (int i = 0; i < KQ; ++i)
+            sv[i] = reinterpret_cast<const V*>(s_row)[i];
+    }
+#pragma unroll
+    for (int i = 0; i < KQ; ++i)
+        gv[i] = reinterpret_cast<const V*>(g_row)[i];
+    if (z_row) {
+#pragma unroll
+        for (int i = 0; i < KQ; ++i)
+            zv[i] = reinterpret_cast<const V*>(z_row)[i];
+    }
+    if (s_row) {
+#pragma unroll
+        for (int i = 0; i < KQ; ++i) {
+            gv[i] -= sv[i] * delta;
+            reinterpret_cast<V*>(g_row)[i] = gv[i];
+        }
+    }
+    if (z_row) {
+        G bestv = (G)-1;
+        G bd = (G)0;
+        int bk = 0;
+#pragma unroll
+        for (int i = 0; i < KQ; ++i)
+#pragma unroll
+            for (int c = 0; c < N; ++c) {
+                const int k = i * N + c;
+                bool zr;
+                const G d = coord_delta<G>(gv[i][c], zv[i][c], n2r[k], invr[k], lam, &zr);
+                const G ad = fabs(d);
+                const bool b = ad > bestv;
+                bestv = b ? ad : bestv;
+                bd = b ? d : bd;
+                bk = b ? k : bk;
+            }
+        key = KeyOps<G>::make(bestv, idx_base + (unsigned)bk);
+        dbest = bd;
+    }
 }
 
-template <typename G, int KC, int NQ>
+// Byte offset of the argmax slots after the g and Z arrays, 16-byte aligned.
+__host__ __device__ constexpr size_t slot_offset(size_t elem, int KP, int lx, int lm)
+{
+    return ((elem * (size_t)KP * ((size_t)lx + (size_t)lm)) + 15) & ~(size_t)15;
+}
+
+template <typename G, int KQ, int NQ>
 __global__ void __launch_bounds__(kPhaseThreads)
 k_lgcd_phase(PhaseArgs a)
 {
+    typedef KeyOps<G> KO;
+    typedef typename KO::T KeyT;
     constexpr int NT = kPhaseThreads;
     constexpr int NW = NT / 64;
-    const int K = KC ? KC : a.K;
+    constexpr int KP = KQ * Vec<G>::N;
+    const int K = a.K;
     const int W = a.W;
     const int nd = 2 * W - 1;
     const int tid = threadIdx.x;
@@ -437,62 +579,59 @@ k_lgcd_phase(PhaseArgs a)
     const int lx = a.lext_max;
     const int lm = a.lm_max;
 
-    G* g_l = reinterpret_cast<G*>(smem);
-    G* z_l = g_l + (size_t)K * lx;
-    Slot<G>* slots = reinterpret_cast<Slot<G>*>(
-        smem + slot_offset(sizeof(G), K, lx, lm));
+    G* g_l = reinterpret_cast<G*>(smem);          // [lx][KP]
+    G* z_l = g_l + (size_t)lx * KP;               // [lm][KP]
+    Slot<G>* slots = reinterpret_cast<Slot<G>*>(smem + slot_offset(sizeof(G), KP, lx, lm));
+    G* n2l = reinterpret_cast<G*>(slots + 2 * NW);  // [KP]
+    G* invl = n2l + KP;                             // [KP]
 
     G* __restrict__ gs = reinterpret_cast<G*>(a.g) + sd.z_off;
     double* __restrict__ Zs = a.Z + sd.z_off;
-    const G* __restrict__ S = reinterpret_cast<const G*>(a.S);
-    const G* __restrict__ n2v = reinterpret_cast<const G*>(a.n2);
-    const G* __restrict__ inv2v = reinterpret_cast<const G*>(a.inv_n2);
+    const G* __restrict__ St = reinterpret_cast<const G*>(a.S);  // [K][nd][KP]
     const G lam = (G)a.sigs[sd.sig].lam;
 
-    for (int i = tid; i < K * Lext; i += NT) {
+    // |D_k|^2 and its inverse: registers for the per-position passes, LDS for
+    // the data-dependent updated atom.  Padded atoms get 1.
+    G n2r[KP], invr[KP];
+#pragma unroll
+    for (int k = 0; k < KP; ++k) {
+        n2r[k] = k < K ? reinterpret_cast<const G*>(a.n2)[k] : (G)1;
+        invr[k] = k < K ? reinterpret_cast<const G*>(a.inv_n2)[k] : (G)1;
+    }
+    for (int k = tid; k < KP; k += NT) {
+        n2l[k] = k < K ? reinterpret_cast<const G*>(a.n2)[k] : (G)1;
+        invl[k] = k < K ? reinterpret_cast<const G*>(a.inv_n2)[k] : (G)1;
+    }
+    // state in: [k][t] in HBM -> [q][k] in LDS, padding zeroed
+    for (int i = tid; i < KP * Lext; i += NT) {
         const int k = i / Lext;
         const int q = i - k * Lext;
-        g_l[k * lx + q] = gs[(int64_t)k * L + ext_lo + q];
+        g_l[q * KP + k] = k < K ? gs[(int64_t)k * L + ext_lo + q] : (G)0;
     }
-    for (int i = tid; i < K * Lm; i += NT) {
+    for (int i = tid; i < KP * Lm; i += NT) {
         const int k = i / Lm;
         const int j = i - k * Lm;
-        z_l[k * lm + j] = (G)Zs[(int64_t)k * L + b + j];
+        z_l[j * KP + k] = k < K ? (G)Zs[(int64_t)k * L + b + j] : (G)0;
     }
     __syncthreads();
 
-    const Key knull = {0ull, 0xffffffffu};
-    Key best[NQ];
+    KeyT best[NQ];
     G dl[NQ];
     static_for<NQ>([&](auto ic) __attribute__((always_inline)) {
         constexpr int i = decltype(ic)::value;
-        best[i] = knull;
+        best[i] = KO::null();
         dl[i] = (G)0;
         const int q = tid + i * NT;
         const int j = q - off;
-        if (q < Lext && j >= 0 && j < Lm) {
-            Key kbest = knull;
-            G dbest = (G)0;
-            for (int k = 0; k < K; ++k) {
-                bool zr;
-                const G d = coord_delta<G>(g_l[k * lx + q], z_l[k * lm + j], n2v[k],
-                                           inv2v[k], lam, &zr);
-                const Key kc = {(unsigned long long)__double_as_longlong(fabs((double)d)),
-                                (unsigned)(j * K + k)};
-                if (better(kc, kbest)) {
-                    kbest = kc;
-                    dbest = d;
-                }
-            }
-            best[i] = kbest;
-            dl[i] = dbest;
-        }
+        if (q < Lext && j >= 0 && j < Lm)
+            visit<G, KQ>(g_l + q * KP, z_l + j * KP, nullptr, (G)0, n2r, invr, lam,
+                         (unsigned)(j * K), best[i], dl[i]);
     });
 
     int it = 0;
-    Key kb;
+    KeyT kb;
     G db;
-    block_argmax<NQ, G>(best, dl, slots + (it & 1) * NW, kb, db);
+    block_argmax<G, NQ>(best, dl, slots + (it & 1) * NW, kb, db);
     ++it;
 
     int n = 0;
@@ -500,26 +639,26 @@ k_lgcd_phase(PhaseArgs a)
     bool touch_l = false, touch_r = false;
     int tlo = INT_MAX, thi = -1;
     for (;;) {
-        const double v = __longlong_as_double((long long)kb.v);
-        if (v < a.eps_stop) {
+        if (KO::value(kb) < a.eps_stop) {
             conv = true;
             break;
         }
         if (n == a.cap)
             break;
-        const int j0 = (int)(kb.i / (unsigned)K);
-        const int k0 = (int)kb.i - j0 * K;
+        const unsigned kidx = KO::index(kb);
+        const int j0 = (int)(kidx / (unsigned)K);
+        const int k0 = (int)kidx - j0 * K;
         const int q0 = j0 + off;
         const G delta = db;
 
         if (tid == (q0 % NT)) {
             // Owner of the updated position: new Z value (exactly 0 when the
             // soft threshold is active), in LDS and in the double-precision Z.
-            const G zo = z_l[k0 * lm + j0];
+            const G zo = z_l[j0 * KP + k0];
             bool zr;
-            (void)coord_delta<G>(g_l[k0 * lx + q0], zo, n2v[k0], inv2v[k0], lam, &zr);
+            (void)coord_delta<G>(g_l[q0 * KP + k0], zo, n2l[k0], invl[k0], lam, &zr);
             const G zn = zr ? (G)0 : zo + delta;
-            z_l[k0 * lm + j0] = zn;
+            z_l[j0 * KP + k0] = zn;
             double* zp = Zs + (int64_t)k0 * L + b + j0;
             if (sizeof(G) == sizeof(double)) {
                 *zp = (double)zn;
@@ -553,7 +692,7 @@ k_lgcd_phase(PhaseArgs a)
         if (q0 + (W - 1) >= off + Lm && sd.right >= 0)
             touch_r = true;
 
-        const G* __restrict__ Srow = S + (size_t)k0 * K * nd;
+        const G* __restrict__ Sk = St + (size_t)k0 * nd * KP;
         static_for<NQ>([&](auto ic) __attribute__((always_inline)) {
             constexpr int i = decltype(ic)::value;
             const int q = tid + i * NT;
@@ -561,33 +700,12 @@ k_lgcd_phase(PhaseArgs a)
                 return;
             const int dj = q - q0 + (W - 1);
             const int j = q - off;
-            if (j >= 0 && j < Lm) {
-                Key kbest = knull;
-                G dbest = (G)0;
-                for (int k = 0; k < K; ++k) {
-                    const G sv = Srow[k * nd + dj];
-                    const G gv = g_l[k * lx + q] - sv * delta;
-                    g_l[k * lx + q] = gv;
-                    bool zr;
-                    const G d = coord_delta<G>(gv, z_l[k * lm + j], n2v[k], inv2v[k],
-                                               lam, &zr);
-                    const Key kc = {
-                        (unsigned long long)__double_as_longlong(fabs((double)d)),
-                        (unsigned)(j * K + k)};
-                    if (better(kc, kbest)) {
-                        kbest = kc;
-                        dbest = d;
-                    }
-                }
-                best[i] = kbest;
-                dl[i] = dbest;
-            } else {
-                for (int k = 0; k < K; ++k)
-                    g_l[k * lx + q] -= Srow[k * nd + dj] * delta;
-            }
+            const bool own = j >= 0 && j < Lm;
+            visit<G, KQ>(g_l + q * KP, own ? z_l + j * KP : nullptr, Sk + (size_t)dj * KP,
+                         delta, n2r, invr, lam, (unsigned)(j * K), best[i], dl[i]);
         });
         ++n;
-        block_argmax<NQ, G>(best, dl, slots + (it & 1) * NW, kb, db);
+        block_argmax<G, NQ>(best, dl, slots + (it & 1) * NW, kb, db);
         ++it;
     }
 
@@ -596,7 +714,7 @@ k_lgcd_phase(PhaseArgs a)
         for (int i = tid; i < K * wdt; i += NT) {
             const int k = i / wdt;
             const int q = tlo + (i - k * wdt);
-            gs[(int64_t)k * L + ext_lo + q] = g_l[k * lx + q];
+            gs[(int64_t)k * L + ext_lo + q] = g_l[q * KP + k];
         }
         if (tid == 0) {
             atomicAdd(&a.phase_upd[a.phase], (unsigned long long)n);
@@ -614,23 +732,48 @@ k_lgcd_phase(PhaseArgs a)
     }
 }
 
+// Atoms per position in the kernel instantiations: K is padded to one of
+// these multiples of the 16-byte vector width.
+static int pick_kq(int K, bool fp64)
+{
+    const int n = fp64 ? 2 : 4;
+    const int need = (K + n - 1) / n;
+    static const int f32[] = {1, 2, 4, 7, 8, 16};
+    static const int f64[] = {1, 2, 3, 4, 8, 13, 16, 32};
+    const int* t = fp64 ? f64 : f32;
+    const int m = fp64 ? 8 : 6;
+    for (int i = 0; i < m; ++i)
+        if (t[i] >= need)
+            return t[i];
+    return -1;
+}
+
+int lgcd_k_padded(int K, bool fp64)
+{
+    const int kq = pick_kq(K, fp64);
+    return kq < 0 ? -1 : kq * (fp64 ? 2 : 4);
+}
+
 size_t lgcd_lds_bytes(int K, int lm_max, int lext_max, bool fp64)
 {
+    const int KP = lgcd_k_padded(K, fp64);
+    if (KP < 0)
+        return (size_t)-1;
     const size_t e = fp64 ? sizeof(double) : sizeof(float);
     const size_t slots = 2 * (kPhaseThreads / 64) *
                          (fp64 ? sizeof(Slot<double>) : sizeof(Slot<float>));
-    return slot_offset(e, K, lext_max, lm_max) + slots;
+    return slot_offset(e, KP, lext_max, lm_max) + slots + 2 * e * (size_t)KP;
 }
 
-template <typename G, int KC>
-static hipError_t launch_phase_k(const PhaseArgs& a, int nq, size_t lds, hipStream_t s)
+template <typename G, int KQ>
+static hipError_t launch_phase_kq(const PhaseArgs& a, int nq, size_t lds, hipStream_t s)
 {
     const void* fn;
     switch (nq) {
-    case 1: fn = (const void*)k_lgcd_phase<G, KC, 1>; break;
-    case 2: fn = (const void*)k_lgcd_phase<G, KC, 2>; break;
-    case 3: fn = (const void*)k_lgcd_phase<G, KC, 3>; break;
-    case 4: fn = (const void*)k_lgcd_phase<G, KC, 4>; break;
+    case 1: fn = (const void*)k_lgcd_phase<G, KQ, 1>; break;
+    case 2: fn = (const void*)k_lgcd_phase<G, KQ, 2>; break;
+    case 3: fn = (const void*)k_lgcd_phase<G, KQ, 3>; break;
+    case 4: fn = (const void*)k_lgcd_phase<G, KQ, 4>; break;
     default: return hipErrorInvalidValue;
     }
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -639,10 +782,10 @@ static hipError_t launch_phase_k(const PhaseArgs& a, int nq, size_t lds, hipStre
         return e;
     dim3 grid((unsigned)a.n_list);
     switch (nq) {
-    case 1: hipLaunchKernelGGL((k_lgcd_phase<G, KC, 1>), grid, dim3(kPhaseThreads), lds, s, a); break;
-    case 2: hipLaunchKernelGGL((k_lgcd_phase<G, KC, 2>), grid, dim3(kPhaseThreads), lds, s, a); break;
-    case 3: hipLaunchKernelGGL((k_lgcd_phase<G, KC, 3>), grid, dim3(kPhaseThreads), lds, s, a); break;
-    case 4: hipLaunchKernelGGL((k_lgcd_phase<G, KC, 4>), grid, dim3(kPhaseThreads), lds, s, a); break;
+    case 1: hipLaunchKernelGGL((k_lgcd_phase<G, KQ, 1>), grid, dim3(kPhaseThreads), lds, s, a); break;
+    case 2: hipLaunchKernelGGL((k_lgcd_phase<G, KQ, 2>), grid, dim3(kPhaseThreads), lds, s, a); break;
+    case 3: hipLaunchKernelGGL((k_lgcd_phase<G, KQ, 3>), grid, dim3(kPhaseThreads), lds, s, a); break;
+    case 4: hipLaunchKernelGGL((k_lgcd_phase<G, KQ, 4>), grid, dim3(kPhaseThreads), lds, s, a); break;
     }
     return hipGetLastError();
 }
@@ -660,11 +803,318 @@ hipError_t launch_lgcd_phase(const PhaseArgs& a, bool fp64, size_t* lds_bytes,
         *lds_bytes = lds;
     if (lds > kLdsBytes)
         return hipErrorInvalidValue;
+    const int kq = pick_kq(a.K, fp64);
+    if (fp64) {
+        switch (kq) {
+        case 1: return launch_phase_kq<double, 1>(a, nq, lds, s);
+        case 2: return launch_phase_kq<double, 2>(a, nq, lds, s);
+        case 3: return launch_phase_kq<double, 3>(a, nq, lds, s);
+        case 4: return launch_phase_kq<double, 4>(a, nq, lds, s);
+        case 8: return launch_phase_kq<double, 8>(a, nq, lds, s);
+        case 13: return launch_phase_kq<double, 13>(a, nq, lds, s);
+        case 16: return launch_phase_kq<double, 16>(a, nq, lds, s);
+        case 32: return launch_phase_kq<double, 32>(a, nq, lds, s);
+        default: return hipErrorInvalidValue;
+        }
+    }
+    switch (kq) {
+    case 1: return launch_phase_kq<float, 1>(a, nq, lds, s);
+    case 2: return launch_phase_kq<float, 2>(a, nq, lds, s);
+    case 4: return launch_phase_kq<float, 4>(a, nq, lds, s);
+    case 7: return launch_phase_kq<float, 7>(a, nq, lds, s);
+    case 8: return launch_phase_kq<float, 8>(a, nq, lds, s);
+    case 16: return launch_phase_kq<float, 16>(a, nq, lds, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+// Correlation table in the phase kernel's layout: St[l][d][k] = S_{k,l}[d-W+1]
+// for k < K, zero for the padded atoms k in [K, KP).
+template <typename G>
+__global__ void k_s_transpose(const double* __restrict__ S64, int K, int W, int KP,
+                              G* __restrict__ St)
+{
+    const int nd = 2 * W - 1;
+    const size_t n = (size_t)K * nd * KP;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const int k = (int)(i % KP);
+        const size_t r = i / KP;
+        const int d = (int)(r % nd);
+        const int l = (int)(r / nd);
+        St[i] = k < K ? (G)S64[((size_t)l * K + k) * nd + d] : (G)0;
+    }
+}
+
+hipError_t launch_s_transpose(const double* S64, int K, int W, bool fp64, void* St,
+                              hipStream_t s)
+{
+    const int KP = lgcd_k_padded(K, fp64);
+    if (KP < 0)
+        return hipErrorInvalidValue;
     if (fp64)
-        return a.K == 25 ? launch_phase_k<double, 25>(a, nq, lds, s)
-                         : launch_phase_k<double, 0>(a, nq, lds, s);
-    return a.K == 25 ? launch_phase_k<float, 25>(a, nq, lds, s)
-                     : launch_phase_k<float, 0>(a, nq, lds, s);
+        hipLaunchKernelGGL(k_s_transpose<double>, dim3(256), dim3(256), 0, s, S64, K, W, KP,
+                           (double*)St);
+    else
+        hipLaunchKernelGGL(k_s_transpose<float>, dim3(256), dim3(256), 0, s, S64, K, W, KP,
+                           (float*)St);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// LGCD phase kernel for segments whose state does not fit in LDS (few long
+// segments, or double-precision state at the paper's sizes).  g and Z stay in
+// HBM/L2; LDS holds one best key per chunk of 64 extended positions.
+//
+// Position q of the extended segment is owned by thread q % 512 for the whole
+// run, so every global read-modify-write of g and Z is done by one thread and
+// needs no synchronisation.  The 64 positions of chunk c = q / 64 are owned by
+// the 64 lanes of wave c % 8: a chunk's maximum is a wave reduction.  After an
+// update only the chunks that meet the 2W - 1 window are recomputed; the
+// segment argmax is then a block reduction over the chunk maxima.
+// ---------------------------------------------------------------------------
+template <typename G>
+struct ChunkBest {
+    typename KeyOps<G>::T key;
+    G d;
+};
+
+// Recompute chunk c (one position per lane): optional eq. (3) update of the
+// positions inside [wlo, whi], then the best candidate of the own positions.
+template <typename G, int KC>
+__device__ __forceinline__ void gm_chunk(int c, int K, int Kr, int W, int off, int Lm,
+                                        int Lext, int ext_lo, int b, int64_t L,
+                                        G* __restrict__ gs, const double* __restrict__ Zs,
+                                        const G* __restrict__ Srow, G delta, int q0,
+                                        int wlo, int whi, const G* __restrict__ n2l,
+                                        const G* __restrict__ invl, G lam,
+                                        ChunkBest<G>* __restrict__ cb)
+{
+    typedef KeyOps<G> KO;
+    const int nd = 2 * W - 1;
+    const int lane = threadIdx.x & 63;
+    const int q = c * 64 + lane;
+    const int j = q - off;
+    const bool inq = q < Lext;
+    const bool upd = Srow && inq && q >= wlo && q <= whi;
+    const bool own = inq && j >= 0 && j < Lm;
+    typename KO::T best = KO::null();
+    G bd = (G)0;
+    if (upd || own) {
+        G* gp = gs + ext_lo + q;
+        const double* zp = Zs + b + j;
+        const int dj = q - q0 + (W - 1);
+        for (int k0 = 0; k0 < K; k0 += 8) {
+            G gv[8], sv[8];
+            double zv[8];
+#pragma unroll
+            for (int c8 = 0; c8 < 8; ++c8) {
+                const int k = k0 + c8;
+                gv[c8] = k < K ? gp[(int64_t)k * L] : (G)0;
+                sv[c8] = (upd && k < K) ? Srow[(int64_t)k * nd + dj] : (G)0;
+                zv[c8] = (own && k < K) ? zp[(int64_t)k * L] : 0.0;
+            }
+            if (upd) {
+#pragma unroll
+                for (int c8 = 0; c8 < 8; ++c8) {
+                    const int k = k0 + c8;
+                    gv[c8] -= sv[c8] * delta;
+                    if (k < K)
+                        gp[(int64_t)k * L] = gv[c8];
+                }
+            }
+            if (own) {
+#pragma unroll
+                for (int c8 = 0; c8 < 8; ++c8) {
+                    const int k = k0 + c8;
+                    if (k < K) {
+                        bool zr;
+                        const G d = coord_delta<G>(gv[c8], (G)zv[c8], n2l[k], invl[k], lam, &zr);
+                        const typename KO::T kc = KO::make(fabs(d), (unsigned)(j * Kr + k));
+                        const bool bt = KO::better(kc, best);
+                        best = KO::select(bt, kc, best);
+                        bd = bt ? d : bd;
+                    }
+                }
+            }
+        }
+    }
+    const typename KO::T w = KO::wave_max(best);
+    if (KO::same(best, w)) {
+        cb[c].key = w;
+        cb[c].d = bd;
+    }
+}
+
+template <typename G, int KC>
+__global__ void __launch_bounds__(kPhaseThreads)
+k_lgcd_phase_gm(PhaseArgs a)
+{
+    typedef KeyOps<G> KO;
+    typedef typename KO::T KeyT;
+    constexpr int NT = kPhaseThreads;
+    constexpr int NW = NT / 64;
+    const int K = KC ? KC : a.K;
+    const int W = a.W;
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6;
+
+    const int sid = a.list[blockIdx.x];
+    if (a.dirty[sid] == 0)
+        return;
+
+    extern __shared__ __align__(16) unsigned char smem[];
+    const SegDesc sd = a.segs[sid];
+    const int64_t L = sd.L;
+    const int b = sd.b;
+    const int Lm = sd.e - sd.b;
+    const int ext_lo = b - (W - 1) > 0 ? b - (W - 1) : 0;
+    const int ext_hi = sd.e + (W - 1) < sd.L ? sd.e + (W - 1) : sd.L;
+    const int Lext = ext_hi - ext_lo;
+    const int off = b - ext_lo;
+    const int nch = (Lext + 63) / 64;
+
+    ChunkBest<G>* cb = reinterpret_cast<ChunkBest<G>*>(smem);        // [nch]
+    Slot<G>* slots = reinterpret_cast<Slot<G>*>(cb + a.lext_max / 64 + 1);  // [2][NW]
+    G* n2l = reinterpret_cast<G*>(slots + 2 * NW);
+    G* invl = n2l + K;
+
+    G* __restrict__ gs = reinterpret_cast<G*>(a.g) + sd.z_off;
+    double* __restrict__ Zs = a.Z + sd.z_off;
+    const G* __restrict__ S = reinterpret_cast<const G*>(a.S);  // [K][K][2W-1]
+    const G lam = (G)a.sigs[sd.sig].lam;
+    const int nd = 2 * W - 1;
+    for (int k = tid; k < K; k += NT) {
+        n2l[k] = reinterpret_cast<const G*>(a.n2)[k];
+        invl[k] = reinterpret_cast<const G*>(a.inv_n2)[k];
+    }
+    __syncthreads();
+
+    for (int c = wave; c < nch; c += NW)
+        gm_chunk<G, KC>(c, K, a.K, W, off, Lm, Lext, ext_lo, b, L, gs, Zs, nullptr, (G)0, 0, 0,
+                        -1, n2l, invl, lam, cb);
+    __syncthreads();
+
+    int it = 0;
+    auto argmax = [&](KeyT& out, G& dout) __attribute__((always_inline)) {
+        KeyT m = KO::null();
+        G d = (G)0;
+        for (int c = tid; c < nch; c += NT) {
+            const KeyT kc = cb[c].key;
+            const bool bt = KO::better(kc, m);
+            m = KO::select(bt, kc, m);
+            d = bt ? cb[c].d : d;
+        }
+        KeyT bm[1] = {m};
+        G bdl[1] = {d};
+        block_argmax<G, 1>(bm, bdl, slots + (it & 1) * NW, out, dout);
+        ++it;
+    };
+    KeyT kb;
+    G db;
+    argmax(kb, db);
+
+    int n = 0;
+    bool conv = false;
+    bool touch_l = false, touch_r = false;
+    for (;;) {
+        if (KO::value(kb) < a.eps_stop) {
+            conv = true;
+            break;
+        }
+        if (n == a.cap)
+            break;
+        const unsigned kidx = KO::index(kb);
+        const int j0 = (int)(kidx / (unsigned)K);
+        const int k0 = (int)kidx - j0 * K;
+        const int q0 = j0 + off;
+        const G delta = db;
+
+        if (tid == (q0 % NT)) {
+            double* zp = Zs + (int64_t)k0 * L + b + j0;
+            const double zo = *zp;
+            bool zr;
+            (void)coord_delta<G>(gs[(int64_t)k0 * L + ext_lo + q0], (G)zo, n2l[k0], invl[k0],
+                                 lam, &zr);
+            *zp = zr ? 0.0 : zo + (double)delta;
+            if (a.trace) {
+                const unsigned long long r = atomicAdd(&a.counters->trace_n, 1ull);
+                if ((long long)r < a.trace_cap) {
+                    dicod_trace_rec rec;
+                    rec.phase = a.phase;
+                    rec.seg = sid;
+                    rec.k0 = k0;
+                    rec.n_local = n;
+                    rec.t0 = (int64_t)b + j0;
+                    rec.delta = zr ? -zo : (double)delta;
+                    a.trace[r] = rec;
+                }
+            }
+        }
+        // (the chunk pass below reads this Z entry on the same thread)
+        const int wlo = q0 - (W - 1) > 0 ? q0 - (W - 1) : 0;
+        const int whi = q0 + (W - 1) < Lext - 1 ? q0 + (W - 1) : Lext - 1;
+        if (q0 - (W - 1) < off && sd.left >= 0)
+            touch_l = true;
+        if (q0 + (W - 1) >= off + Lm && sd.right >= 0)
+            touch_r = true;
+        const G* __restrict__ Srow = S + (size_t)k0 * K * nd;
+        for (int c = wlo / 64 + ((wave - wlo / 64) % NW + NW) % NW; c <= whi / 64; c += NW)
+            gm_chunk<G, KC>(c, K, a.K, W, off, Lm, Lext, ext_lo, b, L, gs, Zs, Srow, delta,
+                            q0, wlo, whi, n2l, invl, lam, cb);
+        __syncthreads();
+        ++n;
+        argmax(kb, db);
+    }
+
+    if (n > 0 && tid == 0) {
+        atomicAdd(&a.phase_upd[a.phase], (unsigned long long)n);
+        atomicAdd(&a.sig_upd[sd.sig], (unsigned long long)n);
+        atomicMax(&a.sig_last_upd[sd.sig], a.phase);
+        atomicAdd(&a.counters->seg_runs, 1ull);
+    }
+    if (tid == 0) {
+        a.dirty[sid] = conv ? 0u : 1u;
+        if (touch_l)
+            a.dirty[sd.left] = 1u;
+        if (touch_r)
+            a.dirty[sd.right] = 1u;
+    }
+}
+
+size_t lgcd_gm_lds_bytes(int K, int lext_max, bool fp64)
+{
+    const size_t cbs = fp64 ? sizeof(ChunkBest<double>) : sizeof(ChunkBest<float>);
+    const size_t sls = fp64 ? sizeof(Slot<double>) : sizeof(Slot<float>);
+    const size_t e = fp64 ? sizeof(double) : sizeof(float);
+    return cbs * ((size_t)lext_max / 64 + 1) + sls * 2 * (kPhaseThreads / 64) + 2 * e * (size_t)K;
+}
+
+template <typename G, int KC>
+static hipError_t launch_gm_k(const PhaseArgs& a, size_t lds, hipStream_t s)
+{
+    hipError_t e = hipFuncSetAttribute((const void*)k_lgcd_phase_gm<G, KC>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL((k_lgcd_phase_gm<G, KC>), dim3((unsigned)a.n_list), dim3(kPhaseThreads),
+                       lds, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_lgcd_phase_gm(const PhaseArgs& a, bool fp64, size_t* lds_bytes,
+                                hipStream_t s)
+{
+    if (a.n_list <= 0)
+        return hipSuccess;
+    const size_t lds = lgcd_gm_lds_bytes(a.K, a.lext_max, fp64);
+    if (lds_bytes)
+        *lds_bytes = lds;
+    if (lds > kLdsBytes)
+        return hipErrorInvalidValue;
+    if (fp64)
+        return a.K == 25 ? launch_gm_k<double, 25>(a, lds, s) : launch_gm_k<double, 0>(a, lds, s);
+    return a.K == 25 ? launch_gm_k<float, 25>(a, lds, s) : launch_gm_k<float, 0>(a, lds, s);
 }
 
 // ---------------------------------------------------------------------------

@@ -85,17 +85,21 @@ def _sorted_oracle_trace(tr):
     return tr[order]
 
 
-@pytest.mark.parametrize("M,cap", [(4, 0), (4, 1), (4, 8), (1, 0), (63, 16)])
+@pytest.mark.parametrize("M,cap,lds", [(4, 0, 1), (4, 1, 1), (4, 8, 1), (1, 0, 1),
+                                       (63, 16, 1), (4, 8, 0), (63, 16, 0)])
 @pytest.mark.parametrize("seed", [0, 1])
-def test_fp64_trajectory_matches_oracle(dicod, M, cap, seed):
-    print(f"\ncase: FP64 trajectory small seed={seed} M={M} cap={cap}", flush=True)
+def test_fp64_trajectory_matches_oracle(dicod, M, cap, lds, seed):
+    """Both phase kernels (state in LDS, state in HBM) reproduce the oracle's
+    even/odd sequence of updates; M = 1 is Algorithm 1 (greedy CD)."""
+    print(f"\ncase: FP64 trajectory small seed={seed} M={M} cap={cap} lds={lds}", flush=True)
     X, D, _ = small(seed)
     lam = 0.1 * oracle.lambda_max(f64(X), f64(D))
     Zo, so, tro = oracle.lgcd(f64(X), f64(D), lam, EPS, M, cap=cap, trace_cap=10**6)
     with ctx_of(dicod, precision=dicod.DICOD_PREC_FP64, update_cap=cap,
-                trace_capacity=10**6) as c:
+                trace_capacity=10**6, state_in_lds=lds) as c:
         Z, st = c.solve(X, lam, EPS, n_seg=M, D=D)
         tr = c.trace()
+    assert st["state_in_hbm"] == (1 if (lds == 0 or M == 1) else 0)
     assert st["converged"] == 1 and so["converged"] == 1
     assert st["n_updates"] == so["n_updates"] == len(tr)
     assert st["n_phases"] == so["n_phases"]
@@ -137,16 +141,57 @@ def test_fp32_small_matches_oracle(dicod, seed, M):
     _check_solution(X, D, lam, Z, st, Zo)
 
 
-def test_paper_shaped_fp32_matches_oracle(dicod):
+def test_paper_shaped_fp32_matches_oracle(dicod, paper_problem):
     print("\ncase: FP32 paper-shaped P=7 K=25 W=200 T=150000 (auto segments)", flush=True)
-    X, D, _ = synth.workload(synth.PAPER, 0)
-    lam = 0.1 * oracle.lambda_max(f64(X), f64(D))
+    X, D, lam, Zo = paper_problem
     with ctx_of(dicod) as c:
         Z, st = c.solve(X, -0.1, EPS, n_seg=0, D=D)
     print(f"gpu: {st['n_updates']} updates, {st['n_phases']} phases, M={st['n_seg']}, "
           f"refresh={st['n_refresh']}, cd={st['t_cd_ms']:.2f} ms", flush=True)
     assert st["n_seg"] == 374
+    _check_solution(X, D, lam, Z, st, Zo)
+
+
+@pytest.fixture(scope="module")
+def paper_problem():
+    X, D, _ = synth.workload(synth.PAPER, 0)
+    lam = 0.1 * oracle.lambda_max(f64(X), f64(D))
     Zo, so, _ = oracle.lgcd(f64(X), f64(D), lam, EPS, 374, cap=16)
+    return X, D, lam, Zo
+
+
+@pytest.mark.parametrize("M", [8, 32, 128, 256])
+def test_paper_shaped_segment_sweep(dicod, paper_problem, M):
+    """Few long segments run with the state in HBM; every segment count gives
+    an eps-solution of the same problem."""
+    print(f"\ncase: paper-shaped FP32 M={M}", flush=True)
+    X, D, lam, Zo = paper_problem
+    with ctx_of(dicod) as c:
+        Z, st = c.solve(X, -0.1, EPS, n_seg=M, D=D)
+    print(f"gpu: {st['n_updates']} updates, {st['n_phases']} phases, hbm={st['state_in_hbm']}, "
+          f"cd={st['t_cd_ms']:.2f} ms", flush=True)
+    assert st["n_seg"] == M
+    _check_solution(X, D, lam, Z, st, Zo)
+
+
+def test_paper_shaped_fp64_hbm_state(dicod, paper_problem):
+    print("\ncase: paper-shaped FP64 (double state in HBM)", flush=True)
+    X, D, lam, Zo = paper_problem
+    with ctx_of(dicod, precision=dicod.DICOD_PREC_FP64) as c:
+        Z, st = c.solve(X, -0.1, EPS, n_seg=0, D=D)
+    assert st["state_in_hbm"] == 1 and st["n_refresh"] == 0
+    _check_solution(X, D, lam, Z, st, Zo)
+
+
+@pytest.mark.parametrize("polish", [0, 1, 2])
+def test_paper_shaped_fp32_polish_policies(dicod, paper_problem, polish):
+    print(f"\ncase: paper-shaped FP32 fp64_polish_after={polish}", flush=True)
+    X, D, lam, Zo = paper_problem
+    with ctx_of(dicod, fp64_polish_after=polish) as c:
+        Z, st = c.solve(X, -0.1, EPS, n_seg=0, D=D)
+    print(f"gpu: rounds {st['round_updates']} / {st['round_phases']}, refresh={st['n_refresh']}, "
+          f"polished={st['polished_fp64']}, cd={st['t_cd_ms']:.2f} verify={st['t_verify_ms']:.2f}",
+          flush=True)
     _check_solution(X, D, lam, Z, st, Zo)
 
 
