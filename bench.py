@@ -142,7 +142,9 @@ def main():
                   "n_phase_launches": s0["n_phase_launches"], "n_refresh": s0["n_refresh"],
                   "nnz": s0["nnz"], "objective": s0["objective"], "max_dz": s0["max_dz"],
                   "converged": s0["converged"], "t_init_ms": s0["t_init_ms"],
-                  "t_cd_ms": s0["t_cd_ms"], "t_verify_ms": s0["t_verify_ms"]},
+                  "t_cd_ms": s0["t_cd_ms"], "t_verify_ms": s0["t_verify_ms"],
+                  "round_updates": s0["round_updates"], "round_phases": s0["round_phases"],
+                  "polished_fp64": s0["polished_fp64"]},
         "roofline": {"kernel": "k_lgcd_phase", "bound": "hbm", "achieved": achieved,
                      "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
                      "traffic": traffic,
