@@ -47,15 +47,16 @@ def measured_traffic():
     return rec.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(X, D, lam, eps, M, cap):
+def cpu_baseline(X, D, lam, eps, M, cap, colors):
     import oracle
     t0 = time.perf_counter()
-    Z, st, _ = oracle.lgcd(X.astype(np.float64), D.astype(np.float64), lam, eps, M, cap=cap)
+    Z, st, _ = oracle.lgcd(X.astype(np.float64), D.astype(np.float64), lam, eps, M, cap=cap,
+                           colors=colors)
     dt = time.perf_counter() - t0
     return {"value": st["n_updates"] / dt, "unit": "coord updates/s", "cores": 1,
             "kind": "oracle", "time_to_eps_s": dt, "n_updates": int(st["n_updates"]),
-            "sample": f"one full solve of the same workload by the FP64 C oracle, even/odd "
-                      f"schedule, M={M}, update cap {cap}, single thread"}
+            "sample": f"one full solve of the same workload by the FP64 C oracle, same "
+                      f"schedule ({colors} colours, M={M}, update cap {cap}), single thread"}
 
 
 def main():
@@ -65,7 +66,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cap", type=int, default=16, help="updates per segment per phase")
-    ap.add_argument("--n-seg", type=int, default=0, help="0 = library default (L // 2W)")
+    ap.add_argument("--n-seg", type=int, default=0, help="0 = library default")
+    ap.add_argument("--colors", type=int, default=3, help="phase classes of the schedule")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-sweep", action="store_true")
     args = ap.parse_args()
@@ -91,7 +93,7 @@ def main():
     print(f"[bench] workload {w.name}; steps={args.steps} warmup={args.warmup}",
           file=sys.stderr, flush=True)
 
-    with d.Context(update_cap=args.cap) as c:
+    with d.Context(update_cap=args.cap, colors=args.colors) as c:
         c.set_dictionary(D)
         for i in range(args.warmup):
             _, st, _ = c.solve_device(Xd, -w.lam_rel, w.eps, args.n_seg, Zd, stream)
@@ -105,7 +107,7 @@ def main():
         wall = time.perf_counter() - t0
         print(f"[bench] timed {args.steps} solves in {wall:.3f} s", file=sys.stderr, flush=True)
 
-    with d.Context(update_cap=args.cap, timing=1) as c:
+    with d.Context(update_cap=args.cap, timing=1, colors=args.colors) as c:
         c.set_dictionary(D)
         _, tst, _ = c.solve_device(Xd, -w.lam_rel, w.eps, args.n_seg, Zd, stream)
         torch.cuda.synchronize()
@@ -137,7 +139,7 @@ def main():
                    "sigma_noise": w.sigma_noise, "lambda": "0.1*lambda_max",
                    "eps": w.eps, "n_seg": s0["n_seg"], "seg_len": s0["seg_len"],
                    "update_cap": args.cap, "precision": "FP32 descent, FP64 stop test",
-                   "schedule": "even/odd", "seed": args.seed},
+                   "schedule": f"{args.colors}-colour phases", "seed": args.seed},
         "solve": {"n_updates": s0["n_updates"], "n_phases": s0["n_phases"],
                   "n_phase_launches": s0["n_phase_launches"], "n_refresh": s0["n_refresh"],
                   "nnz": s0["nnz"], "objective": s0["objective"], "max_dz": s0["max_dz"],
@@ -155,9 +157,9 @@ def main():
     }
     if not args.no_sweep:
         sweep = []
-        with d.Context(update_cap=args.cap) as c:
+        with d.Context(update_cap=args.cap, colors=args.colors) as c:
             c.set_dictionary(D)
-            for M in (8, 16, 32, 64, 128, 256, 374, 512):
+            for M in (8, 16, 32, 64, 128, 256, 374, 512, 749):
                 try:
                     t1 = time.perf_counter()
                     _, st, _ = c.solve_device(Xd, -w.lam_rel, w.eps, M, Zd, stream)
@@ -169,7 +171,7 @@ def main():
         out["segment_sweep"] = sweep
     if not args.no_cpu_baseline:
         lam = s0["lambda"]
-        out["cpu_baseline"] = cpu_baseline(X, D, lam, w.eps, s0["n_seg"], args.cap)
+        out["cpu_baseline"] = cpu_baseline(X, D, lam, w.eps, s0["n_seg"], args.cap, args.colors)
     print(json.dumps(out), flush=True)
 
 

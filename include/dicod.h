@@ -11,11 +11,11 @@
  * solver runs the locally greedy coordinate descent of Algorithm 3 over M
  * time segments (Sec. 2.2, the DICOD segments C_m): each segment picks the
  * coordinate with the largest |Delta Z| (eq. (pb_coord)) inside itself and
- * applies the beta update of eq. (3).  Segments of one parity run at the same
- * time, one GPU workgroup each, then the other parity (even/odd schedule);
- * an update whose window reaches a neighbouring segment writes the
- * neighbour's state directly, which plays the part of the paper's boundary
- * messages (Algorithm 2).  The run stops when every coordinate has
+ * applies the beta update of eq. (3).  The segments are coloured m % C; the
+ * segments of one colour run at the same time, one GPU workgroup each, then
+ * the next colour (C = 2 is an even/odd schedule); an update whose window
+ * reaches a neighbouring segment writes the neighbour's state directly, which
+ * plays the part of the paper's boundary messages (Algorithm 2).  The run stops when every coordinate has
  * |Delta Z| < eps (Sec. 2.1, last paragraph), checked in double precision.
  *
  * Conventions for every entry point:
@@ -89,11 +89,14 @@ typedef struct {
                              /* (else in HBM); 0 = always in HBM                     */
     int fp64_polish_after;   /* FP32: after this many failed double-precision checks */
                              /* the descent continues on a double state; 0 = never   */
+    int colors;              /* phase classes C in 2..4: segment m runs in phases p  */
+                             /* with p % C == m % C (2 = even/odd); segments must be */
+                             /* >= max(W, (2W - 2) / (C - 1)) long                    */
 } dicod_config;
 
 typedef struct {
     int64_t n_updates;        /* coordinate updates applied                         */
-    int64_t n_phases;         /* even/odd phases until the stop test held           */
+    int64_t n_phases;         /* coloured phases until the stop test held           */
     int64_t n_phase_launches; /* LGCD kernel launches (>= n_phases)                 */
     int64_t n_segment_runs;   /* segment runs that made at least one update         */
     int64_t nnz;              /* non-zeros of the returned Z                        */
@@ -122,7 +125,7 @@ typedef struct {
 
 /* One record per applied update (dicod_get_trace); 32 bytes. */
 typedef struct {
-    int32_t phase;    /* even/odd phase index                 */
+    int32_t phase;    /* phase index                          */
     int32_t seg;      /* global segment index                 */
     int32_t k0;       /* atom                                 */
     int32_t n_local;  /* update index within the segment run  */
@@ -130,10 +133,10 @@ typedef struct {
     double delta;     /* applied change of Z_{k0}[t0]         */
 } dicod_trace_rec;
 
-/* Fills *cfg with the defaults: device 0, FP32, even/odd, update_cap 16,
+/* Fills *cfg with the defaults: device 0, FP32, coloured phases, update_cap 16,
  * max_phases 1e6, max_refresh 8, phases_per_poll 16, inner_eps_factor 0.5,
- * timing 0, no trace, state_in_lds 1, fp64_polish_after 1.  Returns DICOD_OK,
- * or DICOD_EINVAL if cfg is NULL. */
+ * timing 0, no trace, state_in_lds 1, fp64_polish_after 1, colors 3.  Returns
+ * DICOD_OK, or DICOD_EINVAL if cfg is NULL. */
 int dicod_config_init(dicod_config *cfg);
 
 /* Creates a context on cfg->device (cfg NULL = defaults) with its own HIP
@@ -162,10 +165,11 @@ int dicod_set_dictionary(dicod_ctx *ctx, const float *D, int K, int P, int W);
  *   D      host float [K][P][W]; NULL = use the resident dictionary (then K, W
  *          must match it); non-NULL replaces the resident dictionary
  *   lambda see conventions above; eps > 0 is the stop threshold on |Delta Z|
- *   n_seg  number of segments M; 0 = chosen by the library.  M > 1 requires
- *          floor(L / M) >= 2W so that segments of one parity never touch the
- *          same coordinates (Sec. 2.2: an update changes beta on 2W - 1
- *          positions)
+ *   n_seg  number of segments M; 0 = chosen by the library (the largest M
+ *          allowed).  M > 1 requires floor(L / M) >= max(W, (2W - 2) / (C - 1))
+ *          for C = cfg.colors, so that segments running in the same phase never
+ *          touch the same coordinates (Sec. 2.2: an update changes beta on
+ *          2W - 1 positions)
  *   Z_out  host double [K][L], written on DICOD_OK and DICOD_ENOTCONV
  *   st     optional statistics
  * Errors: EINVAL, ENOTSUP (segment too long for the on-chip kernel), ENOMEM,
@@ -184,7 +188,7 @@ int dicod_solve_device(dicod_ctx *ctx, const float *X_dev, int64_t T, double lam
 
 /* Solves n_sig independent signals of different lengths against the resident
  * dictionary in one set of launches: their segments are packed into the same
- * even/odd phases (batching).
+ * phases (batching).
  *   X_dev   device float, signal i is [P][T[i]] starting at element x_off[i]
  *   T, x_off, z_off: host int64 arrays of n_sig entries
  *   lambda  host double[n_sig] (each with the sign convention above)
@@ -221,7 +225,7 @@ int dicod_get_trace(dicod_ctx *ctx, dicod_trace_rec *out, int64_t cap, int64_t *
 /* Enqueues one signal (host float [P][T], copied before return) against the
  * resident dictionary; a scheduler thread admits requests while the HBM
  * budget and the in-flight limit allow, packs their segments into the
- * running even/odd phases, and retires each one when its own stop test holds
+ * running phases, and retires each one when its own stop test holds
  * (requests that arrive while others run join the next phase).
  * *req_id receives the request id.  Errors: EINVAL, ENOMEM (request larger
  * than the whole budget), EDEVICE. */

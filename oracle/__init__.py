@@ -100,7 +100,7 @@ def load_library(path):
     lib.oracle_lgcd.argtypes = [
         dp, dp, ci, ci, ci, i64, ctypes.c_double, ctypes.c_double, ci, ci,
         ctypes.POINTER(ctypes.c_int32), i64, ci, i64, dp,
-        ctypes.POINTER(OracleStats), ctypes.c_void_p, i64]
+        ctypes.POINTER(OracleStats), ctypes.c_void_p, i64, ci]
     return lib
 
 
@@ -186,8 +186,9 @@ def max_dz(X, D, Z, lam):
 
 
 def lgcd(X, D, lam, eps, M, schedule=SCHED_EVENODD, seq=None, cap=0,
-         max_steps=10**9, trace_cap=0):
-    """Locally greedy CD (Algorithm 3; even/odd phases or a given segment order).
+         max_steps=10**9, trace_cap=0, colors=2):
+    """Locally greedy CD (Algorithm 3; coloured phases (2 = even/odd) or a given
+    segment order).
 
     Returns (Z, stats dict, trace array or None).  Raises on bad arguments;
     stats['converged'] tells whether the stop test was met.
@@ -209,7 +210,7 @@ def lgcd(X, D, lam, eps, M, schedule=SCHED_EVENODD, seq=None, cap=0,
         _ptr(X), _ptr(D), K, P, W, T, float(lam), float(eps), int(M),
         int(schedule), seq_arr.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
         int(seq_len), int(cap), int(max_steps), _ptr(Z), ctypes.byref(st),
-        trace.ctypes.data if trace_cap > 0 else None, int(trace_cap))
+        trace.ctypes.data if trace_cap > 0 else None, int(trace_cap), int(colors))
     if rc < 0:
         raise ValueError(f"oracle_lgcd rejected its arguments (rc={rc})")
     stats = {name: getattr(st, name) for name, _ in OracleStats._fields_}

@@ -336,13 +336,14 @@ static void record(oracle_trace_rec *tr, int64_t cap, const oracle_stats *st,
  *   eps.
  *
  * schedule = ORACLE_SCHED_EVENODD: phases p = 0, 1, ...; in phase p the
- *   segments with m % 2 == p % 2 that are marked dirty each run locally greedy
- *   updates until their local maximum is below eps or `cap` updates were made
- *   (cap <= 0: no cap).  A segment stays dirty only if it stopped on the cap; a
- *   segment whose update window reaches a neighbour marks that neighbour dirty.
- *   Because segments are at least 2W long, segments of one parity never touch
- *   the same beta entries, so each phase equals running its segments one after
- *   the other.  The run stops after two consecutive phases without updates.
+ *   segments with m % C == p % C (C = `colors`, 2 gives even/odd) that are
+ *   marked dirty each run locally greedy updates until their local maximum is
+ *   below eps or `cap` updates were made (cap <= 0: no cap).  A segment stays
+ *   dirty only if it stopped on the cap; a segment whose update window reaches
+ *   a neighbour marks that neighbour dirty.  Segments are at least W long and
+ *   at least (2W - 2) / (C - 1) long, so segments of one colour never touch the
+ *   same beta entries and each phase equals running its segments one after the
+ *   other.  The run stops after C consecutive phases without updates.
  *
  * Returns 0 when converged, 1 when max_steps (updates) or max_phases ran out,
  * negative on bad arguments.
@@ -350,7 +351,8 @@ static void record(oracle_trace_rec *tr, int64_t cap, const oracle_stats *st,
 int oracle_lgcd(const double *X, const double *D, int K, int P, int W, int64_t T,
                 double lam, double eps, int M, int schedule, const int32_t *seq,
                 int64_t seq_len, int cap, int64_t max_steps, double *Z,
-                oracle_stats *st, oracle_trace_rec *trace, int64_t trace_cap)
+                oracle_stats *st, oracle_trace_rec *trace, int64_t trace_cap,
+                int colors)
 {
     if (K <= 0 || P <= 0 || W <= 0 || T < W || !(lam > 0.0) || !(eps > 0.0) ||
         M <= 0)
@@ -358,8 +360,14 @@ int oracle_lgcd(const double *X, const double *D, int K, int P, int W, int64_t T
     const int64_t L = T - W + 1;
     if (M > L)
         return -1;
-    if (schedule == ORACLE_SCHED_EVENODD && M > 1 && L / M < 2 * W)
-        return -2;
+    if (schedule == ORACLE_SCHED_EVENODD) {
+        if (colors < 2)
+            return -1;
+        /* segments of one colour must be 2W - 2 apart, and a window may only
+         * reach the adjacent segments */
+        if (M > 1 && (L / M < W || (colors - 1) * (L / M) < 2 * W - 2))
+            return -2;
+    }
     if (schedule == ORACLE_SCHED_SEQUENCE && (!seq || seq_len <= 0))
         return -1;
     const int nd = 2 * W - 1;
@@ -425,11 +433,11 @@ int oracle_lgcd(const double *X, const double *D, int K, int P, int W, int64_t T
     } else if (schedule == ORACLE_SCHED_EVENODD) {
         unsigned char *dirty = (unsigned char *)malloc((size_t)M);
         memset(dirty, 1, (size_t)M);
-        int64_t prev = -1;
+        int64_t quiet = 0; /* consecutive phases without updates */
         for (int64_t p = 0; local.n_updates < max_steps; ++p) {
-            int par = (int)(p & 1);
+            int par = (int)(p % colors);
             int64_t upd = 0;
-            for (int m = par; m < M; m += 2) {
+            for (int m = par; m < M; m += colors) {
                 if (!dirty[m])
                     continue;
                 local.n_steps++;
@@ -467,11 +475,11 @@ int oracle_lgcd(const double *X, const double *D, int K, int P, int W, int64_t T
                 upd += n;
             }
             local.n_phases = p + 1;
-            if (p >= 1 && upd == 0 && prev == 0) {
+            quiet = upd == 0 ? quiet + 1 : 0;
+            if (quiet >= colors) {
                 rc = 0;
                 break;
             }
-            prev = upd;
         }
         free(dirty);
     } else {

@@ -54,6 +54,7 @@ class dicod_config(ctypes.Structure):
         ("trace_capacity", ctypes.c_int64),
         ("state_in_lds", ctypes.c_int),
         ("fp64_polish_after", ctypes.c_int),
+        ("colors", ctypes.c_int),
     ]
 
 

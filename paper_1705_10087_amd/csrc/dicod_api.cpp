@@ -4,8 +4,9 @@
 // M time segments (Sec. 2.2):
 //   1. beta at Z = 0 (Algorithm 1 init) on MFMA, in double;
 //   2. lambda = |lambda| * max |beta| when lambda is relative;
-//   3. even/odd phases of segment runs (kernels.hip: k_lgcd_phase) until two
-//      consecutive phases apply no update;
+//   3. coloured phases of segment runs (kernels.hip: k_lgcd_phase, or
+//      k_lgcd_phase_gm when the state stays in HBM) until C consecutive
+//      phases apply no update;
 //   4. a double-precision check of max |Delta Z| over all coordinates (the
 //      stop test of Sec. 2.1); in the FP32 policy a failed check refreshes g
 //      from the double recompute and resumes step 3.
@@ -63,7 +64,7 @@ hipError_t ensure(DevBuf& b, size_t bytes)
 struct Workspace {
     DevBuf X, Zout;                       // staging for the host-pointer API
     DevBuf beta0, g, g64;                 // [K][L] per signal (g64: double finish)
-    DevBuf sig, segs, list0, list1;
+    DevBuf sig, segs, lists[kMaxColors];
     DevBuf tilesL, tilesT, tilesA;
     DevBuf dirty, phase_upd, sig_upd, sig_last, counters;
     DevBuf part_r2, part6, results, lmax, done;
@@ -129,11 +130,22 @@ double now_ms()
     return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
 }
 
-// Segment count M chosen by the library: the largest M with floor(L/M) >= 2W,
-// close to the paper's optimum M* ~ T / (2W) (Corollary 1).
-int auto_segments(int64_t L, int W)
+// Shortest segment for C colours: segments of one colour run together and
+// must stay 2W - 2 apart (two half-windows), and a window may only reach the
+// adjacent segments.
+int64_t min_segment(int W, int C)
 {
-    const int64_t M = L / (2 * (int64_t)W);
+    const int64_t gap = (2 * (int64_t)W - 2 + (C - 2)) / (C - 1);
+    return std::max<int64_t>(W, gap);
+}
+
+// Segment count M chosen by the library: the largest M allowed by
+// min_segment (with 2 colours this is close to the paper's optimum
+// M* ~ T / (2W) of Corollary 1; 3 colours give segments of length W, the
+// paper's M = T / W choice for SeqDICOD).
+int auto_segments(int64_t L, int W, int C)
+{
+    const int64_t M = L / min_segment(W, C);
     return M < 1 ? 1 : (int)std::min<int64_t>(M, INT32_MAX);
 }
 
@@ -161,6 +173,7 @@ extern "C" int dicod_config_init(dicod_config* cfg)
     cfg->trace_capacity = 0;
     cfg->state_in_lds = 1;
     cfg->fp64_polish_after = 1;
+    cfg->colors = 3;
     return DICOD_OK;
 }
 
@@ -180,7 +193,8 @@ extern "C" int dicod_init(dicod_ctx** out, const dicod_config* cfg)
         return fail(nullptr, DICOD_EINVAL, "dicod_init: unknown schedule %d", c.schedule);
     if (c.update_cap < 0 || c.max_phases < 2 || c.max_refresh < 0 ||
         c.phases_per_poll < 1 || !(c.inner_eps_factor > 0.0 && c.inner_eps_factor <= 1.0) ||
-        c.trace_capacity < 0 || c.max_inflight < 1 || c.fp64_polish_after < 0)
+        c.trace_capacity < 0 || c.max_inflight < 1 || c.fp64_polish_after < 0 ||
+        c.colors < 2 || c.colors > kMaxColors)
         return fail(nullptr, DICOD_EINVAL, "dicod_init: invalid configuration field");
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0)
@@ -345,7 +359,8 @@ namespace {
 struct Plan {
     std::vector<SigDesc> sig;
     std::vector<SegDesc> segs;
-    std::vector<int32_t> list[2];
+    std::vector<int32_t> list[kMaxColors];
+    int colors = 2;
     std::vector<int64_t> prefL, prefT, prefA;
     int lm_max = 0, lext_max = 0;
     size_t zext = 0;  // extent of the [K][L] arrays (elements)
@@ -371,6 +386,7 @@ int make_plan(dicod_ctx* ctx, int n_sig, const int64_t* T, const int64_t* x_off,
     const int K = ctx->K, W = ctx->W;
     const bool fp64 = ctx->cfg.precision == DICOD_PREC_FP64;
     (void)K;
+    pl.colors = ctx->cfg.colors;
     pl.sig.resize(n_sig);
     pl.prefL.assign(n_sig + 1, 0);
     pl.prefT.assign(n_sig + 1, 0);
@@ -389,13 +405,14 @@ int make_plan(dicod_ctx* ctx, int n_sig, const int64_t* T, const int64_t* x_off,
         if (M < 0)
             return fail(ctx, DICOD_EINVAL, "signal %d: n_seg=%d < 0", i, M);
         if (M == 0)
-            M = auto_segments(L, W);
+            M = auto_segments(L, W, pl.colors);
         if (M > L)
             return fail(ctx, DICOD_EINVAL, "signal %d: n_seg=%d > L=%lld", i, M, (long long)L);
-        if (M > 1 && L / M < 2 * (int64_t)W)
+        if (M > 1 && L / M < min_segment(W, pl.colors))
             return fail(ctx, DICOD_EINVAL,
-                        "signal %d: n_seg=%d gives segments of %lld < 2W=%d coefficients", i,
-                        M, (long long)(L / M), 2 * W);
+                        "signal %d: n_seg=%d gives segments of %lld < %lld coefficients "
+                        "(W=%d, %d colours)", i, M, (long long)(L / M),
+                        (long long)min_segment(W, pl.colors), W, pl.colors);
         const int64_t lm = ceil_div(L, M);
         int64_t lx = lm + 2 * (int64_t)(W - 1);
         if (lx > L)
@@ -423,7 +440,7 @@ int make_plan(dicod_ctx* ctx, int n_sig, const int64_t* T, const int64_t* x_off,
             d.sig = i;
             d.left = m > 0 ? s.seg_base + m - 1 : -1;
             d.right = m < M - 1 ? s.seg_base + m + 1 : -1;
-            pl.list[m & 1].push_back(s.seg_base + m);
+            pl.list[m % pl.colors].push_back(s.seg_base + m);
             pl.segs.push_back(d);
         }
         pl.prefL[i + 1] = pl.prefL[i] + ceil_div(L, kTile);
@@ -514,8 +531,8 @@ int solve_device_batch(dicod_ctx* ctx, int n_sig, const float* dX, const int64_t
     }
     HIPCHECK(ctx, upload(ws.sig, pl.sig, s));
     HIPCHECK(ctx, upload(ws.segs, pl.segs, s));
-    HIPCHECK(ctx, upload(ws.list0, pl.list[0], s));
-    HIPCHECK(ctx, upload(ws.list1, pl.list[1], s));
+    for (int c = 0; c < pl.colors; ++c)
+        HIPCHECK(ctx, upload(ws.lists[c], pl.list[c], s));
     HIPCHECK(ctx, upload(ws.tilesL, pl.prefL, s));
     HIPCHECK(ctx, upload(ws.tilesT, pl.prefT, s));
     HIPCHECK(ctx, upload(ws.tilesA, pl.prefA, s));
@@ -616,7 +633,7 @@ int solve_device_batch(dicod_ctx* ctx, int n_sig, const float* dX, const int64_t
     std::vector<uint32_t> done(n_sig, 0u);
 
     for (;;) {
-        // ---- 3. even/odd phases until two consecutive phases apply nothing
+        // ---- 3. coloured phases until C consecutive phases apply nothing
         HIPCHECK(ctx, hipEventRecord(ev2, s));
         const int64_t start = phase;
         conv_phase = -1;
@@ -633,8 +650,8 @@ int solve_device_batch(dicod_ctx* ctx, int n_sig, const float* dX, const int64_t
             const int64_t chunk = std::min<int64_t>(cfg.phases_per_poll, max_ph - phase);
             size_t evi = 4;
             for (int64_t c = 0; c < chunk; ++c, ++phase) {
-                const int par = (int)(phase & 1);
-                a.list = par ? ws.list1.as<int32_t>() : ws.list0.as<int32_t>();
+                const int par = (int)(phase % pl.colors);
+                a.list = ws.lists[par].as<int32_t>();
                 a.n_list = (int)pl.list[par].size();
                 a.phase = (int)phase;
                 if (a.n_list == 0)
@@ -657,7 +674,7 @@ int solve_device_batch(dicod_ctx* ctx, int n_sig, const float* dX, const int64_t
                 if (cfg.timing)
                     HIPCHECK(ctx, hipEventRecord(e1, s));
             }
-            const int64_t from = std::max<int64_t>(start, phase - chunk - 1);
+            const int64_t from = std::max<int64_t>(start, phase - chunk - pl.colors);
             HIPCHECK(ctx, hipMemcpyAsync(ctx->h_upd + from, ws.phase_upd.as<unsigned long long>() + from,
                                          (size_t)(phase - from) * sizeof(unsigned long long),
                                          hipMemcpyDeviceToHost, s));
@@ -665,11 +682,17 @@ int solve_device_batch(dicod_ctx* ctx, int n_sig, const float* dX, const int64_t
             if (cfg.timing)
                 for (size_t i = 4; i < evi; i += 2)
                     t_kernel += elapsed_ms(ctx->ev_pool[i], ctx->ev_pool[i + 1]);
-            for (int64_t p = std::max<int64_t>(start + 1, from + 1); p < phase; ++p)
-                if (ctx->h_upd[p] == 0 && ctx->h_upd[p - 1] == 0) {
+            // converged once `colors` consecutive phases applied nothing
+            for (int64_t p = std::max<int64_t>(start + pl.colors - 1, from + 1); p < phase;
+                 ++p) {
+                bool quiet = true;
+                for (int c = 0; c < pl.colors; ++c)
+                    quiet &= ctx->h_upd[p - c] == 0;
+                if (quiet) {
                     conv_phase = p;
                     break;
                 }
+            }
         }
         HIPCHECK(ctx, hipEventRecord(ev3, s));
         HIPCHECK(ctx, hipEventSynchronize(ev3));
@@ -716,7 +739,7 @@ int solve_device_batch(dicod_ctx* ctx, int n_sig, const float* dX, const int64_t
         if (accepted || out_of_phases || n_refresh >= cfg.max_refresh)
             break;
         // Signals that passed are frozen; the others had g refreshed and their
-        // offending segments marked dirty.  Resuming on an even phase keeps a
+        // offending segments marked dirty.  Resuming on colour 0 keeps a
         // signal's sequence of segment runs independent of its co-runners.
         ++n_refresh;
         if (next64 != cur64) {
@@ -727,7 +750,7 @@ int solve_device_batch(dicod_ctx* ctx, int n_sig, const float* dX, const int64_t
         }
         set_state(cur64, in_lds);
         HIPCHECK(ctx, upload(ws.done, done, s));
-        if (phase & 1)
+        while (phase % pl.colors)
             ++phase;
     }
 

@@ -13,6 +13,8 @@ namespace dicod {
 constexpr int kMaxK = 32;        // atoms handled by the verify kernels per pass
 constexpr int kMaxP = 16;        // channels handled by the residual kernel
 constexpr int kPhaseThreads = 512;
+constexpr int kPhaseThreadsMax = 1024;
+constexpr int kMaxColors = 4;  // phase classes of the segment schedule
 constexpr int kTile = 256;       // positions per workgroup in the tiled kernels
 constexpr size_t kLdsBytes = 163840;  // LDS per workgroup on gfx950
 constexpr int kRunUpdateBound = 1 << 16;  // updates per segment run when uncapped

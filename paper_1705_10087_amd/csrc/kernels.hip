@@ -360,6 +360,34 @@ struct Key64 {
 template <typename G>
 struct KeyOps;
 
+// One DPP step of a wave-wide maximum of a 64-bit unsigned key: the lanes in
+// rows enabled by RM read the lane selected by CTRL; others keep their value.
+template <int CTRL, int RM>
+__device__ __forceinline__ unsigned long long dpp_max_step(unsigned long long a)
+{
+    const unsigned lo = (unsigned)a, hi = (unsigned)(a >> 32);
+    const unsigned olo = (unsigned)__builtin_amdgcn_update_dpp((int)lo, (int)lo, CTRL, RM, 0xf, false);
+    const unsigned ohi = (unsigned)__builtin_amdgcn_update_dpp((int)hi, (int)hi, CTRL, RM, 0xf, false);
+    const unsigned long long o = ((unsigned long long)ohi << 32) | olo;
+    return o > a ? o : a;
+}
+
+// Wave-wide maximum with DPP row operations: quad swaps, half-row and row
+// mirrors, then the row broadcasts of lanes 15 and 31; lane 63 ends with the
+// maximum of all 64 lanes, which is broadcast through a scalar register.
+__device__ __forceinline__ unsigned long long dpp_wave_max_u64(unsigned long long a)
+{
+    a = dpp_max_step<0xB1, 0xf>(a);   // quad_perm [1,0,3,2]
+    a = dpp_max_step<0x4E, 0xf>(a);   // quad_perm [2,3,0,1]
+    a = dpp_max_step<0x141, 0xf>(a);  // row_half_mirror
+    a = dpp_max_step<0x140, 0xf>(a);  // row_mirror
+    a = dpp_max_step<0x142, 0xa>(a);  // row_bcast:15 into rows 1 and 3
+    a = dpp_max_step<0x143, 0xc>(a);  // row_bcast:31 into rows 2 and 3
+    const unsigned lo = __builtin_amdgcn_readlane((unsigned)a, 63);
+    const unsigned hi = __builtin_amdgcn_readlane((unsigned)(a >> 32), 63);
+    return ((unsigned long long)hi << 32) | lo;
+}
+
 template <>
 struct KeyOps<float> {
     typedef unsigned long long T;
@@ -378,15 +406,7 @@ struct KeyOps<float> {
     {
         return 0xffffffffu - (unsigned)(a & 0xffffffffull);
     }
-    static __device__ __forceinline__ T wave_max(T a)
-    {
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) {
-            const T b = __shfl_xor(a, o);
-            a = b > a ? b : a;
-        }
-        return a;
-    }
+    static __device__ __forceinline__ T wave_max(T a) { return dpp_wave_max_u64(a); }
     static __device__ __forceinline__ bool same(T a, T b) { return a == b; }
     static __device__ __forceinline__ T select(bool c, T a, T b) { return c ? a : b; }
 };
@@ -452,13 +472,13 @@ __device__ __forceinline__ G coord_delta(G g, G z, G n2, G inv_n2, G lam, bool* 
 // Block argmax over every thread's NQ position keys; returns the winner's key
 // and Delta Z in all threads.  One barrier; slots are double-buffered by the
 // caller.
-template <typename G, int NQ>
+template <typename G, int NQ, int NT = kPhaseThreads>
 __device__ __forceinline__ void block_argmax(const typename KeyOps<G>::T (&best)[NQ],
                                              const G (&dl)[NQ], Slot<G>* __restrict__ slot,
                                              typename KeyOps<G>::T& out, G& dout)
 {
     typedef KeyOps<G> KO;
-    constexpr int NW = kPhaseThreads / 64;
+    constexpr int NW = NT / 64;
     typename KO::T m = best[0];
     G d = dl[0];
     static_for<NQ>([&](auto ic) __attribute__((always_inline)) {
@@ -495,8 +515,10 @@ template <typename G, int KQ>
 __device__ __forceinline__ void visit(G* __restrict__ g_row, const G* __restrict__ z_row,
                                       const G* __restrict__ s_row, G delta,
                                       const G (&n2r)[KQ * Vec<G>::N],
-                                      const G (&invr)[KQ * Vec<G>::N], G lam,
-                                      unsigned idx_base, typename KeyOps<G>::T& key, G& dbest)
+                                      const G (&invr)[KQ * Vec<G>::N],
+                                      const G* __restrict__ n2l, const G* __restrict__ invl,
+                                      G lam, unsigned idx_base, typename KeyOps<G>::T& key,
+                                      G& dbest)
 {
     typedef typename Vec<G>::T V;
     constexpr int N = Vec<G>::N;
@@ -523,7 +545,6 @@ __device__ __forceinline__ void visit(G* __restrict__ g_row, const G* __restrict
     }
     if (z_row) {
         G bestv = (G)-1;
-        G bd = (G)0;
         int bk = 0;
 #pragma unroll
         for (int i = 0; i < KQ; ++i)
@@ -535,11 +556,12 @@ __device__ __forceinline__ void visit(G* __restrict__ g_row, const G* __restrict
                 const G ad = fabs(d);
                 const bool b = ad > bestv;
                 bestv = b ? ad : bestv;
-                bd = b ? d : bd;
                 bk = b ? k : bk;
             }
         key = KeyOps<G>::make(bestv, idx_base + (unsigned)bk);
-        dbest = bd;
+        // the signed change of the winning atom, recomputed from the stored state
+        bool zr;
+        dbest = coord_delta<G>(g_row[bk], z_row[bk], n2l[bk], invl[bk], lam, &zr);
     }
 }
 
@@ -549,13 +571,12 @@ __host__ __device__ constexpr size_t slot_offset(size_t elem, int KP, int lx, in
     return ((elem * (size_t)KP * ((size_t)lx + (size_t)lm)) + 15) & ~(size_t)15;
 }
 
-template <typename G, int KQ, int NQ>
-__global__ void __launch_bounds__(kPhaseThreads)
+template <typename G, int KQ, int NQ, int NT>
+__global__ void __launch_bounds__(NT)
 k_lgcd_phase(PhaseArgs a)
 {
     typedef KeyOps<G> KO;
     typedef typename KO::T KeyT;
-    constexpr int NT = kPhaseThreads;
     constexpr int NW = NT / 64;
     constexpr int KP = KQ * Vec<G>::N;
     const int K = a.K;
@@ -624,14 +645,14 @@ k_lgcd_phase(PhaseArgs a)
         const int q = tid + i * NT;
         const int j = q - off;
         if (q < Lext && j >= 0 && j < Lm)
-            visit<G, KQ>(g_l + q * KP, z_l + j * KP, nullptr, (G)0, n2r, invr, lam,
+            visit<G, KQ>(g_l + q * KP, z_l + j * KP, nullptr, (G)0, n2r, invr, n2l, invl, lam,
                          (unsigned)(j * K), best[i], dl[i]);
     });
 
     int it = 0;
     KeyT kb;
     G db;
-    block_argmax<G, NQ>(best, dl, slots + (it & 1) * NW, kb, db);
+    block_argmax<G, NQ, NT>(best, dl, slots + (it & 1) * NW, kb, db);
     ++it;
 
     int n = 0;
@@ -702,10 +723,10 @@ k_lgcd_phase(PhaseArgs a)
             const int j = q - off;
             const bool own = j >= 0 && j < Lm;
             visit<G, KQ>(g_l + q * KP, own ? z_l + j * KP : nullptr, Sk + (size_t)dj * KP,
-                         delta, n2r, invr, lam, (unsigned)(j * K), best[i], dl[i]);
+                         delta, n2r, invr, n2l, invl, lam, (unsigned)(j * K), best[i], dl[i]);
         });
         ++n;
-        block_argmax<G, NQ>(best, dl, slots + (it & 1) * NW, kb, db);
+        block_argmax<G, NQ, NT>(best, dl, slots + (it & 1) * NW, kb, db);
         ++it;
     }
 
@@ -760,34 +781,38 @@ size_t lgcd_lds_bytes(int K, int lm_max, int lext_max, bool fp64)
     if (KP < 0)
         return (size_t)-1;
     const size_t e = fp64 ? sizeof(double) : sizeof(float);
-    const size_t slots = 2 * (kPhaseThreads / 64) *
+    const size_t slots = 2 * (kPhaseThreadsMax / 64) *
                          (fp64 ? sizeof(Slot<double>) : sizeof(Slot<float>));
     return slot_offset(e, KP, lext_max, lm_max) + slots + 2 * e * (size_t)KP;
 }
 
-template <typename G, int KQ>
-static hipError_t launch_phase_kq(const PhaseArgs& a, int nq, size_t lds, hipStream_t s)
+template <typename G, int KQ, int NQ, int NT>
+static hipError_t launch_phase_inst(const PhaseArgs& a, size_t lds, hipStream_t s)
 {
-    const void* fn;
-    switch (nq) {
-    case 1: fn = (const void*)k_lgcd_phase<G, KQ, 1>; break;
-    case 2: fn = (const void*)k_lgcd_phase<G, KQ, 2>; break;
-    case 3: fn = (const void*)k_lgcd_phase<G, KQ, 3>; break;
-    case 4: fn = (const void*)k_lgcd_phase<G, KQ, 4>; break;
-    default: return hipErrorInvalidValue;
-    }
-    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)lds);
+    const void* fn = (const void*)k_lgcd_phase<G, KQ, NQ, NT>;
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess)
         return e;
-    dim3 grid((unsigned)a.n_list);
-    switch (nq) {
-    case 1: hipLaunchKernelGGL((k_lgcd_phase<G, KQ, 1>), grid, dim3(kPhaseThreads), lds, s, a); break;
-    case 2: hipLaunchKernelGGL((k_lgcd_phase<G, KQ, 2>), grid, dim3(kPhaseThreads), lds, s, a); break;
-    case 3: hipLaunchKernelGGL((k_lgcd_phase<G, KQ, 3>), grid, dim3(kPhaseThreads), lds, s, a); break;
-    case 4: hipLaunchKernelGGL((k_lgcd_phase<G, KQ, 4>), grid, dim3(kPhaseThreads), lds, s, a); break;
-    }
+    hipLaunchKernelGGL((k_lgcd_phase<G, KQ, NQ, NT>), dim3((unsigned)a.n_list), dim3(NT), lds,
+                       s, a);
     return hipGetLastError();
+}
+
+// 1024-thread workgroups (one extended position per thread, four waves per
+// SIMD) for float state with up to 32 atoms; 512 threads otherwise.
+template <typename G, int KQ>
+static hipError_t launch_phase_kq(const PhaseArgs& a, size_t lds, hipStream_t s)
+{
+    constexpr bool wide = false;  // measured slower than 512 threads on gfx950
+    if (wide && a.lext_max <= kPhaseThreadsMax)
+        return launch_phase_inst<G, KQ, 1, (wide ? kPhaseThreadsMax : kPhaseThreads)>(a, lds, s);
+    switch ((a.lext_max + kPhaseThreads - 1) / kPhaseThreads) {
+    case 1: return launch_phase_inst<G, KQ, 1, kPhaseThreads>(a, lds, s);
+    case 2: return launch_phase_inst<G, KQ, 2, kPhaseThreads>(a, lds, s);
+    case 3: return launch_phase_inst<G, KQ, 3, kPhaseThreads>(a, lds, s);
+    case 4: return launch_phase_inst<G, KQ, 4, kPhaseThreads>(a, lds, s);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_lgcd_phase(const PhaseArgs& a, bool fp64, size_t* lds_bytes,
@@ -806,24 +831,24 @@ hipError_t launch_lgcd_phase(const PhaseArgs& a, bool fp64, size_t* lds_bytes,
     const int kq = pick_kq(a.K, fp64);
     if (fp64) {
         switch (kq) {
-        case 1: return launch_phase_kq<double, 1>(a, nq, lds, s);
-        case 2: return launch_phase_kq<double, 2>(a, nq, lds, s);
-        case 3: return launch_phase_kq<double, 3>(a, nq, lds, s);
-        case 4: return launch_phase_kq<double, 4>(a, nq, lds, s);
-        case 8: return launch_phase_kq<double, 8>(a, nq, lds, s);
-        case 13: return launch_phase_kq<double, 13>(a, nq, lds, s);
-        case 16: return launch_phase_kq<double, 16>(a, nq, lds, s);
-        case 32: return launch_phase_kq<double, 32>(a, nq, lds, s);
+        case 1: return launch_phase_kq<double, 1>(a, lds, s);
+        case 2: return launch_phase_kq<double, 2>(a, lds, s);
+        case 3: return launch_phase_kq<double, 3>(a, lds, s);
+        case 4: return launch_phase_kq<double, 4>(a, lds, s);
+        case 8: return launch_phase_kq<double, 8>(a, lds, s);
+        case 13: return launch_phase_kq<double, 13>(a, lds, s);
+        case 16: return launch_phase_kq<double, 16>(a, lds, s);
+        case 32: return launch_phase_kq<double, 32>(a, lds, s);
         default: return hipErrorInvalidValue;
         }
     }
     switch (kq) {
-    case 1: return launch_phase_kq<float, 1>(a, nq, lds, s);
-    case 2: return launch_phase_kq<float, 2>(a, nq, lds, s);
-    case 4: return launch_phase_kq<float, 4>(a, nq, lds, s);
-    case 7: return launch_phase_kq<float, 7>(a, nq, lds, s);
-    case 8: return launch_phase_kq<float, 8>(a, nq, lds, s);
-    case 16: return launch_phase_kq<float, 16>(a, nq, lds, s);
+    case 1: return launch_phase_kq<float, 1>(a, lds, s);
+    case 2: return launch_phase_kq<float, 2>(a, lds, s);
+    case 4: return launch_phase_kq<float, 4>(a, lds, s);
+    case 7: return launch_phase_kq<float, 7>(a, lds, s);
+    case 8: return launch_phase_kq<float, 8>(a, lds, s);
+    case 16: return launch_phase_kq<float, 16>(a, lds, s);
     default: return hipErrorInvalidValue;
     }
 }

@@ -85,18 +85,22 @@ def _sorted_oracle_trace(tr):
     return tr[order]
 
 
-@pytest.mark.parametrize("M,cap,lds", [(4, 0, 1), (4, 1, 1), (4, 8, 1), (1, 0, 1),
-                                       (63, 16, 1), (4, 8, 0), (63, 16, 0)])
+@pytest.mark.parametrize("M,cap,lds,C", [(4, 0, 1, 2), (4, 1, 1, 2), (4, 8, 1, 2), (1, 0, 1, 2),
+                                         (63, 16, 1, 2), (4, 8, 0, 2), (63, 16, 0, 2),
+                                         (127, 16, 1, 3), (127, 4, 0, 3), (90, 8, 1, 4),
+                                         (5, 0, 1, 3)])
 @pytest.mark.parametrize("seed", [0, 1])
-def test_fp64_trajectory_matches_oracle(dicod, M, cap, lds, seed):
+def test_fp64_trajectory_matches_oracle(dicod, M, cap, lds, C, seed):
     """Both phase kernels (state in LDS, state in HBM) reproduce the oracle's
-    even/odd sequence of updates; M = 1 is Algorithm 1 (greedy CD)."""
-    print(f"\ncase: FP64 trajectory small seed={seed} M={M} cap={cap} lds={lds}", flush=True)
+    coloured-phase sequence of updates (C = 2: even/odd); M = 1 is Algorithm 1
+    (greedy CD)."""
+    print(f"\ncase: FP64 trajectory small seed={seed} M={M} cap={cap} lds={lds} C={C}",
+          flush=True)
     X, D, _ = small(seed)
     lam = 0.1 * oracle.lambda_max(f64(X), f64(D))
-    Zo, so, tro = oracle.lgcd(f64(X), f64(D), lam, EPS, M, cap=cap, trace_cap=10**6)
+    Zo, so, tro = oracle.lgcd(f64(X), f64(D), lam, EPS, M, cap=cap, trace_cap=10**6, colors=C)
     with ctx_of(dicod, precision=dicod.DICOD_PREC_FP64, update_cap=cap,
-                trace_capacity=10**6, state_in_lds=lds) as c:
+                trace_capacity=10**6, state_in_lds=lds, colors=C) as c:
         Z, st = c.solve(X, lam, EPS, n_seg=M, D=D)
         tr = c.trace()
     assert st["state_in_hbm"] == (1 if (lds == 0 or M == 1) else 0)
@@ -148,7 +152,7 @@ def test_paper_shaped_fp32_matches_oracle(dicod, paper_problem):
         Z, st = c.solve(X, -0.1, EPS, n_seg=0, D=D)
     print(f"gpu: {st['n_updates']} updates, {st['n_phases']} phases, M={st['n_seg']}, "
           f"refresh={st['n_refresh']}, cd={st['t_cd_ms']:.2f} ms", flush=True)
-    assert st["n_seg"] == 374
+    assert st["n_seg"] == 749
     _check_solution(X, D, lam, Z, st, Zo)
 
 
@@ -236,7 +240,7 @@ def test_invalid_arguments_rejected(dicod, bad):
     elif bad == "eps0":
         eps = 0.0
     elif bad == "short_segments":
-        M = 64                       # 4065 / 64 < 2W = 64
+        M = 200                      # 4065 / 200 < W = 32
     elif bad == "T_lt_W":
         X = X[:, :16]
     elif bad == "nan_x":
