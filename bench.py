@@ -146,6 +146,7 @@ def main():
                   "converged": s0["converged"], "t_init_ms": s0["t_init_ms"],
                   "t_cd_ms": s0["t_cd_ms"], "t_verify_ms": s0["t_verify_ms"],
                   "round_updates": s0["round_updates"], "round_phases": s0["round_phases"],
+                  "round_ms": s0["round_ms"],
                   "polished_fp64": s0["polished_fp64"]},
         "roofline": {"kernel": "k_lgcd_phase", "bound": "hbm", "achieved": achieved,
                      "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,

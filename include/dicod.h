@@ -92,6 +92,8 @@ typedef struct {
     int colors;              /* phase classes C in 2..4: segment m runs in phases p  */
                              /* with p % C == m % C (2 = even/odd); segments must be */
                              /* >= max(W, (2W - 2) / (C - 1)) long                    */
+    int verify_from_scratch; /* 1 = every stop test recomputes g from Z; 0 = after a  */
+                             /* double round the maintained double state is used     */
 } dicod_config;
 
 typedef struct {
@@ -119,6 +121,7 @@ typedef struct {
     double t_lgcd_kernel_ms;  /* sum of LGCD kernel durations (timing = 1)          */
     int64_t round_updates[4]; /* updates of the first four descent rounds            */
     int64_t round_phases[4];  /* phases of the first four descent rounds             */
+    double round_ms[4];       /* wall time of the first four descent rounds          */
     int state_in_hbm;         /* 1 if segment state was kept in HBM, not LDS         */
     int polished_fp64;        /* 1 if the descent finished on a double state         */
 } dicod_stats;
@@ -135,8 +138,8 @@ typedef struct {
 
 /* Fills *cfg with the defaults: device 0, FP32, coloured phases, update_cap 16,
  * max_phases 1e6, max_refresh 8, phases_per_poll 16, inner_eps_factor 0.5,
- * timing 0, no trace, state_in_lds 1, fp64_polish_after 1, colors 3.  Returns
- * DICOD_OK, or DICOD_EINVAL if cfg is NULL. */
+ * timing 0, no trace, state_in_lds 1, fp64_polish_after 1, colors 3,
+ * verify_from_scratch 0.  Returns DICOD_OK, or DICOD_EINVAL if cfg is NULL. */
 int dicod_config_init(dicod_config *cfg);
 
 /* Creates a context on cfg->device (cfg NULL = defaults) with its own HIP

@@ -55,6 +55,7 @@ class dicod_config(ctypes.Structure):
         ("state_in_lds", ctypes.c_int),
         ("fp64_polish_after", ctypes.c_int),
         ("colors", ctypes.c_int),
+        ("verify_from_scratch", ctypes.c_int),
     ]
 
 
@@ -84,6 +85,7 @@ class dicod_stats(ctypes.Structure):
         ("t_lgcd_kernel_ms", ctypes.c_double),
         ("round_updates", ctypes.c_int64 * 4),
         ("round_phases", ctypes.c_int64 * 4),
+        ("round_ms", ctypes.c_double * 4),
         ("state_in_hbm", ctypes.c_int),
         ("polished_fp64", ctypes.c_int),
     ]

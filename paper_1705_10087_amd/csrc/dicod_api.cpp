@@ -67,7 +67,7 @@ struct Workspace {
     DevBuf sig, segs, lists[kMaxColors];
     DevBuf tilesL, tilesT, tilesA;
     DevBuf dirty, phase_upd, sig_upd, sig_last, counters;
-    DevBuf part_r2, part6, results, lmax, done;
+    DevBuf part_r2, part6, results, lmax, done, thr;
     DevBuf trace;
 };
 
@@ -76,11 +76,13 @@ struct Workspace {
 struct dicod_ctx {
     dicod_config cfg;
     hipStream_t stream = nullptr;
+    hipStream_t side = nullptr;          // double beta0, overlapped with the descent
+    hipEvent_t ev_in = nullptr, ev_beta = nullptr;
     std::string err;
     // resident dictionary
     bool has_dict = false;
     int K = 0, P = 0, W = 0;
-    DevBuf D64, S64, S32, n2_64, inv64, n2_32, inv32;
+    DevBuf D64, D32, S64, S32, n2_64, inv64, n2_32, inv32;
     DevBuf St32, St64;  // phase-kernel layouts of S (float, double)
     Workspace ws;
     unsigned long long* h_upd = nullptr;  // pinned copy of per-phase counts
@@ -174,6 +176,7 @@ extern "C" int dicod_config_init(dicod_config* cfg)
     cfg->state_in_lds = 1;
     cfg->fp64_polish_after = 1;
     cfg->colors = 3;
+    cfg->verify_from_scratch = 0;
     return DICOD_OK;
 }
 
@@ -208,9 +211,12 @@ extern "C" int dicod_init(dicod_ctx** out, const dicod_config* cfg)
     if (!ctx)
         return fail(nullptr, DICOD_ENOMEM, "dicod_init: out of host memory");
     ctx->cfg = c;
-    if (hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess) {
-        delete ctx;
-        return fail(nullptr, DICOD_EDEVICE, "dicod_init: hipStreamCreate failed");
+    if (hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess ||
+        hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&ctx->ev_in, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&ctx->ev_beta, hipEventDisableTiming) != hipSuccess) {
+        dicod_finalize(ctx);
+        return fail(nullptr, DICOD_EDEVICE, "dicod_init: stream or event creation failed");
     }
     *out = ctx;
     return DICOD_OK;
@@ -227,12 +233,20 @@ extern "C" void dicod_finalize(dicod_ctx* ctx)
     }
     if (ctx->stream)
         (void)hipStreamSynchronize(ctx->stream);
+    if (ctx->side)
+        (void)hipStreamSynchronize(ctx->side);
     for (hipEvent_t e : ctx->ev_pool)
         (void)hipEventDestroy(e);
+    if (ctx->ev_in)
+        (void)hipEventDestroy(ctx->ev_in);
+    if (ctx->ev_beta)
+        (void)hipEventDestroy(ctx->ev_beta);
     if (ctx->h_upd)
         (void)hipHostFree(ctx->h_upd);
     if (ctx->stream)
         (void)hipStreamDestroy(ctx->stream);
+    if (ctx->side)
+        (void)hipStreamDestroy(ctx->side);
     delete ctx;
 }
 
@@ -295,6 +309,7 @@ extern "C" int dicod_set_dictionary(dicod_ctx* ctx, const float* D, int K, int P
     }
     DevBuf dpad, dsig, dpref;
     HIPCHECK(ctx, ensure(ctx->D64, n * sizeof(double)));
+    HIPCHECK(ctx, ensure(ctx->D32, n * sizeof(float)));
     HIPCHECK(ctx, ensure(ctx->S64, (size_t)K * K * nd * sizeof(double)));
     HIPCHECK(ctx, ensure(ctx->S32, (size_t)K * K * nd * sizeof(float)));
     HIPCHECK(ctx, ensure(ctx->n2_64, K * sizeof(double)));
@@ -306,6 +321,7 @@ extern "C" int dicod_set_dictionary(dicod_ctx* ctx, const float* D, int K, int P
     HIPCHECK(ctx, ensure(dpref, pref.size() * sizeof(int64_t)));
     HIPCHECK(ctx, hipMemcpyAsync(ctx->D64.p, d64.data(), n * sizeof(double),
                                  hipMemcpyHostToDevice, s));
+    HIPCHECK(ctx, hipMemcpyAsync(ctx->D32.p, D, n * sizeof(float), hipMemcpyHostToDevice, s));
     HIPCHECK(ctx, hipMemcpyAsync(dpad.p, pad.data(), pad.size() * sizeof(double),
                                  hipMemcpyHostToDevice, s));
     HIPCHECK(ctx, hipMemcpyAsync(dsig.p, sd.data(), sd.size() * sizeof(SigDesc),
@@ -445,7 +461,7 @@ int make_plan(dicod_ctx* ctx, int n_sig, const int64_t* T, const int64_t* x_off,
         }
         pl.prefL[i + 1] = pl.prefL[i] + ceil_div(L, kTile);
         pl.prefT[i + 1] = pl.prefT[i] + ceil_div(T[i], kTile);
-        pl.prefA[i + 1] = pl.prefA[i] + ceil_div((int64_t)K * L, 4096);
+        pl.prefA[i + 1] = pl.prefA[i] + ceil_div((int64_t)K * L, kAbsChunk);
         pl.zext = std::max(pl.zext, (size_t)(z_off[i] + (int64_t)K * L));
     }
     return DICOD_OK;
@@ -543,22 +559,66 @@ int solve_device_batch(dicod_ctx* ctx, int n_sig, const float* dX, const int64_t
         return fail(ctx, DICOD_EDEVICE, "hipEventCreate failed");
     HIPCHECK(ctx, hipEventRecord(ev0, s));
 
-    // ---- 1. beta at Z = 0 (double MFMA); g starts equal to it -------------
-    HIPCHECK(ctx, launch_corr_f64_x32(ctx->D64.as<double>(), K, P, W, dX, ws.sig.as<SigDesc>(),
-                                      ws.tilesL.as<int64_t>(), n_sig, nL, ws.beta0.as<double>(),
-                                      fp64 ? nullptr : ws.g.as<float>(),
-                                      fp64 ? ws.g.as<double>() : nullptr, s));
+    // ---- 1. beta at Z = 0 ------------------------------------------------
+    // FP64 and FP32 policies: double MFMA, and g starts equal to it (rounded
+    // to float in FP32: the most accurate float start, which keeps the
+    // double-precision finish short).  MIXED: the float state starts from a
+    // cheaper float beta; the double beta0, needed only by the first
+    // double-precision check, runs on a side stream meanwhile.
+    const bool fast_init = ctx->cfg.precision == DICOD_PREC_MIXED;
+    if (!fast_init) {
+        HIPCHECK(ctx, launch_corr_f64_x32(ctx->D64.as<double>(), K, P, W, dX,
+                                          ws.sig.as<SigDesc>(), ws.tilesL.as<int64_t>(), n_sig,
+                                          nL, ws.beta0.as<double>(),
+                                          fp64 ? nullptr : ws.g.as<float>(),
+                                          fp64 ? ws.g.as<double>() : nullptr, s));
+    } else {
+        HIPCHECK(ctx, hipEventRecord(ctx->ev_in, s));
+        HIPCHECK(ctx, hipStreamWaitEvent(ctx->side, ctx->ev_in, 0));
+        HIPCHECK(ctx, launch_corr_f64_x32(ctx->D64.as<double>(), K, P, W, dX,
+                                          ws.sig.as<SigDesc>(), ws.tilesL.as<int64_t>(), n_sig,
+                                          nL, ws.beta0.as<double>(), nullptr, nullptr,
+                                          ctx->side));
+        HIPCHECK(ctx, hipEventRecord(ctx->ev_beta, ctx->side));
+        HIPCHECK(ctx, launch_corr_f32(ctx->D32.as<float>(), K, P, W, dX, ws.sig.as<SigDesc>(),
+                                      ws.tilesL.as<int64_t>(), n_sig, nL, ws.g.as<float>(), s));
+    }
+    bool beta_waited = !fast_init;
     // ---- 2. lambda --------------------------------------------------------
     std::vector<double> lmax(n_sig, 0.0);
     bool any_rel = false;
     for (int i = 0; i < n_sig; ++i)
         any_rel |= lam_in[i] < 0.0;
     if (any_rel) {
-        HIPCHECK(ctx, launch_fill_u64(ws.lmax.as<unsigned long long>(), 0ull, n_sig, s));
-        HIPCHECK(ctx, launch_absmax(ws.beta0.as<double>(), K, ws.sig.as<SigDesc>(),
-                                    ws.tilesA.as<int64_t>(), n_sig, nA,
-                                    ws.lmax.as<unsigned long long>(), s));
         std::vector<unsigned long long> bits(n_sig);
+        HIPCHECK(ctx, launch_fill_u64(ws.lmax.as<unsigned long long>(), 0ull, n_sig, s));
+        if (!fast_init) {
+            HIPCHECK(ctx, launch_absmax(ws.beta0.as<double>(), K, ws.sig.as<SigDesc>(),
+                                        ws.tilesA.as<int64_t>(), n_sig, nA,
+                                        ws.lmax.as<unsigned long long>(), s));
+        } else {
+            // max of the float beta, then the exact maximum over the entries
+            // within 1e-3 (relative) of it, recomputed in double
+            HIPCHECK(ctx, launch_absmax_f32(ws.g.as<float>(), K, ws.sig.as<SigDesc>(),
+                                            ws.tilesA.as<int64_t>(), n_sig, nA,
+                                            ws.lmax.as<unsigned long long>(), s));
+            HIPCHECK(ctx, hipMemcpyAsync(bits.data(), ws.lmax.p,
+                                         n_sig * sizeof(unsigned long long),
+                                         hipMemcpyDeviceToHost, s));
+            HIPCHECK(ctx, hipStreamSynchronize(s));
+            std::vector<double> thr(n_sig);
+            for (int i = 0; i < n_sig; ++i) {
+                double v;
+                std::memcpy(&v, &bits[i], sizeof v);
+                thr[i] = v * (1.0 - 1e-3);
+            }
+            HIPCHECK(ctx, upload(ws.thr, thr, s));
+            HIPCHECK(ctx, launch_fill_u64(ws.lmax.as<unsigned long long>(), 0ull, n_sig, s));
+            HIPCHECK(ctx, launch_refine_absmax(ws.g.as<float>(), ctx->D64.as<double>(), dX, K, P,
+                                               W, ws.sig.as<SigDesc>(), ws.tilesA.as<int64_t>(),
+                                               n_sig, nA, ws.thr.as<double>(),
+                                               ws.lmax.as<unsigned long long>(), s));
+        }
         HIPCHECK(ctx, hipMemcpyAsync(bits.data(), ws.lmax.p, n_sig * sizeof(unsigned long long),
                                      hipMemcpyDeviceToHost, s));
         HIPCHECK(ctx, hipStreamSynchronize(s));
@@ -629,6 +689,7 @@ int solve_device_batch(dicod_ctx* ctx, int n_sig, const float* dX, const int64_t
     bool accepted = false, out_of_phases = false;
     double t_cd = 0.0, t_verify = 0.0, t_kernel = 0.0;
     int64_t round_upd[4] = {0, 0, 0, 0}, round_ph[4] = {0, 0, 0, 0};
+    double round_ms[4] = {0.0, 0.0, 0.0, 0.0};
     std::vector<CheckResult> res(n_sig);
     std::vector<uint32_t> done(n_sig, 0u);
 
@@ -696,8 +757,10 @@ int solve_device_batch(dicod_ctx* ctx, int n_sig, const float* dX, const int64_t
         }
         HIPCHECK(ctx, hipEventRecord(ev3, s));
         HIPCHECK(ctx, hipEventSynchronize(ev3));
-        t_cd += elapsed_ms(ev2, ev3);
+        const double t_round = elapsed_ms(ev2, ev3);
+        t_cd += t_round;
         if (round < 4) {
+            round_ms[round] = t_round;
             const int64_t last = conv_phase >= 0 ? conv_phase + 1 : phase;
             round_ph[round] = last - start;
             for (int64_t p = start; p < last; ++p)
@@ -716,13 +779,23 @@ int solve_device_batch(dicod_ctx* ctx, int n_sig, const float* dX, const int64_t
         void* g_next = next64 && !fp64 ? ws.g64.p : ws.g.p;
         const double flag_eps = next64 ? eps : eps * cfg.inner_eps_factor;
         HIPCHECK(ctx, hipEventRecord(ev2, s));
+        if (!beta_waited) {
+            HIPCHECK(ctx, hipStreamWaitEvent(s, ctx->ev_beta, 0));
+            beta_waited = true;
+        }
+        // After a double round the maintained state is exact to rounding, and
+        // the stop test reads it directly; otherwise g is recomputed from Z.
+        const double* g_in = (cur64 && !cfg.verify_from_scratch)
+                                 ? (fp64 ? ws.g.as<double>() : ws.g64.as<double>())
+                                 : nullptr;
         HIPCHECK(ctx, launch_resid(dX, ctx->D64.as<double>(), dZ, K, P, W, ws.sig.as<SigDesc>(),
                                    ws.tilesT.as<int64_t>(), n_sig, nT, ws.part_r2.as<double>(), s));
         HIPCHECK(ctx, launch_grad_check(ws.beta0.as<double>(), dZ, ctx->S64.as<double>(),
                                         ctx->n2_64.as<double>(), K, W, ws.sig.as<SigDesc>(),
                                         ws.tilesL.as<int64_t>(), n_sig, nL, flag_eps,
                                         ws.done.as<uint32_t>(), ws.dirty.as<uint32_t>(),
-                                        g_next, next64, ws.part6.as<double>(), s));
+                                        g_in ? nullptr : g_next, next64, g_in,
+                                        ws.part6.as<double>(), s));
         HIPCHECK(ctx, launch_check_reduce(ws.part_r2.as<double>(), ws.tilesT.as<int64_t>(),
                                           ws.part6.as<double>(), ws.tilesL.as<int64_t>(), nL,
                                           n_kblk, n_sig, ws.results.as<CheckResult>(), s));
@@ -796,6 +869,7 @@ int solve_device_batch(dicod_ctx* ctx, int n_sig, const float* dX, const int64_t
             for (int r = 0; r < 4; ++r) {
                 o.round_updates[r] = n_sig == 1 ? round_upd[r] : 0;
                 o.round_phases[r] = round_ph[r];
+                o.round_ms[r] = round_ms[r];
             }
             o.state_in_hbm = any_hbm ? 1 : 0;
             o.polished_fp64 = polished ? 1 : 0;

@@ -16,6 +16,7 @@ constexpr int kPhaseThreads = 512;
 constexpr int kPhaseThreadsMax = 1024;
 constexpr int kMaxColors = 4;  // phase classes of the segment schedule
 constexpr int kTile = 256;       // positions per workgroup in the tiled kernels
+constexpr int kAbsChunk = 4096;  // [K][L] elements per workgroup in the max kernels
 constexpr size_t kLdsBytes = 163840;  // LDS per workgroup on gfx950
 constexpr int kRunUpdateBound = 1 << 16;  // updates per segment run when uncapped
 constexpr int64_t kRoundPhaseLimit = 4096; // float descent phases between checks
@@ -142,7 +143,11 @@ hipError_t launch_grad_check(const double* beta0, const double* Z,
                              const SigDesc* sig, const int64_t* tile_pref, int n_sig,
                              int64_t n_tiles, double flag_eps, const uint32_t* sig_done,
                              uint32_t* dirty, void* g_state, bool state_fp64,
-                             double* part6, hipStream_t s);
+                             const double* g_in, double* part6, hipStream_t s);
+// Float beta init on f32 MFMA (D float [K][P][W]).
+hipError_t launch_corr_f32(const float* D, int K, int P, int W, const float* Y,
+                           const SigDesc* sig, const int64_t* tile_pref, int n_sig,
+                           int64_t n_tiles, float* g32, hipStream_t s);
 hipError_t launch_check_reduce(const double* part_r2, const int64_t* tile_pref_T,
                                const double* part6, const int64_t* tile_pref_L,
                                int64_t n_tiles_L, int n_kblk, int n_sig,

@@ -230,6 +230,144 @@ hipError_t launch_corr_f64_x64(const double* D, int K, int P, int W,
     return hipGetLastError();
 }
 
+// The same implicit-im2col correlation in float on v_mfma_f32_16x16x4f32:
+// the starting point of the float descent state (the double beta0 needed by
+// the double-precision check is computed separately).
+typedef float f4_t __attribute__((ext_vector_type(4)));
+
+__global__ void __launch_bounds__(256)
+k_corr_f32(const float* __restrict__ D, int K, int P, int W, const float* __restrict__ Y,
+           const SigDesc* __restrict__ sig, const int64_t* __restrict__ tile_pref, int n_sig,
+           float* __restrict__ g32)
+{
+    extern __shared__ float ldsf[];
+    const int R = P * W;
+    const int ystride = kTile + W - 1;
+    float* Dc = ldsf;                          // [32][kCorrDStride]
+    float* Ys = ldsf + 32 * kCorrDStride;      // [P][ystride]
+
+    const int64_t tile = blockIdx.x;
+    const int si = find_sig(tile_pref, n_sig, tile);
+    const SigDesc sd = sig[si];
+    const int64_t t_a = (tile - tile_pref[si]) * kTile;
+    const int kbase = blockIdx.y * 32;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+
+    for (int i = tid; i < P * ystride; i += 256) {
+        const int p = i / ystride;
+        const int u = i - p * ystride;
+        const int64_t t = t_a + u;
+        Ys[i] = t < sd.T ? Y[sd.x_off + (int64_t)p * sd.T + t] : 0.f;
+    }
+    f4_t acc[2][4];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+            acc[a][b] = f4_t{0.f, 0.f, 0.f, 0.f};
+    const int arow = lane & 15;
+    const int kk = lane >> 4;
+    for (int r0 = 0; r0 < R; r0 += kCorrRC) {
+        __syncthreads();
+        for (int i = tid; i < 32 * kCorrRC; i += 256) {
+            const int m = i / kCorrRC;
+            const int rr = i - m * kCorrRC;
+            const int k = kbase + m;
+            const int r = r0 + rr;
+            Dc[m * kCorrDStride + rr] = (k < K && r < R) ? D[(int64_t)k * R + r] : 0.f;
+        }
+        __syncthreads();
+        for (int ks = 0; ks < kCorrRC / 4; ++ks) {
+            if (r0 + ks * 4 >= R)
+                break;
+            const int rr = ks * 4 + kk;
+            const int r = r0 + rr;
+            const float a0 = Dc[arow * kCorrDStride + rr];
+            const float a1 = Dc[(16 + arow) * kCorrDStride + rr];
+            const bool valid = r < R;
+            const int p = valid ? r / W : 0;
+            const int tau = valid ? r - p * W : 0;
+            const float* yrow = Ys + p * ystride + wave * 64 + arow + tau;
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) {
+                const float bv = valid ? yrow[nt * 16] : 0.f;
+                acc[0][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, bv, acc[0][nt], 0, 0, 0);
+                acc[1][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, bv, acc[1][nt], 0, 0, 0);
+            }
+        }
+    }
+    // C[i][j] of a 16x16 f32 MFMA tile sits in lane (i / 4) * 16 + j, item i % 4.
+#pragma unroll
+    for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int k = kbase + mi * 16 + 4 * kk + v;
+                const int64_t t = t_a + wave * 64 + nt * 16 + arow;
+                if (k < K && t < sd.L)
+                    g32[sd.z_off + (int64_t)k * sd.L + t] = acc[mi][nt][v];
+            }
+}
+
+hipError_t launch_corr_f32(const float* D, int K, int P, int W, const float* Y,
+                           const SigDesc* sig, const int64_t* tile_pref, int n_sig,
+                           int64_t n_tiles, float* g32, hipStream_t s)
+{
+    const size_t lds = sizeof(float) * (32 * kCorrDStride + (size_t)P * (kTile + W - 1));
+    if (lds > kLdsBytes)
+        return hipErrorInvalidValue;
+    (void)hipFuncSetAttribute((const void*)k_corr_f32,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    dim3 grid((unsigned)n_tiles, (unsigned)((K + 31) / 32));
+    hipLaunchKernelGGL(k_corr_f32, grid, dim3(256), lds, s, D, K, P, W, Y, sig, tile_pref,
+                       n_sig, g32);
+    return hipGetLastError();
+}
+
+// lambda_max made exact: every coordinate whose float beta is within the
+// float error margin of the float maximum is recomputed in double, and the
+// per-signal maximum of those exact values is kept.
+__global__ void __launch_bounds__(256)
+k_refine_absmax(const float* __restrict__ beta32, const double* __restrict__ D,
+                const float* __restrict__ X, int K, int P, int W,
+                const SigDesc* __restrict__ sig, const int64_t* __restrict__ tile_pref,
+                int n_sig, const double* __restrict__ thr,
+                unsigned long long* __restrict__ out_bits)
+{
+    const int64_t tile = blockIdx.x;
+    const int si = find_sig(tile_pref, n_sig, tile);
+    const SigDesc sd = sig[si];
+    const int64_t n = (int64_t)K * sd.L;
+    const int64_t i0 = (tile - tile_pref[si]) * kAbsChunk;
+    for (int64_t i = i0 + threadIdx.x; i < n && i < i0 + kAbsChunk; i += 256) {
+        if (fabs((double)beta32[sd.z_off + i]) < thr[si])
+            continue;
+        const int k = (int)(i / sd.L);
+        const int64_t t = i - (int64_t)k * sd.L;
+        double acc = 0.0;
+        for (int p = 0; p < P; ++p) {
+            const double* dr = D + ((int64_t)k * P + p) * W;
+            const float* xr = X + sd.x_off + (int64_t)p * sd.T + t;
+            for (int tau = 0; tau < W; ++tau)
+                acc += dr[tau] * (double)xr[tau];
+        }
+        atomicMax(&out_bits[si], (unsigned long long)__double_as_longlong(fabs(acc)));
+    }
+}
+
+hipError_t launch_refine_absmax(const float* beta32, const double* D, const float* X, int K,
+                                int P, int W, const SigDesc* sig, const int64_t* tile_pref,
+                                int n_sig, int64_t n_tiles, const double* thr,
+                                unsigned long long* out_bits, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_refine_absmax, dim3((unsigned)n_tiles), dim3(256), 0, s, beta32, D, X,
+                       K, P, W, sig, tile_pref, n_sig, thr, out_bits);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // Dictionary finish: float copy of S, norms |D_k|^2 = S_{k,k}[0] and inverses.
 // ---------------------------------------------------------------------------
@@ -266,7 +404,7 @@ hipError_t launch_dict_finish(const double* S64, int K, int W, float* S32,
 // lambda_max = max |beta| per signal (bit pattern of a non-negative double,
 // whose unsigned order is the numeric order).
 // ---------------------------------------------------------------------------
-constexpr int kAbsChunk = 4096;
+
 
 template <typename T>
 __global__ void __launch_bounds__(256)
@@ -1304,7 +1442,7 @@ k_grad_check(const double* __restrict__ beta0, const double* __restrict__ Z,
              const int64_t* __restrict__ tile_pref, int n_sig, double flag_eps,
              const uint32_t* __restrict__ sig_done, uint32_t* __restrict__ dirty,
              float* __restrict__ g32, double* __restrict__ g64,
-             double* __restrict__ part6)
+             const double* __restrict__ g_in, double* __restrict__ part6)
 {
     __shared__ NzEnt list[kNzCap];
     __shared__ int wcnt[4];
@@ -1325,12 +1463,15 @@ k_grad_check(const double* __restrict__ beta0, const double* __restrict__ Z,
     double acc[kMaxK];
 #pragma unroll
     for (int k = 0; k < kMaxK; ++k)
-        acc[k] = (act && k < kn) ? beta0[sd.z_off + (int64_t)(kb + k) * sd.L + t] : 0.0;
+        acc[k] = (act && k < kn) ? (g_in ? g_in : beta0)[sd.z_off + (int64_t)(kb + k) * sd.L + t]
+                                 : 0.0;
 
+    // from scratch: g = beta0 - S Z over the non-zeros; with g_in the
+    // maintained double state is checked as it is
     const int s_lo = t_a - (W - 1) > 0 ? (int)(t_a - (W - 1)) : 0;
     const int s_hi = t_a + kTile + (W - 1) < sd.L ? (int)(t_a + kTile + (W - 1))
                                                    : (int)sd.L;
-    const int ns = s_hi > s_lo ? s_hi - s_lo : 0;
+    const int ns = (s_hi > s_lo && !g_in) ? s_hi - s_lo : 0;
     const int64_t total = (int64_t)K * ns;
     int64_t pos = 0;
     while (pos < total) {
@@ -1415,13 +1556,14 @@ hipError_t launch_grad_check(const double* beta0, const double* Z, const double*
                              const double* n2, int K, int W, const SigDesc* sig,
                              const int64_t* tile_pref, int n_sig, int64_t n_tiles,
                              double flag_eps, const uint32_t* sig_done, uint32_t* dirty,
-                             void* g_state, bool state_fp64, double* part6, hipStream_t s)
+                             void* g_state, bool state_fp64, const double* g_in,
+                             double* part6, hipStream_t s)
 {
     dim3 grid((unsigned)n_tiles, (unsigned)((K + kMaxK - 1) / kMaxK));
     hipLaunchKernelGGL(k_grad_check, grid, dim3(256), 0, s, beta0, Z, S64, n2, K, W,
                        sig, tile_pref, n_sig, flag_eps, sig_done, dirty,
                        state_fp64 ? (float*)nullptr : (float*)g_state,
-                       state_fp64 ? (double*)g_state : (double*)nullptr, part6);
+                       state_fp64 ? (double*)g_state : (double*)nullptr, g_in, part6);
     return hipGetLastError();
 }
 

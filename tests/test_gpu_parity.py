@@ -199,6 +199,22 @@ def test_paper_shaped_fp32_polish_policies(dicod, paper_problem, polish):
     _check_solution(X, D, lam, Z, st, Zo)
 
 
+def test_state_check_agrees_with_recompute(dicod, paper_problem):
+    """The final stop test on the maintained double state and the one that
+    recomputes g from Z in double see the same iterate and agree."""
+    X, D, lam, Zo = paper_problem
+    out = []
+    for scratch in (0, 1):
+        with ctx_of(dicod, verify_from_scratch=scratch) as c:
+            out.append(c.solve(X, -0.1, EPS, n_seg=0, D=D))
+    (Z0, s0), (Z1, s1) = out
+    assert np.array_equal(Z0, Z1)
+    assert s0["objective"] == s1["objective"]
+    assert abs(s0["max_dz"] - s1["max_dz"]) <= 1e-12
+    assert abs(s0["kkt_on"] - s1["kkt_on"]) <= 1e-12 and abs(s0["kkt_off"] - s1["kkt_off"]) <= 1e-12
+    _check_solution(X, D, lam, Z0, s0, Zo)
+
+
 # ------------------------------------------------------------- edge cases
 
 def test_lambda_at_lambda_max_gives_zero(dicod):
