@@ -3,7 +3,7 @@
 A step is one complete solve of the paper-shaped workload (P=7, K=25, W=200,
 T=150,000, Bernoulli(0.007) x N(0, 10^2) activations, noise sigma 0.1,
 lambda = 0.1 lambda_max, eps = 1e-6, float descent with double-precision
-stop test) with X already resident in HBM: beta init, lambda_max, the even/odd
+stop test) with X already resident in HBM: beta init, lambda_max, the coloured
 descent phases and the final double-precision check, through the C ABI.
 
 Prints one JSON line.  value = coordinate updates per second over the timed
@@ -70,6 +70,8 @@ def main():
     ap.add_argument("--colors", type=int, default=3, help="phase classes of the schedule")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-sweep", action="store_true")
+    ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
+                    help="first run one plain device copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; --gpus "
@@ -90,6 +92,16 @@ def main():
     Xd = torch.from_numpy(X).to(dev)
     Zd = torch.empty((K, L), dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream(dev).cuda_stream
+    if args.copy_calib > 0:
+        # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE readings
+        # convert the counters of the LGCD kernels into bytes
+        n = args.copy_calib * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     print(f"[bench] workload {w.name}; steps={args.steps} warmup={args.warmup}",
           file=sys.stderr, flush=True)
 
@@ -115,9 +127,13 @@ def main():
     n_upd = sum(s["n_updates"] for s in stats)
     ms_per_step = 1e3 * wall / args.steps
     bpu = algorithmic_bytes_per_update(K, W)
-    launches = tst["n_phase_launches"]
-    kern_ms = tst["t_lgcd_kernel_ms"]
-    achieved = (tst["n_updates"] * bpu / launches) / (kern_ms / launches * 1e-3) / 1e9
+    # dominant kernel: the float LDS-state phase kernel of the first round
+    # (the double finish round, if any, runs the HBM-state kernel)
+    assert tst["round_state"][0] == 0, "first round expected on the float LDS-state kernel"
+    launches = tst["round_launches"][0]
+    kern_ms = tst["round_kernel_ms"][0]
+    upd0 = tst["round_updates"][0]
+    achieved = (upd0 * bpu / launches) / (kern_ms / launches * 1e-3) / 1e9
     traffic = measured_traffic()
     s0 = stats[-1]
     out = {
@@ -148,14 +164,19 @@ def main():
                   "round_updates": s0["round_updates"], "round_phases": s0["round_phases"],
                   "round_ms": s0["round_ms"],
                   "polished_fp64": s0["polished_fp64"]},
-        "roofline": {"kernel": "k_lgcd_phase", "bound": "hbm", "achieved": achieved,
-                     "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
-                     "traffic": traffic,
+        "roofline": {"kernel": "k_lgcd_phase<float> (LDS state)", "bound": "hbm",
+                     "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
                      "bytes_per_update": bpu,
-                     "updates_per_launch": tst["n_updates"] / launches,
+                     "updates_per_launch": upd0 / launches,
                      "avg_launch_us": 1e3 * kern_ms / launches,
                      "launches": launches, "kernel_ms": kern_ms},
     }
+    if tst["round_launches"][1] > 0:
+        l1, k1, u1 = tst["round_launches"][1], tst["round_kernel_ms"][1], tst["round_updates"][1]
+        out["finish_round"] = {"state": "double, HBM" if tst["round_state"][1] & 2
+                               else "double, LDS", "launches": l1, "kernel_ms": k1,
+                               "updates": u1, "avg_launch_us": 1e3 * k1 / l1}
     if not args.no_sweep:
         sweep = []
         with d.Context(update_cap=args.cap, colors=args.colors) as c:

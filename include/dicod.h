@@ -122,6 +122,9 @@ typedef struct {
     int64_t round_updates[4]; /* updates of the first four descent rounds            */
     int64_t round_phases[4];  /* phases of the first four descent rounds             */
     double round_ms[4];       /* wall time of the first four descent rounds          */
+    double round_kernel_ms[4]; /* phase-kernel time of those rounds (timing = 1)     */
+    int64_t round_launches[4]; /* phase-kernel launches of those rounds              */
+    int round_state[4];       /* state of those rounds: bit 0 double, bit 1 HBM      */
     int state_in_hbm;         /* 1 if segment state was kept in HBM, not LDS         */
     int polished_fp64;        /* 1 if the descent finished on a double state         */
 } dicod_stats;

@@ -86,6 +86,9 @@ class dicod_stats(ctypes.Structure):
         ("round_updates", ctypes.c_int64 * 4),
         ("round_phases", ctypes.c_int64 * 4),
         ("round_ms", ctypes.c_double * 4),
+        ("round_kernel_ms", ctypes.c_double * 4),
+        ("round_launches", ctypes.c_int64 * 4),
+        ("round_state", ctypes.c_int * 4),
         ("state_in_hbm", ctypes.c_int),
         ("polished_fp64", ctypes.c_int),
     ]

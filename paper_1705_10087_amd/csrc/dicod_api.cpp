@@ -689,7 +689,9 @@ int solve_device_batch(dicod_ctx* ctx, int n_sig, const float* dX, const int64_t
     bool accepted = false, out_of_phases = false;
     double t_cd = 0.0, t_verify = 0.0, t_kernel = 0.0;
     int64_t round_upd[4] = {0, 0, 0, 0}, round_ph[4] = {0, 0, 0, 0};
-    double round_ms[4] = {0.0, 0.0, 0.0, 0.0};
+    int64_t round_launch[4] = {0, 0, 0, 0};
+    double round_ms[4] = {0.0, 0.0, 0.0, 0.0}, round_kms[4] = {0.0, 0.0, 0.0, 0.0};
+    int round_state[4] = {0, 0, 0, 0};
     std::vector<CheckResult> res(n_sig);
     std::vector<uint32_t> done(n_sig, 0u);
 
@@ -697,6 +699,8 @@ int solve_device_batch(dicod_ctx* ctx, int n_sig, const float* dX, const int64_t
         // ---- 3. coloured phases until C consecutive phases apply nothing
         HIPCHECK(ctx, hipEventRecord(ev2, s));
         const int64_t start = phase;
+        const int64_t launch0 = n_launch;
+        const double kern0 = t_kernel;
         conv_phase = -1;
         while (conv_phase < 0) {
             if (phase >= max_ph) {
@@ -763,6 +767,9 @@ int solve_device_batch(dicod_ctx* ctx, int n_sig, const float* dX, const int64_t
             round_ms[round] = t_round;
             const int64_t last = conv_phase >= 0 ? conv_phase + 1 : phase;
             round_ph[round] = last - start;
+            round_launch[round] = n_launch - launch0;
+            round_kms[round] = t_kernel - kern0;
+            round_state[round] = (cur64 ? 1 : 0) | (in_lds ? 0 : 2);
             for (int64_t p = start; p < last; ++p)
                 round_upd[round] += (int64_t)ctx->h_upd[p];
         }
@@ -870,6 +877,9 @@ int solve_device_batch(dicod_ctx* ctx, int n_sig, const float* dX, const int64_t
                 o.round_updates[r] = n_sig == 1 ? round_upd[r] : 0;
                 o.round_phases[r] = round_ph[r];
                 o.round_ms[r] = round_ms[r];
+                o.round_kernel_ms[r] = round_kms[r];
+                o.round_launches[r] = round_launch[r];
+                o.round_state[r] = round_state[r];
             }
             o.state_in_hbm = any_hbm ? 1 : 0;
             o.polished_fp64 = polished ? 1 : 0;
