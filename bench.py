@@ -8,6 +8,16 @@ descent phases and the final double-precision check, through the C ABI.
 
 Prints one JSON line.  value = coordinate updates per second over the timed
 steps (whole job); ms_per_step = time-to-eps of one solve.
+
+Two more workloads are measured beside it (skip with --no-batched /
+--no-served):
+  * batched: 256 signals, T uniform in [10,000, 500,000], shared dictionary
+    P=7 K=25 W=64, Bernoulli(0.005) activations, solved in one batched call,
+    against the same signals solved one call per signal on the same GPU;
+  * served: a Poisson stream of encode requests (lengths log-uniform in
+    [2,000, 2,000,000], P=7 K=25 W=200) through dicod_submit / dicod_poll at
+    0.5 and 0.8 of the measured saturation rate: p50/p99 latency and
+    updates/s, against the same requests solved one at a time.
 """
 import argparse
 import hashlib
@@ -59,6 +69,144 @@ def cpu_baseline(X, D, lam, eps, M, cap, colors):
                       f"schedule ({colors} colours, M={M}, update cap {cap}), single thread"}
 
 
+def _gen_signal(job):
+    import synth
+    P, K, W, T, rho, sigma, seed, D = job
+    return synth.generate_fast(P, K, W, int(T), rho, sigma, seed, D)
+
+
+def gen_signals(P, K, W, lengths, rho, sigma, seed0, D, workers=8):
+    """Seeded signals of the given lengths with a shared dictionary, generated
+    in a process pool (before the GPU is initialised)."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    jobs = [(P, K, W, T, rho, sigma, seed0 + i, D) for i, T in enumerate(lengths)]
+    with cf.ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("fork")) as ex:
+        return list(ex.map(_gen_signal, jobs, chunksize=4))
+
+
+def batched_bench(d, torch, D, Ts, Xs, cap, colors):
+    """One batched call over all signals vs one call per signal."""
+    K, P, W = D.shape
+    n = len(Ts)
+    Ls = [int(T) - W + 1 for T in Ts]
+    x_off = np.concatenate([[0], np.cumsum([P * int(T) for T in Ts])[:-1]]).astype(np.int64)
+    z_off = np.concatenate([[0], np.cumsum([K * L for L in Ls])[:-1]]).astype(np.int64)
+    dev = torch.device("cuda:0")
+    Xd = torch.from_numpy(np.concatenate([X.ravel() for X in Xs])).to(dev)
+    nz = int(sum(K * L for L in Ls))
+    Zb = torch.empty(nz, dtype=torch.float64, device=dev)
+    Zs = torch.empty(nz, dtype=torch.float64, device=dev)
+    lam = np.full(n, -0.1)
+    with d.Context(update_cap=cap, colors=colors) as c:
+        c.set_dictionary(D)
+        c.solve_batch_device(Xd, Ts, x_off, lam, 1e-6, None, Zb, z_off)   # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sts = c.solve_batch_device(Xd, Ts, x_off, lam, 1e-6, None, Zb, z_off)
+        torch.cuda.synchronize()
+        t_batch = time.perf_counter() - t0
+        upd_b = sum(s["n_updates"] for s in sts)
+        t0 = time.perf_counter()
+        upd_s = 0
+        for i in range(n):
+            Xi = Xd[x_off[i]:x_off[i] + P * int(Ts[i])].view(P, int(Ts[i]))
+            Zi = Zs[z_off[i]:z_off[i] + K * Ls[i]].view(K, Ls[i])
+            _, st, _ = c.solve_device(Xi, -0.1, 1e-6, 0, Zi)
+            upd_s += st["n_updates"]
+        torch.cuda.synchronize()
+        t_seq = time.perf_counter() - t0
+    same = bool(torch.equal(Zb, Zs))
+    return {"workload": f"{n} signals, T uniform in [10000, 500000], P={P} K={K} W={W}, "
+                        "rho=0.005, sigma=0.1, lambda=0.1*lambda_max per signal, eps=1e-6",
+            "total_samples": int(sum(int(T) for T in Ts)), "coefficients": nz,
+            "batched": {"time_to_eps_s": t_batch, "updates": int(upd_b),
+                        "updates_per_s": upd_b / t_batch,
+                        "converged": int(sum(s["converged"] for s in sts))},
+            "per_signal": {"time_to_eps_s": t_seq, "updates": int(upd_s),
+                           "updates_per_s": upd_s / t_seq},
+            "speedup": t_seq / t_batch, "batched_equals_per_signal": same}
+
+
+def served_bench(d, torch, D, pool_T, pool_X, n_req, cap, colors, seed):
+    """Poisson stream through dicod_submit / dicod_poll vs requests solved alone."""
+    import threading
+    import synth
+    K, P, W = D.shape
+    Lmax = max(int(T) for T in pool_T) - W + 1
+    out_buf = torch.empty(K * Lmax, dtype=torch.float64, pin_memory=True).numpy()
+    npool = len(pool_X)
+    res = {"workload": f"requests drawn from {npool} signals with T log-uniform in [2000, "
+                       f"2000000], P={P} K={K} W={W}, rho=0.007, sigma=0.1, "
+                       "lambda=0.1*lambda_max, eps=1e-6",
+           "requests": n_req}
+
+    def run_stream(c, rate):
+        """Submits n_req requests (closed batch if rate is None) and polls
+        them; returns (makespan s, client latencies ms, server latencies ms,
+        updates)."""
+        arrivals = (np.zeros(n_req) if rate is None else
+                    synth.poisson_arrivals(n_req, rate, seed + int(rate or 0)))
+        t_sub = [0.0] * n_req
+        ids = [None] * n_req
+        done = {}
+        start = time.perf_counter()
+
+        def submitter():
+            for i in range(n_req):
+                dt = start + arrivals[i] - time.perf_counter()
+                if dt > 0:
+                    time.sleep(dt)
+                t_sub[i] = time.perf_counter()
+                ids[i] = c.submit(pool_X[i % npool], -0.1, 1e-6)
+
+        th = threading.Thread(target=submitter)
+        th.start()
+        lat_c, lat_s, upd = [], [], 0
+        while len(done) < n_req:
+            for i in range(n_req):
+                if i in done or ids[i] is None:
+                    continue
+                ok, _, st = c.poll(ids[i], int(pool_T[i % npool]), out_buf)
+                if ok:
+                    done[i] = time.perf_counter()
+                    lat_c.append(1e3 * (done[i] - t_sub[i]))
+                    lat_s.append(st["t_latency_ms"])
+                    upd += st["n_updates"]
+            time.sleep(5e-5)
+        th.join()
+        return max(done.values()) - start, np.array(lat_c), np.array(lat_s), upd
+
+    with d.Context(update_cap=cap, colors=colors) as c:
+        c.set_dictionary(D)
+        # alone: every distinct request solved by itself
+        alone, upd_alone = [], 0
+        for i in range(min(n_req, npool)):
+            t0 = time.perf_counter()
+            _, st = c.solve(pool_X[i], -0.1, 1e-6)
+            alone.append(1e3 * (time.perf_counter() - t0))
+            upd_alone += st["n_updates"]
+        alone = np.array(alone)
+        res["alone"] = {"p50_ms": float(np.percentile(alone, 50)),
+                        "p99_ms": float(np.percentile(alone, 99)),
+                        "requests_per_s": 1e3 / alone.mean(),
+                        "updates_per_s": upd_alone / (alone.sum() / 1e3)}
+        run_stream(c, None)  # warm-up of the serving path
+        mk, lc, ls, upd = run_stream(c, None)
+        sat = n_req / mk
+        res["saturation"] = {"requests_per_s": sat, "updates_per_s": upd / mk,
+                             "makespan_s": mk}
+        for frac in (0.5, 0.8):
+            mk, lc, ls, upd = run_stream(c, frac * sat)
+            res[f"rate_{frac}"] = {"rate_per_s": frac * sat,
+                                   "p50_ms": float(np.percentile(lc, 50)),
+                                   "p99_ms": float(np.percentile(lc, 99)),
+                                   "server_p50_ms": float(np.percentile(ls, 50)),
+                                   "server_p99_ms": float(np.percentile(ls, 99)),
+                                   "updates_per_s": upd / mk}
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -72,6 +220,10 @@ def main():
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="first run one plain device copy of MIB MiB (counter calibration)")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--batch-signals", type=int, default=256)
+    ap.add_argument("--served-requests", type=int, default=200)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; --gpus "
@@ -82,6 +234,28 @@ def main():
     import torch
     import synth
     import paper_1705_10087_amd as d
+
+    # inputs of the batched and served workloads, drawn before the GPU starts
+    batch_data = served_data = None
+    if not args.no_batched:
+        a = synth.BATCH_ATOM
+        Db = synth.dictionary(np.random.Generator(np.random.PCG64(args.seed + 11)),
+                              a["K"], a["P"], a["W"]).astype(np.float32)
+        Tb = synth.batch_lengths(args.batch_signals, 10_000, 500_000, args.seed + 12)
+        Xb = gen_signals(a["P"], a["K"], a["W"], Tb, a["rho"], a["sigma_noise"],
+                         args.seed + 1000, Db)
+        batch_data = (Db, Tb, Xb)
+        print(f"[bench] batched inputs: {len(Tb)} signals, {int(Tb.sum())} samples",
+              file=sys.stderr, flush=True)
+    if not args.no_served:
+        Ds = synth.dictionary(np.random.Generator(np.random.PCG64(args.seed + 21)),
+                              25, 7, 200).astype(np.float32)
+        Ts = synth.served_lengths(min(64, args.served_requests), 2_000, 2_000_000,
+                                  args.seed + 22)
+        Xs = gen_signals(7, 25, 200, Ts, 0.007, 0.1, args.seed + 5000, Ds)
+        served_data = (Ds, Ts, Xs)
+        print(f"[bench] served inputs: {len(Ts)} signals, {int(Ts.sum())} samples",
+              file=sys.stderr, flush=True)
 
     w = synth.PAPER
     X, D, _ = synth.workload(w, args.seed)
@@ -191,6 +365,13 @@ def main():
                 except d.DicodError as e:
                     sweep.append({"n_seg": M, "error": str(e)[:120]})
         out["segment_sweep"] = sweep
+    if batch_data is not None:
+        out["batched"] = batched_bench(d, torch, *batch_data, args.cap, args.colors)
+        print(f"[bench] batched done", file=sys.stderr, flush=True)
+    if served_data is not None:
+        out["served"] = served_bench(d, torch, *served_data, args.served_requests, args.cap,
+                                     args.colors, args.seed)
+        print(f"[bench] served done", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         lam = s0["lambda"]
         out["cpu_baseline"] = cpu_baseline(X, D, lam, w.eps, s0["n_seg"], args.cap, args.colors)

@@ -127,6 +127,8 @@ typedef struct {
     int round_state[4];       /* state of those rounds: bit 0 double, bit 1 HBM      */
     int state_in_hbm;         /* 1 if segment state was kept in HBM, not LDS         */
     int polished_fp64;        /* 1 if the descent finished on a double state         */
+    double t_queue_ms;        /* served: dicod_submit until admission to the device  */
+    double t_latency_ms;      /* served: dicod_submit until the result was complete  */
 } dicod_stats;
 
 /* One record per applied update (dicod_get_trace); 32 bytes. */

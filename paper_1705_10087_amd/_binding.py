@@ -91,6 +91,8 @@ class dicod_stats(ctypes.Structure):
         ("round_state", ctypes.c_int * 4),
         ("state_in_hbm", ctypes.c_int),
         ("polished_fp64", ctypes.c_int),
+        ("t_queue_ms", ctypes.c_double),
+        ("t_latency_ms", ctypes.c_double),
     ]
 
     def to_dict(self):
@@ -280,9 +282,14 @@ def dicod_submit(ctx, X, lam, eps, n_seg=0):
     return rid.value
 
 
-def dicod_poll(ctx, req_id, K, L):
-    """Returns (done, Z or None, stats or None)."""
-    Z = np.zeros((K, L), dtype=np.float64)
+def dicod_poll(ctx, req_id, K, L, out=None):
+    """Returns (done, Z or None, stats or None).  out: optional float64 buffer of
+    at least K * L elements that receives Z (the returned array is a view)."""
+    if out is None:
+        Z = np.empty((K, L), dtype=np.float64)
+    else:
+        Z = out.reshape(-1)[:K * L].reshape(K, L)
+        assert Z.dtype == np.float64 and Z.flags.c_contiguous
     st = dicod_stats()
     rc = lib().dicod_poll(ctx, ctypes.c_uint64(req_id), _np_ptr(Z), ctypes.byref(st))
     _check(ctx, rc, allow=(DICOD_OK, DICOD_PENDING))
@@ -345,5 +352,5 @@ class Context:
     def submit(self, X, lam, eps, n_seg=0):
         return dicod_submit(self.h, X, lam, eps, n_seg)
 
-    def poll(self, req_id, T):
-        return dicod_poll(self.h, req_id, self.K, T - self.W + 1)
+    def poll(self, req_id, T, out=None):
+        return dicod_poll(self.h, req_id, self.K, T - self.W + 1, out)

@@ -305,6 +305,7 @@ extern "C" int dicod_set_dictionary(dicod_ctx* ctx, const float* D, int K, int P
         sd[k].seg_base = 0;
         sd[k].M = 1;
         sd[k].lam = 0.0;
+        sd[k].eps_stop = 0.0;
         pref[k + 1] = pref[k] + ceil_div(nd, kTile);
     }
     DevBuf dpad, dsig, dpref;
@@ -447,6 +448,7 @@ int make_plan(dicod_ctx* ctx, int n_sig, const int64_t* T, const int64_t* x_off,
         s.seg_base = (int32_t)pl.segs.size();
         s.M = M;
         s.lam = lam[i];
+        s.eps_stop = 0.0;
         for (int m = 0; m < M; ++m) {
             SegDesc d;
             d.z_off = z_off[i];
@@ -675,14 +677,17 @@ int solve_device_batch(dicod_ctx* ctx, int n_sig, const float* dX, const int64_t
     a.trace_cap = cfg.trace_capacity;
     a.lm_max = pl.lm_max;
     a.lext_max = pl.lext_max;
+    a.phase_stride = 0;
     auto set_state = [&](bool use64, bool lds) {
         a.g = use64 && !fp64 ? ws.g64.p : ws.g.p;
         a.S = use64 ? (lds ? ctx->St64.p : ctx->S64.p) : (lds ? ctx->St32.p : ctx->S32.p);
         a.n2 = use64 ? ctx->n2_64.p : ctx->n2_32.p;
         a.inv_n2 = use64 ? ctx->inv64.p : ctx->inv32.p;
-        a.eps_stop = use64 ? eps : eps * cfg.inner_eps_factor;
+        for (int i = 0; i < n_sig; ++i)
+            pl.sig[i].eps_stop = use64 ? eps : eps * cfg.inner_eps_factor;
+        return upload(ws.sig, pl.sig, s);
     };
-    set_state(cur64, in_lds);
+    HIPCHECK(ctx, set_state(cur64, in_lds));
 
     int64_t phase = 0, n_launch = 0, conv_phase = -1;
     int n_refresh = 0, round = 0;
@@ -828,7 +833,7 @@ int solve_device_batch(dicod_ctx* ctx, int n_sig, const float* dX, const int64_t
             polished = true;
             any_hbm |= !in_lds;
         }
-        set_state(cur64, in_lds);
+        HIPCHECK(ctx, set_state(cur64, in_lds));
         HIPCHECK(ctx, upload(ws.done, done, s));
         while (phase % pl.colors)
             ++phase;
@@ -1060,4 +1065,20 @@ int ctx_dims(const dicod_ctx* ctx, int* K, int* P, int* W)
     return ctx->has_dict ? 1 : 0;
 }
 int ctx_fail(dicod_ctx* ctx, int code, const char* msg) { return fail(ctx, code, "%s", msg); }
+DictView ctx_dict(const dicod_ctx* ctx)
+{
+    DictView v;
+    v.D64 = ctx->D64.as<double>();
+    v.S64 = ctx->S64.as<double>();
+    v.S32 = ctx->S32.p;
+    v.St32 = ctx->St32.p;
+    v.St64 = ctx->St64.p;
+    v.n2_32 = ctx->n2_32.p;
+    v.inv32 = ctx->inv32.p;
+    v.n2_64 = ctx->n2_64.p;
+    v.inv64 = ctx->inv64.p;
+    return v;
+}
+int64_t min_segment_len(int W, int C) { return min_segment(W, C); }
+int auto_segment_count(int64_t L, int W, int C) { return auto_segments(L, W, C); }
 }  // namespace dicod

@@ -30,6 +30,7 @@ struct SigDesc {
     int32_t seg_base; // global index of its first segment
     int32_t M;        // number of segments
     double lam;       // lambda used
+    double eps_stop;  // a segment run stops when its best |Delta Z| is below this
 };
 
 // One time segment C_m of one signal.
@@ -104,10 +105,10 @@ struct PhaseArgs {
     const void* inv_n2;   // [K]
     const SigDesc* sigs;
     int K, W, cap;
-    double eps_stop;
     int phase;
+    int phase_stride;     // per-signal rows of phase_upd (0: one row for all)
     uint32_t* dirty;
-    unsigned long long* phase_upd;
+    unsigned long long* phase_upd;  // [sig * phase_stride + phase] updates
     unsigned long long* sig_upd;   // per-signal applied updates
     int* sig_last_upd;
     Counters* counters;
@@ -164,5 +165,12 @@ hipError_t launch_absmax_f32(const float* beta, int K, const SigDesc* sig,
                              const int64_t* tile_pref, int n_sig, int64_t n_tiles,
                              unsigned long long* out_bits, hipStream_t s);
 hipError_t launch_split_bf16(const double* D, size_t n, float* hi_lo, hipStream_t s);
+
+// Serving: tab[slots[i]].lam = lam_in[i] (> 0) or -lam_in[i] * lambda_max[i].
+hipError_t launch_apply_lambda(SigDesc* tab, const int* slots, const double* lam_in,
+                               const unsigned long long* lmax_bits, int n, hipStream_t s);
+// Serving: ring[r][(start + c) % H] = 0 for r < rows, c < n.
+hipError_t launch_clear_ring(unsigned long long* ring, int rows, int H, int start, int n,
+                             hipStream_t s);
 
 }  // namespace dicod

@@ -14,10 +14,25 @@ int server_submit(dicod_ctx* ctx, const float* X, int64_t T, double lambda, doub
                   int n_seg, uint64_t* req_id);
 int server_poll(dicod_ctx* ctx, uint64_t req_id, double* Z_out, dicod_stats* st);
 
+// Device pointers of the resident dictionary (read-only while serving).
+struct DictView {
+    const double* D64;                 // [K][P][W]
+    const double* S64;                 // [l][k][d] double
+    const void* S32;                   // [l][k][d] float
+    const void* St32;                  // phase-kernel layout, float
+    const void* St64;                  // phase-kernel layout, double
+    const void *n2_32, *inv32, *n2_64, *inv64;
+};
+
 // accessors implemented in dicod_api.cpp
 Server*& ctx_server(dicod_ctx* ctx);
 const dicod_config& ctx_config(const dicod_ctx* ctx);
 int ctx_dims(const dicod_ctx* ctx, int* K, int* P, int* W);
+DictView ctx_dict(const dicod_ctx* ctx);
 int ctx_fail(dicod_ctx* ctx, int code, const char* msg);
+
+// Segment-length rules shared with the one-shot solver.
+int64_t min_segment_len(int W, int C);
+int auto_segment_count(int64_t L, int W, int C);
 
 }  // namespace dicod

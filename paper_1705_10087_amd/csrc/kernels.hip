@@ -748,6 +748,7 @@ k_lgcd_phase(PhaseArgs a)
     double* __restrict__ Zs = a.Z + sd.z_off;
     const G* __restrict__ St = reinterpret_cast<const G*>(a.S);  // [K][nd][KP]
     const G lam = (G)a.sigs[sd.sig].lam;
+    const double eps_stop = a.sigs[sd.sig].eps_stop;
 
     // |D_k|^2 and its inverse: registers for the per-position passes, LDS for
     // the data-dependent updated atom.  Padded atoms get 1.
@@ -798,7 +799,7 @@ k_lgcd_phase(PhaseArgs a)
     bool touch_l = false, touch_r = false;
     int tlo = INT_MAX, thi = -1;
     for (;;) {
-        if (KO::value(kb) < a.eps_stop) {
+        if (KO::value(kb) < eps_stop) {
             conv = true;
             break;
         }
@@ -876,7 +877,7 @@ k_lgcd_phase(PhaseArgs a)
             gs[(int64_t)k * L + ext_lo + q] = g_l[q * KP + k];
         }
         if (tid == 0) {
-            atomicAdd(&a.phase_upd[a.phase], (unsigned long long)n);
+            atomicAdd(&a.phase_upd[(size_t)sd.sig * a.phase_stride + a.phase], (unsigned long long)n);
             atomicAdd(&a.sig_upd[sd.sig], (unsigned long long)n);
             atomicMax(&a.sig_last_upd[sd.sig], a.phase);
             atomicAdd(&a.counters->seg_runs, 1ull);
@@ -1146,6 +1147,7 @@ k_lgcd_phase_gm(PhaseArgs a)
     double* __restrict__ Zs = a.Z + sd.z_off;
     const G* __restrict__ S = reinterpret_cast<const G*>(a.S);  // [K][K][2W-1]
     const G lam = (G)a.sigs[sd.sig].lam;
+    const double eps_stop = a.sigs[sd.sig].eps_stop;
     const int nd = 2 * W - 1;
     for (int k = tid; k < K; k += NT) {
         n2l[k] = reinterpret_cast<const G*>(a.n2)[k];
@@ -1181,7 +1183,7 @@ k_lgcd_phase_gm(PhaseArgs a)
     bool conv = false;
     bool touch_l = false, touch_r = false;
     for (;;) {
-        if (KO::value(kb) < a.eps_stop) {
+        if (KO::value(kb) < eps_stop) {
             conv = true;
             break;
         }
@@ -1231,7 +1233,7 @@ k_lgcd_phase_gm(PhaseArgs a)
     }
 
     if (n > 0 && tid == 0) {
-        atomicAdd(&a.phase_upd[a.phase], (unsigned long long)n);
+        atomicAdd(&a.phase_upd[(size_t)sd.sig * a.phase_stride + a.phase], (unsigned long long)n);
         atomicAdd(&a.sig_upd[sd.sig], (unsigned long long)n);
         atomicMax(&a.sig_last_upd[sd.sig], a.phase);
         atomicAdd(&a.counters->seg_runs, 1ull);
@@ -1617,6 +1619,54 @@ hipError_t launch_check_reduce(const double* part_r2, const int64_t* tile_pref_T
 {
     hipLaunchKernelGGL(k_check_reduce, dim3((unsigned)n_sig), dim3(256), 0, s, part_r2,
                        tile_pref_T, part6, tile_pref_L, n_tiles_L, n_kblk, out);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Serving helpers: lambda of newly admitted signals, per-signal phase rings.
+// ---------------------------------------------------------------------------
+__global__ void k_apply_lambda(SigDesc* tab, const int* slots, const double* lam_in,
+                               const unsigned long long* lmax_bits, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n)
+        return;
+    double lam = lam_in[i];
+    if (lam < 0.0) {
+        lam = -lam * __longlong_as_double((long long)lmax_bits[i]);
+        if (!(lam > 0.0))
+            lam = 1e-300;  // X orthogonal to every atom: Z = 0
+    }
+    tab[slots[i]].lam = lam;
+}
+
+hipError_t launch_apply_lambda(SigDesc* tab, const int* slots, const double* lam_in,
+                               const unsigned long long* lmax_bits, int n, hipStream_t s)
+{
+    if (n <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_apply_lambda, dim3((n + 255) / 256), dim3(256), 0, s, tab, slots,
+                       lam_in, lmax_bits, n);
+    return hipGetLastError();
+}
+
+__global__ void k_clear_ring(unsigned long long* ring, int rows, int H, int start, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= rows * n)
+        return;
+    const int r = i / n;
+    const int c = i - r * n;
+    ring[(size_t)r * H + (start + c) % H] = 0ull;
+}
+
+hipError_t launch_clear_ring(unsigned long long* ring, int rows, int H, int start, int n,
+                             hipStream_t s)
+{
+    if (rows <= 0 || n <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_clear_ring, dim3((rows * n + 255) / 256), dim3(256), 0, s, ring, rows,
+                       H, start, n);
     return hipGetLastError();
 }
 

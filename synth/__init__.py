@@ -86,6 +86,35 @@ def generate(P, K, W, T, rho, sigma_noise, seed, sigma_z=10.0, D=None):
     return X.astype(np.float32), D.astype(np.float32), Z
 
 
+def synthesize_fast(D, Z, T):
+    """sum_k Z_k * D_k like ``synthesize``, summed per channel with one
+    bincount over all non-zero activations (other summation order)."""
+    K, P, W = D.shape
+    ks, ts = np.nonzero(Z)
+    z = Z[ks, ts]
+    idx = (ts[:, None] + np.arange(W)[None, :]).ravel()
+    X = np.empty((P, T))
+    for p in range(P):
+        X[p] = np.bincount(idx, weights=(z[:, None] * D[ks, p, :]).ravel(), minlength=T)
+    return X
+
+
+def generate_fast(P, K, W, T, rho, sigma_noise, seed, D, sigma_z=10.0):
+    """The same distributions as ``generate`` with a shared dictionary, drawn in
+    float32 and with Gaussian values only for the non-zero activations (a
+    different random stream from ``generate``): for the large batched and
+    served workloads.  Returns X float32 [P, T]."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    D = np.asarray(D, dtype=np.float64)
+    L = T - W + 1
+    mask = rng.random((K, L), dtype=np.float32) < rho
+    Z = np.zeros((K, L))
+    Z[mask] = rng.standard_normal(int(mask.sum())) * sigma_z
+    X = synthesize_fast(D, Z, T)
+    X += sigma_noise * rng.standard_normal((P, T), dtype=np.float32)
+    return X.astype(np.float32)
+
+
 def workload(w: Workload, seed: int):
     return generate(w.P, w.K, w.W, w.T, w.rho, w.sigma_noise, seed, w.sigma_z)
 

@@ -1,0 +1,185 @@
+"""GPU serving: dicod_submit / dicod_poll (continuous batching) against the
+one-shot solver on the same device.
+
+A served request counts its coloured phases from its own admission, so the
+sequence of segment runs of a request, and its result, does not depend on the
+requests that share the device with it.  The tests therefore require the
+served Z to equal the one-shot Z element by element (FP32 and FP64 policies),
+which implies the stated tolerance (relative objective error <= 1e-6,
+max |z - z_ref| <= 1e-4 max |z_ref|); the one-shot solver itself is held to
+the oracle by the parity tests.
+"""
+import time
+
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+EPS = 1e-6
+
+
+@pytest.fixture(scope="module")
+def dicod():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1705_10087_amd as d
+    return d
+
+
+def wait(c, rid, T, timeout=120.0):
+    t0 = time.perf_counter()
+    while True:
+        done, Z, st = c.poll(rid, T)
+        if done:
+            return Z, st
+        if time.perf_counter() - t0 > timeout:
+            raise TimeoutError(f"request {rid} not complete after {timeout} s")
+        time.sleep(1e-4)
+
+
+def mix(D, lengths, seed0):
+    K, P, W = D.shape
+    return [synth.generate(P, K, W, int(T), 0.007, 0.1, seed=seed0 + i, D=D)[0]
+            for i, T in enumerate(lengths)]
+
+
+def paper_dict():
+    return synth.generate(7, 25, 200, 1000, 0.007, 0.1, seed=77)[1]
+
+
+def solo(c, X, lam=-0.1, n_seg=0):
+    return c.solve(X, lam, EPS, n_seg)
+
+
+# lengths: several segments (L/M >= 200 for 3 colours), one segment (M = 1),
+# and a signal long enough for a few hundred segments
+LENGTHS = [1500, 400, 20_000, 5_000, 60_000, 2_345, 260]
+
+
+@pytest.mark.parametrize("precision", [1, 0])
+def test_served_equals_one_shot(dicod, precision):
+    print(f"\ncase: served mix of {len(LENGTHS)} precision={precision}", flush=True)
+    D = paper_dict()
+    Xs = mix(D, LENGTHS, 100)
+    with dicod.Context(precision=precision, max_phases=50_000) as c:
+        c.set_dictionary(D)
+        ref = [solo(c, X) for X in Xs]
+        ids = [c.submit(X, -0.1, EPS) for X in Xs]
+        out = [wait(c, rid, X.shape[1]) for rid, X in zip(ids, Xs)]
+    for (Zr, sr), (Zs, ss), T in zip(ref, out, LENGTHS):
+        print(f"T={T}: solo {sr['n_updates']} upd obj {sr['objective']:.10g}; served "
+              f"{ss['n_updates']} upd obj {ss['objective']:.10g} latency "
+              f"{ss['t_latency_ms']:.2f} ms queue {ss['t_queue_ms']:.2f} ms", flush=True)
+        assert ss["converged"] == 1 and ss["max_dz"] < EPS
+        assert ss["lambda"] == sr["lambda"] and ss["lambda_max"] == sr["lambda_max"]
+        assert ss["n_updates"] == sr["n_updates"]
+        np.testing.assert_array_equal(Zs, Zr)
+        assert abs(ss["objective"] - sr["objective"]) <= 1e-12 * abs(sr["objective"])
+
+
+def test_served_absolute_lambda_and_eps_mix(dicod):
+    """Requests with different lambda conventions and eps share the device."""
+    print("\ncase: served lambda/eps mix", flush=True)
+    D = paper_dict()
+    Ls = [3_000, 7_000, 1_200]
+    Xs = mix(D, Ls, 300)
+    lams = [-0.2, 4.0, -0.05]
+    epss = [1e-6, 1e-5, 1e-6]
+    with dicod.Context(max_phases=50_000) as c:
+        c.set_dictionary(D)
+        ref = [c.solve(X, lam, e) for X, lam, e in zip(Xs, lams, epss)]
+        ids = [c.submit(X, lam, e) for X, lam, e in zip(Xs, lams, epss)]
+        out = [wait(c, rid, X.shape[1]) for rid, X in zip(ids, Xs)]
+    for (Zr, sr), (Zs, ss), lam, e in zip(ref, out, lams, epss):
+        assert ss["max_dz"] < e and ss["lambda"] == sr["lambda"]
+        if lam > 0:
+            assert ss["lambda"] == lam
+        np.testing.assert_array_equal(Zs, Zr)
+
+
+def test_short_request_overtakes_long(dicod):
+    """Continuous batching: a short request submitted while a long one runs
+    is admitted at once and completes first."""
+    print("\ncase: short behind long", flush=True)
+    D = paper_dict()
+    Xl, Xs = mix(D, [600_000, 2_000], 500)
+    with dicod.Context(max_phases=50_000) as c:
+        c.set_dictionary(D)
+        Zs_ref, _ = solo(c, Xs)
+        rl = c.submit(Xl, -0.1, EPS)
+        rs = c.submit(Xs, -0.1, EPS)
+        order, res = [], {}
+        t0 = time.perf_counter()
+        while len(res) < 2 and time.perf_counter() - t0 < 120:
+            for rid, X in ((rs, Xs), (rl, Xl)):
+                if rid in res:
+                    continue
+                done, Z, st = c.poll(rid, X.shape[1])
+                if done:
+                    res[rid] = (Z, st)
+                    order.append(rid)
+            time.sleep(1e-4)
+    (Zs, ss), (Zl, sl) = res[rs], res[rl]
+    print(f"long latency {sl['t_latency_ms']:.2f} ms, short latency {ss['t_latency_ms']:.2f} "
+          f"ms (queue {ss['t_queue_ms']:.2f} ms); completion order {order} (short={rs})",
+          flush=True)
+    assert order == [rs, rl]
+    assert ss["t_queue_ms"] < 0.5 * sl["t_latency_ms"]
+    np.testing.assert_array_equal(Zs, Zs_ref)
+    assert sl["converged"] == 1
+
+
+def test_footprint_admission(dicod):
+    """A budget that holds about two requests at a time: the rest wait for
+    memory, every result still equals the one-shot solve, and a request larger
+    than the whole budget is refused."""
+    print("\ncase: footprint admission", flush=True)
+    D = paper_dict()
+    Ls = [20_000] * 5 + [3_000] * 3
+    Xs = mix(D, Ls, 700)
+    budget = 40 << 20
+    with dicod.Context(hbm_budget_bytes=budget, max_inflight=8, max_phases=50_000) as c:
+        c.set_dictionary(D)
+        ref = [solo(c, X) for X in Xs]
+        ids = [c.submit(X, -0.1, EPS) for X in Xs]
+        out = [wait(c, rid, X.shape[1]) for rid, X in zip(ids, Xs)]
+        big = mix(D, [400_000], 900)[0]
+        with pytest.raises(dicod.DicodError) as ei:
+            c.submit(big, -0.1, EPS)
+        assert ei.value.code == dicod.DICOD_ENOMEM
+    queued = [s["t_queue_ms"] for _, s in out]
+    print("queue ms:", [round(q, 2) for q in queued], flush=True)
+    # the third request waits until the first one has been polled
+    assert queued[2] >= 0.5 * out[0][1]["t_latency_ms"]
+    for (Zr, _), (Zs, _) in zip(ref, out):
+        np.testing.assert_array_equal(Zs, Zr)
+
+
+def test_serving_errors(dicod):
+    print("\ncase: serving errors", flush=True)
+    D = paper_dict()
+    with dicod.Context() as c:
+        with pytest.raises(dicod.DicodError) as ei:
+            c.submit(np.zeros((7, 500), np.float32), -0.1, EPS)  # no dictionary yet
+        assert ei.value.code == dicod.DICOD_EINVAL
+        c.set_dictionary(D)
+        with pytest.raises(dicod.DicodError) as ei:
+            c.poll(12345, 1000)
+        assert ei.value.code == dicod.DICOD_ENOREQ
+        for bad in [dict(T=100), dict(lam=0.0), dict(eps=-1.0), dict(n_seg=100)]:
+            T = bad.get("T", 2_000)
+            with pytest.raises(dicod.DicodError) as ei:
+                c.submit(np.ones((7, T), np.float32), bad.get("lam", -0.1),
+                         bad.get("eps", EPS), bad.get("n_seg", 0))
+            assert ei.value.code == dicod.DICOD_EINVAL
+        # a request that finished is forgotten after its poll
+        X = mix(D, [1_000], 5)[0]
+        rid = c.submit(X, -0.1, EPS)
+        wait(c, rid, X.shape[1])
+        with pytest.raises(dicod.DicodError) as ei:
+            c.poll(rid, X.shape[1])
+        assert ei.value.code == dicod.DICOD_ENOREQ
