@@ -9,8 +9,9 @@ descent phases and the final double-precision check, through the C ABI.
 Prints one JSON line.  value = coordinate updates per second over the timed
 steps (whole job); ms_per_step = time-to-eps of one solve.
 
-Two more workloads are measured beside it (skip with --no-batched /
---no-served):
+Three more workloads are measured beside it (skip with --no-long /
+--no-batched / --no-served):
+  * long: one signal of T = 5,000,000 (P=7 K=25 W=200), time-to-eps;
   * batched: 256 signals, T uniform in [10,000, 500,000], shared dictionary
     P=7 K=25 W=64, Bernoulli(0.005) activations, solved in one batched call,
     against the same signals solved one call per signal on the same GPU;
@@ -128,6 +129,31 @@ def batched_bench(d, torch, D, Ts, Xs, cap, colors):
             "speedup": t_seq / t_batch, "batched_equals_per_signal": same}
 
 
+def long_bench(d, torch, D, X, cap, colors, steps=2):
+    """Long single signal (T = 5,000,000): time-to-eps on the device."""
+    K, P, W = D.shape
+    dev = torch.device("cuda:0")
+    Xd = torch.from_numpy(X).to(dev)
+    Zd = torch.empty((K, X.shape[1] - W + 1), dtype=torch.float64, device=dev)
+    with d.Context(update_cap=cap, colors=colors) as c:
+        c.set_dictionary(D)
+        c.solve_device(Xd, -0.1, 1e-6, 0, Zd)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            _, st, _ = c.solve_device(Xd, -0.1, 1e-6, 0, Zd)
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - t0) / steps
+    return {"workload": f"single signal P={P} K={K} W={W} T={X.shape[1]}, rho=0.007, "
+                        "sigma=0.1, lambda=0.1*lambda_max, eps=1e-6",
+            "precision": "FP32 descent, FP64 beta init and stop test",
+            "time_to_eps_s": t, "updates": st["n_updates"], "updates_per_s": st["n_updates"] / t,
+            "n_seg": st["n_seg"], "n_phases": st["n_phases"], "t_init_ms": st["t_init_ms"],
+            "t_cd_ms": st["t_cd_ms"], "t_verify_ms": st["t_verify_ms"],
+            "round_updates": st["round_updates"], "round_ms": st["round_ms"],
+            "converged": st["converged"]}
+
+
 def served_bench(d, torch, D, pool_T, pool_X, n_req, cap, colors, seed):
     """Poisson stream through dicod_submit / dicod_poll vs requests solved alone."""
     import threading
@@ -222,6 +248,7 @@ def main():
                     help="first run one plain device copy of MIB MiB (counter calibration)")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--no-long", action="store_true")
     ap.add_argument("--batch-signals", type=int, default=256)
     ap.add_argument("--served-requests", type=int, default=200)
     args = ap.parse_args()
@@ -236,7 +263,7 @@ def main():
     import paper_1705_10087_amd as d
 
     # inputs of the batched and served workloads, drawn before the GPU starts
-    batch_data = served_data = None
+    batch_data = served_data = long_data = None
     if not args.no_batched:
         a = synth.BATCH_ATOM
         Db = synth.dictionary(np.random.Generator(np.random.PCG64(args.seed + 11)),
@@ -247,6 +274,13 @@ def main():
         batch_data = (Db, Tb, Xb)
         print(f"[bench] batched inputs: {len(Tb)} signals, {int(Tb.sum())} samples",
               file=sys.stderr, flush=True)
+    if not args.no_long:
+        w = synth.LONG
+        Dl = synth.dictionary(np.random.Generator(np.random.PCG64(args.seed + 31)),
+                              w.K, w.P, w.W).astype(np.float32)
+        long_data = (Dl, synth.generate_fast(w.P, w.K, w.W, w.T, w.rho, w.sigma_noise,
+                                             args.seed + 32, Dl))
+        print(f"[bench] long input: T={w.T}", file=sys.stderr, flush=True)
     if not args.no_served:
         Ds = synth.dictionary(np.random.Generator(np.random.PCG64(args.seed + 21)),
                               25, 7, 200).astype(np.float32)
@@ -365,6 +399,9 @@ def main():
                 except d.DicodError as e:
                     sweep.append({"n_seg": M, "error": str(e)[:120]})
         out["segment_sweep"] = sweep
+    if long_data is not None:
+        out["long"] = long_bench(d, torch, *long_data, args.cap, args.colors)
+        print(f"[bench] long done", file=sys.stderr, flush=True)
     if batch_data is not None:
         out["batched"] = batched_bench(d, torch, *batch_data, args.cap, args.colors)
         print(f"[bench] batched done", file=sys.stderr, flush=True)

@@ -96,6 +96,10 @@ def load_library(path):
     lib.oracle_max_dz.restype = ctypes.c_double
     lib.oracle_max_dz.argtypes = [dp, dp, dp, ci, ci, ci, i64, ctypes.c_double,
                                   ctypes.POINTER(ci), ctypes.POINTER(i64)]
+    lib.oracle_beta_at.restype = ci
+    lib.oracle_beta_at.argtypes = [dp, dp, dp, ci, ci, ci, i64,
+                                   ctypes.POINTER(ctypes.c_int32),
+                                   ctypes.POINTER(ctypes.c_int64), i64, dp]
     lib.oracle_lgcd.restype = ci
     lib.oracle_lgcd.argtypes = [
         dp, dp, ci, ci, ci, i64, ctypes.c_double, ctypes.c_double, ci, ci,
@@ -171,6 +175,23 @@ def beta(X, D, Z):
                              _ptr(out))
     if rc != 0:
         raise MemoryError("oracle_beta failed")
+    return out
+
+
+def beta_at(X, D, Z, k, t):
+    """beta_k[t] at the coordinates (k[i], t[i]) from the definition in Sec. 2.1,
+    one at a time (for signals too long for a full recompute)."""
+    X, D, Z = _f64(X), _f64(D), _f64(Z)
+    K, P, W = D.shape
+    k = np.ascontiguousarray(k, dtype=np.int32)
+    t = np.ascontiguousarray(t, dtype=np.int64)
+    out = np.empty(k.shape[0])
+    rc = _load().oracle_beta_at(_ptr(X), _ptr(D), _ptr(Z), K, P, W, X.shape[1],
+                                k.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                t.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                k.shape[0], _ptr(out))
+    if rc != 0:
+        raise ValueError("oracle_beta_at: bad coordinate or out of memory")
     return out
 
 

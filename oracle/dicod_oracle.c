@@ -208,6 +208,62 @@ double oracle_max_dz(const double *X, const double *D, const double *Z, int K,
     return best;
 }
 
+/* beta_k[t] at n given coordinates (k[i], t[i]) from the definition of
+ * Sec. 2.1 (reading R1), for signals too long for a full recompute: the
+ * residual X - sum Z * D on the window [t, t + W) from the activations that
+ * reach it, correlated with D_k, plus |D_k|^2 Z_k[t].  Returns 0, or -1 on
+ * a bad coordinate or allocation failure. */
+int oracle_beta_at(const double *X, const double *D, const double *Z, int K, int P,
+                   int W, int64_t T, const int32_t *kk, const int64_t *tt, int64_t n,
+                   double *out)
+{
+    const int64_t L = T - W + 1;
+    double *R = (double *)malloc(sizeof(double) * (size_t)P * (size_t)W);
+    double *n2 = (double *)malloc(sizeof(double) * (size_t)K);
+    if (!R || !n2) {
+        free(R);
+        free(n2);
+        return -1;
+    }
+    oracle_norms(D, K, P, W, n2);
+    for (int64_t i = 0; i < n; ++i) {
+        const int k = kk[i];
+        const int64_t t = tt[i];
+        if (k < 0 || k >= K || t < 0 || t >= L) {
+            free(R);
+            free(n2);
+            return -1;
+        }
+        for (int p = 0; p < P; ++p)
+            for (int s = 0; s < W; ++s)
+                R[p * W + s] = X[(int64_t)p * T + t + s];
+        /* activations (k2, u) with u + tau in [t, t + W) for some tau < W */
+        const int64_t u0 = t - W + 1 > 0 ? t - W + 1 : 0;
+        const int64_t u1 = t + W - 1 < L - 1 ? t + W - 1 : L - 1;
+        for (int k2 = 0; k2 < K; ++k2)
+            for (int64_t u = u0; u <= u1; ++u) {
+                const double z = Z[(int64_t)k2 * L + u];
+                if (z == 0.0)
+                    continue;
+                for (int s = 0; s < W; ++s) {
+                    const int64_t tau = t + s - u;
+                    if (tau < 0 || tau >= W)
+                        continue;
+                    for (int p = 0; p < P; ++p)
+                        R[p * W + s] -= z * D[IDX3(k2, p, tau, P, W)];
+                }
+            }
+        double b = 0.0;
+        for (int p = 0; p < P; ++p)
+            for (int s = 0; s < W; ++s)
+                b += D[IDX3(k, p, s, P, W)] * R[p * W + s];
+        out[i] = b + n2[k] * Z[(int64_t)k * L + t];
+    }
+    free(R);
+    free(n2);
+    return 0;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Solver                                                                     */
 /* ------------------------------------------------------------------------ */

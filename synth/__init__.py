@@ -91,11 +91,19 @@ def synthesize_fast(D, Z, T):
     bincount over all non-zero activations (other summation order)."""
     K, P, W = D.shape
     ks, ts = np.nonzero(Z)
+    order = np.argsort(ts, kind="stable")
+    ks, ts = ks[order], ts[order]
     z = Z[ks, ts]
-    idx = (ts[:, None] + np.arange(W)[None, :]).ravel()
-    X = np.empty((P, T))
-    for p in range(P):
-        X[p] = np.bincount(idx, weights=(z[:, None] * D[ks, p, :]).ravel(), minlength=T)
+    X = np.zeros((P, T))
+    step = max(1, (1 << 22) // W)  # bounded temporaries
+    for a in range(0, z.size, step):
+        k, t, v = ks[a:a + step], ts[a:a + step], z[a:a + step]
+        lo = int(t[0])
+        idx = (t[:, None] - lo + np.arange(W)[None, :]).ravel()
+        n = int(t[-1]) - lo + W
+        for p in range(P):
+            X[p, lo:lo + n] += np.bincount(idx, weights=(v[:, None] * D[k, p, :]).ravel(),
+                                           minlength=n)
     return X
 
 

@@ -316,3 +316,43 @@ def test_batch_equals_solo_bitwise(dicod):
         assert np.array_equal(Zb, Zs), f"signal {i} differs between batch and solo"
         assert sts[i]["n_updates"] == st["n_updates"]
         assert sts[i]["converged"] == 1
+
+
+# ------------------------------------------- long signal: sampled oracle checks
+
+def test_long_signal_sampled_against_oracle(dicod):
+    """T = 5,000,000 (P=7, K=25, W=200): too long for an oracle solve, so the
+    oracle recomputes beta from its definition at sampled coordinates (random
+    non-zeros of Z and random coordinates) and the objective of the returned
+    Z; every sampled |Delta Z| must be below eps (the stop test of Sec. 2.1)
+    and the objective must agree with the library's double-precision value."""
+    import torch
+    w = synth.LONG
+    print(f"\ncase: long signal T={w.T}", flush=True)
+    D = synth.dictionary(np.random.Generator(np.random.PCG64(31)), w.K, w.P, w.W).astype(np.float32)
+    X = synth.generate_fast(w.P, w.K, w.W, w.T, w.rho, w.sigma_noise, 32, D)
+    print("inputs ready", flush=True)
+    with ctx_of(dicod) as c:
+        c.set_dictionary(D)
+        Xd = torch.from_numpy(X).cuda()
+        Zd, st, _ = c.solve_device(Xd, -w.lam_rel, EPS)
+        Z = Zd.cpu().numpy()
+    print(f"gpu: {st['n_updates']} updates, {st['n_phases']} phases, M={st['n_seg']}, "
+          f"time {st['t_total_ms']:.1f} ms, max_dz {st['max_dz']:.3g}", flush=True)
+    assert st["converged"] == 1 and st["max_dz"] < EPS
+    assert st["lambda"] == pytest.approx(w.lam_rel * st["lambda_max"], rel=1e-15)
+    K, L = Z.shape
+    rng = np.random.default_rng(5)
+    nzk, nzt = np.nonzero(Z)
+    pick = rng.choice(nzk.size, size=min(3000, nzk.size), replace=False)
+    k = np.concatenate([nzk[pick], rng.integers(0, K, 3000)])
+    t = np.concatenate([nzt[pick], rng.integers(0, L, 3000)])
+    B = oracle.beta_at(f64(X), f64(D), Z, k, t)
+    n2 = oracle.norms(f64(D))
+    lam = st["lambda"]
+    zp = np.sign(B) * np.maximum(np.abs(B) - lam, 0.0) / n2[k]
+    dz = np.abs(zp - Z[k, t])
+    print(f"sampled max |Delta Z| {dz.max():.3g} over {dz.size} coordinates", flush=True)
+    assert dz.max() < EPS
+    obj = oracle.objective(f64(X), f64(D), Z, lam)
+    assert abs(obj - st["objective"]) <= 1e-10 * abs(obj)

@@ -92,6 +92,17 @@ def test_beta_matches_definition_with_replacement_operator():
                                rtol=0, atol=1e-12)
 
 
+def test_beta_at_matches_definition():
+    # sampled beta (one coordinate at a time, from the window's residual)
+    X, D, Zt = tiny_problem(6, P=2, K=3, W=5, T=30, rho=0.3)
+    K, L = Zt.shape
+    kk, tt = np.meshgrid(np.arange(K), np.arange(L), indexing="ij")
+    B = oracle.beta_at(X, D, Zt, kk.ravel(), tt.ravel()).reshape(K, L)
+    np.testing.assert_allclose(B, _beta_by_definition(X, D, Zt), rtol=0, atol=1e-12)
+    with pytest.raises(ValueError):
+        oracle.beta_at(X, D, Zt, [0], [L])
+
+
 # ------------------------------------------------------------ solver checks
 
 def _greedy_brute_force(X, D, lam, eps, n_steps):
