@@ -385,6 +385,23 @@ def main():
         out["finish_round"] = {"state": "double, HBM" if tst["round_state"][1] & 2
                                else "double, LDS", "launches": l1, "kernel_ms": k1,
                                "updates": u1, "avg_launch_us": 1e3 * k1 / l1}
+    # the same solve under each precision policy (time-to-eps, 5 solves each)
+    variants = {}
+    for name, prec in (("FP64", d.DICOD_PREC_FP64), ("FP32", d.DICOD_PREC_FP32),
+                       ("MIXED", d.DICOD_PREC_MIXED)):
+        with d.Context(update_cap=args.cap, colors=args.colors, precision=prec) as c:
+            c.set_dictionary(D)
+            c.solve_device(Xd, -w.lam_rel, w.eps, args.n_seg, Zd, stream)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for _ in range(5):
+                _, st, _ = c.solve_device(Xd, -w.lam_rel, w.eps, args.n_seg, Zd, stream)
+            torch.cuda.synchronize()
+            variants[name] = {"time_to_eps_ms": 1e3 * (time.perf_counter() - t1) / 5,
+                              "n_updates": st["n_updates"], "t_init_ms": st["t_init_ms"],
+                              "round_updates": st["round_updates"][:3],
+                              "objective": st["objective"]}
+    out["precision_variants"] = variants
     if not args.no_sweep:
         sweep = []
         with d.Context(update_cap=args.cap, colors=args.colors) as c:

@@ -60,9 +60,12 @@ extern "C" {
  * FP32: beta init and the final check in double; the descent keeps g in
  *       float (Z in double) and is refreshed from a double recompute until
  *       the double-precision stop test holds.
- * MIXED: as FP32, but beta init uses split-bf16 MFMA with fp32 accumulation
- *       (three products hi*hi + hi*lo + lo*hi); lambda_max is made exact by
- *       recomputing the near-maximal entries in double.                    */
+ * MIXED: as FP32, but the float state starts from split-bf16 MFMA with fp32
+ *       accumulation (three products hi*hi + hi*lo + lo*hi); lambda_max is
+ *       made exact by recomputing the near-maximal entries in double, and the
+ *       double beta of the check is computed on a second stream during the
+ *       first descent round.  Served requests (dicod_submit) start from the
+ *       double beta in every policy.                                         */
 #define DICOD_PREC_FP64 0
 #define DICOD_PREC_FP32 1
 #define DICOD_PREC_MIXED 2

@@ -507,8 +507,6 @@ int solve_device_batch(dicod_ctx* ctx, int n_sig, const float* dX, const int64_t
         return fail(ctx, DICOD_EINVAL, "solve: NULL argument or n_sig <= 0");
     if (!(eps > 0.0) || !std::isfinite(eps))
         return fail(ctx, DICOD_EINVAL, "solve: eps must be finite and > 0");
-    if (ctx->cfg.precision == DICOD_PREC_MIXED)
-        return fail(ctx, DICOD_ENOTSUP, "solve: the MIXED policy is not available in this build");
     const int K = ctx->K, P = ctx->P, W = ctx->W;
     const bool fp64 = ctx->cfg.precision == DICOD_PREC_FP64;
     const dicod_config& cfg = ctx->cfg;
@@ -582,8 +580,8 @@ int solve_device_batch(dicod_ctx* ctx, int n_sig, const float* dX, const int64_t
                                           nL, ws.beta0.as<double>(), nullptr, nullptr,
                                           ctx->side));
         HIPCHECK(ctx, hipEventRecord(ctx->ev_beta, ctx->side));
-        HIPCHECK(ctx, launch_corr_f32(ctx->D32.as<float>(), K, P, W, dX, ws.sig.as<SigDesc>(),
-                                      ws.tilesL.as<int64_t>(), n_sig, nL, ws.g.as<float>(), s));
+        HIPCHECK(ctx, launch_corr_bf16x3(ctx->D32.as<float>(), K, P, W, dX, ws.sig.as<SigDesc>(),
+                                         ws.tilesL.as<int64_t>(), n_sig, nL, ws.g.as<float>(), s));
     }
     bool beta_waited = !fast_init;
     // ---- 2. lambda --------------------------------------------------------
@@ -987,8 +985,9 @@ extern "C" int dicod_correlate(dicod_ctx* ctx, const float* X, int64_t T, int pr
     const int K = ctx->K, P = ctx->P, W = ctx->W;
     if (T < W)
         return fail(ctx, DICOD_EINVAL, "dicod_correlate: T < W");
-    if (precision != DICOD_PREC_FP64)
-        return fail(ctx, DICOD_ENOTSUP, "dicod_correlate: precision %d not available", precision);
+    if (precision != DICOD_PREC_FP64 && precision != DICOD_PREC_MIXED)
+        return fail(ctx, DICOD_EINVAL, "dicod_correlate: precision %d is not FP64 or MIXED",
+                    precision);
     HIPCHECK(ctx, hipSetDevice(ctx->cfg.device));
     hipStream_t s = ctx->stream;
     const int64_t L = T - W + 1;
@@ -1007,6 +1006,18 @@ extern "C" int dicod_correlate(dicod_ctx* ctx, const float* X, int64_t T, int pr
     HIPCHECK(ctx, upload(dsig, sd, s));
     HIPCHECK(ctx, upload(dpref, pref, s));
     HIPCHECK(ctx, hipMemcpyAsync(dx.p, X, (size_t)P * T * sizeof(float), hipMemcpyHostToDevice, s));
+    if (precision == DICOD_PREC_MIXED) {
+        HIPCHECK(ctx, launch_corr_bf16x3(ctx->D32.as<float>(), K, P, W, dx.as<float>(),
+                                         dsig.as<SigDesc>(), dpref.as<int64_t>(), 1, pref[1],
+                                         dout.as<float>(), s));
+        std::vector<float> o32((size_t)K * L);
+        HIPCHECK(ctx, hipMemcpyAsync(o32.data(), dout.p, o32.size() * sizeof(float),
+                                     hipMemcpyDeviceToHost, s));
+        HIPCHECK(ctx, hipStreamSynchronize(s));
+        for (size_t i = 0; i < o32.size(); ++i)
+            out[i] = (double)o32[i];
+        return DICOD_OK;
+    }
     HIPCHECK(ctx, launch_corr_f64_x32(ctx->D64.as<double>(), K, P, W, dx.as<float>(),
                                       dsig.as<SigDesc>(), dpref.as<int64_t>(), 1, pref[1],
                                       dout.as<double>(), nullptr, nullptr, s));

@@ -77,11 +77,11 @@ hipError_t launch_corr_f64_x64(const double* D, int K, int P, int W,
                                const double* Y, const SigDesc* sig,
                                const int64_t* tile_pref, int n_sig,
                                int64_t n_tiles, double* out64, hipStream_t s);
-// Same contraction with split-bf16 MFMA (16x16x32 bf16, fp32 accumulation).
-hipError_t launch_corr_bf16x3(const float* Dhi_lo, int K, int P, int W,
-                              const float* Y, const SigDesc* sig,
-                              const int64_t* tile_pref, int n_sig, int64_t n_tiles,
-                              float* out32, hipStream_t s);
+// Same contraction in float with split bf16 on MFMA (16x16x32 bf16, fp32
+// accumulation of hi*hi + hi*lo + lo*hi); D float [K][P][W].
+hipError_t launch_corr_bf16x3(const float* D, int K, int P, int W, const float* Y,
+                              const SigDesc* sig, const int64_t* tile_pref, int n_sig,
+                              int64_t n_tiles, float* g32, hipStream_t s);
 
 // Dictionary finish: S32 = (float)S64, n2 = S64[k][k][W-1], inverses.
 hipError_t launch_dict_finish(const double* S64, int K, int W, float* S32,
@@ -145,10 +145,6 @@ hipError_t launch_grad_check(const double* beta0, const double* Z,
                              int64_t n_tiles, double flag_eps, const uint32_t* sig_done,
                              uint32_t* dirty, void* g_state, bool state_fp64,
                              const double* g_in, double* part6, hipStream_t s);
-// Float beta init on f32 MFMA (D float [K][P][W]).
-hipError_t launch_corr_f32(const float* D, int K, int P, int W, const float* Y,
-                           const SigDesc* sig, const int64_t* tile_pref, int n_sig,
-                           int64_t n_tiles, float* g32, hipStream_t s);
 hipError_t launch_check_reduce(const double* part_r2, const int64_t* tile_pref_T,
                                const double* part6, const int64_t* tile_pref_L,
                                int64_t n_tiles_L, int n_kblk, int n_sig,
@@ -164,7 +160,6 @@ hipError_t launch_refine_absmax(const float* beta32, const double* D, const floa
 hipError_t launch_absmax_f32(const float* beta, int K, const SigDesc* sig,
                              const int64_t* tile_pref, int n_sig, int64_t n_tiles,
                              unsigned long long* out_bits, hipStream_t s);
-hipError_t launch_split_bf16(const double* D, size_t n, float* hi_lo, hipStream_t s);
 
 // Serving: tab[slots[i]].lam = lam_in[i] (> 0) or -lam_in[i] * lambda_max[i].
 hipError_t launch_apply_lambda(SigDesc* tab, const int* slots, const double* lam_in,

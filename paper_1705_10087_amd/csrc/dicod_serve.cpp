@@ -9,7 +9,8 @@
 // with its own HIP stream and phase cadence, so that short requests do not
 // wait for the phases of long ones.  A lane admits its requests in arrival
 // order while a slot and the three ranges are free (admission by footprint).
-// An admitted request is initialised (beta at Z = 0 on MFMA, lambda, Z = 0)
+// An admitted request is initialised (beta at Z = 0 on double MFMA in every
+// precision policy, lambda, Z = 0)
 // and joins the coloured phases ("ticks") of the lane's running set: every
 // tick launches one phase kernel per state class over the segments of all
 // running requests that their own phase counter selects.
@@ -912,8 +913,6 @@ int server_submit(dicod_ctx* ctx, const float* X, int64_t T, double lambda, doub
     if (!X || !req_id)
         return ctx_fail(ctx, DICOD_EINVAL, "dicod_submit: NULL argument");
     const dicod_config& cfg = ctx_config(ctx);
-    if (cfg.precision == DICOD_PREC_MIXED)
-        return ctx_fail(ctx, DICOD_ENOTSUP, "dicod_submit: the MIXED policy is not available");
     if (T < W)
         return ctx_fail(ctx, DICOD_EINVAL, "dicod_submit: T < W");
     if (T > (int64_t)INT32_MAX / 2)

@@ -230,21 +230,48 @@ hipError_t launch_corr_f64_x64(const double* D, int K, int P, int W,
     return hipGetLastError();
 }
 
-// The same implicit-im2col correlation in float on v_mfma_f32_16x16x4f32:
-// the starting point of the float descent state (the double beta0 needed by
-// the double-precision check is computed separately).
+// The same implicit-im2col correlation with split bf16 on
+// v_mfma_f32_16x16x32_bf16 (MIXED policy): every float x is split into
+// hi = bf16(x) and lo = bf16(x - hi), and the products hi*hi + hi*lo + lo*hi
+// accumulate in fp32 (lo*lo, about 2^-16 of the rest, is dropped).  This is
+// the starting point of the float descent state; the double beta0 needed by
+// the double-precision check is computed separately.
 typedef float f4_t __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef unsigned short u16x8_t __attribute__((ext_vector_type(8)));
+
+constexpr int kBfRC = 64;       // reduction indices staged per pass (two MFMA k-steps)
+constexpr int kBfDStride = 72;  // ushort row stride of the staged atoms (16-byte rows)
+
+__device__ __forceinline__ unsigned short bf16_rne(float x)
+{
+    const unsigned u = __float_as_uint(x);
+    return (unsigned short)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+
+__device__ __forceinline__ float bf16_value(unsigned short h)
+{
+    return __uint_as_float((unsigned)h << 16);
+}
+
+static size_t corr_bf16_lds(int P, int W)
+{
+    return sizeof(unsigned short) *
+           (2 * 32 * (size_t)kBfDStride + 2 * (size_t)P * (kTile + W - 1));
+}
 
 __global__ void __launch_bounds__(256)
-k_corr_f32(const float* __restrict__ D, int K, int P, int W, const float* __restrict__ Y,
-           const SigDesc* __restrict__ sig, const int64_t* __restrict__ tile_pref, int n_sig,
-           float* __restrict__ g32)
+k_corr_bf16x3(const float* __restrict__ D, int K, int P, int W, const float* __restrict__ Y,
+              const SigDesc* __restrict__ sig, const int64_t* __restrict__ tile_pref,
+              int n_sig, float* __restrict__ g32)
 {
-    extern __shared__ float ldsf[];
+    extern __shared__ __align__(16) unsigned short lds16[];
     const int R = P * W;
     const int ystride = kTile + W - 1;
-    float* Dc = ldsf;                          // [32][kCorrDStride]
-    float* Ys = ldsf + 32 * kCorrDStride;      // [P][ystride]
+    unsigned short* Dh = lds16;                     // [32][kBfDStride]
+    unsigned short* Dl = Dh + 32 * kBfDStride;
+    unsigned short* Yh = Dl + 32 * kBfDStride;      // [P][ystride]
+    unsigned short* Yl = Yh + (size_t)P * ystride;
 
     const int64_t tile = blockIdx.x;
     const int si = find_sig(tile_pref, n_sig, tile);
@@ -259,7 +286,10 @@ k_corr_f32(const float* __restrict__ D, int K, int P, int W, const float* __rest
         const int p = i / ystride;
         const int u = i - p * ystride;
         const int64_t t = t_a + u;
-        Ys[i] = t < sd.T ? Y[sd.x_off + (int64_t)p * sd.T + t] : 0.f;
+        const float y = t < sd.T ? Y[sd.x_off + (int64_t)p * sd.T + t] : 0.f;
+        const unsigned short h = bf16_rne(y);
+        Yh[i] = h;
+        Yl[i] = bf16_rne(y - bf16_value(h));
     }
     f4_t acc[2][4];
 #pragma unroll
@@ -267,62 +297,103 @@ k_corr_f32(const float* __restrict__ D, int K, int P, int W, const float* __rest
 #pragma unroll
         for (int b = 0; b < 4; ++b)
             acc[a][b] = f4_t{0.f, 0.f, 0.f, 0.f};
+    // A[i][k] (atom i, reduction k) and B[k][j] (position j) sit in lane
+    // i (or j) + 16 * (k / 8), element k % 8.
     const int arow = lane & 15;
-    const int kk = lane >> 4;
-    for (int r0 = 0; r0 < R; r0 += kCorrRC) {
+    const int kq = lane >> 4;
+    for (int r0 = 0; r0 < R; r0 += kBfRC) {
         __syncthreads();
-        for (int i = tid; i < 32 * kCorrRC; i += 256) {
-            const int m = i / kCorrRC;
-            const int rr = i - m * kCorrRC;
+        for (int i = tid; i < 32 * kBfRC; i += 256) {
+            const int m = i / kBfRC;
+            const int rr = i - m * kBfRC;
             const int k = kbase + m;
             const int r = r0 + rr;
-            Dc[m * kCorrDStride + rr] = (k < K && r < R) ? D[(int64_t)k * R + r] : 0.f;
+            const float dv = (k < K && r < R) ? D[(int64_t)k * R + r] : 0.f;
+            const unsigned short h = bf16_rne(dv);
+            Dh[m * kBfDStride + rr] = h;
+            Dl[m * kBfDStride + rr] = bf16_rne(dv - bf16_value(h));
         }
         __syncthreads();
-        for (int ks = 0; ks < kCorrRC / 4; ++ks) {
-            if (r0 + ks * 4 >= R)
+#pragma unroll
+        for (int ks = 0; ks < kBfRC / 32; ++ks) {
+            if (r0 + ks * 32 >= R)
                 break;
-            const int rr = ks * 4 + kk;
-            const int r = r0 + rr;
-            const float a0 = Dc[arow * kCorrDStride + rr];
-            const float a1 = Dc[(16 + arow) * kCorrDStride + rr];
-            const bool valid = r < R;
-            const int p = valid ? r / W : 0;
-            const int tau = valid ? r - p * W : 0;
-            const float* yrow = Ys + p * ystride + wave * 64 + arow + tau;
+            const int rr0 = ks * 32 + 8 * kq;
+            const u16x8_t ah0 = *reinterpret_cast<const u16x8_t*>(Dh + arow * kBfDStride + rr0);
+            const u16x8_t al0 = *reinterpret_cast<const u16x8_t*>(Dl + arow * kBfDStride + rr0);
+            const u16x8_t ah1 =
+                *reinterpret_cast<const u16x8_t*>(Dh + (16 + arow) * kBfDStride + rr0);
+            const u16x8_t al1 =
+                *reinterpret_cast<const u16x8_t*>(Dl + (16 + arow) * kBfDStride + rr0);
+            // (p, tau) of the lane's 8 reduction indices
+            int off[8];
+            bool val[8];
+            {
+                const int r = r0 + rr0;
+                int p = r / W;
+                int tau = r - p * W;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    val[e] = r + e < R;
+                    off[e] = val[e] ? p * ystride + tau : 0;
+                    if (++tau == W) {
+                        tau = 0;
+                        ++p;
+                    }
+                }
+            }
 #pragma unroll
             for (int nt = 0; nt < 4; ++nt) {
-                const float bv = valid ? yrow[nt * 16] : 0.f;
-                acc[0][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, bv, acc[0][nt], 0, 0, 0);
-                acc[1][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, bv, acc[1][nt], 0, 0, 0);
+                const int base = wave * 64 + nt * 16 + arow;
+                u16x8_t bh, bl;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    bh[e] = val[e] ? Yh[off[e] + base] : (unsigned short)0;
+                    bl[e] = val[e] ? Yl[off[e] + base] : (unsigned short)0;
+                }
+                const bf16x8_t bhv = __builtin_bit_cast(bf16x8_t, bh);
+                const bf16x8_t blv = __builtin_bit_cast(bf16x8_t, bl);
+                acc[0][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                    __builtin_bit_cast(bf16x8_t, ah0), bhv, acc[0][nt], 0, 0, 0);
+                acc[0][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                    __builtin_bit_cast(bf16x8_t, ah0), blv, acc[0][nt], 0, 0, 0);
+                acc[0][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                    __builtin_bit_cast(bf16x8_t, al0), bhv, acc[0][nt], 0, 0, 0);
+                acc[1][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                    __builtin_bit_cast(bf16x8_t, ah1), bhv, acc[1][nt], 0, 0, 0);
+                acc[1][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                    __builtin_bit_cast(bf16x8_t, ah1), blv, acc[1][nt], 0, 0, 0);
+                acc[1][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                    __builtin_bit_cast(bf16x8_t, al1), bhv, acc[1][nt], 0, 0, 0);
             }
         }
     }
-    // C[i][j] of a 16x16 f32 MFMA tile sits in lane (i / 4) * 16 + j, item i % 4.
+    // C[i][j] of a 16x16 f32-accumulating MFMA tile sits in lane (i / 4) * 16 + j,
+    // item i % 4 (measured on gfx950).
 #pragma unroll
     for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
         for (int nt = 0; nt < 4; ++nt)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int k = kbase + mi * 16 + 4 * kk + v;
+                const int k = kbase + mi * 16 + 4 * kq + v;
                 const int64_t t = t_a + wave * 64 + nt * 16 + arow;
                 if (k < K && t < sd.L)
                     g32[sd.z_off + (int64_t)k * sd.L + t] = acc[mi][nt][v];
             }
 }
 
-hipError_t launch_corr_f32(const float* D, int K, int P, int W, const float* Y,
-                           const SigDesc* sig, const int64_t* tile_pref, int n_sig,
-                           int64_t n_tiles, float* g32, hipStream_t s)
+hipError_t launch_corr_bf16x3(const float* D, int K, int P, int W, const float* Y,
+                              const SigDesc* sig, const int64_t* tile_pref, int n_sig,
+                              int64_t n_tiles, float* g32, hipStream_t s)
 {
-    const size_t lds = sizeof(float) * (32 * kCorrDStride + (size_t)P * (kTile + W - 1));
+    const size_t lds = corr_bf16_lds(P, W);
     if (lds > kLdsBytes)
         return hipErrorInvalidValue;
-    (void)hipFuncSetAttribute((const void*)k_corr_f32,
+    (void)hipFuncSetAttribute((const void*)k_corr_bf16x3,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     dim3 grid((unsigned)n_tiles, (unsigned)((K + 31) / 32));
-    hipLaunchKernelGGL(k_corr_f32, grid, dim3(256), lds, s, D, K, P, W, Y, sig, tile_pref,
+    hipLaunchKernelGGL(k_corr_bf16x3, grid, dim3(256), lds, s, D, K, P, W, Y, sig, tile_pref,
                        n_sig, g32);
     return hipGetLastError();
 }

@@ -119,6 +119,43 @@ def test_fp64_trajectory_matches_oracle(dicod, M, cap, lds, C, seed):
     assert abs(st["objective"] - Eo) <= 1e-10 * Eo
 
 
+# ------------------------------------- MIXED: split-bf16 beta at Z = 0
+
+@pytest.mark.parametrize("K,P,W,T", [(5, 1, 32, 4096), (37, 3, 17, 1013), (25, 7, 200, 150_000),
+                                     (2, 1, 1, 300), (4, 2, 9, 9)])
+def test_beta_init_split_bf16_error_bound(dicod, K, P, W, T):
+    """bf16 rounding to nearest has unit roundoff u = 2^-8.  Split bf16 keeps
+    hi = bf16(x) and lo = bf16(x - hi): |lo| <= u |x| and |x - hi - lo| <= u^2 |x|,
+    so hi_d hi_x + hi_d lo_x + lo_d hi_x misses at most (3 u^2 + O(u^3)) |d x| of
+    each product (lo_d lo_x and the two remainders), and fp32 accumulation of the
+    P W terms adds at most P W 2^-24 of their absolute sum:
+    |beta_mixed - beta| <= (3.1 * 2^-16 + P W 2^-24) sum |d| |x|."""
+    print(f"\ncase: split-bf16 beta K={K} P={P} W={W} T={T}", flush=True)
+    X, D, _ = synth.generate(P, K, W, T, 0.01, 0.1, seed=T + 1)
+    with ctx_of(dicod) as c:
+        c.set_dictionary(D)
+        B = c.correlate(X, precision=dicod.DICOD_PREC_MIXED)
+    Bo = oracle.correlate(f64(D), f64(X))
+    A = oracle.correlate(np.abs(f64(D)), np.abs(f64(X)))
+    bound = (3.1 * 2.0 ** -16 + P * W * 2.0 ** -24) * A + 1e-30
+    err = np.abs(B - Bo)
+    print(f"max error / bound {np.max(err / bound):.3f}, max rel to sum|dx| "
+          f"{np.max(err / (A + 1e-30)):.3g}", flush=True)
+    assert np.all(err <= bound)
+
+
+def test_paper_shaped_mixed_matches_oracle(dicod, paper_problem):
+    print("\ncase: MIXED paper-shaped P=7 K=25 W=200 T=150000", flush=True)
+    X, D, lam, Zo = paper_problem
+    with ctx_of(dicod, precision=dicod.DICOD_PREC_MIXED) as c:
+        Z, st = c.solve(X, -0.1, EPS, n_seg=0, D=D)
+    print(f"gpu: {st['n_updates']} updates, rounds {st['round_updates']}, "
+          f"init {st['t_init_ms']:.3f} cd {st['t_cd_ms']:.3f} verify {st['t_verify_ms']:.3f} ms",
+          flush=True)
+    assert abs(st["lambda"] - lam) <= 1e-12 * lam   # exact lambda_max refinement
+    _check_solution(X, D, lam, Z, st, Zo)
+
+
 # ------------------------------------------------ FP32 policy: eps-solutions
 
 def _check_solution(X, D, lam, Z, st, Zo):
@@ -225,7 +262,7 @@ def test_lambda_at_lambda_max_gives_zero(dicod):
     assert st["objective"] == pytest.approx(0.5 * float(np.sum(f64(X) ** 2)), rel=1e-12)
 
 
-@pytest.mark.parametrize("prec", ["FP64", "FP32"])
+@pytest.mark.parametrize("prec", ["FP64", "FP32", "MIXED"])
 @pytest.mark.parametrize("K,P,W,T,M", [
     (1, 1, 8, 8, 1),          # L = 1
     (3, 2, 5, 200, 1),        # single segment, generic K
