@@ -19,6 +19,7 @@ _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
 SCHED_EVENODD = 0
 SCHED_SEQUENCE = 1
+SCHED_DICOD = 2
 
 
 class OracleStats(ctypes.Structure):
@@ -31,6 +32,10 @@ class OracleStats(ctypes.Structure):
         ("dE_min", ctypes.c_double),
         ("lowerbound_gap_min", ctypes.c_double),
         ("converged", ctypes.c_int),
+        ("n_messages", ctypes.c_int64),
+        ("n_interf", ctypes.c_int64),
+        ("n_adjacent", ctypes.c_int64),
+        ("interf_sum", ctypes.c_double),
     ]
 
 
@@ -208,8 +213,10 @@ def max_dz(X, D, Z, lam):
 
 def lgcd(X, D, lam, eps, M, schedule=SCHED_EVENODD, seq=None, cap=0,
          max_steps=10**9, trace_cap=0, colors=2):
-    """Locally greedy CD (Algorithm 3; coloured phases (2 = even/odd) or a given
-    segment order).
+    """Locally greedy CD: Algorithm 3 with coloured phases (SCHED_EVENODD,
+    2 colours = even/odd) or a given segment order (SCHED_SEQUENCE), or
+    Algorithm 2 with the cores in lockstep and messages delivered one phase
+    later (SCHED_DICOD; the stats count interfering concurrent updates).
 
     Returns (Z, stats dict, trace array or None).  Raises on bad arguments;
     stats['converged'] tells whether the stop test was met.

@@ -268,17 +268,24 @@ int oracle_beta_at(const double *X, const double *D, const double *Z, int K, int
 /* Solver                                                                     */
 /* ------------------------------------------------------------------------ */
 
-enum { ORACLE_SCHED_EVENODD = 0, ORACLE_SCHED_SEQUENCE = 1 };
+enum { ORACLE_SCHED_EVENODD = 0, ORACLE_SCHED_SEQUENCE = 1, ORACLE_SCHED_DICOD = 2 };
 
 typedef struct {
     int64_t n_updates;   /* coordinate updates applied                        */
     int64_t n_steps;     /* segment selections (Algorithm 3 iterations)       */
-    int64_t n_phases;    /* even/odd phases run (even/odd schedule only)      */
+    int64_t n_phases;    /* phases run (phase schedules only)                 */
     int64_t n_full_checks; /* O(KL) stopping checks (sequence schedule)       */
     double dE_sum;       /* sum of the per-update cost decreases, Prop. A.1   */
     double dE_min;       /* smallest single-update cost decrease              */
     double lowerbound_gap_min; /* min over updates of dE - |D|^2 delta^2 / 2   */
     int converged;
+    int64_t n_messages;  /* DICOD: (k0, t0, delta) messages sent              */
+    int64_t n_interf;    /* DICOD: pairs of concurrent updates of adjacent    */
+                         /* segments with |t0 - t1| < W (Sec. 3, interferences) */
+    int64_t n_adjacent;  /* DICOD: pairs of concurrent updates of adjacent    */
+                         /* segments (any distance)                           */
+    double interf_sum;   /* DICOD: sum of S_{k0,k1}[t0 - t1] d0 d1 over the   */
+                         /* interfering pairs (Prop. A.2)                     */
 } oracle_stats;
 
 typedef struct {
@@ -350,6 +357,53 @@ static double apply_update(lgcd_state *s, int k0, int64_t t0, double z_new)
     return dE;
 }
 
+/* Algorithm 2, own part of an update: as apply_update, with the eq. (3)
+ * change of beta restricted to the segment [b, e) of the core that made it. */
+static double apply_update_local(lgcd_state *s, int k0, int64_t t0, double z_new,
+                                 int64_t b, int64_t e)
+{
+    const int W = s->W, K = s->K, nd = 2 * W - 1;
+    int64_t i0 = (int64_t)k0 * s->L + t0;
+    double z_old = s->Z[i0];
+    double b0 = s->beta[i0];
+    double delta = z_new - z_old;
+    double dE = 0.5 * s->n2[k0] * (z_old * z_old - z_new * z_new) -
+                b0 * (z_old - z_new) + s->lam * (fabs(z_old) - fabs(z_new));
+    s->Z[i0] = z_new;
+    int64_t lo = t0 - (W - 1) < b ? b : t0 - (W - 1);
+    int64_t hi = t0 + (W - 1) > e - 1 ? e - 1 : t0 + (W - 1);
+    for (int k = 0; k < K; ++k) {
+        const double *Srow = s->S + IDX3(k, k0, 0, K, nd);
+        for (int64_t t = lo; t <= hi; ++t) {
+            if (k == k0 && t == t0)
+                continue;
+            s->beta[(int64_t)k * s->L + t] -= Srow[t - t0 + W - 1] * delta;
+        }
+    }
+    return dE;
+}
+
+/* Algorithm 2, receiving side: the eq. (3) change of beta that the message
+ * (k0, t0, delta) of a neighbour makes on the segment [b, e). */
+static void apply_message(lgcd_state *s, int k0, int64_t t0, double delta, int64_t b,
+                          int64_t e)
+{
+    const int W = s->W, K = s->K, nd = 2 * W - 1;
+    int64_t lo = t0 - (W - 1) < b ? b : t0 - (W - 1);
+    int64_t hi = t0 + (W - 1) > e - 1 ? e - 1 : t0 + (W - 1);
+    for (int k = 0; k < K; ++k) {
+        const double *Srow = s->S + IDX3(k, k0, 0, K, nd);
+        for (int64_t t = lo; t <= hi; ++t)
+            s->beta[(int64_t)k * s->L + t] -= Srow[t - t0 + W - 1] * delta;
+    }
+}
+
+typedef struct {
+    int k0;
+    int64_t t0;
+    double delta;
+} dicod_msg;
+
 static void note_update(oracle_stats *st, double dE, double n2, double delta)
 {
     st->n_updates++;
@@ -379,6 +433,116 @@ static void record(oracle_trace_rec *tr, int64_t cap, const oracle_stats *st,
     tr[i].dE = dE;
 }
 
+/* The ORACLE_SCHED_DICOD schedule of oracle_lgcd (see there). */
+static int dicod_lockstep(lgcd_state *s, int M, const int64_t *bnd, int cap, double eps,
+                          int64_t max_steps, oracle_stats *st, oracle_trace_rec *trace,
+                          int64_t trace_cap)
+{
+    const int W = s->W, K = s->K, nd = 2 * W - 1;
+    const int64_t L = s->L;
+    const int per = cap > 0 ? cap : (int)(L < 65536 ? L : 65536);
+    /* inbox[m][0]: messages from m - 1, inbox[m][1]: from m + 1, for the
+     * current phase; outbox the same for the next phase */
+    dicod_msg *in = (dicod_msg *)malloc(sizeof(dicod_msg) * (size_t)M * 2 * per);
+    dicod_msg *out = (dicod_msg *)malloc(sizeof(dicod_msg) * (size_t)M * 2 * per);
+    int *n_in = (int *)calloc((size_t)M * 2, sizeof(int));
+    int *n_out = (int *)calloc((size_t)M * 2, sizeof(int));
+    unsigned char *dirty = (unsigned char *)malloc((size_t)M);
+    unsigned char *next = (unsigned char *)malloc((size_t)M);
+    /* this phase's updates per segment, for the interference statistics */
+    dicod_msg *upd = (dicod_msg *)malloc(sizeof(dicod_msg) * (size_t)M * per);
+    int *n_upd = (int *)calloc((size_t)M, sizeof(int));
+    int rc = 1;
+    if (!in || !out || !n_in || !n_out || !dirty || !next || !upd || !n_upd) {
+        rc = -3;
+        goto done;
+    }
+    memset(dirty, 1, (size_t)M);
+    for (int64_t p = 0; st->n_updates < max_steps; ++p) {
+        memset(next, 0, (size_t)M);
+        memset(n_out, 0, sizeof(int) * (size_t)M * 2);
+        int64_t phase_upd = 0;
+        for (int m = 0; m < M; ++m) {
+            n_upd[m] = 0;
+            if (!dirty[m])
+                continue;
+            st->n_steps++;
+            const int64_t b = bnd[m], e = bnd[m + 1];
+            for (int side = 0; side < 2; ++side)
+                for (int i = 0; i < n_in[2 * m + side]; ++i) {
+                    const dicod_msg *g = &in[((size_t)m * 2 + side) * per + i];
+                    apply_message(s, g->k0, g->t0, g->delta, b, e);
+                }
+            int n = 0;
+            for (;;) {
+                int k0 = 0;
+                int64_t t0 = 0;
+                double zn = 0.0;
+                double d = local_argmax(s, b, e, &k0, &t0, &zn);
+                if (d < eps)
+                    break;
+                if (n == per) {
+                    next[m] = 1;
+                    break;
+                }
+                if (st->n_updates >= max_steps)
+                    break;
+                double z_old = s->Z[(int64_t)k0 * L + t0];
+                double dE = apply_update_local(s, k0, t0, zn, b, e);
+                note_update(st, dE, s->n2[k0], zn - z_old);
+                record(trace, trace_cap, st, (int)p, m, k0, n, t0, z_old, zn, dE);
+                dicod_msg msg = {k0, t0, zn - z_old};
+                upd[(size_t)m * per + n] = msg;
+                ++n;
+                if (m > 0 && t0 - (W - 1) < b) { /* window reaches m - 1 */
+                    out[((size_t)(m - 1) * 2 + 1) * per + n_out[2 * (m - 1) + 1]++] = msg;
+                    next[m - 1] = 1;
+                    st->n_messages++;
+                }
+                if (m < M - 1 && t0 + (W - 1) >= e) { /* window reaches m + 1 */
+                    out[((size_t)(m + 1) * 2) * per + n_out[2 * (m + 1)]++] = msg;
+                    next[m + 1] = 1;
+                    st->n_messages++;
+                }
+            }
+            n_upd[m] = n;
+            phase_upd += n;
+        }
+        /* interferences: concurrent updates of adjacent segments (Prop. A.2) */
+        for (int m = 0; m + 1 < M; ++m)
+            for (int i = 0; i < n_upd[m]; ++i)
+                for (int j = 0; j < n_upd[m + 1]; ++j) {
+                    const dicod_msg *u = &upd[(size_t)m * per + i];
+                    const dicod_msg *v = &upd[(size_t)(m + 1) * per + j];
+                    st->n_adjacent++;
+                    const int64_t dt = u->t0 - v->t0;
+                    if (dt <= -W || dt >= W)
+                        continue;
+                    st->n_interf++;
+                    st->interf_sum += s->S[IDX3(u->k0, v->k0, dt + W - 1, K, nd)] *
+                                      u->delta * v->delta;
+                }
+        st->n_phases = p + 1;
+        { dicod_msg *t = in; in = out; out = t; }
+        { int *t = n_in; n_in = n_out; n_out = t; }
+        { unsigned char *t = dirty; dirty = next; next = t; }
+        if (phase_upd == 0) {
+            rc = 0;
+            break;
+        }
+    }
+done:
+    free(in);
+    free(out);
+    free(n_in);
+    free(n_out);
+    free(dirty);
+    free(next);
+    free(upd);
+    free(n_upd);
+    return rc;
+}
+
 /*
  * Locally greedy coordinate descent.
  *
@@ -400,6 +564,18 @@ static void record(oracle_trace_rec *tr, int64_t cap, const oracle_stats *st,
  *   at least (2W - 2) / (C - 1) long, so segments of one colour never touch the
  *   same beta entries and each phase equals running its segments one after the
  *   other.  The run stops after C consecutive phases without updates.
+ *
+ * schedule = ORACLE_SCHED_DICOD: Algorithm 2 with the cores in lockstep.  In
+ *   phase p every segment that is dirty (it stopped on the cap, or received
+ *   messages) first applies the messages its neighbours sent in phase p - 1
+ *   (left neighbour first, each in the order sent), then runs locally greedy
+ *   updates from its own beta (up to `cap`), changing beta on its own
+ *   positions only; an update whose window reaches a neighbour is sent to it
+ *   as (k0, t0, delta) (the paper's messages, delivered one phase later).
+ *   Segments are at least W long, so a window reaches only the adjacent
+ *   segments.  Updates of adjacent segments in one phase may interfere
+ *   (Sec. 3, Prop. A.2); the statistics count them.  The run stops after a
+ *   phase without updates (then no message is pending).
  *
  * Returns 0 when converged, 1 when max_steps (updates) or max_phases ran out,
  * negative on bad arguments.
@@ -426,6 +602,8 @@ int oracle_lgcd(const double *X, const double *D, int K, int P, int W, int64_t T
     }
     if (schedule == ORACLE_SCHED_SEQUENCE && (!seq || seq_len <= 0))
         return -1;
+    if (schedule == ORACLE_SCHED_DICOD && M > 1 && L / M < W)
+        return -2;
     const int nd = 2 * W - 1;
 
     double *S = (double *)malloc(sizeof(double) * (size_t)K * K * nd);
@@ -538,6 +716,8 @@ int oracle_lgcd(const double *X, const double *D, int K, int P, int W, int64_t T
             }
         }
         free(dirty);
+    } else if (schedule == ORACLE_SCHED_DICOD) {
+        rc = dicod_lockstep(&s, M, bnd, cap, eps, max_steps, &local, trace, trace_cap);
     } else {
         rc = -1;
     }

@@ -48,6 +48,12 @@ MUTANTS = [
     ("objective_half_dropped",
      "return 0.5 * quad + lam * l1;",
      "return quad + lam * l1;"),
+    ("interference_lag_reversed",
+     "st->interf_sum += s->S[IDX3(u->k0, v->k0, dt + W - 1, K, nd)] *",
+     "st->interf_sum += s->S[IDX3(u->k0, v->k0, -dt + W - 1, K, nd)] *"),
+    ("message_sent_to_wrong_side",
+     "out[((size_t)(m + 1) * 2) * per + n_out[2 * (m + 1)]++] = msg;",
+     "out[((size_t)(m + 1) * 2 + 1) * per + n_out[2 * (m + 1)]++] = msg;"),
 ]
 
 
@@ -67,6 +73,8 @@ def _pins():
         lambda: [pins.test_golden_two_coordinate_lasso(r) for r in rows],
         lambda: pins.test_tiny_brute_force_explicit_toeplitz_lasso(0),
         lambda: pins.test_kkt_conditions_at_solution(),
+        lambda: pins.test_dicod_schedule_cost_identity(1, 4, 3),
+        lambda: pins.test_dicod_schedule_interferes_and_converges(),
     ]
 
 

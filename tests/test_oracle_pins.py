@@ -340,3 +340,86 @@ def test_bad_arguments_rejected():
         oracle.lgcd(X, D, 1.0, 0.0, 1)
     with pytest.raises(ValueError):        # segments shorter than 2W
         oracle.lgcd(X, D, 1.0, 1e-6, 8)
+
+
+# ------------------------------------------- Algorithm 2 in lockstep (DICOD)
+
+def test_prop_a2_two_concurrent_updates():
+    # Prop. A.2: two coordinates moved from the same Z to their own optimal
+    # values change the cost by dE0 + dE1 - S_{k0,k1}[t0 - t1] d0 d1 (each dE
+    # of Prop. A.1 measured alone), checked against the objective directly.
+    X, D, Zt = tiny_problem(9, P=2, K=3, W=6, T=40, rho=0.2)
+    K, P, W = D.shape
+    L = Zt.shape[0 + 1]
+    lam = 0.1 * oracle.lambda_max(X, D)
+    S = oracle.s_table(D)
+    n2 = oracle.norms(D)
+    rng = np.random.default_rng(3)
+    Z = 0.5 * Zt + 0.05 * rng.standard_normal(Zt.shape)
+    B = oracle.beta(X, D, Z)
+    E0 = oracle.objective(X, D, Z, lam)
+    checked = 0
+    for _ in range(40):
+        k0, k1 = rng.integers(0, K, 2)
+        t0 = int(rng.integers(0, L))
+        t1 = int(np.clip(t0 + rng.integers(-W + 1, W), 0, L - 1))
+        if (k0, t0) == (k1, t1):
+            continue
+        z0 = oracle.soft_threshold(B[k0, t0], lam) / n2[k0]
+        z1 = oracle.soft_threshold(B[k1, t1], lam) / n2[k1]
+        d0, d1 = z0 - Z[k0, t0], z1 - Z[k1, t1]
+        Za, Zb, Zab = Z.copy(), Z.copy(), Z.copy()
+        Za[k0, t0] = z0
+        Zb[k1, t1] = z1
+        Zab[k0, t0], Zab[k1, t1] = z0, z1
+        dE0 = E0 - oracle.objective(X, D, Za, lam)
+        dE1 = E0 - oracle.objective(X, D, Zb, lam)
+        dE01 = E0 - oracle.objective(X, D, Zab, lam)
+        pred = dE0 + dE1 - S[k0, k1, t0 - t1 + W - 1] * d0 * d1
+        assert abs(dE01 - pred) <= 1e-9 * max(1.0, abs(dE01)), (k0, t0, k1, t1)
+        checked += abs(t0 - t1) > 0 and abs(d0 * d1) > 0
+    assert checked > 10
+
+
+@pytest.mark.parametrize("seed,M,cap", [(0, 4, 1), (1, 4, 3), (2, 8, 1), (3, 5, 0)])
+def test_dicod_schedule_cost_identity(seed, M, cap):
+    # In a lockstep phase every core picks its update from its own beta; the
+    # total cost decrease is the sum of the single-update decreases (Prop. A.1,
+    # each on the state its core saw) minus the interference terms of all
+    # concurrent pairs of adjacent cores within W (Prop. A.2, every pair).
+    X, D, _ = tiny_problem(seed, P=2, K=3, W=6, T=6 * M + 5 + 6 * 6, rho=0.15)
+    lam = 0.08 * oracle.lambda_max(X, D)
+    Z, st, _ = oracle.lgcd(X, D, lam, 1e-9, M, schedule=oracle.SCHED_DICOD, cap=cap)
+    assert st["converged"] == 1
+    E0 = oracle.objective(X, D, np.zeros_like(Z), lam)
+    E1 = oracle.objective(X, D, Z, lam)
+    assert abs((E0 - E1) - (st["dE_sum"] - st["interf_sum"])) <= 1e-9 * (E0 - E1)
+    assert st["n_interf"] <= st["n_adjacent"]
+
+
+def test_dicod_schedule_interferes_and_converges():
+    # Short segments make concurrent neighbouring updates interfere; the run
+    # still reaches an eps-solution (Theorem 1 under H1), the same optimum as
+    # the sequential schedule.
+    X, D, _ = tiny_problem(4, P=2, K=3, W=8, T=200, rho=0.1)
+    lam = 0.05 * oracle.lambda_max(X, D)
+    Zd, sd, _ = oracle.lgcd(X, D, lam, 1e-10, 20, schedule=oracle.SCHED_DICOD, cap=1)
+    Zs, ss, _ = oracle.lgcd(X, D, lam, 1e-10, 20, cap=1, colors=3)
+    assert sd["converged"] == 1 and sd["n_interf"] > 0
+    mdz, _, _ = oracle.max_dz(X, D, Zd, lam)
+    assert mdz < 1e-10
+    Ed, Es = oracle.objective(X, D, Zd, lam), oracle.objective(X, D, Zs, lam)
+    assert abs(Ed - Es) <= 1e-9 * Es
+    np.testing.assert_allclose(Zd, Zs, rtol=0, atol=1e-6 * np.abs(Zs).max())
+
+
+def test_dicod_single_core_is_greedy_cd():
+    # M = 1: no neighbour, no message; Algorithm 2 reduces to Algorithm 1.
+    X, D, _ = tiny_problem(5, P=2, K=2, W=4, T=30, rho=0.15)
+    lam = 0.1 * oracle.lambda_max(X, D)
+    Za, sa, ta = oracle.lgcd(X, D, lam, 1e-9, 1, schedule=oracle.SCHED_DICOD, cap=1,
+                             trace_cap=200)
+    Zb, sb, tb = oracle.lgcd(X, D, lam, 1e-9, 1, cap=1, trace_cap=200)
+    assert sa["n_messages"] == 0 and sa["n_interf"] == 0
+    np.testing.assert_array_equal(ta[["k0", "t0"]], tb[["k0", "t0"]])
+    np.testing.assert_array_equal(Za, Zb)
