@@ -70,6 +70,32 @@ def cpu_baseline(X, D, lam, eps, M, cap, colors):
                       f"schedule ({colors} colours, M={M}, update cap {cap}), single thread"}
 
 
+def ms_per_step_of(stats, wall, steps):
+    return 1e3 * wall / steps
+
+
+def s_last(stats):
+    return stats[-1]
+
+
+def adjacent_pairs(tr, W):
+    """Updates of one phase in adjacent segments: pairs, and pairs closer than
+    W (interfering, Sec. 3)."""
+    by = {}
+    for p, m, t in zip(tr["phase"], tr["seg"], tr["t0"]):
+        by.setdefault((int(p), int(m)), []).append(int(t))
+    n_adj = n_int = 0
+    for (p, m), us in by.items():
+        vs = by.get((p, m + 1))
+        if not vs:
+            continue
+        vs = np.asarray(vs)
+        for u in us:
+            n_adj += vs.size
+            n_int += int(np.count_nonzero(np.abs(u - vs) < W))
+    return n_adj, n_int
+
+
 def _gen_signal(job):
     import synth
     P, K, W, T, rho, sigma, seed, D = job
@@ -402,6 +428,36 @@ def main():
                               "round_updates": st["round_updates"][:3],
                               "objective": st["objective"]}
     out["precision_variants"] = variants
+    # Algorithm 2 in lockstep (DICOD schedule) against the coloured schedule:
+    # time-to-eps, and the interference rate from a traced solve
+    sched = {"coloured": {"time_to_eps_ms": ms_per_step_of(stats, wall, args.steps),
+                          "n_updates": s_last(stats)["n_updates"],
+                          "n_phases": s_last(stats)["n_phases"]}}
+    with d.Context(schedule=d.DICOD_SCHED_DICOD, update_cap=1) as c:
+        c.set_dictionary(D)
+        c.solve_device(Xd, -w.lam_rel, w.eps, args.n_seg, Zd, stream)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(5):
+            _, st, _ = c.solve_device(Xd, -w.lam_rel, w.eps, args.n_seg, Zd, stream)
+        torch.cuda.synchronize()
+        t_dicod = 1e3 * (time.perf_counter() - t1) / 5
+    with d.Context(schedule=d.DICOD_SCHED_DICOD, update_cap=1, trace_capacity=400_000) as c:
+        c.set_dictionary(D)
+        _, stt, _ = c.solve_device(Xd, -w.lam_rel, w.eps, args.n_seg, Zd, stream)
+        torch.cuda.synchronize()
+        tr = c.trace()
+    first = tr[tr["phase"] < stt["round_phases"][0]]   # first (float) round
+    n_adj, n_int = adjacent_pairs(first, W)
+    Lm = (T - W + 1) / stt["n_seg"]
+    sched["dicod_lockstep"] = {
+        "time_to_eps_ms": t_dicod, "n_updates": st["n_updates"], "n_phases": st["n_phases"],
+        "update_cap": 1, "n_seg": stt["n_seg"],
+        "first_round": {"adjacent_concurrent_pairs": n_adj, "interfering_pairs": n_int,
+                        "interference_rate": n_int / max(n_adj, 1),
+                        "model_paper_(MW/T)^2": min(1.0, (W / Lm) ** 2),
+                        "model_uniform_W^2/(2 L_M^2)": min(1.0, W * W / (2 * Lm * Lm))}}
+    out["schedules"] = sched
     if not args.no_sweep:
         sweep = []
         with d.Context(update_cap=args.cap, colors=args.colors) as c:

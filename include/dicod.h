@@ -71,7 +71,21 @@ extern "C" {
 #define DICOD_PREC_MIXED 2
 
 /* ---- schedules --------------------------------------------------------- */
+/* EVENODD: coloured phases (cfg.colors classes; 2 = even/odd): segments of one
+ *          colour run at the same time and write their neighbours' state
+ *          directly, so every phase is a sequential order (Algorithm 3).
+ * DICOD:   Algorithm 2 with the segments in lockstep: in every phase all
+ *          segments with work run at once from their own beta, each keeping
+ *          only its own positions; an update whose window reaches a
+ *          neighbour is sent to it as (k0, t0, delta) and applied there at
+ *          the start of the next phase.  Concurrent updates of adjacent
+ *          segments may interfere (Sec. 3, Prop. A.2).  Segments must be
+ *          >= W long and fit the on-chip kernel; update_cap in 1..1024 is
+ *          the number of updates per segment and phase (1 keeps the message
+ *          delay below one update time, hypothesis H3).  dicod_submit always
+ *          uses the coloured schedule. */
 #define DICOD_SCHED_EVENODD 0
+#define DICOD_SCHED_DICOD 1
 
 typedef struct dicod_ctx dicod_ctx;
 

@@ -28,6 +28,7 @@ DICOD_PREC_FP64 = 0
 DICOD_PREC_FP32 = 1
 DICOD_PREC_MIXED = 2
 DICOD_SCHED_EVENODD = 0
+DICOD_SCHED_DICOD = 1
 
 _CODES = {v: k for k, v in dict(globals()).items() if k.startswith("DICOD_E")}
 

@@ -68,6 +68,7 @@ struct Workspace {
     DevBuf tilesL, tilesT, tilesA;
     DevBuf dirty, phase_upd, sig_upd, sig_last, counters;
     DevBuf part_r2, part6, results, lmax, done, thr;
+    DevBuf msg, msg_n;                    // DICOD schedule: boundary messages
     DevBuf trace;
 };
 
@@ -137,6 +138,8 @@ double now_ms()
 // adjacent segments.
 int64_t min_segment(int W, int C)
 {
+    if (C <= 1)  // Algorithm 2: a window may only reach the adjacent segments
+        return W;
     const int64_t gap = (2 * (int64_t)W - 2 + (C - 2)) / (C - 1);
     return std::max<int64_t>(W, gap);
 }
@@ -192,8 +195,11 @@ extern "C" int dicod_init(dicod_ctx** out, const dicod_config* cfg)
         dicod_config_init(&c);
     if (c.precision < DICOD_PREC_FP64 || c.precision > DICOD_PREC_MIXED)
         return fail(nullptr, DICOD_EINVAL, "dicod_init: unknown precision %d", c.precision);
-    if (c.schedule != DICOD_SCHED_EVENODD)
+    if (c.schedule != DICOD_SCHED_EVENODD && c.schedule != DICOD_SCHED_DICOD)
         return fail(nullptr, DICOD_EINVAL, "dicod_init: unknown schedule %d", c.schedule);
+    if (c.schedule == DICOD_SCHED_DICOD && (c.update_cap < 1 || c.update_cap > 1024))
+        return fail(nullptr, DICOD_EINVAL,
+                    "dicod_init: the DICOD schedule needs update_cap in 1..1024");
     if (c.update_cap < 0 || c.max_phases < 2 || c.max_refresh < 0 ||
         c.phases_per_poll < 1 || !(c.inner_eps_factor > 0.0 && c.inner_eps_factor <= 1.0) ||
         c.trace_capacity < 0 || c.max_inflight < 1 || c.fp64_polish_after < 0 ||
@@ -377,7 +383,8 @@ struct Plan {
     std::vector<SigDesc> sig;
     std::vector<SegDesc> segs;
     std::vector<int32_t> list[kMaxColors];
-    int colors = 2;
+    int colors = 2;   // phase classes; 1 for the DICOD schedule (all segments)
+    bool dicod = false;
     std::vector<int64_t> prefL, prefT, prefA;
     int lm_max = 0, lext_max = 0;
     size_t zext = 0;  // extent of the [K][L] arrays (elements)
@@ -403,7 +410,8 @@ int make_plan(dicod_ctx* ctx, int n_sig, const int64_t* T, const int64_t* x_off,
     const int K = ctx->K, W = ctx->W;
     const bool fp64 = ctx->cfg.precision == DICOD_PREC_FP64;
     (void)K;
-    pl.colors = ctx->cfg.colors;
+    pl.dicod = ctx->cfg.schedule == DICOD_SCHED_DICOD;
+    pl.colors = pl.dicod ? 1 : ctx->cfg.colors;
     pl.sig.resize(n_sig);
     pl.prefL.assign(n_sig + 1, 0);
     pl.prefT.assign(n_sig + 1, 0);
@@ -431,7 +439,7 @@ int make_plan(dicod_ctx* ctx, int n_sig, const int64_t* T, const int64_t* x_off,
                         "(W=%d, %d colours)", i, M, (long long)(L / M),
                         (long long)min_segment(W, pl.colors), W, pl.colors);
         const int64_t lm = ceil_div(L, M);
-        int64_t lx = lm + 2 * (int64_t)(W - 1);
+        int64_t lx = pl.dicod ? lm : lm + 2 * (int64_t)(W - 1);  // DICOD: own positions
         if (lx > L)
             lx = L;
         if (lgcd_gm_lds_bytes(K, (int)lx, fp64) > kLdsBytes)
@@ -523,7 +531,12 @@ int solve_device_batch(dicod_ctx* ctx, int n_sig, const float* dX, const int64_t
 
     HIPCHECK(ctx, ensure(ws.beta0, pl.zext * sizeof(double)));
     HIPCHECK(ctx, ensure(ws.g, pl.zext * (fp64 ? sizeof(double) : sizeof(float))));
-    HIPCHECK(ctx, ensure(ws.dirty, n_seg_tot * sizeof(uint32_t)));
+    HIPCHECK(ctx, ensure(ws.dirty, (pl.dicod ? 2 : 1) * n_seg_tot * sizeof(uint32_t)));
+    const int msg_cap = pl.dicod ? cfg.update_cap : 0;
+    if (pl.dicod) {
+        HIPCHECK(ctx, ensure(ws.msg, (size_t)4 * n_seg_tot * msg_cap * sizeof(DicodMsg)));
+        HIPCHECK(ctx, ensure(ws.msg_n, (size_t)4 * n_seg_tot * sizeof(uint32_t)));
+    }
     HIPCHECK(ctx, ensure(ws.phase_upd, (size_t)(max_ph + 1) * sizeof(unsigned long long)));
     HIPCHECK(ctx, ensure(ws.sig_upd, n_sig * sizeof(unsigned long long)));
     HIPCHECK(ctx, ensure(ws.sig_last, n_sig * sizeof(int)));
@@ -639,6 +652,10 @@ int solve_device_batch(dicod_ctx* ctx, int n_sig, const float* dX, const int64_t
         HIPCHECK(ctx, launch_fill_f64(dZ + pl.sig[i].z_off, 0.0,
                                       (size_t)K * pl.sig[i].L, s));
     HIPCHECK(ctx, launch_fill_u32(ws.dirty.as<uint32_t>(), 1u, n_seg_tot, s));
+    if (pl.dicod) {
+        HIPCHECK(ctx, launch_fill_u32(ws.dirty.as<uint32_t>() + n_seg_tot, 0u, n_seg_tot, s));
+        HIPCHECK(ctx, launch_fill_u32(ws.msg_n.as<uint32_t>(), 0u, (size_t)4 * n_seg_tot, s));
+    }
     HIPCHECK(ctx, launch_fill_u64(ws.phase_upd.as<unsigned long long>(), 0ull, max_ph + 1, s));
     HIPCHECK(ctx, launch_fill_u64(ws.sig_upd.as<unsigned long long>(), 0ull, n_sig, s));
     HIPCHECK(ctx, launch_fill_u32(ws.done.as<uint32_t>(), 0u, n_sig, s));
@@ -654,6 +671,8 @@ int solve_device_batch(dicod_ctx* ctx, int n_sig, const float* dX, const int64_t
     bool in_lds = false;
     if (!state_fits(pl, K, cur64, cfg.state_in_lds != 0, &in_lds))
         return fail(ctx, DICOD_ENOTSUP, "segments do not fit any phase kernel");
+    if (pl.dicod && !in_lds)
+        return fail(ctx, DICOD_ENOTSUP, "the DICOD schedule needs segments whose state fits LDS");
     bool polished = false, any_hbm = !in_lds;
 
     PhaseArgs a;
@@ -675,6 +694,11 @@ int solve_device_batch(dicod_ctx* ctx, int n_sig, const float* dX, const int64_t
     a.trace_cap = cfg.trace_capacity;
     a.lm_max = pl.lm_max;
     a.lext_max = pl.lext_max;
+    a.dicod = pl.dicod ? 1 : 0;
+    a.n_seg = n_seg_tot;
+    a.msg_cap = msg_cap;
+    a.msg = pl.dicod ? ws.msg.as<DicodMsg>() : nullptr;
+    a.msg_n = pl.dicod ? ws.msg_n.as<uint32_t>() : nullptr;
     a.phase_stride = 0;
     auto set_state = [&](bool use64, bool lds) {
         a.g = use64 && !fp64 ? ws.g64.p : ws.g.p;
@@ -782,7 +806,8 @@ int solve_device_batch(dicod_ctx* ctx, int n_sig, const float* dX, const int64_t
         const bool next64 = cur64 || (cfg.fp64_polish_after > 0 &&
                                       n_refresh + 1 >= cfg.fp64_polish_after);
         bool next_lds = in_lds;
-        if (next64 != cur64 && !state_fits(pl, K, true, cfg.state_in_lds != 0, &next_lds))
+        if (next64 != cur64 && (!state_fits(pl, K, true, cfg.state_in_lds != 0, &next_lds) ||
+                                (pl.dicod && !next_lds)))
             return fail(ctx, DICOD_ENOTSUP, "segments do not fit the double-state kernel");
         if (next64 && !fp64)
             HIPCHECK(ctx, ensure(ws.g64, pl.zext * sizeof(double)));
@@ -835,6 +860,13 @@ int solve_device_batch(dicod_ctx* ctx, int n_sig, const float* dX, const int64_t
         HIPCHECK(ctx, upload(ws.done, done, s));
         while (phase % pl.colors)
             ++phase;
+        if (pl.dicod) {
+            // the next round reads the flags of parity 0 (set by the check) and
+            // no message of the previous round
+            phase += phase & 1;
+            HIPCHECK(ctx, launch_fill_u32(ws.dirty.as<uint32_t>() + n_seg_tot, 0u, n_seg_tot, s));
+            HIPCHECK(ctx, launch_fill_u32(ws.msg_n.as<uint32_t>(), 0u, (size_t)4 * n_seg_tot, s));
+        }
     }
 
     std::vector<unsigned long long> supd(n_sig);

@@ -93,7 +93,14 @@ hipError_t launch_absmax(const double* beta, int K, const SigDesc* sig,
                          const int64_t* tile_pref, int n_sig, int64_t n_tiles,
                          unsigned long long* out_bits, hipStream_t s);
 
-// One even/odd phase of locally greedy CD over the segments in list[].
+// A boundary message of Algorithm 2: the neighbour's update (k0, t0, delta).
+struct DicodMsg {
+    int32_t k0;
+    int32_t t0;     // position in the signal
+    double delta;   // applied change of Z_{k0}[t0]
+};
+
+// One phase of locally greedy CD over the segments in list[].
 struct PhaseArgs {
     const SegDesc* segs;
     const int32_t* list;
@@ -115,6 +122,15 @@ struct PhaseArgs {
     dicod_trace_rec* trace;
     long long trace_cap;
     int lm_max, lext_max;
+    // Algorithm 2 in lockstep (schedule DICOD): every segment keeps only its
+    // own positions, applies the messages its neighbours sent in the previous
+    // phase and sends its own; dirty flags and message boxes are
+    // double-buffered by phase parity.
+    int dicod;              // 1 = this schedule (LDS-state kernel only)
+    int n_seg;              // segments in the table: stride of dirty[] and boxes
+    int msg_cap;            // messages per box (>= cap)
+    DicodMsg* msg;          // [2 parity][n_seg][2: 0 leftwards, 1 rightwards][msg_cap]
+    uint32_t* msg_n;        // [2 parity][n_seg][2]
 };
 hipError_t launch_lgcd_phase(const PhaseArgs& a, bool fp64, size_t* lds_bytes,
                              hipStream_t s);

@@ -780,7 +780,7 @@ __host__ __device__ constexpr size_t slot_offset(size_t elem, int KP, int lx, in
     return ((elem * (size_t)KP * ((size_t)lx + (size_t)lm)) + 15) & ~(size_t)15;
 }
 
-template <typename G, int KQ, int NQ, int NT>
+template <typename G, int KQ, int NQ, int NT, bool DI>
 __global__ void __launch_bounds__(NT)
 k_lgcd_phase(PhaseArgs a)
 {
@@ -794,7 +794,15 @@ k_lgcd_phase(PhaseArgs a)
     const int tid = threadIdx.x;
 
     const int sid = a.list[blockIdx.x];
-    if (a.dirty[sid] == 0)
+    // DI (Algorithm 2 in lockstep): flags and boxes of this phase's parity
+    const int par = a.phase & 1;
+    uint32_t* dirty = DI ? a.dirty + (size_t)par * a.n_seg : a.dirty;
+    uint32_t* msg_n_out = DI ? a.msg_n + ((size_t)par * a.n_seg + sid) * 2 : nullptr;
+    if (DI && tid == 0) {
+        msg_n_out[0] = 0u;  // rewritten below when the segment runs
+        msg_n_out[1] = 0u;
+    }
+    if (dirty[sid] == 0)
         return;
 
     extern __shared__ __align__(16) unsigned char smem[];
@@ -802,8 +810,9 @@ k_lgcd_phase(PhaseArgs a)
     const int64_t L = sd.L;
     const int b = sd.b;
     const int Lm = sd.e - sd.b;
-    const int ext_lo = b - (W - 1) > 0 ? b - (W - 1) : 0;
-    const int ext_hi = sd.e + (W - 1) < sd.L ? sd.e + (W - 1) : sd.L;
+    // DI: a segment holds only its own positions; the neighbours get messages
+    const int ext_lo = DI ? b : (b - (W - 1) > 0 ? b - (W - 1) : 0);
+    const int ext_hi = DI ? sd.e : (sd.e + (W - 1) < sd.L ? sd.e + (W - 1) : sd.L);
     const int Lext = ext_hi - ext_lo;
     const int off = b - ext_lo;
     const int lx = a.lext_max;
@@ -845,6 +854,42 @@ k_lgcd_phase(PhaseArgs a)
         z_l[j * KP + k] = k < K ? (G)Zs[(int64_t)k * L + b + j] : (G)0;
     }
     __syncthreads();
+    int tlo = INT_MAX, thi = -1;  // positions whose g changed (written back)
+    if (DI) {
+        // messages of the previous phase: the left neighbour's rightwards box,
+        // then the right neighbour's leftwards box, each in the order sent;
+        // every position is changed by its owner thread only
+        const int prev = par ^ 1;
+        for (int side = 0; side < 2; ++side) {
+            const int nb = side == 0 ? sd.left : sd.right;
+            if (nb < 0)
+                continue;
+            const size_t box = ((size_t)prev * a.n_seg + nb) * 2 + (side == 0 ? 1 : 0);
+            const uint32_t cnt = a.msg_n[box];
+            const DicodMsg* mb = a.msg + box * a.msg_cap;
+            for (uint32_t i = 0; i < cnt; ++i) {
+                const DicodMsg mg = mb[i];
+                const int q0m = mg.t0 - b;
+                const G dm = (G)mg.delta;
+                const int mlo = q0m - (W - 1) > 0 ? q0m - (W - 1) : 0;
+                const int mhi = q0m + (W - 1) < Lext - 1 ? q0m + (W - 1) : Lext - 1;
+                tlo = mlo < tlo ? mlo : tlo;
+                thi = mhi > thi ? mhi : thi;
+                const G* __restrict__ Sk = St + (size_t)mg.k0 * nd * KP;
+                static_for<NQ>([&](auto ic) __attribute__((always_inline)) {
+                    constexpr int i2 = decltype(ic)::value;
+                    const int q = tid + i2 * NT;
+                    const int dj = q - q0m + (W - 1);
+                    if (q >= Lext || dj < 0 || dj >= nd)
+                        return;
+                    KeyT kd = KO::null();
+                    G dd = (G)0;
+                    visit<G, KQ>(g_l + q * KP, nullptr, Sk + (size_t)dj * KP, dm, n2r, invr,
+                                 n2l, invl, lam, 0u, kd, dd);
+                });
+            }
+        }
+    }
 
     KeyT best[NQ];
     G dl[NQ];
@@ -868,7 +913,7 @@ k_lgcd_phase(PhaseArgs a)
     int n = 0;
     bool conv = false;
     bool touch_l = false, touch_r = false;
-    int tlo = INT_MAX, thi = -1;
+    unsigned n_msg_l = 0, n_msg_r = 0;
     for (;;) {
         if (KO::value(kb) < eps_stop) {
             conv = true;
@@ -918,10 +963,23 @@ k_lgcd_phase(PhaseArgs a)
         const int whi = q0 + (W - 1) < Lext - 1 ? q0 + (W - 1) : Lext - 1;
         tlo = wlo < tlo ? wlo : tlo;
         thi = whi > thi ? whi : thi;
-        if (q0 - (W - 1) < off && sd.left >= 0)
-            touch_l = true;
-        if (q0 + (W - 1) >= off + Lm && sd.right >= 0)
-            touch_r = true;
+        const bool to_l = q0 - (W - 1) < off && sd.left >= 0;
+        const bool to_r = q0 + (W - 1) >= off + Lm && sd.right >= 0;
+        if (DI && tid == (q0 % NT) && (to_l || to_r)) {
+            // the update as sent: the delta this segment applied to g
+            DicodMsg mg;
+            mg.k0 = k0;
+            mg.t0 = b + j0;
+            mg.delta = (double)delta;
+            if (to_l)
+                a.msg[(((size_t)par * a.n_seg + sid) * 2 + 0) * a.msg_cap + n_msg_l] = mg;
+            if (to_r)
+                a.msg[(((size_t)par * a.n_seg + sid) * 2 + 1) * a.msg_cap + n_msg_r] = mg;
+        }
+        n_msg_l += to_l ? 1 : 0;
+        n_msg_r += to_r ? 1 : 0;
+        touch_l |= to_l;
+        touch_r |= to_r;
 
         const G* __restrict__ Sk = St + (size_t)k0 * nd * KP;
         static_for<NQ>([&](auto ic) __attribute__((always_inline)) {
@@ -940,13 +998,16 @@ k_lgcd_phase(PhaseArgs a)
         ++it;
     }
 
-    if (n > 0) {
+    if (thi >= tlo) {
+        // g of every position changed by an update or a message
         const int wdt = thi - tlo + 1;
         for (int i = tid; i < K * wdt; i += NT) {
             const int k = i / wdt;
             const int q = tlo + (i - k * wdt);
             gs[(int64_t)k * L + ext_lo + q] = g_l[q * KP + k];
         }
+    }
+    if (n > 0) {
         if (tid == 0) {
             atomicAdd(&a.phase_upd[(size_t)sd.sig * a.phase_stride + a.phase], (unsigned long long)n);
             atomicAdd(&a.sig_upd[sd.sig], (unsigned long long)n);
@@ -955,11 +1016,26 @@ k_lgcd_phase(PhaseArgs a)
         }
     }
     if (tid == 0) {
-        a.dirty[sid] = conv ? 0u : 1u;
-        if (touch_l)
-            a.dirty[sd.left] = 1u;
-        if (touch_r)
-            a.dirty[sd.right] = 1u;
+        if (DI) {
+            // this parity's flag is consumed; the next phase's flags (the other
+            // parity) are only ever set here, so a neighbour's mark survives
+            uint32_t* next = a.dirty + (size_t)(par ^ 1) * a.n_seg;
+            dirty[sid] = 0u;
+            if (!conv)
+                next[sid] = 1u;
+            if (touch_l)
+                next[sd.left] = 1u;
+            if (touch_r)
+                next[sd.right] = 1u;
+            msg_n_out[0] = n_msg_l;
+            msg_n_out[1] = n_msg_r;
+        } else {
+            a.dirty[sid] = conv ? 0u : 1u;
+            if (touch_l)
+                a.dirty[sd.left] = 1u;
+            if (touch_r)
+                a.dirty[sd.right] = 1u;
+        }
     }
 }
 
@@ -999,12 +1075,17 @@ size_t lgcd_lds_bytes(int K, int lm_max, int lext_max, bool fp64)
 template <typename G, int KQ, int NQ, int NT>
 static hipError_t launch_phase_inst(const PhaseArgs& a, size_t lds, hipStream_t s)
 {
-    const void* fn = (const void*)k_lgcd_phase<G, KQ, NQ, NT>;
+    const void* fn = a.dicod ? (const void*)k_lgcd_phase<G, KQ, NQ, NT, true>
+                             : (const void*)k_lgcd_phase<G, KQ, NQ, NT, false>;
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess)
         return e;
-    hipLaunchKernelGGL((k_lgcd_phase<G, KQ, NQ, NT>), dim3((unsigned)a.n_list), dim3(NT), lds,
-                       s, a);
+    if (a.dicod)
+        hipLaunchKernelGGL((k_lgcd_phase<G, KQ, NQ, NT, true>), dim3((unsigned)a.n_list),
+                           dim3(NT), lds, s, a);
+    else
+        hipLaunchKernelGGL((k_lgcd_phase<G, KQ, NQ, NT, false>), dim3((unsigned)a.n_list),
+                           dim3(NT), lds, s, a);
     return hipGetLastError();
 }
 

@@ -393,3 +393,96 @@ def test_long_signal_sampled_against_oracle(dicod):
     assert dz.max() < EPS
     obj = oracle.objective(f64(X), f64(D), Z, lam)
     assert abs(obj - st["objective"]) <= 1e-10 * abs(obj)
+
+
+# ------------------------------- f1: Algorithm 2 in lockstep (DICOD schedule)
+
+def interference_from_trace(phase, seg, k0, t0, delta, S, W):
+    """Concurrent updates of adjacent segments in one phase: pair count, pairs
+    with |t0 - t1| < W (interfering, Sec. 3) and their Prop. A.2 terms."""
+    by = {}
+    for p, m, k, t, d in zip(phase, seg, k0, t0, delta):
+        by.setdefault((int(p), int(m)), []).append((int(k), int(t), float(d)))
+    n_adj = n_int = 0
+    acc = 0.0
+    for (p, m), us in by.items():
+        vs = by.get((p, m + 1))
+        if not vs:
+            continue
+        for ku, tu, du in us:
+            for kv, tv, dv in vs:
+                n_adj += 1
+                dt = tu - tv
+                if -W < dt < W:
+                    n_int += 1
+                    acc += S[ku, kv, dt + W - 1] * du * dv
+    return n_adj, n_int, acc
+
+
+DICOD_CASES = [  # (workload, M, cap): segments >= W
+    ("small", 4, 1), ("small", 16, 1), ("small", 64, 1), ("small", 64, 4),
+    ("k25", 13, 1), ("k25", 100, 2),
+]
+
+
+def _dicod_problem(name, seed):
+    if name == "small":
+        return small(seed)
+    return synth.generate(7, 25, 20, 5003, 0.02, 0.1, seed=40 + seed)
+
+
+@pytest.mark.parametrize("name,M,cap", DICOD_CASES)
+@pytest.mark.parametrize("seed", [0, 1])
+def test_dicod_schedule_fp64_trajectory_matches_oracle(dicod, name, M, cap, seed):
+    print(f"\ncase: DICOD schedule FP64 {name} M={M} cap={cap} seed={seed}", flush=True)
+    X, D, _ = _dicod_problem(name, seed)
+    W = D.shape[2]
+    lam = 0.1 * oracle.lambda_max(f64(X), f64(D))
+    n = 200_000
+    Zo, so, tro = oracle.lgcd(f64(X), f64(D), lam, EPS, M, schedule=oracle.SCHED_DICOD,
+                              cap=cap, trace_cap=n)
+    assert so["converged"] == 1
+    with ctx_of(dicod, precision=dicod.DICOD_PREC_FP64, schedule=dicod.DICOD_SCHED_DICOD,
+                update_cap=cap, trace_capacity=n) as c:
+        Z, st = c.solve(X, lam, EPS, n_seg=M, D=D)
+        tr = _sorted_gpu_trace(c.trace())
+    print(f"oracle: {so['n_updates']} updates, {so['n_phases']} phases, {so['n_interf']} "
+          f"interfering of {so['n_adjacent']} adjacent pairs; gpu: {st['n_updates']} updates",
+          flush=True)
+    assert st["n_refresh"] == 0 and st["converged"] == 1
+    assert len(tr) == len(tro) == so["n_updates"]
+    for f in ("phase", "seg", "k0", "t0", "n_local"):
+        np.testing.assert_array_equal(tr[f], tro[f], err_msg=f)
+    d_o = tro["z_new"] - tro["z_old"]
+    np.testing.assert_allclose(tr["delta"], d_o, rtol=1e-9, atol=1e-12 * np.abs(d_o).max())
+    S = oracle.s_table(f64(D))
+    n_adj, n_int, acc = interference_from_trace(tr["phase"], tr["seg"], tr["k0"], tr["t0"],
+                                                tr["delta"], S, W)
+    assert (n_adj, n_int) == (so["n_adjacent"], so["n_interf"])
+    assert abs(acc - so["interf_sum"]) <= 1e-9 * max(1.0, abs(so["interf_sum"]))
+    np.testing.assert_allclose(Z, Zo, rtol=0, atol=1e-9 * np.abs(Zo).max())
+
+
+def test_dicod_schedule_fp32_paper_shaped(dicod, paper_problem):
+    print("\ncase: DICOD schedule FP32 paper-shaped", flush=True)
+    X, D, lam, Zo = paper_problem
+    with ctx_of(dicod, schedule=dicod.DICOD_SCHED_DICOD, update_cap=1) as c:
+        Z, st = c.solve(X, -0.1, EPS, n_seg=0, D=D)
+    print(f"gpu: {st['n_updates']} updates, {st['n_phases']} phases, M={st['n_seg']}, "
+          f"rounds {st['round_updates']}, cd {st['t_cd_ms']:.2f} ms", flush=True)
+    assert st["n_seg"] == 749
+    _check_solution(X, D, lam, Z, st, Zo)
+
+
+@pytest.mark.parametrize("bad", ["cap0", "short"])
+def test_dicod_schedule_rejects(dicod, bad):
+    X, D, _ = small(0)
+    if bad == "cap0":
+        with pytest.raises(dicod.DicodError) as ei:
+            ctx_of(dicod, schedule=dicod.DICOD_SCHED_DICOD, update_cap=0)
+        assert ei.value.code == dicod.DICOD_EINVAL
+        return
+    with ctx_of(dicod, schedule=dicod.DICOD_SCHED_DICOD, update_cap=1) as c:
+        with pytest.raises(dicod.DicodError) as ei:
+            c.solve(X, -0.1, EPS, n_seg=200, D=D)   # segments of 20 < W = 32
+        assert ei.value.code == dicod.DICOD_EINVAL
