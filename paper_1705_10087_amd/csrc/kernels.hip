@@ -666,16 +666,18 @@ struct Slot {
     G d;
 };
 
-// Delta Z = Z' - Z in terms of g (eq. (pb_coord) with beta = g + |D|^2 z);
-// *zero tells that the soft threshold sends the coordinate to 0.
+// Delta Z = Z' - Z in terms of g (eq. (pb_coord) with beta = g + |D|^2 z):
+// -z where the soft threshold sends the coordinate to 0 (*zero), else
+// (g - lambda sign(beta)) / |D|^2, formed as g * inv - copysign(lambda * inv,
+// beta) with lam_inv = lambda * inv (no cancellation against z).
 template <typename G>
-__device__ __forceinline__ G coord_delta(G g, G z, G n2, G inv_n2, G lam, bool* zero)
+__device__ __forceinline__ G coord_delta(G g, G z, G n2, G inv_n2, G lam_inv, G lam,
+                                         bool* zero)
 {
-    const G bb = g + n2 * z;
-    const G sg = bb > (G)0 ? (G)1 : (G)-1;
+    const G bb = fma(n2, z, g);
     const bool zr = fabs(bb) <= lam;
     *zero = zr;
-    return zr ? -z : (g - lam * sg) * inv_n2;
+    return zr ? -z : fma(g, inv_n2, -copysign(lam_inv, bb));
 }
 
 // Block argmax over every thread's NQ position keys; returns the winner's key
@@ -721,22 +723,29 @@ __device__ __forceinline__ void block_argmax(const typename KeyOps<G>::T (&best)
 // and, for an own position (z_row != null), the best candidate over the atoms.
 // Padded atoms have g = z = S = 0 and |D|^2 = 1, so their candidate is 0.
 template <typename G, int KQ>
+__device__ __forceinline__ void load_s_row(const G* __restrict__ s_row,
+                                           typename Vec<G>::T (&sv)[KQ])
+{
+#pragma unroll
+    for (int i = 0; i < KQ; ++i)
+        sv[i] = reinterpret_cast<const typename Vec<G>::T*>(s_row)[i];
+}
+
+// upd: apply g -= S delta with the S row given in sv (loaded by the caller,
+// early when it can be).
+template <typename G, int KQ>
 __device__ __forceinline__ void visit(G* __restrict__ g_row, const G* __restrict__ z_row,
-                                      const G* __restrict__ s_row, G delta,
+                                      bool upd, const typename Vec<G>::T (&sv)[KQ], G delta,
                                       const G (&n2r)[KQ * Vec<G>::N],
                                       const G (&invr)[KQ * Vec<G>::N],
+                                      const G (&linvr)[KQ * Vec<G>::N],
                                       const G* __restrict__ n2l, const G* __restrict__ invl,
-                                      G lam, unsigned idx_base, typename KeyOps<G>::T& key,
-                                      G& dbest)
+                                      const G* __restrict__ linvl, G lam, unsigned idx_base,
+                                      typename KeyOps<G>::T& key, G& dbest)
 {
     typedef typename Vec<G>::T V;
     constexpr int N = Vec<G>::N;
-    V sv[KQ], gv[KQ], zv[KQ];
-    if (s_row) {
-#pragma unroll
-        for (int i = 0; i < KQ; ++i)
-            sv[i] = reinterpret_cast<const V*>(s_row)[i];
-    }
+    V gv[KQ], zv[KQ];
 #pragma unroll
     for (int i = 0; i < KQ; ++i)
         gv[i] = reinterpret_cast<const V*>(g_row)[i];
@@ -745,7 +754,7 @@ __device__ __forceinline__ void visit(G* __restrict__ g_row, const G* __restrict
         for (int i = 0; i < KQ; ++i)
             zv[i] = reinterpret_cast<const V*>(z_row)[i];
     }
-    if (s_row) {
+    if (upd) {
 #pragma unroll
         for (int i = 0; i < KQ; ++i) {
             gv[i] -= sv[i] * delta;
@@ -756,21 +765,37 @@ __device__ __forceinline__ void visit(G* __restrict__ g_row, const G* __restrict
         G bestv = (G)-1;
         int bk = 0;
 #pragma unroll
-        for (int i = 0; i < KQ; ++i)
+        for (int i = 0; i < KQ; ++i) {
+            // per-atom constants: vector registers in float up to 28 atoms;
+            // otherwise (too many registers) 16-byte LDS broadcast reads
+            V nv, iv, lv;
+            if (sizeof(G) == sizeof(float) && KQ <= 7) {
+#pragma unroll
+                for (int c = 0; c < N; ++c) {
+                    nv[c] = n2r[i * N + c];
+                    iv[c] = invr[i * N + c];
+                    lv[c] = linvr[i * N + c];
+                }
+            } else {
+                nv = reinterpret_cast<const V*>(n2l)[i];
+                iv = reinterpret_cast<const V*>(invl)[i];
+                lv = reinterpret_cast<const V*>(linvl)[i];
+            }
 #pragma unroll
             for (int c = 0; c < N; ++c) {
                 const int k = i * N + c;
                 bool zr;
-                const G d = coord_delta<G>(gv[i][c], zv[i][c], n2r[k], invr[k], lam, &zr);
+                const G d = coord_delta<G>(gv[i][c], zv[i][c], nv[c], iv[c], lv[c], lam, &zr);
                 const G ad = fabs(d);
                 const bool b = ad > bestv;
                 bestv = b ? ad : bestv;
                 bk = b ? k : bk;
             }
+        }
         key = KeyOps<G>::make(bestv, idx_base + (unsigned)bk);
         // the signed change of the winning atom, recomputed from the stored state
         bool zr;
-        dbest = coord_delta<G>(g_row[bk], z_row[bk], n2l[bk], invl[bk], lam, &zr);
+        dbest = coord_delta<G>(g_row[bk], z_row[bk], n2l[bk], invl[bk], linvl[bk], lam, &zr);
     }
 }
 
@@ -823,6 +848,7 @@ k_lgcd_phase(PhaseArgs a)
     Slot<G>* slots = reinterpret_cast<Slot<G>*>(smem + slot_offset(sizeof(G), KP, lx, lm));
     G* n2l = reinterpret_cast<G*>(slots + 2 * NW);  // [KP]
     G* invl = n2l + KP;                             // [KP]
+    G* linvl = invl + KP;                           // [KP] lambda / |D_k|^2
 
     G* __restrict__ gs = reinterpret_cast<G*>(a.g) + sd.z_off;
     double* __restrict__ Zs = a.Z + sd.z_off;
@@ -830,17 +856,15 @@ k_lgcd_phase(PhaseArgs a)
     const G lam = (G)a.sigs[sd.sig].lam;
     const double eps_stop = a.sigs[sd.sig].eps_stop;
 
-    // |D_k|^2 and its inverse: registers for the per-position passes, LDS for
-    // the data-dependent updated atom.  Padded atoms get 1.
-    G n2r[KP], invr[KP];
-#pragma unroll
-    for (int k = 0; k < KP; ++k) {
-        n2r[k] = k < K ? reinterpret_cast<const G*>(a.n2)[k] : (G)1;
-        invr[k] = k < K ? reinterpret_cast<const G*>(a.inv_n2)[k] : (G)1;
-    }
+    // |D_k|^2, its inverse and lambda times it: in LDS for the data-dependent
+    // updated atom, and copied to vector registers (per-thread copies: the
+    // per-position passes use all of them) after the barrier below.  Padded
+    // atoms get 1.
     for (int k = tid; k < KP; k += NT) {
+        const G iv = k < K ? reinterpret_cast<const G*>(a.inv_n2)[k] : (G)1;
         n2l[k] = k < K ? reinterpret_cast<const G*>(a.n2)[k] : (G)1;
-        invl[k] = k < K ? reinterpret_cast<const G*>(a.inv_n2)[k] : (G)1;
+        invl[k] = iv;
+        linvl[k] = lam * iv;
     }
     // state in: [k][t] in HBM -> [q][k] in LDS, padding zeroed
     for (int i = tid; i < KP * Lext; i += NT) {
@@ -854,6 +878,13 @@ k_lgcd_phase(PhaseArgs a)
         z_l[j * KP + k] = k < K ? (G)Zs[(int64_t)k * L + b + j] : (G)0;
     }
     __syncthreads();
+    G n2r[KP], invr[KP], linvr[KP];
+#pragma unroll
+    for (int k = 0; k < KP; ++k) {
+        n2r[k] = n2l[k];
+        invr[k] = invl[k];
+        linvr[k] = linvl[k];
+    }
     int tlo = INT_MAX, thi = -1;  // positions whose g changed (written back)
     if (DI) {
         // messages of the previous phase: the left neighbour's rightwards box,
@@ -884,8 +915,10 @@ k_lgcd_phase(PhaseArgs a)
                         return;
                     KeyT kd = KO::null();
                     G dd = (G)0;
-                    visit<G, KQ>(g_l + q * KP, nullptr, Sk + (size_t)dj * KP, dm, n2r, invr,
-                                 n2l, invl, lam, 0u, kd, dd);
+                    typename Vec<G>::T sv[KQ];
+                    load_s_row<G, KQ>(Sk + (size_t)dj * KP, sv);
+                    visit<G, KQ>(g_l + q * KP, nullptr, true, sv, dm, n2r, invr, linvr, n2l,
+                                 invl, linvl, lam, 0u, kd, dd);
                 });
             }
         }
@@ -899,9 +932,11 @@ k_lgcd_phase(PhaseArgs a)
         dl[i] = (G)0;
         const int q = tid + i * NT;
         const int j = q - off;
-        if (q < Lext && j >= 0 && j < Lm)
-            visit<G, KQ>(g_l + q * KP, z_l + j * KP, nullptr, (G)0, n2r, invr, n2l, invl, lam,
-                         (unsigned)(j * K), best[i], dl[i]);
+        if (q < Lext && j >= 0 && j < Lm) {
+            typename Vec<G>::T sv[KQ];  // unused: no update in this pass
+            visit<G, KQ>(g_l + q * KP, z_l + j * KP, false, sv, (G)0, n2r, invr, linvr, n2l,
+                         invl, linvl, lam, (unsigned)(j * KP), best[i], dl[i]);
+        }
     });
 
     int it = 0;
@@ -922,17 +957,20 @@ k_lgcd_phase(PhaseArgs a)
         if (n == a.cap)
             break;
         const unsigned kidx = KO::index(kb);
-        const int j0 = (int)(kidx / (unsigned)K);
-        const int k0 = (int)kidx - j0 * K;
+        const int j0 = (int)(kidx / (unsigned)KP);  // keys index j * KP + k
+        const int k0 = (int)kidx - j0 * KP;
         const int q0 = j0 + off;
         const G delta = db;
+        const int wlo = q0 - (W - 1) > 0 ? q0 - (W - 1) : 0;
+        const int whi = q0 + (W - 1) < Lext - 1 ? q0 + (W - 1) : Lext - 1;
+        const G* __restrict__ Sk = St + (size_t)k0 * nd * KP;
 
         if (tid == (q0 % NT)) {
             // Owner of the updated position: new Z value (exactly 0 when the
             // soft threshold is active), in LDS and in the double-precision Z.
             const G zo = z_l[j0 * KP + k0];
             bool zr;
-            (void)coord_delta<G>(g_l[q0 * KP + k0], zo, n2l[k0], invl[k0], lam, &zr);
+            (void)coord_delta<G>(g_l[q0 * KP + k0], zo, n2l[k0], invl[k0], linvl[k0], lam, &zr);
             const G zn = zr ? (G)0 : zo + delta;
             z_l[j0 * KP + k0] = zn;
             double* zp = Zs + (int64_t)k0 * L + b + j0;
@@ -959,8 +997,6 @@ k_lgcd_phase(PhaseArgs a)
             }
         }
 
-        const int wlo = q0 - (W - 1) > 0 ? q0 - (W - 1) : 0;
-        const int whi = q0 + (W - 1) < Lext - 1 ? q0 + (W - 1) : Lext - 1;
         tlo = wlo < tlo ? wlo : tlo;
         thi = whi > thi ? whi : thi;
         const bool to_l = q0 - (W - 1) < off && sd.left >= 0;
@@ -981,17 +1017,18 @@ k_lgcd_phase(PhaseArgs a)
         touch_l |= to_l;
         touch_r |= to_r;
 
-        const G* __restrict__ Sk = St + (size_t)k0 * nd * KP;
         static_for<NQ>([&](auto ic) __attribute__((always_inline)) {
             constexpr int i = decltype(ic)::value;
             const int q = tid + i * NT;
             if (q < wlo || q > whi)
                 return;
-            const int dj = q - q0 + (W - 1);
             const int j = q - off;
             const bool own = j >= 0 && j < Lm;
-            visit<G, KQ>(g_l + q * KP, own ? z_l + j * KP : nullptr, Sk + (size_t)dj * KP,
-                         delta, n2r, invr, n2l, invl, lam, (unsigned)(j * K), best[i], dl[i]);
+            typename Vec<G>::T sv[KQ];
+            load_s_row<G, KQ>(Sk + (size_t)(q - q0 + (W - 1)) * KP, sv);
+            visit<G, KQ>(g_l + q * KP, own ? z_l + j * KP : nullptr, true, sv, delta, n2r,
+                         invr, linvr, n2l, invl, linvl, lam, (unsigned)(j * KP), best[i],
+                         dl[i]);
         });
         ++n;
         block_argmax<G, NQ, NT>(best, dl, slots + (it & 1) * NW, kb, db);
@@ -1069,7 +1106,7 @@ size_t lgcd_lds_bytes(int K, int lm_max, int lext_max, bool fp64)
     const size_t e = fp64 ? sizeof(double) : sizeof(float);
     const size_t slots = 2 * (kPhaseThreadsMax / 64) *
                          (fp64 ? sizeof(Slot<double>) : sizeof(Slot<float>));
-    return slot_offset(e, KP, lext_max, lm_max) + slots + 2 * e * (size_t)KP;
+    return slot_offset(e, KP, lext_max, lm_max) + slots + 3 * e * (size_t)KP;
 }
 
 template <typename G, int KQ, int NQ, int NT>
@@ -1203,7 +1240,8 @@ __device__ __forceinline__ void gm_chunk(int c, int K, int Kr, int W, int off, i
                                         G* __restrict__ gs, const double* __restrict__ Zs,
                                         const G* __restrict__ Srow, G delta, int q0,
                                         int wlo, int whi, const G* __restrict__ n2l,
-                                        const G* __restrict__ invl, G lam,
+                                        const G* __restrict__ invl,
+                                        const G* __restrict__ linvl, G lam,
                                         ChunkBest<G>* __restrict__ cb)
 {
     typedef KeyOps<G> KO;
@@ -1245,7 +1283,8 @@ __device__ __forceinline__ void gm_chunk(int c, int K, int Kr, int W, int off, i
                     const int k = k0 + c8;
                     if (k < K) {
                         bool zr;
-                        const G d = coord_delta<G>(gv[c8], (G)zv[c8], n2l[k], invl[k], lam, &zr);
+                        const G d = coord_delta<G>(gv[c8], (G)zv[c8], n2l[k], invl[k], linvl[k],
+                                                   lam, &zr);
                         const typename KO::T kc = KO::make(fabs(d), (unsigned)(j * Kr + k));
                         const bool bt = KO::better(kc, best);
                         best = KO::select(bt, kc, best);
@@ -1294,6 +1333,7 @@ k_lgcd_phase_gm(PhaseArgs a)
     Slot<G>* slots = reinterpret_cast<Slot<G>*>(cb + a.lext_max / 64 + 1);  // [2][NW]
     G* n2l = reinterpret_cast<G*>(slots + 2 * NW);
     G* invl = n2l + K;
+    G* linvl = invl + K;
 
     G* __restrict__ gs = reinterpret_cast<G*>(a.g) + sd.z_off;
     double* __restrict__ Zs = a.Z + sd.z_off;
@@ -1302,14 +1342,16 @@ k_lgcd_phase_gm(PhaseArgs a)
     const double eps_stop = a.sigs[sd.sig].eps_stop;
     const int nd = 2 * W - 1;
     for (int k = tid; k < K; k += NT) {
+        const G iv = reinterpret_cast<const G*>(a.inv_n2)[k];
         n2l[k] = reinterpret_cast<const G*>(a.n2)[k];
-        invl[k] = reinterpret_cast<const G*>(a.inv_n2)[k];
+        invl[k] = iv;
+        linvl[k] = lam * iv;
     }
     __syncthreads();
 
     for (int c = wave; c < nch; c += NW)
         gm_chunk<G, KC>(c, K, a.K, W, off, Lm, Lext, ext_lo, b, L, gs, Zs, nullptr, (G)0, 0, 0,
-                        -1, n2l, invl, lam, cb);
+                        -1, n2l, invl, linvl, lam, cb);
     __syncthreads();
 
     int it = 0;
@@ -1352,6 +1394,7 @@ k_lgcd_phase_gm(PhaseArgs a)
             const double zo = *zp;
             bool zr;
             (void)coord_delta<G>(gs[(int64_t)k0 * L + ext_lo + q0], (G)zo, n2l[k0], invl[k0],
+                                 linvl[k0],
                                  lam, &zr);
             *zp = zr ? 0.0 : zo + (double)delta;
             if (a.trace) {
@@ -1378,7 +1421,7 @@ k_lgcd_phase_gm(PhaseArgs a)
         const G* __restrict__ Srow = S + (size_t)k0 * K * nd;
         for (int c = wlo / 64 + ((wave - wlo / 64) % NW + NW) % NW; c <= whi / 64; c += NW)
             gm_chunk<G, KC>(c, K, a.K, W, off, Lm, Lext, ext_lo, b, L, gs, Zs, Srow, delta,
-                            q0, wlo, whi, n2l, invl, lam, cb);
+                            q0, wlo, whi, n2l, invl, linvl, lam, cb);
         __syncthreads();
         ++n;
         argmax(kb, db);
@@ -1404,7 +1447,7 @@ size_t lgcd_gm_lds_bytes(int K, int lext_max, bool fp64)
     const size_t cbs = fp64 ? sizeof(ChunkBest<double>) : sizeof(ChunkBest<float>);
     const size_t sls = fp64 ? sizeof(Slot<double>) : sizeof(Slot<float>);
     const size_t e = fp64 ? sizeof(double) : sizeof(float);
-    return cbs * ((size_t)lext_max / 64 + 1) + sls * 2 * (kPhaseThreads / 64) + 2 * e * (size_t)K;
+    return cbs * ((size_t)lext_max / 64 + 1) + sls * 2 * (kPhaseThreads / 64) + 3 * e * (size_t)K;
 }
 
 template <typename G, int KC>
