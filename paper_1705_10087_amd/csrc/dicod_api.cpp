@@ -395,7 +395,7 @@ struct Plan {
 // false when neither kernel can hold the segments.
 bool state_fits(const Plan& pl, int K, bool fp64, bool allow_lds, bool* in_lds)
 {
-    if (allow_lds && pl.lext_max <= 4 * kPhaseThreads &&
+    if (allow_lds && pl.lm_max <= 4 * kPhaseThreads &&
         lgcd_lds_bytes(K, pl.lm_max, pl.lext_max, fp64) <= kLdsBytes) {
         *in_lds = true;
         return true;

@@ -941,7 +941,7 @@ int server_submit(dicod_ctx* ctx, const float* X, int64_t T, double lambda, doub
     // state kernels for float and double rounds (the LDS kernel when allowed
     // and it fits, else the HBM-state kernel)
     auto fits = [&](bool f64, bool* lds) {
-        *lds = cfg.state_in_lds && lx <= 4 * kPhaseThreads &&
+        *lds = cfg.state_in_lds && lm <= 4 * kPhaseThreads &&
                lgcd_lds_bytes(K, (int)lm, (int)lx, f64) <= kLdsBytes;
         return *lds || lgcd_gm_lds_bytes(K, (int)lx, f64) <= kLdsBytes;
     };

@@ -799,6 +799,16 @@ __device__ __forceinline__ void visit(G* __restrict__ g_row, const G* __restrict
     }
 }
 
+// An update whose window reaches a neighbour (the halo), kept until the end
+// of the run: (atom, signal position, applied change).
+template <typename G>
+struct HaloRec {
+    int k0;
+    int t0;
+    G delta;
+};
+constexpr int kHaloRecs = 64;  // records held on chip before they are applied
+
 // Byte offset of the argmax slots after the g and Z arrays, 16-byte aligned.
 __host__ __device__ constexpr size_t slot_offset(size_t elem, int KP, int lx, int lm)
 {
@@ -811,6 +821,7 @@ k_lgcd_phase(PhaseArgs a)
 {
     typedef KeyOps<G> KO;
     typedef typename KO::T KeyT;
+    typedef typename Vec<G>::T V;
     constexpr int NW = NT / 64;
     constexpr int KP = KQ * Vec<G>::N;
     const int K = a.K;
@@ -835,20 +846,24 @@ k_lgcd_phase(PhaseArgs a)
     const int64_t L = sd.L;
     const int b = sd.b;
     const int Lm = sd.e - sd.b;
-    // DI: a segment holds only its own positions; the neighbours get messages
+    // The halo: the neighbours' positions within W - 1 of the segment.  The
+    // block keeps only its own positions (index j = t - b) on chip; an
+    // update's change of the halo is recorded and applied to the state in HBM
+    // at the end of the run (the neighbours are idle in this phase).  DI: no
+    // halo, the neighbours get messages.
     const int ext_lo = DI ? b : (b - (W - 1) > 0 ? b - (W - 1) : 0);
     const int ext_hi = DI ? sd.e : (sd.e + (W - 1) < sd.L ? sd.e + (W - 1) : sd.L);
-    const int Lext = ext_hi - ext_lo;
-    const int off = b - ext_lo;
-    const int lx = a.lext_max;
     const int lm = a.lm_max;
 
-    G* g_l = reinterpret_cast<G*>(smem);          // [lx][KP]
-    G* z_l = g_l + (size_t)lx * KP;               // [lm][KP]
-    Slot<G>* slots = reinterpret_cast<Slot<G>*>(smem + slot_offset(sizeof(G), KP, lx, lm));
+    G* g_l = reinterpret_cast<G*>(smem);          // [lm][KP]
+    G* z_l = g_l + (size_t)lm * KP;               // [lm][KP]
+    Slot<G>* slots = reinterpret_cast<Slot<G>*>(smem + slot_offset(sizeof(G), KP, lm, lm));
     G* n2l = reinterpret_cast<G*>(slots + 2 * NW);  // [KP]
     G* invl = n2l + KP;                             // [KP]
     G* linvl = invl + KP;                           // [KP] lambda / |D_k|^2
+    HaloRec<G>* recs = reinterpret_cast<HaloRec<G>*>(
+        reinterpret_cast<unsigned char*>(linvl + KP) +
+        ((16 - (reinterpret_cast<size_t>(linvl + KP) & 15)) & 15));  // [kHaloRecs]
 
     G* __restrict__ gs = reinterpret_cast<G*>(a.g) + sd.z_off;
     double* __restrict__ Zs = a.Z + sd.z_off;
@@ -866,15 +881,11 @@ k_lgcd_phase(PhaseArgs a)
         invl[k] = iv;
         linvl[k] = lam * iv;
     }
-    // state in: [k][t] in HBM -> [q][k] in LDS, padding zeroed
-    for (int i = tid; i < KP * Lext; i += NT) {
-        const int k = i / Lext;
-        const int q = i - k * Lext;
-        g_l[q * KP + k] = k < K ? gs[(int64_t)k * L + ext_lo + q] : (G)0;
-    }
+    // own state in: [k][t] in HBM -> [j][k] in LDS, padding zeroed
     for (int i = tid; i < KP * Lm; i += NT) {
         const int k = i / Lm;
         const int j = i - k * Lm;
+        g_l[j * KP + k] = k < K ? gs[(int64_t)k * L + b + j] : (G)0;
         z_l[j * KP + k] = k < K ? (G)Zs[(int64_t)k * L + b + j] : (G)0;
     }
     __syncthreads();
@@ -885,7 +896,7 @@ k_lgcd_phase(PhaseArgs a)
         invr[k] = invl[k];
         linvr[k] = linvl[k];
     }
-    int tlo = INT_MAX, thi = -1;  // positions whose g changed (written back)
+    int tlo = INT_MAX, thi = -1;  // own positions whose g changed (written back)
     if (DI) {
         // messages of the previous phase: the left neighbour's rightwards box,
         // then the right neighbour's leftwards box, each in the order sent;
@@ -900,29 +911,79 @@ k_lgcd_phase(PhaseArgs a)
             const DicodMsg* mb = a.msg + box * a.msg_cap;
             for (uint32_t i = 0; i < cnt; ++i) {
                 const DicodMsg mg = mb[i];
-                const int q0m = mg.t0 - b;
+                const int j0m = mg.t0 - b;
                 const G dm = (G)mg.delta;
-                const int mlo = q0m - (W - 1) > 0 ? q0m - (W - 1) : 0;
-                const int mhi = q0m + (W - 1) < Lext - 1 ? q0m + (W - 1) : Lext - 1;
+                const int mlo = j0m - (W - 1) > 0 ? j0m - (W - 1) : 0;
+                const int mhi = j0m + (W - 1) < Lm - 1 ? j0m + (W - 1) : Lm - 1;
                 tlo = mlo < tlo ? mlo : tlo;
                 thi = mhi > thi ? mhi : thi;
                 const G* __restrict__ Sk = St + (size_t)mg.k0 * nd * KP;
                 static_for<NQ>([&](auto ic) __attribute__((always_inline)) {
                     constexpr int i2 = decltype(ic)::value;
-                    const int q = tid + i2 * NT;
-                    const int dj = q - q0m + (W - 1);
-                    if (q >= Lext || dj < 0 || dj >= nd)
+                    const int j = tid + i2 * NT;
+                    const int dj = j - j0m + (W - 1);
+                    if (j >= Lm || dj < 0 || dj >= nd)
                         return;
                     KeyT kd = KO::null();
                     G dd = (G)0;
-                    typename Vec<G>::T sv[KQ];
+                    V sv[KQ];
                     load_s_row<G, KQ>(Sk + (size_t)dj * KP, sv);
-                    visit<G, KQ>(g_l + q * KP, nullptr, true, sv, dm, n2r, invr, linvr, n2l,
+                    visit<G, KQ>(g_l + j * KP, nullptr, true, sv, dm, n2r, invr, linvr, n2l,
                                  invl, linvl, lam, 0u, kd, dd);
                 });
             }
         }
     }
+
+    // Halo records recs[0..cnt) applied to the state in HBM, each halo
+    // position by one thread, records in update order (the same operations
+    // in the same order as applying them at each update); atoms in groups of
+    // four vectors to bound the registers.
+    auto flush_halo = [&](int cnt) __attribute__((always_inline)) {
+        constexpr int GV = KQ < 4 ? KQ : 4;
+        const int n_hl = b - ext_lo;
+        const int n_h = n_hl + (ext_hi - sd.e);
+        for (int h = tid; h < n_h; h += NT) {
+            const int t = h < n_hl ? ext_lo + h : sd.e + (h - n_hl);
+#pragma unroll
+            for (int c0 = 0; c0 < KQ; c0 += GV) {
+                bool touched = false;
+                V gv[GV];
+                for (int r = 0; r < cnt; ++r) {
+                    const HaloRec<G> rc = recs[r];
+                    const int dj = t - rc.t0 + (W - 1);
+                    if (dj < 0 || dj >= nd)
+                        continue;
+                    if (!touched) {
+#pragma unroll
+                        for (int c = 0; c < GV; ++c)
+#pragma unroll
+                            for (int e = 0; e < Vec<G>::N; ++e) {
+                                const int k = (c0 + c) * Vec<G>::N + e;
+                                gv[c][e] = (c0 + c < KQ && k < K) ? gs[(int64_t)k * L + t] : (G)0;
+                            }
+                        touched = true;
+                    }
+                    const V* srow = reinterpret_cast<const V*>(
+                        St + ((size_t)rc.k0 * nd + dj) * KP);
+#pragma unroll
+                    for (int c = 0; c < GV; ++c)
+                        if (c0 + c < KQ)
+                            gv[c] -= srow[c0 + c] * rc.delta;
+                }
+                if (touched) {
+#pragma unroll
+                    for (int c = 0; c < GV; ++c)
+#pragma unroll
+                        for (int e = 0; e < Vec<G>::N; ++e) {
+                            const int k = (c0 + c) * Vec<G>::N + e;
+                            if (c0 + c < KQ && k < K)
+                                gs[(int64_t)k * L + t] = gv[c][e];
+                        }
+                }
+            }
+        }
+    };
 
     KeyT best[NQ];
     G dl[NQ];
@@ -930,11 +991,10 @@ k_lgcd_phase(PhaseArgs a)
         constexpr int i = decltype(ic)::value;
         best[i] = KO::null();
         dl[i] = (G)0;
-        const int q = tid + i * NT;
-        const int j = q - off;
-        if (q < Lext && j >= 0 && j < Lm) {
-            typename Vec<G>::T sv[KQ];  // unused: no update in this pass
-            visit<G, KQ>(g_l + q * KP, z_l + j * KP, false, sv, (G)0, n2r, invr, linvr, n2l,
+        const int j = tid + i * NT;
+        if (j < Lm) {
+            V sv[KQ];  // unused: no update in this pass
+            visit<G, KQ>(g_l + j * KP, z_l + j * KP, false, sv, (G)0, n2r, invr, linvr, n2l,
                          invl, linvl, lam, (unsigned)(j * KP), best[i], dl[i]);
         }
     });
@@ -945,7 +1005,7 @@ k_lgcd_phase(PhaseArgs a)
     block_argmax<G, NQ, NT>(best, dl, slots + (it & 1) * NW, kb, db);
     ++it;
 
-    int n = 0;
+    int n = 0, nrec = 0;
     bool conv = false;
     bool touch_l = false, touch_r = false;
     unsigned n_msg_l = 0, n_msg_r = 0;
@@ -959,18 +1019,17 @@ k_lgcd_phase(PhaseArgs a)
         const unsigned kidx = KO::index(kb);
         const int j0 = (int)(kidx / (unsigned)KP);  // keys index j * KP + k
         const int k0 = (int)kidx - j0 * KP;
-        const int q0 = j0 + off;
         const G delta = db;
-        const int wlo = q0 - (W - 1) > 0 ? q0 - (W - 1) : 0;
-        const int whi = q0 + (W - 1) < Lext - 1 ? q0 + (W - 1) : Lext - 1;
+        const int wlo = j0 - (W - 1) > 0 ? j0 - (W - 1) : 0;
+        const int whi = j0 + (W - 1) < Lm - 1 ? j0 + (W - 1) : Lm - 1;
         const G* __restrict__ Sk = St + (size_t)k0 * nd * KP;
 
-        if (tid == (q0 % NT)) {
+        if (tid == (j0 % NT)) {
             // Owner of the updated position: new Z value (exactly 0 when the
             // soft threshold is active), in LDS and in the double-precision Z.
             const G zo = z_l[j0 * KP + k0];
             bool zr;
-            (void)coord_delta<G>(g_l[q0 * KP + k0], zo, n2l[k0], invl[k0], linvl[k0], lam, &zr);
+            (void)coord_delta<G>(g_l[j0 * KP + k0], zo, n2l[k0], invl[k0], linvl[k0], lam, &zr);
             const G zn = zr ? (G)0 : zo + delta;
             z_l[j0 * KP + k0] = zn;
             double* zp = Zs + (int64_t)k0 * L + b + j0;
@@ -999,49 +1058,65 @@ k_lgcd_phase(PhaseArgs a)
 
         tlo = wlo < tlo ? wlo : tlo;
         thi = whi > thi ? whi : thi;
-        const bool to_l = q0 - (W - 1) < off && sd.left >= 0;
-        const bool to_r = q0 + (W - 1) >= off + Lm && sd.right >= 0;
-        if (DI && tid == (q0 % NT) && (to_l || to_r)) {
-            // the update as sent: the delta this segment applied to g
-            DicodMsg mg;
-            mg.k0 = k0;
-            mg.t0 = b + j0;
-            mg.delta = (double)delta;
-            if (to_l)
-                a.msg[(((size_t)par * a.n_seg + sid) * 2 + 0) * a.msg_cap + n_msg_l] = mg;
-            if (to_r)
-                a.msg[(((size_t)par * a.n_seg + sid) * 2 + 1) * a.msg_cap + n_msg_r] = mg;
+        const bool to_l = j0 - (W - 1) < 0 && sd.left >= 0;
+        const bool to_r = j0 + (W - 1) >= Lm && sd.right >= 0;
+        if (tid == (j0 % NT) && (to_l || to_r)) {
+            if (DI) {
+                // the update as sent: the delta this segment applied to g
+                DicodMsg mg;
+                mg.k0 = k0;
+                mg.t0 = b + j0;
+                mg.delta = (double)delta;
+                if (to_l)
+                    a.msg[(((size_t)par * a.n_seg + sid) * 2 + 0) * a.msg_cap + n_msg_l] = mg;
+                if (to_r)
+                    a.msg[(((size_t)par * a.n_seg + sid) * 2 + 1) * a.msg_cap + n_msg_r] = mg;
+            } else {
+                HaloRec<G> rc;
+                rc.k0 = k0;
+                rc.t0 = b + j0;
+                rc.delta = delta;
+                recs[nrec] = rc;
+            }
         }
         n_msg_l += to_l ? 1 : 0;
         n_msg_r += to_r ? 1 : 0;
+        nrec += (!DI && (to_l || to_r)) ? 1 : 0;
         touch_l |= to_l;
         touch_r |= to_r;
 
         static_for<NQ>([&](auto ic) __attribute__((always_inline)) {
             constexpr int i = decltype(ic)::value;
-            const int q = tid + i * NT;
-            if (q < wlo || q > whi)
+            const int j = tid + i * NT;
+            if (j < wlo || j > whi)
                 return;
-            const int j = q - off;
-            const bool own = j >= 0 && j < Lm;
-            typename Vec<G>::T sv[KQ];
-            load_s_row<G, KQ>(Sk + (size_t)(q - q0 + (W - 1)) * KP, sv);
-            visit<G, KQ>(g_l + q * KP, own ? z_l + j * KP : nullptr, true, sv, delta, n2r,
-                         invr, linvr, n2l, invl, linvl, lam, (unsigned)(j * KP), best[i],
-                         dl[i]);
+            V sv[KQ];
+            load_s_row<G, KQ>(Sk + (size_t)(j - j0 + (W - 1)) * KP, sv);
+            visit<G, KQ>(g_l + j * KP, z_l + j * KP, true, sv, delta, n2r, invr, linvr, n2l,
+                         invl, linvl, lam, (unsigned)(j * KP), best[i], dl[i]);
         });
         ++n;
         block_argmax<G, NQ, NT>(best, dl, slots + (it & 1) * NW, kb, db);
         ++it;
+        if (!DI && nrec == kHaloRecs) {
+            // full record list (the records are visible after the barrier in
+            // block_argmax): apply it, and let every thread finish reading it
+            // before it is reused
+            flush_halo(nrec);
+            nrec = 0;
+            __syncthreads();
+        }
     }
+    if (!DI && nrec > 0)
+        flush_halo(nrec);
 
     if (thi >= tlo) {
-        // g of every position changed by an update or a message
+        // own g of every position changed by an update or a message
         const int wdt = thi - tlo + 1;
         for (int i = tid; i < K * wdt; i += NT) {
             const int k = i / wdt;
-            const int q = tlo + (i - k * wdt);
-            gs[(int64_t)k * L + ext_lo + q] = g_l[q * KP + k];
+            const int j = tlo + (i - k * wdt);
+            gs[(int64_t)k * L + b + j] = g_l[j * KP + k];
         }
     }
     if (n > 0) {
@@ -1100,13 +1175,15 @@ int lgcd_k_padded(int K, bool fp64)
 
 size_t lgcd_lds_bytes(int K, int lm_max, int lext_max, bool fp64)
 {
+    (void)lext_max;  // the halo stays in HBM
     const int KP = lgcd_k_padded(K, fp64);
     if (KP < 0)
         return (size_t)-1;
     const size_t e = fp64 ? sizeof(double) : sizeof(float);
     const size_t slots = 2 * (kPhaseThreadsMax / 64) *
                          (fp64 ? sizeof(Slot<double>) : sizeof(Slot<float>));
-    return slot_offset(e, KP, lext_max, lm_max) + slots + 3 * e * (size_t)KP;
+    const size_t recs = kHaloRecs * (fp64 ? sizeof(HaloRec<double>) : sizeof(HaloRec<float>));
+    return slot_offset(e, KP, lm_max, lm_max) + slots + 3 * e * (size_t)KP + 16 + recs;
 }
 
 template <typename G, int KQ, int NQ, int NT>
@@ -1132,9 +1209,9 @@ template <typename G, int KQ>
 static hipError_t launch_phase_kq(const PhaseArgs& a, size_t lds, hipStream_t s)
 {
     constexpr bool wide = false;  // measured slower than 512 threads on gfx950
-    if (wide && a.lext_max <= kPhaseThreadsMax)
+    if (wide && a.lm_max <= kPhaseThreadsMax)
         return launch_phase_inst<G, KQ, 1, (wide ? kPhaseThreadsMax : kPhaseThreads)>(a, lds, s);
-    switch ((a.lext_max + kPhaseThreads - 1) / kPhaseThreads) {
+    switch ((a.lm_max + kPhaseThreads - 1) / kPhaseThreads) {
     case 1: return launch_phase_inst<G, KQ, 1, kPhaseThreads>(a, lds, s);
     case 2: return launch_phase_inst<G, KQ, 2, kPhaseThreads>(a, lds, s);
     case 3: return launch_phase_inst<G, KQ, 3, kPhaseThreads>(a, lds, s);
@@ -1148,7 +1225,7 @@ hipError_t launch_lgcd_phase(const PhaseArgs& a, bool fp64, size_t* lds_bytes,
 {
     if (a.n_list <= 0)
         return hipSuccess;
-    const int nq = (a.lext_max + kPhaseThreads - 1) / kPhaseThreads;
+    const int nq = (a.lm_max + kPhaseThreads - 1) / kPhaseThreads;
     if (nq < 1 || nq > 4)
         return hipErrorInvalidValue;
     const size_t lds = lgcd_lds_bytes(a.K, a.lm_max, a.lext_max, fp64);

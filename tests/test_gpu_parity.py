@@ -215,12 +215,15 @@ def test_paper_shaped_segment_sweep(dicod, paper_problem, M):
     _check_solution(X, D, lam, Z, st, Zo)
 
 
-def test_paper_shaped_fp64_hbm_state(dicod, paper_problem):
-    print("\ncase: paper-shaped FP64 (double state in HBM)", flush=True)
+@pytest.mark.parametrize("lds", [1, 0])
+def test_paper_shaped_fp64(dicod, paper_problem, lds):
+    """Double state of the paper-shaped segments: on chip (own positions in
+    LDS, halo changes applied in HBM) or, forced, entirely in HBM."""
+    print(f"\ncase: paper-shaped FP64 state_in_lds={lds}", flush=True)
     X, D, lam, Zo = paper_problem
-    with ctx_of(dicod, precision=dicod.DICOD_PREC_FP64) as c:
+    with ctx_of(dicod, precision=dicod.DICOD_PREC_FP64, state_in_lds=lds) as c:
         Z, st = c.solve(X, -0.1, EPS, n_seg=0, D=D)
-    assert st["state_in_hbm"] == 1 and st["n_refresh"] == 0
+    assert st["state_in_hbm"] == 1 - lds and st["n_refresh"] == 0
     _check_solution(X, D, lam, Z, st, Zo)
 
 
