@@ -65,7 +65,8 @@ struct Workspace {
     DevBuf X, Zout;                       // staging for the host-pointer API
     DevBuf beta0, g, g64;                 // [K][L] per signal (g64: double finish)
     DevBuf sig, segs, lists[kMaxColors];
-    DevBuf tilesL, tilesT, tilesA;
+    DevBuf tilesL, tilesT, tilesA, tilesN;
+    DevBuf nzmask;                        // non-zero masks of Z for the check kernels
     DevBuf dirty, phase_upd, sig_upd, sig_last, counters;
     DevBuf part_r2, part6, results, lmax, done, thr;
     DevBuf msg, msg_n;                    // DICOD schedule: boundary messages
@@ -344,9 +345,11 @@ extern "C" int dicod_set_dictionary(dicod_ctx* ctx, const float* D, int K, int P
                                      ctx->n2_32.as<float>(), ctx->inv32.as<float>(), s));
     for (int f64 = 0; f64 < 2; ++f64) {
         const int KP = lgcd_k_padded(K, f64 != 0);
-        if (KP < 0)
-            continue;  // the phase kernel reports ENOTSUP for this K
         DevBuf& St = f64 ? ctx->St64 : ctx->St32;
+        if (KP < 0) {
+            St.release();  // no stale table of a previous dictionary
+            continue;      // the phase kernel reports ENOTSUP for this K
+        }
         HIPCHECK(ctx, ensure(St, (size_t)K * nd * KP * (f64 ? sizeof(double) : sizeof(float))));
         HIPCHECK(ctx, launch_s_transpose(ctx->S64.as<double>(), K, W, f64 != 0, St.p, s));
     }
@@ -385,7 +388,7 @@ struct Plan {
     std::vector<int32_t> list[kMaxColors];
     int colors = 2;   // phase classes; 1 for the DICOD schedule (all segments)
     bool dicod = false;
-    std::vector<int64_t> prefL, prefT, prefA;
+    std::vector<int64_t> prefL, prefT, prefA, prefN;  // prefN: non-zero mask words
     int lm_max = 0, lext_max = 0;
     size_t zext = 0;  // extent of the [K][L] arrays (elements)
 };
@@ -409,13 +412,13 @@ int make_plan(dicod_ctx* ctx, int n_sig, const int64_t* T, const int64_t* x_off,
 {
     const int K = ctx->K, W = ctx->W;
     const bool fp64 = ctx->cfg.precision == DICOD_PREC_FP64;
-    (void)K;
     pl.dicod = ctx->cfg.schedule == DICOD_SCHED_DICOD;
     pl.colors = pl.dicod ? 1 : ctx->cfg.colors;
     pl.sig.resize(n_sig);
     pl.prefL.assign(n_sig + 1, 0);
     pl.prefT.assign(n_sig + 1, 0);
     pl.prefA.assign(n_sig + 1, 0);
+    pl.prefN.assign(n_sig + 1, 0);
     for (int i = 0; i < n_sig; ++i) {
         if (T[i] < W)
             return fail(ctx, DICOD_EINVAL, "signal %d: T=%lld < W=%d", i, (long long)T[i], W);
@@ -457,6 +460,7 @@ int make_plan(dicod_ctx* ctx, int n_sig, const int64_t* T, const int64_t* x_off,
         s.M = M;
         s.lam = lam[i];
         s.eps_stop = 0.0;
+        s.nz_off = pl.prefN[i];
         for (int m = 0; m < M; ++m) {
             SegDesc d;
             d.z_off = z_off[i];
@@ -472,6 +476,7 @@ int make_plan(dicod_ctx* ctx, int n_sig, const int64_t* T, const int64_t* x_off,
         pl.prefL[i + 1] = pl.prefL[i] + ceil_div(L, kTile);
         pl.prefT[i + 1] = pl.prefT[i] + ceil_div(T[i], kTile);
         pl.prefA[i + 1] = pl.prefA[i] + ceil_div((int64_t)K * L, kAbsChunk);
+        pl.prefN[i + 1] = pl.prefN[i] + (int64_t)K * ceil_div(L, 64);
         pl.zext = std::max(pl.zext, (size_t)(z_off[i] + (int64_t)K * L));
     }
     return DICOD_OK;
@@ -526,6 +531,7 @@ int solve_device_batch(dicod_ctx* ctx, int n_sig, const float* dX, const int64_t
         return rc;
     const int n_seg_tot = (int)pl.segs.size();
     const int64_t nL = pl.prefL[n_sig], nT = pl.prefT[n_sig], nA = pl.prefA[n_sig];
+    const int64_t nN = pl.prefN[n_sig];
     const int n_kblk = (K + kMaxK - 1) / kMaxK;
     const int64_t max_ph = std::min<int64_t>(cfg.max_phases, (int64_t)1 << 22);
 
@@ -542,6 +548,7 @@ int solve_device_batch(dicod_ctx* ctx, int n_sig, const float* dX, const int64_t
     HIPCHECK(ctx, ensure(ws.sig_last, n_sig * sizeof(int)));
     HIPCHECK(ctx, ensure(ws.counters, sizeof(Counters)));
     HIPCHECK(ctx, ensure(ws.part_r2, nT * sizeof(double)));
+    HIPCHECK(ctx, ensure(ws.nzmask, nN * sizeof(unsigned long long)));
     HIPCHECK(ctx, ensure(ws.part6, (size_t)nL * n_kblk * 6 * sizeof(double)));
     HIPCHECK(ctx, ensure(ws.results, n_sig * sizeof(CheckResult)));
     HIPCHECK(ctx, ensure(ws.lmax, n_sig * sizeof(unsigned long long)));
@@ -565,6 +572,7 @@ int solve_device_batch(dicod_ctx* ctx, int n_sig, const float* dX, const int64_t
     HIPCHECK(ctx, upload(ws.tilesL, pl.prefL, s));
     HIPCHECK(ctx, upload(ws.tilesT, pl.prefT, s));
     HIPCHECK(ctx, upload(ws.tilesA, pl.prefA, s));
+    HIPCHECK(ctx, upload(ws.tilesN, pl.prefN, s));
 
     hipEvent_t ev0 = pool_event(ctx, 0), ev1 = pool_event(ctx, 1);
     hipEvent_t ev2 = pool_event(ctx, 2), ev3 = pool_event(ctx, 3);
@@ -823,9 +831,14 @@ int solve_device_batch(dicod_ctx* ctx, int n_sig, const float* dX, const int64_t
         const double* g_in = (cur64 && !cfg.verify_from_scratch)
                                  ? (fp64 ? ws.g.as<double>() : ws.g64.as<double>())
                                  : nullptr;
-        HIPCHECK(ctx, launch_resid(dX, ctx->D64.as<double>(), dZ, K, P, W, ws.sig.as<SigDesc>(),
-                                   ws.tilesT.as<int64_t>(), n_sig, nT, ws.part_r2.as<double>(), s));
-        HIPCHECK(ctx, launch_grad_check(ws.beta0.as<double>(), dZ, ctx->S64.as<double>(),
+        const unsigned long long* masks = ws.nzmask.as<unsigned long long>();
+        HIPCHECK(ctx, launch_nz_mask(dZ, ws.sig.as<SigDesc>(), ws.tilesN.as<int64_t>(), n_sig, K,
+                                     nN, ws.nzmask.as<unsigned long long>(), s));
+        HIPCHECK(ctx, launch_resid(dX, ctx->D64.as<double>(), dZ, masks, K, P, W,
+                                   ws.sig.as<SigDesc>(), ws.tilesT.as<int64_t>(), n_sig, nT,
+                                   ws.part_r2.as<double>(), s));
+        HIPCHECK(ctx, launch_grad_check(ws.beta0.as<double>(), dZ, masks, ctx->S64.as<double>(),
+                                        ctx->St64.as<double>(),
                                         ctx->n2_64.as<double>(), K, W, ws.sig.as<SigDesc>(),
                                         ws.tilesL.as<int64_t>(), n_sig, nL, flag_eps,
                                         ws.done.as<uint32_t>(), ws.dirty.as<uint32_t>(),

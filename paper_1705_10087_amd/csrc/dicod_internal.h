@@ -31,6 +31,7 @@ struct SigDesc {
     int32_t M;        // number of segments
     double lam;       // lambda used
     double eps_stop;  // a segment run stops when its best |Delta Z| is below this
+    int64_t nz_off;   // first word of its non-zero masks of Z ([K][ceil(L / 64)])
 };
 
 // One time segment C_m of one signal.
@@ -147,16 +148,25 @@ int lgcd_k_padded(int K, bool fp64);
 hipError_t launch_s_transpose(const double* S64, int K, int W, bool fp64, void* St,
                               hipStream_t s);
 
+// Non-zero masks of Z for the check kernels: bit i of word
+// masks[sig.nz_off + k * ceil(L / 64) + b] tells Z_k[64 b + i] != 0.
+// mask_pref: prefix of the signals' word counts (n_sig + 1 entries).
+hipError_t launch_nz_mask(const double* Z, const SigDesc* sig, const int64_t* mask_pref,
+                          int n_sig, int K, int64_t n_words, unsigned long long* masks,
+                          hipStream_t s);
 // Double-precision check: residual energy per tile (partials).
-hipError_t launch_resid(const float* X, const double* D, const double* Z, int K,
-                        int P, int W, const SigDesc* sig, const int64_t* tile_pref,
-                        int n_sig, int64_t n_tiles, double* part_r2,
-                        hipStream_t s);
+hipError_t launch_resid(const float* X, const double* D, const double* Z,
+                        const unsigned long long* masks, int K, int P, int W,
+                        const SigDesc* sig, const int64_t* tile_pref, int n_sig,
+                        int64_t n_tiles, double* part_r2, hipStream_t s);
 // g = beta0 - S * Z, candidates in double, KKT partials, dirty flags for
 // segments holding a coordinate with |Delta Z| >= flag_eps, optional refresh
 // of the state g (float or double).
+// St64 (optional): the lag-major copy St[l][d][k] of S for faster gathers.
 hipError_t launch_grad_check(const double* beta0, const double* Z,
-                             const double* S64, const double* n2, int K, int W,
+                             const unsigned long long* masks,
+                             const double* S64, const double* St64, const double* n2,
+                             int K, int W,
                              const SigDesc* sig, const int64_t* tile_pref, int n_sig,
                              int64_t n_tiles, double flag_eps, const uint32_t* sig_done,
                              uint32_t* dirty, void* g_state, bool state_fp64,

@@ -206,8 +206,8 @@ struct Lane {
     int queued = 0;             // requests of this lane in the queue (mu)
     uint64_t blocked = ~0ull;   // epoch at which admission last found no room (mu)
     std::string msg;            // last HIP failure
-    Mem dRing, dLists, dSub, dTilesL, dTilesT, dTilesA, dPartR2, dPart6, dRes, dLmax, dDone,
-        dSlots, dLamIn;
+    Mem dRing, dLists, dSub, dTilesL, dTilesT, dTilesA, dTilesN, dPartR2, dPart6, dRes, dLmax,
+        dDone, dSlots, dLamIn, dMask;
     unsigned long long* h_ring = nullptr;
     unsigned long long* h_sigupd = nullptr;
     unsigned long long* h_lmax = nullptr;
@@ -245,7 +245,7 @@ struct Server {
     std::vector<int> free_slots;
     RangeAlloc coef, samp, segr;
     int slots = 0;
-    int64_t seg_cap = 0, tilesL_cap = 0, tilesT_cap = 0;
+    int64_t seg_cap = 0, tilesL_cap = 0, tilesT_cap = 0, mask_cap = 0;
     int chunk = 16;
     // shared device state, indexed by ranges and slots
     Mem dX, dZ, dB, dG32, dG64, dSig, dSeg, dDirty, dSigUpd, dSigLast, dCnt;
@@ -292,6 +292,8 @@ int Lane::start()
     SRV_HIP(dTilesL.alloc((size_t)(slots + 1) * sizeof(int64_t)));
     SRV_HIP(dTilesT.alloc((size_t)(slots + 1) * sizeof(int64_t)));
     SRV_HIP(dTilesA.alloc((size_t)(slots + 1) * sizeof(int64_t)));
+    SRV_HIP(dTilesN.alloc((size_t)(slots + 1) * sizeof(int64_t)));
+    SRV_HIP(dMask.alloc((size_t)srv->mask_cap * sizeof(unsigned long long)));
     SRV_HIP(dPartR2.alloc((size_t)srv->tilesT_cap * sizeof(double)));
     SRV_HIP(dPart6.alloc((size_t)srv->tilesL_cap * n_kblk * 6 * sizeof(double)));
     SRV_HIP(dRes.alloc((size_t)slots * sizeof(CheckResult)));
@@ -324,8 +326,8 @@ void Lane::teardown()
         th.join();
     if (s)
         (void)hipStreamSynchronize(s);
-    for (Mem* m : {&dRing, &dLists, &dSub, &dTilesL, &dTilesT, &dTilesA, &dPartR2, &dPart6,
-                   &dRes, &dLmax, &dDone, &dSlots, &dLamIn})
+    for (Mem* m : {&dRing, &dLists, &dSub, &dTilesL, &dTilesT, &dTilesA, &dTilesN, &dPartR2,
+                   &dPart6, &dRes, &dLmax, &dDone, &dSlots, &dLamIn, &dMask})
         m->release();
     for (void* p : {(void*)h_stage, (void*)h_ring, (void*)h_sigupd, (void*)h_lmax,
                     (void*)h_res})
@@ -356,6 +358,8 @@ int Server::start(dicod_ctx* c)
         budget = std::min<size_t>((size_t)(0.8 * (double)fr), (size_t)16 << 30);
     }
     // bytes per coefficient: Z, beta0 and the double g; the float g in FP32
+    // (the lanes' non-zero masks, 1/8 byte per coefficient each, fit in the
+    // 5% left over)
     const int64_t bc = fp64 ? 24 : 28;
     const int64_t bs = 4;
     const double share = (double)(bc * K) / (double)(bc * K + bs * P);
@@ -371,6 +375,8 @@ int Server::start(dicod_ctx* c)
     segr.reset(seg_cap);
     tilesL_cap = n_coef / K / kTile + slots + 1;
     tilesT_cap = n_samp / P / kTile + slots + 1;
+    // each request rounds every atom row up to whole 64-bit words
+    mask_cap = n_coef / 64 + (int64_t)slots * K + 1;
     SRV_HIP(dX.alloc((size_t)n_samp * sizeof(float)));
     SRV_HIP(dZ.alloc((size_t)n_coef * sizeof(double)));
     SRV_HIP(dB.alloc((size_t)n_coef * sizeof(double)));
@@ -644,25 +650,36 @@ int Lane::check_jobs(const std::vector<Job*>& conv)
             const int n = (int)(i1 - i0);
             const double eps = g[i0]->eps;
             std::vector<SigDesc> sub(n);
-            std::vector<int64_t> pL(n + 1, 0), pT(n + 1, 0);
+            std::vector<int64_t> pL(n + 1, 0), pT(n + 1, 0), pN(n + 1, 0);
             for (int i = 0; i < n; ++i) {
                 Job* j = g[i0 + i];
                 sub[i] = v.h_sig[j->slot];
+                sub[i].nz_off = pN[i];
                 pL[i + 1] = pL[i] + ceil_div(j->L, kTile);
                 pT[i + 1] = pT[i] + ceil_div(j->T, kTile);
+                pN[i + 1] = pN[i] + (int64_t)K * ceil_div(j->L, 64);
+            }
+            if (pN[n] > v.mask_cap) {
+                msg = "non-zero mask buffer too small";
+                return DICOD_EDEVICE;
             }
             stage_off = 0;  // the previous group was synchronised
             SRV_HIP(stage(dSub.p, sub.data(), n * sizeof(SigDesc)));
             SRV_HIP(stage(dTilesL.p, pL.data(), (n + 1) * sizeof(int64_t)));
             SRV_HIP(stage(dTilesT.p, pT.data(), (n + 1) * sizeof(int64_t)));
+            SRV_HIP(stage(dTilesN.p, pN.data(), (n + 1) * sizeof(int64_t)));
             const double flag_eps = next64 ? eps : eps * cfg.inner_eps_factor;
             void* g_next = next64 ? v.dG64.p : v.dG32.p;
             const double* g_in =
                 (c64 && !cfg.verify_from_scratch) ? v.dG64.as<double>() : nullptr;
-            SRV_HIP(launch_resid(v.dX.as<float>(), v.dict.D64, v.dZ.as<double>(), K, P, W,
-                                 dSub.as<SigDesc>(), dTilesT.as<int64_t>(), n, pT[n],
-                                 dPartR2.as<double>(), s));
-            SRV_HIP(launch_grad_check(v.dB.as<double>(), v.dZ.as<double>(), v.dict.S64,
+            SRV_HIP(launch_nz_mask(v.dZ.as<double>(), dSub.as<SigDesc>(), dTilesN.as<int64_t>(), n,
+                                   K, pN[n], dMask.as<unsigned long long>(), s));
+            SRV_HIP(launch_resid(v.dX.as<float>(), v.dict.D64, v.dZ.as<double>(),
+                                 dMask.as<unsigned long long>(), K, P, W, dSub.as<SigDesc>(),
+                                 dTilesT.as<int64_t>(), n, pT[n], dPartR2.as<double>(), s));
+            SRV_HIP(launch_grad_check(v.dB.as<double>(), v.dZ.as<double>(),
+                                      dMask.as<unsigned long long>(), v.dict.S64,
+                                      (const double*)v.dict.St64,
                                       (const double*)v.dict.n2_64, K, W, dSub.as<SigDesc>(),
                                       dTilesL.as<int64_t>(), n, pL[n], flag_eps,
                                       dDone.as<uint32_t>(), v.dDirty.as<uint32_t>(),

@@ -1208,7 +1208,9 @@ static hipError_t launch_phase_inst(const PhaseArgs& a, size_t lds, hipStream_t 
 template <typename G, int KQ>
 static hipError_t launch_phase_kq(const PhaseArgs& a, size_t lds, hipStream_t s)
 {
-    constexpr bool wide = false;  // measured slower than 512 threads on gfx950
+    // 512 threads measured faster than 256 (one position per thread) and
+    // than 1024 on gfx950
+    constexpr bool wide = false;
     if (wide && a.lm_max <= kPhaseThreadsMax)
         return launch_phase_inst<G, KQ, 1, (wide ? kPhaseThreadsMax : kPhaseThreads)>(a, lds, s);
     switch ((a.lm_max + kPhaseThreads - 1) / kPhaseThreads) {
@@ -1567,43 +1569,125 @@ struct NzEnt {
 };
 constexpr int kNzCap = 2048;
 
-// Appends up to one round (256 candidates) starting at *pos; returns the
-// number of entries in the list afterwards.  All threads call it.
-__device__ __forceinline__ int nz_round(const double* __restrict__ Zs, int64_t L,
-                                        int s_lo, int ns, int64_t total, int64_t pos,
-                                        NzEnt* __restrict__ list, int cnt,
-                                        int* __restrict__ wcnt)
+// Non-zero masks: word w of a signal is bit i = (Z_k[64 b + i] != 0), with
+// w = k * ceil(L / 64) + b.  One wave per word.
+__global__ void __launch_bounds__(256)
+k_nz_mask(const double* __restrict__ Z, const SigDesc* __restrict__ sig,
+          const int64_t* __restrict__ mask_pref, int n_sig, int K, int64_t n_words,
+          unsigned long long* __restrict__ masks)
 {
-    const int tid = threadIdx.x;
-    const int64_t i = pos + tid;
-    double z = 0.0;
-    int k = 0, s = 0;
-    if (i < total) {
-        k = (int)(i / ns);
-        s = s_lo + (int)(i - (int64_t)k * ns);
-        z = Zs[(int64_t)k * L + s];
+    const int lane = threadIdx.x & 63;
+    const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
+    for (int64_t w = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); w < n_words;
+         w += nw) {
+        const int si = find_sig(mask_pref, n_sig, w);
+        const SigDesc sd = sig[si];
+        const int64_t nb = (sd.L + 63) / 64;
+        const int64_t loc = w - mask_pref[si];
+        const int64_t k = loc / nb;
+        const int64_t t = (loc - k * nb) * 64 + lane;
+        const double z = (k < K && t < sd.L) ? Z[sd.z_off + k * sd.L + t] : 0.0;
+        const unsigned long long m = __ballot(z != 0.0);
+        if (lane == 0)
+            masks[w] = m;
     }
-    const bool f = z != 0.0;
-    const unsigned long long mask = __ballot(f);
-    const int lane = tid & 63;
-    const int wave = tid >> 6;
-    const int pre = __popcll(mask & ((1ull << lane) - 1ull));
-    if (lane == 0)
-        wcnt[wave] = __popcll(mask);
+}
+
+hipError_t launch_nz_mask(const double* Z, const SigDesc* sig, const int64_t* mask_pref,
+                          int n_sig, int K, int64_t n_words, unsigned long long* masks,
+                          hipStream_t s)
+{
+    if (n_words <= 0)
+        return hipSuccess;
+    const int64_t blocks = (n_words + 3) / 4;
+    hipLaunchKernelGGL(k_nz_mask, dim3((unsigned)(blocks < 65536 ? blocks : 65536)), dim3(256),
+                       0, s, Z, sig, mask_pref, n_sig, K, n_words, masks);
+    return hipGetLastError();
+}
+
+// Exclusive prefix sum of v over the 256 threads; *total gets the sum.
+// All threads call it.
+__device__ __forceinline__ int block_scan256(int v, int* total, int* wsum)
+{
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    int x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(x, o);
+        if (lane >= o)
+            x += y;
+    }
+    if (lane == 63)
+        wsum[wave] = x;
     __syncthreads();
-    int woff = 0;
-    for (int w = 0; w < wave; ++w)
-        woff += wcnt[w];
-    const int tot = wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3];
-    if (f) {
-        NzEnt e;
-        e.k = k;
-        e.s = s;
-        e.z = z;
-        list[cnt + woff + pre] = e;
+    int base = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+        base += w < wave ? wsum[w] : 0;
+        tot += wsum[w];
     }
     __syncthreads();
-    return cnt + tot;
+    *total = tot;
+    return base + x - v;
+}
+
+// Calls fn(list, cnt) (all threads, between barriers) for the non-zeros
+// Z_k[s], s in [s_lo, s_hi), in (k, s) order, in chunks of at most kNzCap
+// gathered in LDS from the signal's non-zero masks msk ([K][ceil(L / 64)]).
+// All threads call it with the same window.
+template <typename F>
+__device__ __forceinline__ void for_nonzeros(const unsigned long long* __restrict__ msk,
+                                             const double* __restrict__ Zs, int64_t L, int K,
+                                             int s_lo, int s_hi, NzEnt* __restrict__ list,
+                                             int* __restrict__ wsum, F&& fn)
+{
+    if (s_hi <= s_lo)
+        return;
+    const int64_t nb = (L + 63) / 64;
+    const int b_lo = s_lo >> 6;
+    const int nbw = ((s_hi - 1) >> 6) - b_lo + 1;
+    const int items = K * nbw;
+    for (int i0 = 0; i0 < items; i0 += 256) {
+        const int it = i0 + (int)threadIdx.x;
+        unsigned long long m = 0ull;
+        int k = 0, bb = 0;
+        if (it < items) {
+            k = it / nbw;
+            bb = b_lo + (it - k * nbw);
+            m = msk[(int64_t)k * nb + bb];
+            const int lo = s_lo - bb * 64;  // keep bits [lo, hi)
+            const int hi = s_hi - bb * 64;
+            if (lo > 0)
+                m &= ~0ull << lo;
+            if (hi < 64)
+                m &= (1ull << hi) - 1ull;  // hi >= 1: block bb starts below s_hi
+        }
+        const int cnt_m = __popcll(m);
+        int tot;
+        const int off = block_scan256(cnt_m, &tot, wsum);
+        for (int base = 0; base < tot; base += kNzCap) {
+            if (cnt_m > 0 && off < base + kNzCap && off + cnt_m > base) {
+                unsigned long long mm = m;
+                int idx = off;
+                while (mm && idx < base + kNzCap) {
+                    const int bit = __ffsll(mm) - 1;
+                    mm &= mm - 1ull;
+                    if (idx >= base) {
+                        NzEnt e;
+                        e.k = k;
+                        e.s = bb * 64 + bit;
+                        e.z = Zs[(int64_t)k * L + e.s];
+                        list[idx - base] = e;
+                    }
+                    ++idx;
+                }
+            }
+            __syncthreads();
+            fn(list, tot - base < kNzCap ? tot - base : kNzCap);
+            __syncthreads();
+        }
+    }
 }
 
 __device__ __forceinline__ double block_sum256(double v, double* red)
@@ -1634,7 +1718,8 @@ __device__ __forceinline__ double block_max256(double v, double* red)
 // the convolution taken over the non-zeros of Z only (model eq. (1)).
 __global__ void __launch_bounds__(256)
 k_resid(const float* __restrict__ X, const double* __restrict__ D,
-        const double* __restrict__ Z, int K, int P, int W,
+        const double* __restrict__ Z, const unsigned long long* __restrict__ masks, int K,
+        int P, int W,
         const SigDesc* __restrict__ sig, const int64_t* __restrict__ tile_pref,
         int n_sig, double* __restrict__ part)
 {
@@ -1660,28 +1745,20 @@ k_resid(const float* __restrict__ X, const double* __restrict__ D,
     }
     const int s_lo = t_a - (W - 1) > 0 ? (int)(t_a - (W - 1)) : 0;
     const int s_hi = t_a + kTile < sd.L ? (int)(t_a + kTile) : (int)sd.L;
-    const int ns = s_hi > s_lo ? s_hi - s_lo : 0;
-    const int64_t total = (int64_t)K * ns;
-    int64_t pos = 0;
-    while (pos < total) {
-        int cnt = 0;
-        while (pos < total && cnt <= kNzCap - 256) {
-            cnt = nz_round(Zs, sd.L, s_lo, ns, total, pos, list, cnt, wcnt);
-            pos += 256;
-        }
-        for (int e = 0; e < cnt; ++e) {
-            const NzEnt ne = list[e];
-            const int64_t tau = t - ne.s;
-            if (tau >= 0 && tau < W) {
-                const double* __restrict__ drow = D + (int64_t)ne.k * P * W + tau;
+    for_nonzeros(masks + sd.nz_off, Zs, sd.L, K, s_lo, s_hi, list, wcnt,
+                 [&](const NzEnt* lst, int cnt) {
+                     for (int e = 0; e < cnt; ++e) {
+                         const NzEnt ne = lst[e];
+                         const int64_t tau = t - ne.s;
+                         if (tau >= 0 && tau < W) {
+                             const double* __restrict__ drow = D + (int64_t)ne.k * P * W + tau;
 #pragma unroll
-                for (int p = 0; p < kMaxP; ++p)
-                    if (p < P)
-                        acc[p] -= ne.z * drow[(int64_t)p * W];
-            }
-        }
-        __syncthreads();
-    }
+                             for (int p = 0; p < kMaxP; ++p)
+                                 if (p < P)
+                                     acc[p] -= ne.z * drow[(int64_t)p * W];
+                         }
+                     }
+                 });
     double e2 = 0.0;
     if (t < sd.T) {
 #pragma unroll
@@ -1694,13 +1771,14 @@ k_resid(const float* __restrict__ X, const double* __restrict__ D,
         part[tile] = e2;
 }
 
-hipError_t launch_resid(const float* X, const double* D, const double* Z, int K,
-                        int P, int W, const SigDesc* sig, const int64_t* tile_pref,
-                        int n_sig, int64_t n_tiles, double* part_r2, hipStream_t s)
+hipError_t launch_resid(const float* X, const double* D, const double* Z,
+                        const unsigned long long* masks, int K, int P, int W,
+                        const SigDesc* sig, const int64_t* tile_pref, int n_sig,
+                        int64_t n_tiles, double* part_r2, hipStream_t s)
 {
     if (P > kMaxP)
         return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_resid, dim3((unsigned)n_tiles), dim3(256), 0, s, X, D, Z, K,
+    hipLaunchKernelGGL(k_resid, dim3((unsigned)n_tiles), dim3(256), 0, s, X, D, Z, masks, K,
                        P, W, sig, tile_pref, n_sig, part_r2);
     return hipGetLastError();
 }
@@ -1711,7 +1789,8 @@ hipError_t launch_resid(const float* X, const double* D, const double* Z, int K,
 // part6 per tile: max|dz|, kkt_on, kkt_off, l1, max|z|, nnz.
 __global__ void __launch_bounds__(256)
 k_grad_check(const double* __restrict__ beta0, const double* __restrict__ Z,
-             const double* __restrict__ S64, const double* __restrict__ n2v, int K,
+             const unsigned long long* __restrict__ masks, const double* __restrict__ S64, const double* __restrict__ St64, int KP,
+             const double* __restrict__ n2v, int K,
              int W, const SigDesc* __restrict__ sig,
              const int64_t* __restrict__ tile_pref, int n_sig, double flag_eps,
              const uint32_t* __restrict__ sig_done, uint32_t* __restrict__ dirty,
@@ -1745,30 +1824,60 @@ k_grad_check(const double* __restrict__ beta0, const double* __restrict__ Z,
     const int s_lo = t_a - (W - 1) > 0 ? (int)(t_a - (W - 1)) : 0;
     const int s_hi = t_a + kTile + (W - 1) < sd.L ? (int)(t_a + kTile + (W - 1))
                                                    : (int)sd.L;
-    const int ns = (s_hi > s_lo && !g_in) ? s_hi - s_lo : 0;
-    const int64_t total = (int64_t)K * ns;
-    int64_t pos = 0;
-    while (pos < total) {
-        int cnt = 0;
-        while (pos < total && cnt <= kNzCap - 256) {
-            cnt = nz_round(Zs, sd.L, s_lo, ns, total, pos, list, cnt, wcnt);
-            pos += 256;
-        }
-        for (int e = 0; e < cnt; ++e) {
-            const NzEnt ne = list[e];
-            const int64_t dd = t - ne.s;
-            if (dd > -W && dd < W) {
-                // S[l][k][d + W - 1] = S_{k,l}[d]: the slice for atom l = ne.k
-                const double* __restrict__ srow =
-                    S64 + ((int64_t)ne.k * K + kb) * nd + (dd + W - 1);
+    if (!g_in)
+        for_nonzeros(masks + sd.nz_off, Zs, sd.L, K, s_lo, s_hi, list, wcnt,
+                     [&](const NzEnt* lst, int cnt) {
+            if (St64) {
+                // lag-major rows St[l][d][0..KP): the atoms of one lag are
+                // contiguous; two non-zeros per step so that their loads
+                // overlap (a non-zero out of reach contributes 0 * S)
+                for (int e = 0; e < cnt; e += 2) {
+                    const NzEnt n0 = lst[e];
+                    const NzEnt n1 = e + 1 < cnt ? lst[e + 1] : n0;
+                    const int64_t d0 = t - n0.s, d1 = t - n1.s;
+                    const bool v0 = d0 > -W && d0 < W;
+                    const bool v1 = e + 1 < cnt && d1 > -W && d1 < W;
+                    const double z0 = v0 ? n0.z : 0.0, z1 = v1 ? n1.z : 0.0;
+                    const double2* __restrict__ r0 = reinterpret_cast<const double2*>(
+                        St64 + ((int64_t)n0.k * nd + (v0 ? d0 + W - 1 : 0)) * KP + kb);
+                    const double2* __restrict__ r1 = reinterpret_cast<const double2*>(
+                        St64 + ((int64_t)n1.k * nd + (v1 ? d1 + W - 1 : 0)) * KP + kb);
+                    double2 s0[kMaxK / 2], s1[kMaxK / 2];
 #pragma unroll
-                for (int k = 0; k < kMaxK; ++k)
-                    if (k < kn)
-                        acc[k] -= srow[(int64_t)k * nd] * ne.z;
+                    for (int v = 0; v < kMaxK / 2; ++v)
+                        if (2 * v < kn) {
+                            s0[v] = r0[v];
+                            s1[v] = r1[v];
+                        }
+#pragma unroll
+                    for (int v = 0; v < kMaxK / 2; ++v)
+                        if (2 * v < kn) {
+                            acc[2 * v] -= s0[v].x * z0;
+                            acc[2 * v + 1] -= s0[v].y * z0;
+                        }
+#pragma unroll
+                    for (int v = 0; v < kMaxK / 2; ++v)
+                        if (2 * v < kn) {
+                            acc[2 * v] -= s1[v].x * z1;
+                            acc[2 * v + 1] -= s1[v].y * z1;
+                        }
+                }
+            } else {
+                for (int e = 0; e < cnt; ++e) {
+                    const NzEnt ne = lst[e];
+                    const int64_t dd = t - ne.s;
+                    if (dd > -W && dd < W) {
+                        // S[l][k][d + W - 1] = S_{k,l}[d]: the slice for atom l = ne.k
+                        const double* __restrict__ srow =
+                            S64 + ((int64_t)ne.k * K + kb) * nd + (dd + W - 1);
+#pragma unroll
+                        for (int k = 0; k < kMaxK; ++k)
+                            if (k < kn)
+                                acc[k] -= srow[(int64_t)k * nd] * ne.z;
+                    }
+                }
             }
-        }
-        __syncthreads();
-    }
+        });
 
     double mdz = 0.0, kon = 0.0, koff = 0.0, l1 = 0.0, mz = 0.0, nnz = 0.0;
     bool flag = false;
@@ -1826,15 +1935,22 @@ k_grad_check(const double* __restrict__ beta0, const double* __restrict__ Z,
     }
 }
 
-hipError_t launch_grad_check(const double* beta0, const double* Z, const double* S64,
-                             const double* n2, int K, int W, const SigDesc* sig,
+hipError_t launch_grad_check(const double* beta0, const double* Z,
+                             const unsigned long long* masks, const double* S64,
+                             const double* St64, const double* n2, int K, int W,
+                             const SigDesc* sig,
                              const int64_t* tile_pref, int n_sig, int64_t n_tiles,
                              double flag_eps, const uint32_t* sig_done, uint32_t* dirty,
                              void* g_state, bool state_fp64, const double* g_in,
                              double* part6, hipStream_t s)
 {
     dim3 grid((unsigned)n_tiles, (unsigned)((K + kMaxK - 1) / kMaxK));
-    hipLaunchKernelGGL(k_grad_check, grid, dim3(256), 0, s, beta0, Z, S64, n2, K, W,
+    // lag-major rows hold K rounded up to even atoms: every 16-byte read of
+    // an atom block stays inside its row
+    const int KP = lgcd_k_padded(K, true);
+    const bool use_t = St64 && KP > 0;
+    hipLaunchKernelGGL(k_grad_check, grid, dim3(256), 0, s, beta0, Z, masks, S64,
+                       use_t ? St64 : (const double*)nullptr, KP, n2, K, W,
                        sig, tile_pref, n_sig, flag_eps, sig_done, dirty,
                        state_fp64 ? (float*)nullptr : (float*)g_state,
                        state_fp64 ? (double*)g_state : (double*)nullptr, g_in, part6);
