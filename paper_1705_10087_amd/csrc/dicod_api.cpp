@@ -65,10 +65,10 @@ struct Workspace {
     DevBuf X, Zout;                       // staging for the host-pointer API
     DevBuf beta0, g, g64;                 // [K][L] per signal (g64: double finish)
     DevBuf sig, segs, lists[kMaxColors];
-    DevBuf tilesL, tilesT, tilesA, tilesN;
+    DevBuf tilesL, tilesC, tilesA, tilesN;
     DevBuf nzmask;                        // non-zero masks of Z for the check kernels
     DevBuf dirty, phase_upd, sig_upd, sig_last, counters;
-    DevBuf part_r2, part6, results, lmax, done, thr;
+    DevBuf part, results, lmax, done, thr;
     DevBuf msg, msg_n;                    // DICOD schedule: boundary messages
     DevBuf trace;
 };
@@ -86,6 +86,7 @@ struct dicod_ctx {
     int K = 0, P = 0, W = 0;
     DevBuf D64, D32, S64, S32, n2_64, inv64, n2_32, inv32;
     DevBuf St32, St64;  // phase-kernel layouts of S (float, double)
+    DevBuf Sc64;        // S with rows padded to 2W doubles, for the double check
     Workspace ws;
     unsigned long long* h_upd = nullptr;  // pinned copy of per-phase counts
     size_t h_upd_cap = 0;
@@ -353,6 +354,15 @@ extern "C" int dicod_set_dictionary(dicod_ctx* ctx, const float* D, int K, int P
         HIPCHECK(ctx, ensure(St, (size_t)K * nd * KP * (f64 ? sizeof(double) : sizeof(float))));
         HIPCHECK(ctx, launch_s_transpose(ctx->S64.as<double>(), K, W, f64 != 0, St.p, s));
     }
+    if (check_kblocks(K, W) > 0) {
+        HIPCHECK(ctx, ensure(ctx->Sc64, check_s_elems(K, W) * sizeof(double)));
+        HIPCHECK(ctx, hipMemsetAsync(ctx->Sc64.p, 0, check_s_elems(K, W) * sizeof(double), s));
+        HIPCHECK(ctx, hipMemcpy2DAsync(ctx->Sc64.p, (size_t)2 * W * sizeof(double), ctx->S64.p,
+                                       (size_t)nd * sizeof(double), (size_t)nd * sizeof(double),
+                                       (size_t)K * K, hipMemcpyDeviceToDevice, s));
+    } else {
+        ctx->Sc64.release();  // solves report ENOTSUP for this W
+    }
     HIPCHECK(ctx, hipStreamSynchronize(s));
     ctx->K = K;
     ctx->P = P;
@@ -388,7 +398,8 @@ struct Plan {
     std::vector<int32_t> list[kMaxColors];
     int colors = 2;   // phase classes; 1 for the DICOD schedule (all segments)
     bool dicod = false;
-    std::vector<int64_t> prefL, prefT, prefA, prefN;  // prefN: non-zero mask words
+    // tiles of kTile (L) and of the check (C) positions; mask words (N)
+    std::vector<int64_t> prefL, prefC, prefA, prefN;
     int lm_max = 0, lext_max = 0;
     size_t zext = 0;  // extent of the [K][L] arrays (elements)
 };
@@ -412,11 +423,13 @@ int make_plan(dicod_ctx* ctx, int n_sig, const int64_t* T, const int64_t* x_off,
 {
     const int K = ctx->K, W = ctx->W;
     const bool fp64 = ctx->cfg.precision == DICOD_PREC_FP64;
+    if (check_kblocks(K, W) < 1)
+        return fail(ctx, DICOD_ENOTSUP, "W=%d: one row of S does not fit the check kernel", W);
     pl.dicod = ctx->cfg.schedule == DICOD_SCHED_DICOD;
     pl.colors = pl.dicod ? 1 : ctx->cfg.colors;
     pl.sig.resize(n_sig);
     pl.prefL.assign(n_sig + 1, 0);
-    pl.prefT.assign(n_sig + 1, 0);
+    pl.prefC.assign(n_sig + 1, 0);
     pl.prefA.assign(n_sig + 1, 0);
     pl.prefN.assign(n_sig + 1, 0);
     for (int i = 0; i < n_sig; ++i) {
@@ -474,7 +487,7 @@ int make_plan(dicod_ctx* ctx, int n_sig, const int64_t* T, const int64_t* x_off,
             pl.segs.push_back(d);
         }
         pl.prefL[i + 1] = pl.prefL[i] + ceil_div(L, kTile);
-        pl.prefT[i + 1] = pl.prefT[i] + ceil_div(T[i], kTile);
+        pl.prefC[i + 1] = pl.prefC[i] + ceil_div(L, kCheckSpan);
         pl.prefA[i + 1] = pl.prefA[i] + ceil_div((int64_t)K * L, kAbsChunk);
         pl.prefN[i + 1] = pl.prefN[i] + (int64_t)K * ceil_div(L, 64);
         pl.zext = std::max(pl.zext, (size_t)(z_off[i] + (int64_t)K * L));
@@ -530,9 +543,9 @@ int solve_device_batch(dicod_ctx* ctx, int n_sig, const float* dX, const int64_t
     if (rc != DICOD_OK)
         return rc;
     const int n_seg_tot = (int)pl.segs.size();
-    const int64_t nL = pl.prefL[n_sig], nT = pl.prefT[n_sig], nA = pl.prefA[n_sig];
+    const int64_t nL = pl.prefL[n_sig], nC = pl.prefC[n_sig], nA = pl.prefA[n_sig];
     const int64_t nN = pl.prefN[n_sig];
-    const int n_kblk = (K + kMaxK - 1) / kMaxK;
+    const int n_kblk = check_kblocks(K, W);
     const int64_t max_ph = std::min<int64_t>(cfg.max_phases, (int64_t)1 << 22);
 
     HIPCHECK(ctx, ensure(ws.beta0, pl.zext * sizeof(double)));
@@ -547,9 +560,8 @@ int solve_device_batch(dicod_ctx* ctx, int n_sig, const float* dX, const int64_t
     HIPCHECK(ctx, ensure(ws.sig_upd, n_sig * sizeof(unsigned long long)));
     HIPCHECK(ctx, ensure(ws.sig_last, n_sig * sizeof(int)));
     HIPCHECK(ctx, ensure(ws.counters, sizeof(Counters)));
-    HIPCHECK(ctx, ensure(ws.part_r2, nT * sizeof(double)));
     HIPCHECK(ctx, ensure(ws.nzmask, nN * sizeof(unsigned long long)));
-    HIPCHECK(ctx, ensure(ws.part6, (size_t)nL * n_kblk * 6 * sizeof(double)));
+    HIPCHECK(ctx, ensure(ws.part, (size_t)nC * n_kblk * kCheckParts * sizeof(double)));
     HIPCHECK(ctx, ensure(ws.results, n_sig * sizeof(CheckResult)));
     HIPCHECK(ctx, ensure(ws.lmax, n_sig * sizeof(unsigned long long)));
     HIPCHECK(ctx, ensure(ws.done, n_sig * sizeof(uint32_t)));
@@ -570,7 +582,7 @@ int solve_device_batch(dicod_ctx* ctx, int n_sig, const float* dX, const int64_t
     for (int c = 0; c < pl.colors; ++c)
         HIPCHECK(ctx, upload(ws.lists[c], pl.list[c], s));
     HIPCHECK(ctx, upload(ws.tilesL, pl.prefL, s));
-    HIPCHECK(ctx, upload(ws.tilesT, pl.prefT, s));
+    HIPCHECK(ctx, upload(ws.tilesC, pl.prefC, s));
     HIPCHECK(ctx, upload(ws.tilesA, pl.prefA, s));
     HIPCHECK(ctx, upload(ws.tilesN, pl.prefN, s));
 
@@ -831,21 +843,17 @@ int solve_device_batch(dicod_ctx* ctx, int n_sig, const float* dX, const int64_t
         const double* g_in = (cur64 && !cfg.verify_from_scratch)
                                  ? (fp64 ? ws.g.as<double>() : ws.g64.as<double>())
                                  : nullptr;
-        const unsigned long long* masks = ws.nzmask.as<unsigned long long>();
-        HIPCHECK(ctx, launch_nz_mask(dZ, ws.sig.as<SigDesc>(), ws.tilesN.as<int64_t>(), n_sig, K,
-                                     nN, ws.nzmask.as<unsigned long long>(), s));
-        HIPCHECK(ctx, launch_resid(dX, ctx->D64.as<double>(), dZ, masks, K, P, W,
-                                   ws.sig.as<SigDesc>(), ws.tilesT.as<int64_t>(), n_sig, nT,
-                                   ws.part_r2.as<double>(), s));
-        HIPCHECK(ctx, launch_grad_check(ws.beta0.as<double>(), dZ, masks, ctx->S64.as<double>(),
-                                        ctx->St64.as<double>(),
-                                        ctx->n2_64.as<double>(), K, W, ws.sig.as<SigDesc>(),
-                                        ws.tilesL.as<int64_t>(), n_sig, nL, flag_eps,
-                                        ws.done.as<uint32_t>(), ws.dirty.as<uint32_t>(),
-                                        g_in ? nullptr : g_next, next64, g_in,
-                                        ws.part6.as<double>(), s));
-        HIPCHECK(ctx, launch_check_reduce(ws.part_r2.as<double>(), ws.tilesT.as<int64_t>(),
-                                          ws.part6.as<double>(), ws.tilesL.as<int64_t>(), nL,
+        if (!g_in)
+            HIPCHECK(ctx, launch_nz_mask(dZ, ws.sig.as<SigDesc>(), ws.tilesN.as<int64_t>(), n_sig,
+                                         K, nN, ws.nzmask.as<unsigned long long>(), s));
+        HIPCHECK(ctx, launch_grad_check(dX, ws.beta0.as<double>(), dZ,
+                                        ws.nzmask.as<unsigned long long>(),
+                                        ctx->Sc64.as<double>(), ctx->n2_64.as<double>(), K, P, W,
+                                        ws.sig.as<SigDesc>(), ws.tilesC.as<int64_t>(), n_sig, nC,
+                                        flag_eps, ws.done.as<uint32_t>(),
+                                        ws.dirty.as<uint32_t>(), g_in ? nullptr : g_next, next64,
+                                        g_in, ws.part.as<double>(), s));
+        HIPCHECK(ctx, launch_check_reduce(ws.part.as<double>(), ws.tilesC.as<int64_t>(), nC,
                                           n_kblk, n_sig, ws.results.as<CheckResult>(), s));
         HIPCHECK(ctx, hipMemcpyAsync(res.data(), ws.results.p, n_sig * sizeof(CheckResult),
                                      hipMemcpyDeviceToHost, s));
@@ -1129,6 +1137,7 @@ DictView ctx_dict(const dicod_ctx* ctx)
     v.S32 = ctx->S32.p;
     v.St32 = ctx->St32.p;
     v.St64 = ctx->St64.p;
+    v.Sc64 = ctx->Sc64.as<double>();
     v.n2_32 = ctx->n2_32.p;
     v.inv32 = ctx->inv32.p;
     v.n2_64 = ctx->n2_64.p;

@@ -10,8 +10,10 @@
 
 namespace dicod {
 
-constexpr int kMaxK = 32;        // atoms handled by the verify kernels per pass
-constexpr int kMaxP = 16;        // channels handled by the residual kernel
+constexpr int kCheckKB = 8;      // most atoms of one block of the double check
+constexpr int kCheckSpan = 1024; // positions of one tile of the double check
+constexpr int kCheckParts = 8;   // partials per check tile
+constexpr int kMaxP = 16;        // channels accepted (the correlation kernels stage P rows)
 constexpr int kPhaseThreads = 512;
 constexpr int kPhaseThreadsMax = 1024;
 constexpr int kMaxColors = 4;  // phase classes of the segment schedule
@@ -154,27 +156,30 @@ hipError_t launch_s_transpose(const double* S64, int K, int W, bool fp64, void* 
 hipError_t launch_nz_mask(const double* Z, const SigDesc* sig, const int64_t* mask_pref,
                           int n_sig, int K, int64_t n_words, unsigned long long* masks,
                           hipStream_t s);
-// Double-precision check: residual energy per tile (partials).
-hipError_t launch_resid(const float* X, const double* D, const double* Z,
-                        const unsigned long long* masks, int K, int P, int W,
-                        const SigDesc* sig, const int64_t* tile_pref, int n_sig,
-                        int64_t n_tiles, double* part_r2, hipStream_t s);
-// g = beta0 - S * Z, candidates in double, KKT partials, dirty flags for
-// segments holding a coordinate with |Delta Z| >= flag_eps, optional refresh
-// of the state g (float or double).
-// St64 (optional): the lag-major copy St[l][d][k] of S for faster gathers.
-hipError_t launch_grad_check(const double* beta0, const double* Z,
-                             const unsigned long long* masks,
-                             const double* S64, const double* St64, const double* n2,
-                             int K, int W,
-                             const SigDesc* sig, const int64_t* tile_pref, int n_sig,
-                             int64_t n_tiles, double flag_eps, const uint32_t* sig_done,
-                             uint32_t* dirty, void* g_state, bool state_fp64,
-                             const double* g_in, double* part6, hipStream_t s);
-hipError_t launch_check_reduce(const double* part_r2, const int64_t* tile_pref_T,
-                               const double* part6, const int64_t* tile_pref_L,
-                               int64_t n_tiles_L, int n_kblk, int n_sig,
-                               CheckResult* out, hipStream_t s);
+// Double-precision stop test and refresh: g = beta0 - S * Z from the
+// non-zeros of Z (masks from launch_nz_mask) or the maintained double state
+// g_in, Delta Z of every coordinate in double, the optimality residuals, the
+// objective partials |X|^2 and <beta0 + g, Z> (their difference is
+// |X - Z * D|^2), dirty flags for segments holding a coordinate with
+// |Delta Z| >= flag_eps, and an optional refresh of the state g (float or
+// double).  Tiles of kCheckSpan positions (tile_pref: prefix of
+// ceil(L / kCheckSpan)); part: [check_kblocks(K, W)][n_tiles][kCheckParts].
+// Sc: the padded copy of S described at check_s_elems.
+hipError_t launch_grad_check(const float* X, const double* beta0, const double* Z,
+                             const unsigned long long* masks, const double* Sc,
+                             const double* n2, int K, int P, int W, const SigDesc* sig,
+                             const int64_t* tile_pref, int n_sig, int64_t n_tiles,
+                             double flag_eps, const uint32_t* sig_done, uint32_t* dirty,
+                             void* g_state, bool state_fp64, const double* g_in,
+                             double* part, hipStream_t s);
+// Atom blocks of the check (grid y); 0 when W is too large for it.
+int check_kblocks(int K, int W);
+int check_atoms_per_block(int K, int W);
+// Sc: S in the [l][k][2W] layout (row d = 0..2W-2, one pad element per row)
+// followed by 128 doubles of padding; check_s_elems(K, W) elements.
+size_t check_s_elems(int K, int W);
+hipError_t launch_check_reduce(const double* part, const int64_t* tile_pref, int64_t n_tiles,
+                               int n_kblk, int n_sig, CheckResult* out, hipStream_t s);
 
 // MIXED precision: gather candidates with |beta| >= thr and recompute them in
 // double; per-signal max of the exact values.

@@ -206,7 +206,7 @@ struct Lane {
     int queued = 0;             // requests of this lane in the queue (mu)
     uint64_t blocked = ~0ull;   // epoch at which admission last found no room (mu)
     std::string msg;            // last HIP failure
-    Mem dRing, dLists, dSub, dTilesL, dTilesT, dTilesA, dTilesN, dPartR2, dPart6, dRes, dLmax,
+    Mem dRing, dLists, dSub, dTilesL, dTilesC, dTilesA, dTilesN, dPart, dRes, dLmax,
         dDone, dSlots, dLamIn, dMask;
     unsigned long long* h_ring = nullptr;
     unsigned long long* h_sigupd = nullptr;
@@ -245,7 +245,7 @@ struct Server {
     std::vector<int> free_slots;
     RangeAlloc coef, samp, segr;
     int slots = 0;
-    int64_t seg_cap = 0, tilesL_cap = 0, tilesT_cap = 0, mask_cap = 0;
+    int64_t seg_cap = 0, tilesC_cap = 0, mask_cap = 0;
     int chunk = 16;
     // shared device state, indexed by ranges and slots
     Mem dX, dZ, dB, dG32, dG64, dSig, dSeg, dDirty, dSigUpd, dSigLast, dCnt;
@@ -284,18 +284,17 @@ hipError_t Lane::stage(void* dst, const void* src, size_t bytes)
 int Lane::start()
 {
     const int slots = srv->slots;
-    const int n_kblk = (srv->K + kMaxK - 1) / kMaxK;
+    const int n_kblk = check_kblocks(srv->K, srv->W);
     SRV_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
     SRV_HIP(dRing.alloc((size_t)slots * kRing * sizeof(unsigned long long)));
     SRV_HIP(dLists.alloc((size_t)srv->seg_cap * sizeof(int32_t)));
     SRV_HIP(dSub.alloc((size_t)slots * sizeof(SigDesc)));
     SRV_HIP(dTilesL.alloc((size_t)(slots + 1) * sizeof(int64_t)));
-    SRV_HIP(dTilesT.alloc((size_t)(slots + 1) * sizeof(int64_t)));
+    SRV_HIP(dTilesC.alloc((size_t)(slots + 1) * sizeof(int64_t)));
     SRV_HIP(dTilesA.alloc((size_t)(slots + 1) * sizeof(int64_t)));
     SRV_HIP(dTilesN.alloc((size_t)(slots + 1) * sizeof(int64_t)));
     SRV_HIP(dMask.alloc((size_t)srv->mask_cap * sizeof(unsigned long long)));
-    SRV_HIP(dPartR2.alloc((size_t)srv->tilesT_cap * sizeof(double)));
-    SRV_HIP(dPart6.alloc((size_t)srv->tilesL_cap * n_kblk * 6 * sizeof(double)));
+    SRV_HIP(dPart.alloc((size_t)srv->tilesC_cap * n_kblk * kCheckParts * sizeof(double)));
     SRV_HIP(dRes.alloc((size_t)slots * sizeof(CheckResult)));
     SRV_HIP(dLmax.alloc((size_t)slots * sizeof(unsigned long long)));
     SRV_HIP(dDone.alloc((size_t)slots * sizeof(uint32_t)));
@@ -326,8 +325,8 @@ void Lane::teardown()
         th.join();
     if (s)
         (void)hipStreamSynchronize(s);
-    for (Mem* m : {&dRing, &dLists, &dSub, &dTilesL, &dTilesT, &dTilesA, &dTilesN, &dPartR2,
-                   &dPart6, &dRes, &dLmax, &dDone, &dSlots, &dLamIn, &dMask})
+    for (Mem* m : {&dRing, &dLists, &dSub, &dTilesL, &dTilesC, &dTilesA, &dTilesN, &dPart,
+                   &dRes, &dLmax, &dDone, &dSlots, &dLamIn, &dMask})
         m->release();
     for (void* p : {(void*)h_stage, (void*)h_ring, (void*)h_sigupd, (void*)h_lmax,
                     (void*)h_res})
@@ -373,8 +372,7 @@ int Server::start(dicod_ctx* c)
     samp.reset(n_samp);
     seg_cap = n_coef / ((int64_t)K * min_segment_len(W, C)) + slots + 16;
     segr.reset(seg_cap);
-    tilesL_cap = n_coef / K / kTile + slots + 1;
-    tilesT_cap = n_samp / P / kTile + slots + 1;
+    tilesC_cap = n_coef / K / kCheckSpan + slots + 1;
     // each request rounds every atom row up to whole 64-bit words
     mask_cap = n_coef / 64 + (int64_t)slots * K + 1;
     SRV_HIP(dX.alloc((size_t)n_samp * sizeof(float)));
@@ -627,7 +625,7 @@ int Lane::check_jobs(const std::vector<Job*>& conv)
 {
     Server& v = *srv;
     const int K = v.K, P = v.P, W = v.W;
-    const int n_kblk = (K + kMaxK - 1) / kMaxK;
+    const int n_kblk = check_kblocks(K, W);
     const dicod_config& cfg = v.cfg;
     for (int grp = 0; grp < 4; ++grp) {
         const bool c64 = grp & 1;
@@ -650,13 +648,12 @@ int Lane::check_jobs(const std::vector<Job*>& conv)
             const int n = (int)(i1 - i0);
             const double eps = g[i0]->eps;
             std::vector<SigDesc> sub(n);
-            std::vector<int64_t> pL(n + 1, 0), pT(n + 1, 0), pN(n + 1, 0);
+            std::vector<int64_t> pC(n + 1, 0), pN(n + 1, 0);
             for (int i = 0; i < n; ++i) {
                 Job* j = g[i0 + i];
                 sub[i] = v.h_sig[j->slot];
                 sub[i].nz_off = pN[i];
-                pL[i + 1] = pL[i] + ceil_div(j->L, kTile);
-                pT[i + 1] = pT[i] + ceil_div(j->T, kTile);
+                pC[i + 1] = pC[i] + ceil_div(j->L, kCheckSpan);
                 pN[i + 1] = pN[i] + (int64_t)K * ceil_div(j->L, 64);
             }
             if (pN[n] > v.mask_cap) {
@@ -665,29 +662,25 @@ int Lane::check_jobs(const std::vector<Job*>& conv)
             }
             stage_off = 0;  // the previous group was synchronised
             SRV_HIP(stage(dSub.p, sub.data(), n * sizeof(SigDesc)));
-            SRV_HIP(stage(dTilesL.p, pL.data(), (n + 1) * sizeof(int64_t)));
-            SRV_HIP(stage(dTilesT.p, pT.data(), (n + 1) * sizeof(int64_t)));
+            SRV_HIP(stage(dTilesC.p, pC.data(), (n + 1) * sizeof(int64_t)));
             SRV_HIP(stage(dTilesN.p, pN.data(), (n + 1) * sizeof(int64_t)));
             const double flag_eps = next64 ? eps : eps * cfg.inner_eps_factor;
             void* g_next = next64 ? v.dG64.p : v.dG32.p;
             const double* g_in =
                 (c64 && !cfg.verify_from_scratch) ? v.dG64.as<double>() : nullptr;
-            SRV_HIP(launch_nz_mask(v.dZ.as<double>(), dSub.as<SigDesc>(), dTilesN.as<int64_t>(), n,
-                                   K, pN[n], dMask.as<unsigned long long>(), s));
-            SRV_HIP(launch_resid(v.dX.as<float>(), v.dict.D64, v.dZ.as<double>(),
-                                 dMask.as<unsigned long long>(), K, P, W, dSub.as<SigDesc>(),
-                                 dTilesT.as<int64_t>(), n, pT[n], dPartR2.as<double>(), s));
-            SRV_HIP(launch_grad_check(v.dB.as<double>(), v.dZ.as<double>(),
-                                      dMask.as<unsigned long long>(), v.dict.S64,
-                                      (const double*)v.dict.St64,
-                                      (const double*)v.dict.n2_64, K, W, dSub.as<SigDesc>(),
-                                      dTilesL.as<int64_t>(), n, pL[n], flag_eps,
+            if (!g_in)
+                SRV_HIP(launch_nz_mask(v.dZ.as<double>(), dSub.as<SigDesc>(),
+                                       dTilesN.as<int64_t>(), n, K, pN[n],
+                                       dMask.as<unsigned long long>(), s));
+            SRV_HIP(launch_grad_check(v.dX.as<float>(), v.dB.as<double>(), v.dZ.as<double>(),
+                                      dMask.as<unsigned long long>(), v.dict.Sc64,
+                                      (const double*)v.dict.n2_64, K, P, W, dSub.as<SigDesc>(),
+                                      dTilesC.as<int64_t>(), n, pC[n], flag_eps,
                                       dDone.as<uint32_t>(), v.dDirty.as<uint32_t>(),
-                                      g_in ? nullptr : g_next, next64, g_in,
-                                      dPart6.as<double>(), s));
-            SRV_HIP(launch_check_reduce(dPartR2.as<double>(), dTilesT.as<int64_t>(),
-                                        dPart6.as<double>(), dTilesL.as<int64_t>(), pL[n],
-                                        n_kblk, n, dRes.as<CheckResult>(), s));
+                                      g_in ? nullptr : g_next, next64, g_in, dPart.as<double>(),
+                                      s));
+            SRV_HIP(launch_check_reduce(dPart.as<double>(), dTilesC.as<int64_t>(), pC[n], n_kblk,
+                                        n, dRes.as<CheckResult>(), s));
             SRV_HIP(hipMemcpyAsync(h_res, dRes.p, n * sizeof(CheckResult),
                                    hipMemcpyDeviceToHost, s));
             std::vector<SigDesc> upd;

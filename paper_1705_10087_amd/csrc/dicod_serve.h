@@ -21,6 +21,7 @@ struct DictView {
     const void* S32;                   // [l][k][d] float
     const void* St32;                  // phase-kernel layout, float
     const void* St64;                  // phase-kernel layout, double
+    const double* Sc64;                // [l][k][2W] double, the check's copy
     const void *n2_32, *inv32, *n2_64, *inv64;
 };
 

@@ -1560,15 +1560,6 @@ hipError_t launch_lgcd_phase_gm(const PhaseArgs& a, bool fp64, size_t* lds_bytes
 // Double-precision check (final stop test and refresh).
 // ---------------------------------------------------------------------------
 
-// Deterministic stream compaction of the non-zeros of Z over a window
-// [s_lo, s_hi) x [0, K) into an LDS list, in (k, s) order.
-struct NzEnt {
-    int k;
-    int s;
-    double z;
-};
-constexpr int kNzCap = 2048;
-
 // Non-zero masks: word w of a signal is bit i = (Z_k[64 b + i] != 0), with
 // w = k * ceil(L / 64) + b.  One wave per word.
 __global__ void __launch_bounds__(256)
@@ -1605,6 +1596,75 @@ hipError_t launch_nz_mask(const double* Z, const SigDesc* sig, const int64_t* ma
     return hipGetLastError();
 }
 
+__device__ __forceinline__ double block_sum256(double v, double* red)
+{
+    for (int o = 32; o > 0; o >>= 1)
+        v += __shfl_xor(v, o);
+    if ((threadIdx.x & 63) == 0)
+        red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double r = (red[0] + red[1]) + (red[2] + red[3]);
+    __syncthreads();
+    return r;
+}
+
+__device__ __forceinline__ double block_max256(double v, double* red)
+{
+    for (int o = 32; o > 0; o >>= 1)
+        v = fmax(v, __shfl_xor(v, o));
+    if ((threadIdx.x & 63) == 0)
+        red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double r = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    __syncthreads();
+    return r;
+}
+
+// Atoms of one check block: the block stages kper padded rows of S (2W
+// doubles each) per source atom in each of its two LDS buffers; 0 when one
+// row does not fit.
+int check_atoms_per_block(int K, int W)
+{
+    const size_t row = (size_t)2 * W * sizeof(double);
+    size_t budget = (size_t)24 << 10;  // per buffer: three blocks per CU
+    if (row > budget)
+        budget = (kLdsBytes - ((size_t)16 << 10)) / 2;
+    const int kmax = (int)std::min<size_t>((size_t)kCheckKB, budget / row);
+    if (kmax < 1 || K < 1)
+        return 0;
+    const int nb = (K + kmax - 1) / kmax;
+    return (K + nb - 1) / nb;
+}
+
+int check_kblocks(int K, int W)
+{
+    const int kp = check_atoms_per_block(K, W);
+    return kp > 0 ? (K + kp - 1) / kp : 0;
+}
+
+size_t check_s_elems(int K, int W)
+{
+    return (size_t)K * K * 2 * W + 128;  // + 1 KB read past the last block by the copies
+}
+
+// doubles per LDS stage buffer (whole 1 KB copy chunks)
+static int check_stage_stride(int kper, int W)
+{
+    return (int)((((size_t)kper * 2 * W * sizeof(double) + 1023) / 1024) * 128);
+}
+
+constexpr int kCheckList = 448;  // listed non-zeros per pass (LDS)
+constexpr int kCheckJ = kCheckSpan / 256;
+
+// Workgroup barrier that orders LDS only: unlike __syncthreads() it does not
+// wait for the block's outstanding global loads.
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // Exclusive prefix sum of v over the 256 threads; *total gets the sum.
 // All threads call it.
 __device__ __forceinline__ int block_scan256(int v, int* total, int* wsum)
@@ -1632,266 +1692,209 @@ __device__ __forceinline__ int block_scan256(int v, int* total, int* wsum)
     return base + x - v;
 }
 
-// Calls fn(list, cnt) (all threads, between barriers) for the non-zeros
-// Z_k[s], s in [s_lo, s_hi), in (k, s) order, in chunks of at most kNzCap
-// gathered in LDS from the signal's non-zero masks msk ([K][ceil(L / 64)]).
-// All threads call it with the same window.
-template <typename F>
-__device__ __forceinline__ void for_nonzeros(const unsigned long long* __restrict__ msk,
-                                             const double* __restrict__ Zs, int64_t L, int K,
-                                             int s_lo, int s_hi, NzEnt* __restrict__ list,
-                                             int* __restrict__ wsum, F&& fn)
-{
-    if (s_hi <= s_lo)
-        return;
-    const int64_t nb = (L + 63) / 64;
-    const int b_lo = s_lo >> 6;
-    const int nbw = ((s_hi - 1) >> 6) - b_lo + 1;
-    const int items = K * nbw;
-    for (int i0 = 0; i0 < items; i0 += 256) {
-        const int it = i0 + (int)threadIdx.x;
-        unsigned long long m = 0ull;
-        int k = 0, bb = 0;
-        if (it < items) {
-            k = it / nbw;
-            bb = b_lo + (it - k * nbw);
-            m = msk[(int64_t)k * nb + bb];
-            const int lo = s_lo - bb * 64;  // keep bits [lo, hi)
-            const int hi = s_hi - bb * 64;
-            if (lo > 0)
-                m &= ~0ull << lo;
-            if (hi < 64)
-                m &= (1ull << hi) - 1ull;  // hi >= 1: block bb starts below s_hi
-        }
-        const int cnt_m = __popcll(m);
-        int tot;
-        const int off = block_scan256(cnt_m, &tot, wsum);
-        for (int base = 0; base < tot; base += kNzCap) {
-            if (cnt_m > 0 && off < base + kNzCap && off + cnt_m > base) {
-                unsigned long long mm = m;
-                int idx = off;
-                while (mm && idx < base + kNzCap) {
-                    const int bit = __ffsll(mm) - 1;
-                    mm &= mm - 1ull;
-                    if (idx >= base) {
-                        NzEnt e;
-                        e.k = k;
-                        e.s = bb * 64 + bit;
-                        e.z = Zs[(int64_t)k * L + e.s];
-                        list[idx - base] = e;
-                    }
-                    ++idx;
-                }
-            }
-            __syncthreads();
-            fn(list, tot - base < kNzCap ? tot - base : kNzCap);
-            __syncthreads();
-        }
-    }
-}
-
-__device__ __forceinline__ double block_sum256(double v, double* red)
-{
-    for (int o = 32; o > 0; o >>= 1)
-        v += __shfl_xor(v, o);
-    if ((threadIdx.x & 63) == 0)
-        red[threadIdx.x >> 6] = v;
-    __syncthreads();
-    double r = (red[0] + red[1]) + (red[2] + red[3]);
-    __syncthreads();
-    return r;
-}
-
-__device__ __forceinline__ double block_max256(double v, double* red)
-{
-    for (int o = 32; o > 0; o >>= 1)
-        v = fmax(v, __shfl_xor(v, o));
-    if ((threadIdx.x & 63) == 0)
-        red[threadIdx.x >> 6] = v;
-    __syncthreads();
-    double r = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
-    __syncthreads();
-    return r;
-}
-
-// Residual energy: per tile of 256 samples, sum_p (X - sum_k Z_k * D_k)^2,
-// the convolution taken over the non-zeros of Z only (model eq. (1)).
+// g_k[t] = beta0_k[t] - sum_{l, s} S_{k,l}[t - s] Z_l[s] over the non-zeros of
+// Z (eq. (3) summed over every applied update), then in double for every
+// coordinate: Delta Z = Sh(g + |D_k|^2 z, lambda) / |D_k|^2 - z, the optimality
+// residuals, and the objective partials.  The residual energy follows from g:
+// with S Z = D^T (Z * D) and beta0 = D^T X,
+//   |X - Z * D|^2 = |X|^2 - 2 <beta0, Z> + <Z, S Z> = |X|^2 - <beta0 + g, Z>.
+// A block owns kCheckSpan positions of one signal (thread tid: t_a + tid +
+// 256 j) and the atoms [kb, kb + kper).  It lists the non-zeros within reach
+// (from the masks, in (l, s) order) in LDS; for each source atom l the rows
+// S_{kb.., l}[.] (contiguous in the padded [l][k][2W] copy Sc) are copied
+// into one of two LDS buffers by direct global-to-LDS loads, the next atom's
+// copy in flight while the current one is summed.  The sums run over (l, s)
+// in increasing order.  With g_in the maintained double state is checked as
+// it is.  part per (y-block, tile): max|dz|, kkt_on, kkt_off, l1, max|z|, nnz,
+// |X|^2 (y-block 0 only), <beta0 + g, Z>.  KB >= kper atoms are summed
+// without branches (rows past the block's last atom repeat it; their sums
+// are never read).
+template <int J, int KB>
 __global__ void __launch_bounds__(256)
-k_resid(const float* __restrict__ X, const double* __restrict__ D,
-        const double* __restrict__ Z, const unsigned long long* __restrict__ masks, int K,
-        int P, int W,
-        const SigDesc* __restrict__ sig, const int64_t* __restrict__ tile_pref,
-        int n_sig, double* __restrict__ part)
-{
-    __shared__ NzEnt list[kNzCap];
-    __shared__ int wcnt[4];
-    __shared__ double red[4];
-    const int64_t tile = blockIdx.x;
-    const int si = find_sig(tile_pref, n_sig, tile);
-    const SigDesc sd = sig[si];
-    const int64_t t_a = (tile - tile_pref[si]) * kTile;
-    const int64_t t = t_a + threadIdx.x;
-    const double* __restrict__ Zs = Z + sd.z_off;
-
-    double acc[kMaxP];
-#pragma unroll
-    for (int p = 0; p < kMaxP; ++p)
-        acc[p] = 0.0;
-    if (t < sd.T) {
-#pragma unroll
-        for (int p = 0; p < kMaxP; ++p)
-            if (p < P)
-                acc[p] = (double)X[sd.x_off + (int64_t)p * sd.T + t];
-    }
-    const int s_lo = t_a - (W - 1) > 0 ? (int)(t_a - (W - 1)) : 0;
-    const int s_hi = t_a + kTile < sd.L ? (int)(t_a + kTile) : (int)sd.L;
-    for_nonzeros(masks + sd.nz_off, Zs, sd.L, K, s_lo, s_hi, list, wcnt,
-                 [&](const NzEnt* lst, int cnt) {
-                     for (int e = 0; e < cnt; ++e) {
-                         const NzEnt ne = lst[e];
-                         const int64_t tau = t - ne.s;
-                         if (tau >= 0 && tau < W) {
-                             const double* __restrict__ drow = D + (int64_t)ne.k * P * W + tau;
-#pragma unroll
-                             for (int p = 0; p < kMaxP; ++p)
-                                 if (p < P)
-                                     acc[p] -= ne.z * drow[(int64_t)p * W];
-                         }
-                     }
-                 });
-    double e2 = 0.0;
-    if (t < sd.T) {
-#pragma unroll
-        for (int p = 0; p < kMaxP; ++p)
-            if (p < P)
-                e2 += acc[p] * acc[p];
-    }
-    e2 = block_sum256(e2, red);
-    if (threadIdx.x == 0)
-        part[tile] = e2;
-}
-
-hipError_t launch_resid(const float* X, const double* D, const double* Z,
-                        const unsigned long long* masks, int K, int P, int W,
-                        const SigDesc* sig, const int64_t* tile_pref, int n_sig,
-                        int64_t n_tiles, double* part_r2, hipStream_t s)
-{
-    if (P > kMaxP)
-        return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_resid, dim3((unsigned)n_tiles), dim3(256), 0, s, X, D, Z, masks, K,
-                       P, W, sig, tile_pref, n_sig, part_r2);
-    return hipGetLastError();
-}
-
-// g_k[t] = beta0_k[t] - sum_{l, s} S_{k,l}[t - s] Z_l[s] over the non-zeros
-// of Z (eq. (3) summed over all applied updates), then in double:
-// Delta Z = Sh(g + |D|^2 z, lambda)/|D|^2 - z and the optimality residuals.
-// part6 per tile: max|dz|, kkt_on, kkt_off, l1, max|z|, nnz.
-__global__ void __launch_bounds__(256)
-k_grad_check(const double* __restrict__ beta0, const double* __restrict__ Z,
-             const unsigned long long* __restrict__ masks, const double* __restrict__ S64, const double* __restrict__ St64, int KP,
-             const double* __restrict__ n2v, int K,
-             int W, const SigDesc* __restrict__ sig,
+k_grad_check(const float* __restrict__ X, const double* __restrict__ beta0,
+             const double* __restrict__ Z, const unsigned long long* __restrict__ masks,
+             const double* __restrict__ Sc, const double* __restrict__ n2v, int K, int P,
+             int W, int kper, const SigDesc* __restrict__ sig,
              const int64_t* __restrict__ tile_pref, int n_sig, double flag_eps,
              const uint32_t* __restrict__ sig_done, uint32_t* __restrict__ dirty,
              float* __restrict__ g32, double* __restrict__ g64,
-             const double* __restrict__ g_in, double* __restrict__ part6)
+             const double* __restrict__ g_in, double* __restrict__ part)
 {
-    __shared__ NzEnt list[kNzCap];
-    __shared__ int wcnt[4];
+    extern __shared__ __align__(16) double sst[];  // 2 x [kper][2W]: S_{kb+k,l}[d - W + 1]
+    __shared__ int ls[kCheckList];                 // listed non-zeros (l, s, Z_l[s])
+    __shared__ int lk[kCheckList];
+    __shared__ double lz[kCheckList];
+    __shared__ int wsum[4];
     __shared__ double red[4];
     const int nd = 2 * W - 1;
+    const int ndp = 2 * W;  // padded row: 16-byte multiple
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
     const int64_t tile = blockIdx.x;
     const int si = find_sig(tile_pref, n_sig, tile);
     const SigDesc sd = sig[si];
-    const int64_t t_a = (tile - tile_pref[si]) * kTile;
-    const int64_t t = t_a + threadIdx.x;
-    const bool act = t < sd.L;
+    const int64_t L = sd.L;
+    const int64_t t_a = (tile - tile_pref[si]) * (int64_t)(256 * J);
+    const int kb = blockIdx.y * kper;
+    const int kn = K - kb < kper ? K - kb : kper;
     const double* __restrict__ Zs = Z + sd.z_off;
-    const int kb = blockIdx.y * kMaxK;
-    const int kn = K - kb < kMaxK ? K - kb : kMaxK;
     // accepted signals are only measured: no refresh, no new dirty segments
     const bool frozen = sig_done && sig_done[si] != 0u;
 
-    double acc[kMaxK];
+    // loads at clamped (valid) indices, unconditional so that they are all in
+    // flight together; the values past the ends are never used
+    double acc[J][KB];
+    {
+        const double* __restrict__ a0 = (g_in ? g_in : beta0) + sd.z_off;
 #pragma unroll
-    for (int k = 0; k < kMaxK; ++k)
-        acc[k] = (act && k < kn) ? (g_in ? g_in : beta0)[sd.z_off + (int64_t)(kb + k) * sd.L + t]
-                                 : 0.0;
+        for (int j = 0; j < J; ++j) {
+            const int64_t t = t_a + tid + 256 * j;
+            const int64_t tc = t < L ? t : L - 1;
+#pragma unroll
+            for (int k = 0; k < KB; ++k)
+                acc[j][k] = a0[(int64_t)(kb + (k < kn ? k : kn - 1)) * L + tc];
+        }
+    }
 
-    // from scratch: g = beta0 - S Z over the non-zeros; with g_in the
-    // maintained double state is checked as it is
-    const int s_lo = t_a - (W - 1) > 0 ? (int)(t_a - (W - 1)) : 0;
-    const int s_hi = t_a + kTile + (W - 1) < sd.L ? (int)(t_a + kTile + (W - 1))
-                                                   : (int)sd.L;
-    if (!g_in)
-        for_nonzeros(masks + sd.nz_off, Zs, sd.L, K, s_lo, s_hi, list, wcnt,
-                     [&](const NzEnt* lst, int cnt) {
-            if (St64) {
-                // lag-major rows St[l][d][0..KP): the atoms of one lag are
-                // contiguous; two non-zeros per step so that their loads
-                // overlap (a non-zero out of reach contributes 0 * S)
-                for (int e = 0; e < cnt; e += 2) {
-                    const NzEnt n0 = lst[e];
-                    const NzEnt n1 = e + 1 < cnt ? lst[e + 1] : n0;
-                    const int64_t d0 = t - n0.s, d1 = t - n1.s;
-                    const bool v0 = d0 > -W && d0 < W;
-                    const bool v1 = e + 1 < cnt && d1 > -W && d1 < W;
-                    const double z0 = v0 ? n0.z : 0.0, z1 = v1 ? n1.z : 0.0;
-                    const double2* __restrict__ r0 = reinterpret_cast<const double2*>(
-                        St64 + ((int64_t)n0.k * nd + (v0 ? d0 + W - 1 : 0)) * KP + kb);
-                    const double2* __restrict__ r1 = reinterpret_cast<const double2*>(
-                        St64 + ((int64_t)n1.k * nd + (v1 ? d1 + W - 1 : 0)) * KP + kb);
-                    double2 s0[kMaxK / 2], s1[kMaxK / 2];
+    if (!g_in) {
+        const int bstride = (int)(((size_t)kper * ndp * sizeof(double) + 1023) / 1024 * 128);
+        const int nch = (kn * ndp * (int)sizeof(double) + 1023) >> 10;  // 1 KB copy chunks
+        // rows of atom l into buffer buf: 64 lanes x 16 bytes per wave and chunk
+        auto stage = [&](int l, int buf) __attribute__((always_inline)) {
+            const char* src = reinterpret_cast<const char*>(Sc + ((int64_t)l * K + kb) * ndp) +
+                              lane * 16;
+            char* dst = reinterpret_cast<char*>(sst + (size_t)buf * bstride);
+            for (int c = wave; c < nch; c += 4)
+                __builtin_amdgcn_global_load_lds(
+                    (const void*)(src + (size_t)c * 1024),
+                    (__attribute__((address_space(3))) void*)(dst + (size_t)c * 1024), 16, 0,
+                    0);
+        };
+        const int64_t s_lo = t_a - (W - 1) > 0 ? t_a - (W - 1) : 0;
+        const int64_t s_hi = t_a + 256 * J + (W - 1) < L ? t_a + 256 * J + (W - 1) : L;
+        const int64_t nbk = (L + 63) / 64;
+        const int64_t b_lo = s_lo >> 6;
+        const int nbw = (int)(((s_hi - 1) >> 6) - b_lo + 1);
+        const int items = K * nbw;  // mask words in reach, atom-major
+        const unsigned long long* __restrict__ msk = masks + sd.nz_off;
+        // row offsets of the block's atoms in a buffer (past the last atom: its row)
+        int rowoff[KB];
 #pragma unroll
-                    for (int v = 0; v < kMaxK / 2; ++v)
-                        if (2 * v < kn) {
-                            s0[v] = r0[v];
-                            s1[v] = r1[v];
+        for (int kk = 0; kk < KB; ++kk)
+            rowoff[kk] = (kk < kn ? kk : kn - 1) * ndp;
+        const int n_own = L - t_a < 256 * J ? (int)(L - t_a) : 256 * J;  // positions in the tile
+        int cur_l = -1, cb = 0;  // atom whose rows sit in buffer cb
+        int staged_l = -1;       // atom whose copy into buffer cb ^ 1 is in flight
+        for (int i0 = 0; i0 < items; i0 += 256) {
+            const int it = i0 + tid;
+            unsigned long long m = 0ull;
+            int k = 0;
+            int64_t pos0 = 0;
+            if (it < items) {
+                k = it / nbw;
+                const int64_t bb = b_lo + (it - k * nbw);
+                pos0 = bb * 64;
+                m = msk[(int64_t)k * nbk + bb];
+                if (pos0 < s_lo)
+                    m &= ~0ull << (int)(s_lo - pos0);
+                if (pos0 + 64 > s_hi)
+                    m &= (1ull << (int)(s_hi - pos0)) - 1ull;  // s_hi - pos0 in [1, 63]
+            }
+            const int cm = __popcll(m);
+            int tot;
+            const int off = block_scan256(cm, &tot, wsum);
+            for (int base = 0; base < tot; base += kCheckList) {
+                // list entries [base, base + kCheckList) of this round
+                if (cm > 0 && off < base + kCheckList && off + cm > base) {
+                    unsigned long long mm = m;
+                    int idx = off;
+                    while (mm && idx < base + kCheckList) {
+                        const int bit = __ffsll(mm) - 1;
+                        mm &= mm - 1ull;
+                        if (idx >= base) {
+                            const int sp = (int)(pos0 + bit);
+                            ls[idx - base] = sp;
+                            lk[idx - base] = k;
+                            lz[idx - base] = Zs[(int64_t)k * L + sp];
                         }
-#pragma unroll
-                    for (int v = 0; v < kMaxK / 2; ++v)
-                        if (2 * v < kn) {
-                            acc[2 * v] -= s0[v].x * z0;
-                            acc[2 * v + 1] -= s0[v].y * z0;
-                        }
-#pragma unroll
-                    for (int v = 0; v < kMaxK / 2; ++v)
-                        if (2 * v < kn) {
-                            acc[2 * v] -= s1[v].x * z1;
-                            acc[2 * v + 1] -= s1[v].y * z1;
-                        }
-                }
-            } else {
-                for (int e = 0; e < cnt; ++e) {
-                    const NzEnt ne = lst[e];
-                    const int64_t dd = t - ne.s;
-                    if (dd > -W && dd < W) {
-                        // S[l][k][d + W - 1] = S_{k,l}[d]: the slice for atom l = ne.k
-                        const double* __restrict__ srow =
-                            S64 + ((int64_t)ne.k * K + kb) * nd + (dd + W - 1);
-#pragma unroll
-                        for (int k = 0; k < kMaxK; ++k)
-                            if (k < kn)
-                                acc[k] -= srow[(int64_t)k * nd] * ne.z;
+                        ++idx;
                     }
                 }
-            }
-        });
-
-    double mdz = 0.0, kon = 0.0, koff = 0.0, l1 = 0.0, mz = 0.0, nnz = 0.0;
-    bool flag = false;
-    if (act) {
-        const double lam = sd.lam;
+                lds_barrier();
+                const int cnt = tot - base < kCheckList ? tot - base : kCheckList;
+                int e = 0;
+                while (e < cnt) {
+                    const int l = lk[e];
+                    int e1 = e + 1;
+                    while (e1 < cnt && lk[e1] == l)
+                        ++e1;
+                    if (l != cur_l) {
+                        if (staged_l != l)
+                            stage(l, cb ^ 1);  // not copied ahead
+                        __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this wave's copies landed
+                        lds_barrier();  // every copy landed; the previous rows are consumed
+                        cb ^= 1;
+                        cur_l = l;
+                        staged_l = -1;
+                        if (e1 < cnt) {
+                            staged_l = lk[e1];
+                            stage(staged_l, cb ^ 1);  // in flight during this atom's sums
+                        }
+                    }
+                    const double* __restrict__ rows = sst + (size_t)cb * bstride + tid;
+                    for (int q = e; q < e1; ++q) {
+                        // lag of position t_a + tid + 256 j: d0 + tid + 256 j (32-bit:
+                        // positions are below 2^31)
+                        const int d0 = (int)(t_a - ls[q]) + (W - 1);
+                        const double z = lz[q];
 #pragma unroll
-        for (int k = 0; k < kMaxK; ++k) {
+                        for (int j = 0; j < J; ++j) {
+                            const int d = d0 + tid + 256 * j;
+                            if ((unsigned)d < (unsigned)nd && tid + 256 * j < n_own) {
+                                const double* __restrict__ sr = rows + (d0 + 256 * j);
+                                double sv[KB];
+#pragma unroll
+                                for (int kk = 0; kk < KB; ++kk)
+                                    sv[kk] = sr[rowoff[kk]];
+#pragma unroll
+                                for (int kk = 0; kk < KB; ++kk)
+                                    acc[j][kk] -= sv[kk] * z;
+                            }
+                        }
+                    }
+                    e = e1;
+                }
+                lds_barrier();  // the list is consumed
+            }
+        }
+        __builtin_amdgcn_s_waitcnt(0x0F70);  // no copy left in flight at exit
+    }
+
+    double mdz = 0.0, kon = 0.0, koff = 0.0, l1 = 0.0, mz = 0.0, nnz = 0.0, x2 = 0.0, bz = 0.0;
+    const double lam = sd.lam;
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+        const int64_t t = t_a + tid + 256 * j;
+        double zv[KB];
+        {
+            const int64_t tc = t < L ? t : L - 1;
+#pragma unroll
+            for (int k = 0; k < KB; ++k)
+                zv[k] = Zs[(int64_t)(kb + (k < kn ? k : kn - 1)) * L + tc];
+        }
+        if (t >= L)
+            continue;
+        bool flag = false;
+#pragma unroll
+        for (int k = 0; k < KB; ++k) {
             if (k >= kn)
                 continue;
             const int kk = kb + k;
-            const int64_t o = sd.z_off + (int64_t)kk * sd.L + t;
-            const double z = Zs[(int64_t)kk * sd.L + t];
+            const int64_t o = sd.z_off + (int64_t)kk * L + t;
+            const double z = zv[k];
             const double n2 = n2v[kk];
-            const double g = acc[k];
+            const double g = acc[j][k];
             const double bb = g + n2 * z;
             const double ab = fabs(bb) - lam;
             const double zp = ab > 0.0 ? (bb > 0.0 ? ab : -ab) / n2 : 0.0;
@@ -1904,6 +1907,7 @@ k_grad_check(const double* __restrict__ beta0, const double* __restrict__ Z,
                 l1 += fabs(z);
                 mz = fmax(mz, fabs(z));
                 nnz += 1.0;
+                bz += (beta0[o] + g) * z;
             } else {
                 koff = fmax(koff, fmax(fabs(g) - lam, 0.0) / n2);
             }
@@ -1914,9 +1918,19 @@ k_grad_check(const double* __restrict__ beta0, const double* __restrict__ Z,
         }
         if (flag && dirty && !frozen) {
             // segment m holds t iff floor(m L / M) <= t < floor((m+1) L / M)
-            const int64_t m = ((t + 1) * (int64_t)sd.M - 1) / sd.L;
+            const int64_t m = ((t + 1) * (int64_t)sd.M - 1) / L;
             dirty[sd.seg_base + m] = 1u;
         }
+    }
+    if (blockIdx.y == 0) {
+        // |X|^2 over the samples [t_a, t_a + span); the last tile of a signal
+        // also takes the final W - 1 samples
+        const int64_t u_hi = t_a + 256 * J >= L ? sd.T : t_a + 256 * J;
+        for (int64_t u = t_a + tid; u < u_hi; u += 256)
+            for (int p = 0; p < P; ++p) {
+                const double x = (double)X[sd.x_off + (int64_t)p * sd.T + u];
+                x2 += x * x;
+            }
     }
     mdz = block_max256(mdz, red);
     kon = block_max256(kon, red);
@@ -1924,75 +1938,91 @@ k_grad_check(const double* __restrict__ beta0, const double* __restrict__ Z,
     l1 = block_sum256(l1, red);
     mz = block_max256(mz, red);
     nnz = block_sum256(nnz, red);
-    if (threadIdx.x == 0) {
-        double* o = part6 + ((int64_t)blockIdx.y * gridDim.x + tile) * 6;
+    x2 = block_sum256(x2, red);
+    bz = block_sum256(bz, red);
+    if (tid == 0) {
+        double* o = part + ((int64_t)blockIdx.y * gridDim.x + tile) * kCheckParts;
         o[0] = mdz;
         o[1] = kon;
         o[2] = koff;
         o[3] = l1;
         o[4] = mz;
         o[5] = nnz;
+        o[6] = x2;
+        o[7] = bz;
     }
 }
 
-hipError_t launch_grad_check(const double* beta0, const double* Z,
-                             const unsigned long long* masks, const double* S64,
-                             const double* St64, const double* n2, int K, int W,
-                             const SigDesc* sig,
+hipError_t launch_grad_check(const float* X, const double* beta0, const double* Z,
+                             const unsigned long long* masks, const double* Sc,
+                             const double* n2, int K, int P, int W, const SigDesc* sig,
                              const int64_t* tile_pref, int n_sig, int64_t n_tiles,
                              double flag_eps, const uint32_t* sig_done, uint32_t* dirty,
                              void* g_state, bool state_fp64, const double* g_in,
-                             double* part6, hipStream_t s)
+                             double* part, hipStream_t s)
 {
-    dim3 grid((unsigned)n_tiles, (unsigned)((K + kMaxK - 1) / kMaxK));
-    // lag-major rows hold K rounded up to even atoms: every 16-byte read of
-    // an atom block stays inside its row
-    const int KP = lgcd_k_padded(K, true);
-    const bool use_t = St64 && KP > 0;
-    hipLaunchKernelGGL(k_grad_check, grid, dim3(256), 0, s, beta0, Z, masks, S64,
-                       use_t ? St64 : (const double*)nullptr, KP, n2, K, W,
-                       sig, tile_pref, n_sig, flag_eps, sig_done, dirty,
-                       state_fp64 ? (float*)nullptr : (float*)g_state,
-                       state_fp64 ? (double*)g_state : (double*)nullptr, g_in, part6);
-    return hipGetLastError();
+    const int kper = check_atoms_per_block(K, W);
+    if (kper < 1)
+        return hipErrorInvalidValue;
+    if (n_tiles <= 0)
+        return hipSuccess;
+    const size_t lds = 2 * (size_t)check_stage_stride(kper, W) * sizeof(double);
+    dim3 grid((unsigned)n_tiles, (unsigned)((K + kper - 1) / kper));
+    float* g32 = state_fp64 ? (float*)nullptr : (float*)g_state;
+    double* g64 = state_fp64 ? (double*)g_state : (double*)nullptr;
+    auto go = [&](auto kern) {
+        (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)lds);
+        hipLaunchKernelGGL(kern, grid, dim3(256), lds, s, X, beta0, Z, masks, Sc, n2, K, P, W,
+                           kper, sig, tile_pref, n_sig, flag_eps, sig_done, dirty, g32, g64,
+                           g_in, part);
+        return hipGetLastError();
+    };
+    static_assert(kCheckKB == 8, "instantiated atom counts");
+    if (kper <= 2)
+        return go(k_grad_check<kCheckJ, 2>);
+    if (kper <= 4)
+        return go(k_grad_check<kCheckJ, 4>);
+    if (kper <= 7)
+        return go(k_grad_check<kCheckJ, 7>);
+    return go(k_grad_check<kCheckJ, 8>);
 }
 
 // One workgroup per signal reduces its tiles' partials in a fixed order.
 __global__ void __launch_bounds__(256)
-k_check_reduce(const double* __restrict__ part_r2, const int64_t* __restrict__ prefT,
-               const double* __restrict__ part6, const int64_t* __restrict__ prefL,
-               int64_t n_tiles_L, int n_kblk, CheckResult* __restrict__ out)
+k_check_reduce(const double* __restrict__ part, const int64_t* __restrict__ pref,
+               int64_t n_tiles, int n_kblk, CheckResult* __restrict__ out)
 {
     __shared__ double red[4];
     const int si = blockIdx.x;
-    double r2 = 0.0;
-    for (int64_t i = prefT[si] + threadIdx.x; i < prefT[si + 1]; i += 256)
-        r2 += part_r2[i];
-    double mdz = 0.0, kon = 0.0, koff = 0.0, l1 = 0.0, mz = 0.0, nnz = 0.0;
+    double mdz = 0.0, kon = 0.0, koff = 0.0, l1 = 0.0, mz = 0.0, nnz = 0.0, x2 = 0.0, bz = 0.0;
     for (int kbk = 0; kbk < n_kblk; ++kbk)
-        for (int64_t i = prefL[si] + threadIdx.x; i < prefL[si + 1]; i += 256) {
-            const double* p = part6 + ((int64_t)kbk * n_tiles_L + i) * 6;
+        for (int64_t i = pref[si] + threadIdx.x; i < pref[si + 1]; i += 256) {
+            const double* p = part + ((int64_t)kbk * n_tiles + i) * kCheckParts;
             mdz = fmax(mdz, p[0]);
             kon = fmax(kon, p[1]);
             koff = fmax(koff, p[2]);
             l1 += p[3];
             mz = fmax(mz, p[4]);
             nnz += p[5];
+            x2 += p[6];
+            bz += p[7];
         }
-    r2 = block_sum256(r2, red);
     mdz = block_max256(mdz, red);
     kon = block_max256(kon, red);
     koff = block_max256(koff, red);
     l1 = block_sum256(l1, red);
     mz = block_max256(mz, red);
     nnz = block_sum256(nnz, red);
+    x2 = block_sum256(x2, red);
+    bz = block_sum256(bz, red);
     if (threadIdx.x == 0) {
         CheckResult c;
         c.max_dz = mdz;
         c.kkt_on = kon;
         c.kkt_off = koff;
         c.l1 = l1;
-        c.sum_r2 = r2;
+        c.sum_r2 = fmax(x2 - bz, 0.0);  // rounding could leave an exact fit just below 0
         c.max_abs_z = mz;
         c.nnz = nnz;
         c.pad = 0.0;
@@ -2000,13 +2030,11 @@ k_check_reduce(const double* __restrict__ part_r2, const int64_t* __restrict__ p
     }
 }
 
-hipError_t launch_check_reduce(const double* part_r2, const int64_t* tile_pref_T,
-                                const double* part6, const int64_t* tile_pref_L,
-                                int64_t n_tiles_L, int n_kblk, int n_sig,
-                                CheckResult* out, hipStream_t s)
+hipError_t launch_check_reduce(const double* part, const int64_t* tile_pref, int64_t n_tiles,
+                               int n_kblk, int n_sig, CheckResult* out, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_check_reduce, dim3((unsigned)n_sig), dim3(256), 0, s, part_r2,
-                       tile_pref_T, part6, tile_pref_L, n_tiles_L, n_kblk, out);
+    hipLaunchKernelGGL(k_check_reduce, dim3((unsigned)n_sig), dim3(256), 0, s, part, tile_pref,
+                       n_tiles, n_kblk, out);
     return hipGetLastError();
 }
 

@@ -249,7 +249,9 @@ def test_state_check_agrees_with_recompute(dicod, paper_problem):
             out.append(c.solve(X, -0.1, EPS, n_seg=0, D=D))
     (Z0, s0), (Z1, s1) = out
     assert np.array_equal(Z0, Z1)
-    assert s0["objective"] == s1["objective"]
+    # the residual energy comes from g (|X|^2 - <beta0 + g, Z>): the two g
+    # agree to rounding, and so do the objectives
+    assert abs(s0["objective"] - s1["objective"]) <= 1e-12 * s1["objective"]
     assert abs(s0["max_dz"] - s1["max_dz"]) <= 1e-12
     assert abs(s0["kkt_on"] - s1["kkt_on"]) <= 1e-12 and abs(s0["kkt_off"] - s1["kkt_off"]) <= 1e-12
     _check_solution(X, D, lam, Z0, s0, Zo)
