@@ -79,6 +79,7 @@ struct dicod_ctx {
     dicod_config cfg;
     hipStream_t stream = nullptr;
     hipStream_t side = nullptr;          // double beta0, overlapped with the descent
+    int n_cu = 256;                      // compute units of the device
     hipEvent_t ev_in = nullptr, ev_beta = nullptr;
     std::string err;
     // resident dictionary
@@ -87,6 +88,7 @@ struct dicod_ctx {
     DevBuf D64, D32, S64, S32, n2_64, inv64, n2_32, inv32;
     DevBuf St32, St64;  // phase-kernel layouts of S (float, double)
     DevBuf Sc64;        // S with rows padded to 2W doubles, for the double check
+    DevBuf Dsp;         // bf16 hi/lo split of D for the MIXED correlation
     Workspace ws;
     unsigned long long* h_upd = nullptr;  // pinned copy of per-phase counts
     size_t h_upd_cap = 0;
@@ -226,6 +228,10 @@ extern "C" int dicod_init(dicod_ctx** out, const dicod_config* cfg)
         dicod_finalize(ctx);
         return fail(nullptr, DICOD_EDEVICE, "dicod_init: stream or event creation failed");
     }
+    int n_cu = 0;
+    if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, c.device) ==
+            hipSuccess && n_cu > 0)
+        ctx->n_cu = n_cu;
     *out = ctx;
     return DICOD_OK;
 }
@@ -354,6 +360,8 @@ extern "C" int dicod_set_dictionary(dicod_ctx* ctx, const float* D, int K, int P
         HIPCHECK(ctx, ensure(St, (size_t)K * nd * KP * (f64 ? sizeof(double) : sizeof(float))));
         HIPCHECK(ctx, launch_s_transpose(ctx->S64.as<double>(), K, W, f64 != 0, St.p, s));
     }
+    HIPCHECK(ctx, ensure(ctx->Dsp, corr_bf16_dsp_elems(K, P, W) * sizeof(unsigned short)));
+    HIPCHECK(ctx, launch_split_d(ctx->D32.as<float>(), K, P, W, ctx->Dsp.as<unsigned short>(), s));
     if (check_kblocks(K, W) > 0) {
         HIPCHECK(ctx, ensure(ctx->Sc64, check_s_elems(K, W) * sizeof(double)));
         HIPCHECK(ctx, hipMemsetAsync(ctx->Sc64.p, 0, check_s_elems(K, W) * sizeof(double), s));
@@ -606,6 +614,11 @@ int solve_device_batch(dicod_ctx* ctx, int n_sig, const float* dX, const int64_t
                                           fp64 ? nullptr : ws.g.as<float>(),
                                           fp64 ? ws.g.as<double>() : nullptr, s));
     } else {
+        // the float start first; the double beta0 then runs beside the
+        // descent (it is needed after the first float round only)
+        HIPCHECK(ctx, launch_corr_bf16x3(ctx->Dsp.as<unsigned short>(), K, P, W, dX,
+                                         ws.sig.as<SigDesc>(), ws.tilesL.as<int64_t>(), n_sig,
+                                         nL, ws.g.as<float>(), s));
         HIPCHECK(ctx, hipEventRecord(ctx->ev_in, s));
         HIPCHECK(ctx, hipStreamWaitEvent(ctx->side, ctx->ev_in, 0));
         HIPCHECK(ctx, launch_corr_f64_x32(ctx->D64.as<double>(), K, P, W, dX,
@@ -613,8 +626,6 @@ int solve_device_batch(dicod_ctx* ctx, int n_sig, const float* dX, const int64_t
                                           nL, ws.beta0.as<double>(), nullptr, nullptr,
                                           ctx->side));
         HIPCHECK(ctx, hipEventRecord(ctx->ev_beta, ctx->side));
-        HIPCHECK(ctx, launch_corr_bf16x3(ctx->D32.as<float>(), K, P, W, dX, ws.sig.as<SigDesc>(),
-                                         ws.tilesL.as<int64_t>(), n_sig, nL, ws.g.as<float>(), s));
     }
     bool beta_waited = !fast_init;
     // ---- 2. lambda --------------------------------------------------------
@@ -1060,7 +1071,7 @@ extern "C" int dicod_correlate(dicod_ctx* ctx, const float* X, int64_t T, int pr
     HIPCHECK(ctx, upload(dpref, pref, s));
     HIPCHECK(ctx, hipMemcpyAsync(dx.p, X, (size_t)P * T * sizeof(float), hipMemcpyHostToDevice, s));
     if (precision == DICOD_PREC_MIXED) {
-        HIPCHECK(ctx, launch_corr_bf16x3(ctx->D32.as<float>(), K, P, W, dx.as<float>(),
+        HIPCHECK(ctx, launch_corr_bf16x3(ctx->Dsp.as<unsigned short>(), K, P, W, dx.as<float>(),
                                          dsig.as<SigDesc>(), dpref.as<int64_t>(), 1, pref[1],
                                          dout.as<float>(), s));
         std::vector<float> o32((size_t)K * L);

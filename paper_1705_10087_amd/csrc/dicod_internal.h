@@ -81,10 +81,15 @@ hipError_t launch_corr_f64_x64(const double* D, int K, int P, int W,
                                const int64_t* tile_pref, int n_sig,
                                int64_t n_tiles, double* out64, hipStream_t s);
 // Same contraction in float with split bf16 on MFMA (16x16x32 bf16, fp32
-// accumulation of hi*hi + hi*lo + lo*hi); D float [K][P][W].
-hipError_t launch_corr_bf16x3(const float* D, int K, int P, int W, const float* Y,
+// accumulation of hi*hi + hi*lo + lo*hi); Dsp from launch_split_d.
+hipError_t launch_corr_bf16x3(const unsigned short* Dsp, int K, int P, int W, const float* Y,
                               const SigDesc* sig, const int64_t* tile_pref, int n_sig,
                               int64_t n_tiles, float* g32, hipStream_t s);
+// Dsp = {hi, lo}[p][Kp][Wp] bf16 split of D float [K][P][W] (Kp, Wp: K and W
+// rounded up to multiples of 32, zero padded); corr_bf16_dsp_elems elements.
+size_t corr_bf16_dsp_elems(int K, int P, int W);
+hipError_t launch_split_d(const float* D, int K, int P, int W, unsigned short* Dsp,
+                          hipStream_t s);
 
 // Dictionary finish: S32 = (float)S64, n2 = S64[k][k][W-1], inverses.
 hipError_t launch_dict_finish(const double* S64, int K, int W, float* S32,

@@ -97,8 +97,16 @@ hipError_t launch_fill_f64(double* p, double v, size_t n, hipStream_t s)
 // matching slice of D.  Each wave computes 32 atoms x 64 positions with
 // v_mfma_f64_16x16x4f64 (A = D slice, B = shifted Y rows).
 // ---------------------------------------------------------------------------
-constexpr int kCorrRC = 64;
-constexpr int kCorrDStride = kCorrRC + 1;  // odd stride: no LDS bank aliasing
+constexpr int kCorrRCMax = 100;  // staged atom taus per pass, at most
+
+// taus per staged pass: W rounded up to a multiple of 4, split into equal
+// passes of at most kCorrRCMax (also multiples of 4)
+__host__ __device__ inline int corr_chunk(int W)
+{
+    const int Wq = (W + 3) & ~3;
+    const int n = (Wq + kCorrRCMax - 1) / kCorrRCMax;
+    return ((Wq + n - 1) / n + 3) & ~3;
+}
 
 template <typename TY>
 __global__ void __launch_bounds__(256)
@@ -109,10 +117,9 @@ k_corr_f64(const double* __restrict__ D, int K, int P, int W,
            double* __restrict__ g64)
 {
     extern __shared__ double lds[];
-    const int R = P * W;
-    const int ystride = kTile + W - 1;
-    double* Dc = lds;                          // [32][kCorrDStride]
-    double* Ys = lds + 32 * kCorrDStride;      // [P][ystride]
+    const int ystride = kTile + ((W + 3) & ~3);          // window + padded taus
+    double* Dc = lds;                                     // [32][corr_chunk + 1]
+    double* Ys = lds + 32 * (corr_chunk(W) + 1);          // [P][ystride]
 
     const int64_t tile = blockIdx.x;
     const int si = find_sig(tile_pref, n_sig, tile);
@@ -123,11 +130,13 @@ k_corr_f64(const double* __restrict__ D, int K, int P, int W,
     const int lane = tid & 63;
     const int wave = tid >> 6;
 
+    // loads at clamped (valid) indices, unconditional: several in flight
+#pragma unroll 4
     for (int i = tid; i < P * ystride; i += 256) {
-        int p = i / ystride;
-        int u = i - p * ystride;
-        int64_t t = t_a + u;
-        Ys[i] = t < sd.T ? (double)Y[sd.x_off + (int64_t)p * sd.T + t] : 0.0;
+        const int p = i / ystride;
+        const int64_t t = t_a + (i - p * ystride);
+        const double y = (double)Y[sd.x_off + (int64_t)p * sd.T + (t < sd.T ? t : sd.T - 1)];
+        Ys[i] = t < sd.T ? y : 0.0;
     }
 
     d4_t acc[2][4];
@@ -137,38 +146,39 @@ k_corr_f64(const double* __restrict__ D, int K, int P, int W,
         for (int b = 0; b < 4; ++b)
             acc[a][b] = d4_t{0.0, 0.0, 0.0, 0.0};
 
+    // the reduction runs channel by channel over tau in chunks of rc (a
+    // multiple of 4; taus past W have zero atoms), so a lane's B row needs no
+    // index division
     const int arow = lane & 15;
     const int kk = lane >> 4;
-    for (int r0 = 0; r0 < R; r0 += kCorrRC) {
-        __syncthreads();
-        for (int i = tid; i < 32 * kCorrRC; i += 256) {
-            int m = i / kCorrRC;
-            int rr = i - m * kCorrRC;
-            int k = kbase + m;
-            int r = r0 + rr;
-            Dc[m * kCorrDStride + rr] =
-                (k < K && r < R) ? D[(int64_t)k * R + r] : 0.0;
-        }
-        __syncthreads();
-        for (int ks = 0; ks < kCorrRC / 4; ++ks) {
-            if (r0 + ks * 4 >= R)
-                break;
-            const int rr = ks * 4 + kk;
-            const int r = r0 + rr;
-            const double a0 = Dc[arow * kCorrDStride + rr];
-            const double a1 = Dc[(16 + arow) * kCorrDStride + rr];
-            const bool valid = r < R;
-            const int p = valid ? r / W : 0;
-            const int tau = valid ? r - p * W : 0;
-            const double* yrow = Ys + p * ystride + wave * 64 + arow + tau;
+    const int Wq = (W + 3) & ~3;
+    const int rc = corr_chunk(W);
+    const int ds = rc + 1;  // odd stride: no LDS bank aliasing
+    for (int p = 0; p < P; ++p)
+        for (int tau0 = 0; tau0 < Wq; tau0 += rc) {
+            const int nr = Wq - tau0 < rc ? Wq - tau0 : rc;
+            __syncthreads();
+            for (int i = tid; i < 32 * rc; i += 256) {
+                const int m = i / rc;
+                const int rr = i - m * rc;
+                const int k = kbase + m;
+                const int tau = tau0 + rr;
+                Dc[m * ds + rr] = (k < K && tau < W) ? D[((int64_t)k * P + p) * W + tau] : 0.0;
+            }
+            __syncthreads();
+            const double* __restrict__ da = Dc + arow * ds + kk;
+            const double* __restrict__ yb = Ys + p * ystride + wave * 64 + arow + tau0 + kk;
+            for (int ks = 0; ks < nr; ks += 4) {
+                const double a0 = da[ks];
+                const double a1 = da[16 * ds + ks];
 #pragma unroll
-            for (int nt = 0; nt < 4; ++nt) {
-                const double bv = valid ? yrow[nt * 16] : 0.0;
-                acc[0][nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, bv, acc[0][nt], 0, 0, 0);
-                acc[1][nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, bv, acc[1][nt], 0, 0, 0);
+                for (int nt = 0; nt < 4; ++nt) {
+                    const double bv = yb[ks + nt * 16];
+                    acc[0][nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, bv, acc[0][nt], 0, 0, 0);
+                    acc[1][nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, bv, acc[1][nt], 0, 0, 0);
+                }
             }
         }
-    }
 
     // C[i][j] of a 16x16 f64 MFMA tile sits in lane (i % 4) * 16 + j, item i / 4
     // (measured on gfx950; the f32/bf16 tiles use lane (i / 4) * 16 + j, item i % 4).
@@ -194,7 +204,7 @@ k_corr_f64(const double* __restrict__ D, int K, int P, int W,
 
 static size_t corr_lds(int P, int W)
 {
-    return sizeof(double) * (32 * kCorrDStride + (size_t)P * (kTile + W - 1));
+    return sizeof(double) * (32 * (size_t)(corr_chunk(W) + 1) + (size_t)P * (kTile + ((W + 3) & ~3)));
 }
 
 hipError_t launch_corr_f64_x32(const double* D, int K, int P, int W, const float* Y,
@@ -207,6 +217,8 @@ hipError_t launch_corr_f64_x32(const double* D, int K, int P, int W, const float
         return hipErrorInvalidValue;
     (void)hipFuncSetAttribute((const void*)k_corr_f64<float>,
                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (n_tiles <= 0)
+        return hipSuccess;
     dim3 grid((unsigned)n_tiles, (unsigned)((K + 31) / 32));
     hipLaunchKernelGGL(k_corr_f64<float>, grid, dim3(256), lds, s, D, K, P, W, Y,
                        sig, tile_pref, n_sig, out64, g32, g64);
@@ -223,6 +235,8 @@ hipError_t launch_corr_f64_x64(const double* D, int K, int P, int W,
         return hipErrorInvalidValue;
     (void)hipFuncSetAttribute((const void*)k_corr_f64<double>,
                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (n_tiles <= 0)
+        return hipSuccess;
     dim3 grid((unsigned)n_tiles, (unsigned)((K + 31) / 32));
     hipLaunchKernelGGL(k_corr_f64<double>, grid, dim3(256), lds, s, D, K, P, W, Y,
                        sig, tile_pref, n_sig, out64, (float*)nullptr,
@@ -230,18 +244,25 @@ hipError_t launch_corr_f64_x64(const double* D, int K, int P, int W,
     return hipGetLastError();
 }
 
-// The same implicit-im2col correlation with split bf16 on
-// v_mfma_f32_16x16x32_bf16 (MIXED policy): every float x is split into
-// hi = bf16(x) and lo = bf16(x - hi), and the products hi*hi + hi*lo + lo*hi
-// accumulate in fp32 (lo*lo, about 2^-16 of the rest, is dropped).  This is
-// the starting point of the float descent state; the double beta0 needed by
-// the double-precision check is computed separately.
+// Split-bf16 correlation (MIXED policy): every float x is split into
+// hi = bf16(x) and lo = bf16(x - hi), and hi*hi + hi*lo + lo*hi accumulate in
+// fp32 on v_mfma_f32_16x16x32_bf16 (lo*lo, about 2^-16 of the rest, is
+// dropped).  This is the starting point of the float descent state; the double
+// beta0 needed by the double-precision check is computed separately.
+//
+// The GEMM is [K x P Wp] . [P Wp x L] with the reduction index r = (p, tau),
+// tau padded to Wp = 32 ceil(W / 32) with zero atom entries.  A (the atoms)
+// comes pre-split from Dsp = {hi, lo}[p][Kp][Wp] (Kp = 32 ceil(K / 32)): one
+// 16-byte load per lane.  B is the Hankel matrix Y[p][t + tau]: lane (j, g)
+// of a 16x16x32 tile needs Y[p][t_j + tau0 + 8 g .. + 7], a window that is
+// not 16-byte aligned.  Per channel the block stages 8 copies of its signal
+// window, copy sigma shifted by sigma elements (it holds Y[t_a + u + sigma] at
+// u); tile starts and tau0 are multiples of 8, so lane j always reads copy
+// j mod 8 at a multiple of 8: one 16-byte LDS read per operand.  A copy
+// stride of 8 (mod 64) elements puts the 8 copies' reads in distinct banks.
 typedef float f4_t __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef unsigned short u16x8_t __attribute__((ext_vector_type(8)));
-
-constexpr int kBfRC = 64;       // reduction indices staged per pass (two MFMA k-steps)
-constexpr int kBfDStride = 72;  // ushort row stride of the staged atoms (16-byte rows)
 
 __device__ __forceinline__ unsigned short bf16_rne(float x)
 {
@@ -254,24 +275,60 @@ __device__ __forceinline__ float bf16_value(unsigned short h)
     return __uint_as_float((unsigned)h << 16);
 }
 
-static size_t corr_bf16_lds(int P, int W)
+__host__ __device__ inline int bf_pad_w(int W) { return (W + 31) / 32 * 32; }
+__host__ __device__ inline int bf_pad_k(int K) { return (K + 31) / 32 * 32; }
+// elements per staged copy: >= 256 + Wp, = 8 (mod 64)
+__host__ __device__ inline int bf_copy_stride(int W) { return (256 + bf_pad_w(W) + 63) / 64 * 64 + 8; }
+
+size_t corr_bf16_dsp_elems(int K, int P, int W)
 {
-    return sizeof(unsigned short) *
-           (2 * 32 * (size_t)kBfDStride + 2 * (size_t)P * (kTile + W - 1));
+    return 2 * (size_t)P * bf_pad_k(K) * bf_pad_w(W);
 }
 
 __global__ void __launch_bounds__(256)
-k_corr_bf16x3(const float* __restrict__ D, int K, int P, int W, const float* __restrict__ Y,
-              const SigDesc* __restrict__ sig, const int64_t* __restrict__ tile_pref,
-              int n_sig, float* __restrict__ g32)
+k_split_d(const float* __restrict__ D, int K, int P, int W, unsigned short* __restrict__ Dsp)
 {
-    extern __shared__ __align__(16) unsigned short lds16[];
-    const int R = P * W;
-    const int ystride = kTile + W - 1;
-    unsigned short* Dh = lds16;                     // [32][kBfDStride]
-    unsigned short* Dl = Dh + 32 * kBfDStride;
-    unsigned short* Yh = Dl + 32 * kBfDStride;      // [P][ystride]
-    unsigned short* Yl = Yh + (size_t)P * ystride;
+    const int Kp = bf_pad_k(K), Wp = bf_pad_w(W);
+    const size_t n = (size_t)P * Kp * Wp;
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
+        const int tau = (int)(i % Wp);
+        const size_t r = i / Wp;
+        const int k = (int)(r % Kp);
+        const int p = (int)(r / Kp);
+        const float x = (k < K && tau < W) ? D[((size_t)k * P + p) * W + tau] : 0.f;
+        const unsigned short h = bf16_rne(x);
+        Dsp[i] = h;
+        Dsp[n + i] = bf16_rne(x - bf16_value(h));
+    }
+}
+
+hipError_t launch_split_d(const float* D, int K, int P, int W, unsigned short* Dsp,
+                          hipStream_t s)
+{
+    const size_t n = corr_bf16_dsp_elems(K, P, W) / 2;
+    const size_t blocks = std::min<size_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_split_d, dim3((unsigned)blocks), dim3(256), 0, s, D, K, P, W, Dsp);
+    return hipGetLastError();
+}
+
+constexpr int kBfGroups = 3;   // staged signal groups (8 elements) per thread and batch
+constexpr int kBfDChunks = 4;  // staged 16-byte atom chunks per thread and batch
+
+static size_t corr_bf16_lds(int W)
+{
+    // 8 shifted signal copies {hi, lo} + the channel's atom slice {hi, lo}[32][Wp + 8]
+    return sizeof(unsigned short) * (2 * 8 * (size_t)bf_copy_stride(W) +
+                                     2 * 32 * (size_t)(bf_pad_w(W) + 8));
+}
+
+__global__ void __launch_bounds__(256)
+k_corr_bf16x3(const unsigned short* __restrict__ Dsp, int K, int P, int W,
+              const float* __restrict__ Y, const SigDesc* __restrict__ sig,
+              const int64_t* __restrict__ tile_pref, int n_sig, float* __restrict__ g32)
+{
+    extern __shared__ __align__(16) unsigned short ysh[];  // [hi, lo][sigma][cs], then atoms
+    const int Kp = bf_pad_k(K), Wp = bf_pad_w(W), cs = bf_copy_stride(W);
+    const size_t dn = (size_t)P * Kp * Wp;  // offset of the lo half of Dsp
 
     const int64_t tile = blockIdx.x;
     const int si = find_sig(tile_pref, n_sig, tile);
@@ -281,90 +338,113 @@ k_corr_bf16x3(const float* __restrict__ D, int K, int P, int W, const float* __r
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
+    const int j = lane & 15;  // tile row (A) / column (B)
+    const int g = lane >> 4;  // reduction octet
 
-    for (int i = tid; i < P * ystride; i += 256) {
-        const int p = i / ystride;
-        const int u = i - p * ystride;
-        const int64_t t = t_a + u;
-        const float y = t < sd.T ? Y[sd.x_off + (int64_t)p * sd.T + t] : 0.f;
-        const unsigned short h = bf16_rne(y);
-        Yh[i] = h;
-        Yl[i] = bf16_rne(y - bf16_value(h));
-    }
     f4_t acc[2][4];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 4; ++b)
             acc[a][b] = f4_t{0.f, 0.f, 0.f, 0.f};
-    // A[i][k] (atom i, reduction k) and B[k][j] (position j) sit in lane
-    // i (or j) + 16 * (k / 8), element k % 8.
-    const int arow = lane & 15;
-    const int kq = lane >> 4;
-    for (int r0 = 0; r0 < R; r0 += kBfRC) {
-        __syncthreads();
-        for (int i = tid; i < 32 * kBfRC; i += 256) {
-            const int m = i / kBfRC;
-            const int rr = i - m * kBfRC;
-            const int k = kbase + m;
-            const int r = r0 + rr;
-            const float dv = (k < K && r < R) ? D[(int64_t)k * R + r] : 0.f;
-            const unsigned short h = bf16_rne(dv);
-            Dh[m * kBfDStride + rr] = h;
-            Dl[m * kBfDStride + rr] = bf16_rne(dv - bf16_value(h));
-        }
-        __syncthreads();
+
+    // Per channel the block stages the 8 shifted copies of its signal window
+    // (group idx = (sigma, a) holds Y[t_a + 8 a + sigma + e], e < 8) and the
+    // channel's atom slice {hi, lo}[32][Wp] (rows padded to ds = Wp + 8
+    // elements: 16-byte reads of 8 consecutive rows hit distinct banks); all
+    // loads are at valid (clamped) indices and unconditional, so they are in
+    // flight together, and the products read LDS only.
+    const int na = cs / 8;  // 8-element groups per copy
+    const int ng = 8 * na;
+    const int ds = Wp + 8;
+    unsigned short* __restrict__ dsh = ysh + 16 * cs;  // [hi, lo][32][ds]
+    const int nq = 2 * 32 * (Wp / 8);                 // 16-byte chunks of the atom slice
+    const int yoff = (j & 7) * cs + 64 * wave + 8 * (j >> 3) + 8 * g;
+    for (int p = 0; p < P; ++p) {
+        __syncthreads();  // the previous channel's operands are consumed
+        const float* __restrict__ yr = Y + sd.x_off + (int64_t)p * sd.T;
+        for (int i0 = 0; i0 < ng; i0 += 256 * kBfGroups) {
+            float yv[kBfGroups][8];
 #pragma unroll
-        for (int ks = 0; ks < kBfRC / 32; ++ks) {
-            if (r0 + ks * 32 >= R)
-                break;
-            const int rr0 = ks * 32 + 8 * kq;
-            const u16x8_t ah0 = *reinterpret_cast<const u16x8_t*>(Dh + arow * kBfDStride + rr0);
-            const u16x8_t al0 = *reinterpret_cast<const u16x8_t*>(Dl + arow * kBfDStride + rr0);
-            const u16x8_t ah1 =
-                *reinterpret_cast<const u16x8_t*>(Dh + (16 + arow) * kBfDStride + rr0);
-            const u16x8_t al1 =
-                *reinterpret_cast<const u16x8_t*>(Dl + (16 + arow) * kBfDStride + rr0);
-            // (p, tau) of the lane's 8 reduction indices
-            int off[8];
-            bool val[8];
-            {
-                const int r = r0 + rr0;
-                int p = r / W;
-                int tau = r - p * W;
+            for (int q = 0; q < kBfGroups; ++q) {
+                const int idx = i0 + tid + 256 * q;
+                const int sg = idx / na;
+                const int64_t u0 = t_a + 8 * (idx - sg * na) + sg;
 #pragma unroll
-                for (int e = 0; e < 8; ++e) {
-                    val[e] = r + e < R;
-                    off[e] = val[e] ? p * ystride + tau : 0;
-                    if (++tau == W) {
-                        tau = 0;
-                        ++p;
-                    }
-                }
+                for (int e = 0; e < 8; ++e)
+                    yv[q][e] = yr[u0 + e < sd.T ? u0 + e : sd.T - 1];
             }
 #pragma unroll
-            for (int nt = 0; nt < 4; ++nt) {
-                const int base = wave * 64 + nt * 16 + arow;
-                u16x8_t bh, bl;
+            for (int q = 0; q < kBfGroups; ++q) {
+                const int idx = i0 + tid + 256 * q;
+                if (idx >= ng)
+                    continue;
+                const int sg = idx / na;
+                const int a = idx - sg * na;
+                const int64_t u0 = t_a + 8 * a + sg;
+                u16x8_t h, l;
 #pragma unroll
                 for (int e = 0; e < 8; ++e) {
-                    bh[e] = val[e] ? Yh[off[e] + base] : (unsigned short)0;
-                    bl[e] = val[e] ? Yl[off[e] + base] : (unsigned short)0;
+                    const float y = u0 + e < sd.T ? yv[q][e] : 0.f;
+                    const unsigned short hh = bf16_rne(y);
+                    h[e] = hh;
+                    l[e] = bf16_rne(y - bf16_value(hh));
                 }
-                const bf16x8_t bhv = __builtin_bit_cast(bf16x8_t, bh);
-                const bf16x8_t blv = __builtin_bit_cast(bf16x8_t, bl);
-                acc[0][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                    __builtin_bit_cast(bf16x8_t, ah0), bhv, acc[0][nt], 0, 0, 0);
-                acc[0][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                    __builtin_bit_cast(bf16x8_t, ah0), blv, acc[0][nt], 0, 0, 0);
-                acc[0][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                    __builtin_bit_cast(bf16x8_t, al0), bhv, acc[0][nt], 0, 0, 0);
-                acc[1][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                    __builtin_bit_cast(bf16x8_t, ah1), bhv, acc[1][nt], 0, 0, 0);
-                acc[1][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                    __builtin_bit_cast(bf16x8_t, ah1), blv, acc[1][nt], 0, 0, 0);
-                acc[1][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                    __builtin_bit_cast(bf16x8_t, al1), bhv, acc[1][nt], 0, 0, 0);
+                *reinterpret_cast<u16x8_t*>(ysh + sg * cs + 8 * a) = h;
+                *reinterpret_cast<u16x8_t*>(ysh + (8 + sg) * cs + 8 * a) = l;
+            }
+        }
+        {
+            const unsigned short* __restrict__ src = Dsp + ((size_t)p * Kp + kbase) * Wp;
+            for (int q0 = 0; q0 < nq; q0 += 256 * kBfDChunks) {
+                u16x8_t v[kBfDChunks];
+#pragma unroll
+                for (int c = 0; c < kBfDChunks; ++c) {
+                    int q = q0 + tid + 256 * c;
+                    q = q < nq ? q : nq - 1;
+                    const int hl = q / (nq / 2);
+                    const int r = q - hl * (nq / 2);
+                    v[c] = *reinterpret_cast<const u16x8_t*>(src + hl * dn + (size_t)r * 8);
+                }
+#pragma unroll
+                for (int c = 0; c < kBfDChunks; ++c) {
+                    const int q = q0 + tid + 256 * c;
+                    if (q >= nq)
+                        continue;
+                    const int hl = q / (nq / 2);
+                    const int r = q - hl * (nq / 2);  // row r / (Wp / 8), octet r % (Wp / 8)
+                    const int row = r / (Wp / 8);
+                    const int oc = r - row * (Wp / 8);
+                    *reinterpret_cast<u16x8_t*>(dsh + (hl * 32 + row) * ds + 8 * oc) = v[c];
+                }
+            }
+        }
+        __syncthreads();
+        // A[i][k] (atom i, reduction k) and B[k][j] (position j) sit in lane
+        // i (or j) + 16 * (k / 8), element k % 8
+        const unsigned short* __restrict__ yh = ysh + yoff;
+        const unsigned short* __restrict__ yl = yh + 8 * cs;
+        const unsigned short* __restrict__ ah = dsh + j * ds + 8 * g;
+        const unsigned short* __restrict__ al = ah + 32 * ds;
+        for (int t0 = 0; t0 < Wp; t0 += 32) {
+            const bf16x8_t ah0 = __builtin_bit_cast(bf16x8_t, *reinterpret_cast<const u16x8_t*>(ah + t0));
+            const bf16x8_t al0 = __builtin_bit_cast(bf16x8_t, *reinterpret_cast<const u16x8_t*>(al + t0));
+            const bf16x8_t ah1 =
+                __builtin_bit_cast(bf16x8_t, *reinterpret_cast<const u16x8_t*>(ah + 16 * ds + t0));
+            const bf16x8_t al1 =
+                __builtin_bit_cast(bf16x8_t, *reinterpret_cast<const u16x8_t*>(al + 16 * ds + t0));
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) {
+                const bf16x8_t bhv =
+                    __builtin_bit_cast(bf16x8_t, *reinterpret_cast<const u16x8_t*>(yh + 16 * nt + t0));
+                const bf16x8_t blv =
+                    __builtin_bit_cast(bf16x8_t, *reinterpret_cast<const u16x8_t*>(yl + 16 * nt + t0));
+                acc[0][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah0, bhv, acc[0][nt], 0, 0, 0);
+                acc[0][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah0, blv, acc[0][nt], 0, 0, 0);
+                acc[0][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al0, bhv, acc[0][nt], 0, 0, 0);
+                acc[1][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah1, bhv, acc[1][nt], 0, 0, 0);
+                acc[1][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah1, blv, acc[1][nt], 0, 0, 0);
+                acc[1][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al1, bhv, acc[1][nt], 0, 0, 0);
             }
         }
     }
@@ -376,24 +456,26 @@ k_corr_bf16x3(const float* __restrict__ D, int K, int P, int W, const float* __r
         for (int nt = 0; nt < 4; ++nt)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int k = kbase + mi * 16 + 4 * kq + v;
-                const int64_t t = t_a + wave * 64 + nt * 16 + arow;
+                const int k = kbase + mi * 16 + 4 * g + v;
+                const int64_t t = t_a + wave * 64 + nt * 16 + j;
                 if (k < K && t < sd.L)
                     g32[sd.z_off + (int64_t)k * sd.L + t] = acc[mi][nt][v];
             }
 }
 
-hipError_t launch_corr_bf16x3(const float* D, int K, int P, int W, const float* Y,
+hipError_t launch_corr_bf16x3(const unsigned short* Dsp, int K, int P, int W, const float* Y,
                               const SigDesc* sig, const int64_t* tile_pref, int n_sig,
                               int64_t n_tiles, float* g32, hipStream_t s)
 {
-    const size_t lds = corr_bf16_lds(P, W);
+    const size_t lds = corr_bf16_lds(W);
     if (lds > kLdsBytes)
         return hipErrorInvalidValue;
+    if (n_tiles <= 0)
+        return hipSuccess;
     (void)hipFuncSetAttribute((const void*)k_corr_bf16x3,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    dim3 grid((unsigned)n_tiles, (unsigned)((K + 31) / 32));
-    hipLaunchKernelGGL(k_corr_bf16x3, grid, dim3(256), lds, s, D, K, P, W, Y, sig, tile_pref,
+    dim3 grid((unsigned)n_tiles, (unsigned)(bf_pad_k(K) / 32));
+    hipLaunchKernelGGL(k_corr_bf16x3, grid, dim3(256), lds, s, Dsp, K, P, W, Y, sig, tile_pref,
                        n_sig, g32);
     return hipGetLastError();
 }
