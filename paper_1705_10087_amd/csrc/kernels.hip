@@ -97,7 +97,17 @@ hipError_t launch_fill_f64(double* p, double v, size_t n, hipStream_t s)
 // matching slice of D.  Each wave computes 32 atoms x 64 positions with
 // v_mfma_f64_16x16x4f64 (A = D slice, B = shifted Y rows).
 // ---------------------------------------------------------------------------
+// Workgroup barrier that orders LDS only: unlike __syncthreads() it does not
+// wait for the block's outstanding global loads.
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 constexpr int kCorrRCMax = 100;  // staged atom taus per pass, at most
+constexpr int kCorrPre = 13;     // staged atom values per thread: 32 x 100 <= 13 x 256
 
 // taus per staged pass: W rounded up to a multiple of 4, split into equal
 // passes of at most kCorrRCMax (also multiples of 4)
@@ -154,31 +164,55 @@ k_corr_f64(const double* __restrict__ D, int K, int P, int W,
     const int Wq = (W + 3) & ~3;
     const int rc = corr_chunk(W);
     const int ds = rc + 1;  // odd stride: no LDS bank aliasing
-    for (int p = 0; p < P; ++p)
-        for (int tau0 = 0; tau0 < Wq; tau0 += rc) {
-            const int nr = Wq - tau0 < rc ? Wq - tau0 : rc;
-            __syncthreads();
-            for (int i = tid; i < 32 * rc; i += 256) {
+    // The next pass's atom values are loaded into registers (at clamped, valid
+    // indices, all in flight together) while the current pass's products run;
+    // the barriers order LDS only, so they do not wait for those loads.
+    const int ncp = (Wq + rc - 1) / rc;  // passes per channel
+    const int npass = P * ncp;
+    double dv[kCorrPre];
+    auto load_d = [&](int pass) __attribute__((always_inline)) {
+        const int p = pass / ncp;
+        const int tau0 = (pass - p * ncp) * rc;
+#pragma unroll
+        for (int q = 0; q < kCorrPre; ++q) {
+            const int i = tid + 256 * q;
+            const int m = i / rc;
+            const int k = kbase + m < K ? kbase + m : K - 1;
+            const int tau = tau0 + (i - m * rc) < W ? tau0 + (i - m * rc) : W - 1;
+            dv[q] = D[((int64_t)k * P + p) * W + tau];
+        }
+    };
+    load_d(0);
+    for (int pass = 0; pass < npass; ++pass) {
+        const int p = pass / ncp;
+        const int tau0 = (pass - p * ncp) * rc;
+        const int nr = Wq - tau0 < rc ? Wq - tau0 : rc;
+        lds_barrier();  // the previous pass's atoms are consumed
+#pragma unroll
+        for (int q = 0; q < kCorrPre; ++q) {
+            const int i = tid + 256 * q;
+            if (i < 32 * rc) {
                 const int m = i / rc;
                 const int rr = i - m * rc;
-                const int k = kbase + m;
-                const int tau = tau0 + rr;
-                Dc[m * ds + rr] = (k < K && tau < W) ? D[((int64_t)k * P + p) * W + tau] : 0.0;
-            }
-            __syncthreads();
-            const double* __restrict__ da = Dc + arow * ds + kk;
-            const double* __restrict__ yb = Ys + p * ystride + wave * 64 + arow + tau0 + kk;
-            for (int ks = 0; ks < nr; ks += 4) {
-                const double a0 = da[ks];
-                const double a1 = da[16 * ds + ks];
-#pragma unroll
-                for (int nt = 0; nt < 4; ++nt) {
-                    const double bv = yb[ks + nt * 16];
-                    acc[0][nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, bv, acc[0][nt], 0, 0, 0);
-                    acc[1][nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, bv, acc[1][nt], 0, 0, 0);
-                }
+                Dc[m * ds + rr] = (kbase + m < K && tau0 + rr < W) ? dv[q] : 0.0;
             }
         }
+        if (pass + 1 < npass)
+            load_d(pass + 1);
+        lds_barrier();
+        const double* __restrict__ da = Dc + arow * ds + kk;
+        const double* __restrict__ yb = Ys + p * ystride + wave * 64 + arow + tau0 + kk;
+        for (int ks = 0; ks < nr; ks += 4) {
+            const double a0 = da[ks];
+            const double a1 = da[16 * ds + ks];
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) {
+                const double bv = yb[ks + nt * 16];
+                acc[0][nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, bv, acc[0][nt], 0, 0, 0);
+                acc[1][nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, bv, acc[1][nt], 0, 0, 0);
+            }
+        }
+    }
 
     // C[i][j] of a 16x16 f64 MFMA tile sits in lane (i % 4) * 16 + j, item i / 4
     // (measured on gfx950; the f32/bf16 tiles use lane (i / 4) * 16 + j, item i % 4).
@@ -1737,15 +1771,6 @@ static int check_stage_stride(int kper, int W)
 
 constexpr int kCheckList = 448;  // listed non-zeros per pass (LDS)
 constexpr int kCheckJ = kCheckSpan / 256;
-
-// Workgroup barrier that orders LDS only: unlike __syncthreads() it does not
-// wait for the block's outstanding global loads.
-__device__ __forceinline__ void lds_barrier()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-    __builtin_amdgcn_s_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
-}
 
 // Exclusive prefix sum of v over the 256 threads; *total gets the sum.
 // All threads call it.
