@@ -265,7 +265,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--cap", type=int, default=16, help="updates per segment per phase")
+    ap.add_argument("--cap", type=int, default=28, help="updates per segment per phase")
     ap.add_argument("--n-seg", type=int, default=0, help="0 = library default")
     ap.add_argument("--colors", type=int, default=3, help="phase classes of the schedule")
     ap.add_argument("--no-cpu-baseline", action="store_true")

@@ -158,7 +158,7 @@ typedef struct {
     double delta;     /* applied change of Z_{k0}[t0]         */
 } dicod_trace_rec;
 
-/* Fills *cfg with the defaults: device 0, FP32, coloured phases, update_cap 16,
+/* Fills *cfg with the defaults: device 0, FP32, coloured phases, update_cap 28,
  * max_phases 1e6, max_refresh 8, phases_per_poll 16, inner_eps_factor 0.5,
  * timing 0, no trace, state_in_lds 1, fp64_polish_after 1, colors 3,
  * verify_from_scratch 0.  Returns DICOD_OK, or DICOD_EINVAL if cfg is NULL. */

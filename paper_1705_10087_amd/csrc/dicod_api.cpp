@@ -171,7 +171,7 @@ extern "C" int dicod_config_init(dicod_config* cfg)
     cfg->device = 0;
     cfg->precision = DICOD_PREC_FP32;
     cfg->schedule = DICOD_SCHED_EVENODD;
-    cfg->update_cap = 16;
+    cfg->update_cap = 28;
     cfg->max_phases = 1000000;
     cfg->max_refresh = 8;
     cfg->phases_per_poll = 16;
