@@ -71,6 +71,10 @@ struct Workspace {
     DevBuf part, results, lmax, done, thr;
     DevBuf msg, msg_n;                    // DICOD schedule: boundary messages
     DevBuf trace;
+    DevBuf slots, lamin;                  // device-side lambda: signal indices, inputs
+    // host copies of what the read-only plan tables hold on the device: an
+    // identical plan is not uploaded again
+    std::vector<unsigned char> sh_segs, sh_lists[kMaxColors], sh_tL, sh_tC, sh_tA, sh_tN, sh_slots;
 };
 
 }  // namespace
@@ -92,6 +96,9 @@ struct dicod_ctx {
     Workspace ws;
     unsigned long long* h_upd = nullptr;  // pinned copy of per-phase counts
     size_t h_upd_cap = 0;
+    hipEvent_t ev_poll[2] = {nullptr, nullptr};  // queued chunks of phases
+    unsigned char* h_pin = nullptr;       // pinned staging of per-round uploads
+    size_t h_pin_cap = 0;
     std::vector<hipEvent_t> ev_pool;
     int64_t last_trace_n = 0;
     dicod::Server* server = nullptr;
@@ -224,7 +231,9 @@ extern "C" int dicod_init(dicod_ctx** out, const dicod_config* cfg)
     if (hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess ||
         hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&ctx->ev_in, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&ctx->ev_beta, hipEventDisableTiming) != hipSuccess) {
+        hipEventCreateWithFlags(&ctx->ev_beta, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&ctx->ev_poll[0], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&ctx->ev_poll[1], hipEventDisableTiming) != hipSuccess) {
         dicod_finalize(ctx);
         return fail(nullptr, DICOD_EDEVICE, "dicod_init: stream or event creation failed");
     }
@@ -255,8 +264,13 @@ extern "C" void dicod_finalize(dicod_ctx* ctx)
         (void)hipEventDestroy(ctx->ev_in);
     if (ctx->ev_beta)
         (void)hipEventDestroy(ctx->ev_beta);
+    for (hipEvent_t e : ctx->ev_poll)
+        if (e)
+            (void)hipEventDestroy(e);
     if (ctx->h_upd)
         (void)hipHostFree(ctx->h_upd);
+    if (ctx->h_pin)
+        (void)hipHostFree(ctx->h_pin);
     if (ctx->stream)
         (void)hipStreamDestroy(ctx->stream);
     if (ctx->side)
@@ -512,6 +526,24 @@ hipError_t upload(DevBuf& b, const std::vector<T>& v, hipStream_t s)
     return hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s);
 }
 
+// Uploads v unless the buffer already holds exactly these bytes (as recorded
+// in shadow); for read-only tables.
+template <typename T>
+hipError_t upload_cached(DevBuf& b, const std::vector<T>& v, std::vector<unsigned char>& shadow,
+                         hipStream_t s)
+{
+    const size_t bytes = v.size() * sizeof(T);
+    if (b.p && b.n >= bytes && shadow.size() == bytes &&
+        (bytes == 0 || std::memcmp(shadow.data(), v.data(), bytes) == 0))
+        return hipSuccess;
+    shadow.clear();
+    hipError_t e = upload(b, v, s);
+    if (e == hipSuccess)
+        shadow.assign(reinterpret_cast<const unsigned char*>(v.data()),
+                      reinterpret_cast<const unsigned char*>(v.data()) + bytes);
+    return e;
+}
+
 hipEvent_t pool_event(dicod_ctx* ctx, size_t i)
 {
     while (ctx->ev_pool.size() <= i) {
@@ -575,6 +607,27 @@ int solve_device_batch(dicod_ctx* ctx, int n_sig, const float* dX, const int64_t
     HIPCHECK(ctx, ensure(ws.done, n_sig * sizeof(uint32_t)));
     if (cfg.trace_capacity > 0)
         HIPCHECK(ctx, ensure(ws.trace, cfg.trace_capacity * sizeof(dicod_trace_rec)));
+    // pinned staging of the per-round uploads (descriptors, done flags): the
+    // copies then leave the host at once; every use is separated from the next
+    // by a synchronisation of the stream (the double check)
+    const size_t pin_lam = ((size_t)n_sig * sizeof(uint32_t) + 255) & ~(size_t)255;
+    const size_t pin_sig = pin_lam + (((size_t)n_sig * sizeof(double) + 255) & ~(size_t)255);
+    const size_t pin_need = pin_sig + (size_t)n_sig * sizeof(SigDesc);
+    if (pin_need > ctx->h_pin_cap) {
+        if (ctx->h_pin)
+            (void)hipHostFree(ctx->h_pin);
+        ctx->h_pin = nullptr;
+        ctx->h_pin_cap = 0;
+        HIPCHECK(ctx, hipHostMalloc((void**)&ctx->h_pin, pin_need, hipHostMallocDefault));
+        ctx->h_pin_cap = pin_need;
+    }
+    auto upload_pinned = [&](DevBuf& b, const void* src, size_t bytes, size_t off) {
+        hipError_t e = ensure(b, bytes);
+        if (e != hipSuccess || bytes == 0)
+            return e;
+        std::memcpy(ctx->h_pin + off, src, bytes);
+        return hipMemcpyAsync(b.p, ctx->h_pin + off, bytes, hipMemcpyHostToDevice, s);
+    };
     if ((size_t)(max_ph + 1) > ctx->h_upd_cap) {
         if (ctx->h_upd)
             (void)hipHostFree(ctx->h_upd);
@@ -585,14 +638,14 @@ int solve_device_batch(dicod_ctx* ctx, int n_sig, const float* dX, const int64_t
                                     hipHostMallocDefault));
         ctx->h_upd_cap = (size_t)(max_ph + 1);
     }
-    HIPCHECK(ctx, upload(ws.sig, pl.sig, s));
-    HIPCHECK(ctx, upload(ws.segs, pl.segs, s));
+    HIPCHECK(ctx, upload_pinned(ws.sig, pl.sig.data(), (size_t)n_sig * sizeof(SigDesc), pin_sig));
+    HIPCHECK(ctx, upload_cached(ws.segs, pl.segs, ws.sh_segs, s));
     for (int c = 0; c < pl.colors; ++c)
-        HIPCHECK(ctx, upload(ws.lists[c], pl.list[c], s));
-    HIPCHECK(ctx, upload(ws.tilesL, pl.prefL, s));
-    HIPCHECK(ctx, upload(ws.tilesC, pl.prefC, s));
-    HIPCHECK(ctx, upload(ws.tilesA, pl.prefA, s));
-    HIPCHECK(ctx, upload(ws.tilesN, pl.prefN, s));
+        HIPCHECK(ctx, upload_cached(ws.lists[c], pl.list[c], ws.sh_lists[c], s));
+    HIPCHECK(ctx, upload_cached(ws.tilesL, pl.prefL, ws.sh_tL, s));
+    HIPCHECK(ctx, upload_cached(ws.tilesC, pl.prefC, ws.sh_tC, s));
+    HIPCHECK(ctx, upload_cached(ws.tilesA, pl.prefA, ws.sh_tA, s));
+    HIPCHECK(ctx, upload_cached(ws.tilesN, pl.prefN, ws.sh_tN, s));
 
     hipEvent_t ev0 = pool_event(ctx, 0), ev1 = pool_event(ctx, 1);
     hipEvent_t ev2 = pool_event(ctx, 2), ev3 = pool_event(ctx, 3);
@@ -628,6 +681,39 @@ int solve_device_batch(dicod_ctx* ctx, int n_sig, const float* dX, const int64_t
         HIPCHECK(ctx, hipEventRecord(ctx->ev_beta, ctx->side));
     }
     bool beta_waited = !fast_init;
+    // ---- descent state (queued behind the correlation, before the lambda
+    // read-back, so that these small launches do not wait for the host) ----
+    {
+        // Z = 0 over the union of the signals' [K][L] ranges (one launch per
+        // contiguous run)
+        std::vector<std::pair<int64_t, int64_t>> zr(n_sig);
+        for (int i = 0; i < n_sig; ++i)
+            zr[i] = {pl.sig[i].z_off, pl.sig[i].z_off + (int64_t)K * pl.sig[i].L};
+        std::sort(zr.begin(), zr.end());
+        int64_t lo = zr[0].first, hi = zr[0].second;
+        for (int i = 1; i <= n_sig; ++i) {
+            if (i < n_sig && zr[i].first <= hi) {
+                hi = std::max(hi, zr[i].second);
+                continue;
+            }
+            HIPCHECK(ctx, launch_fill_f64(dZ + lo, 0.0, (size_t)(hi - lo), s));
+            if (i < n_sig) {
+                lo = zr[i].first;
+                hi = zr[i].second;
+            }
+        }
+    }
+    HIPCHECK(ctx, launch_fill_u32(ws.dirty.as<uint32_t>(), 1u, n_seg_tot, s));
+    if (pl.dicod) {
+        HIPCHECK(ctx, launch_fill_u32(ws.dirty.as<uint32_t>() + n_seg_tot, 0u, n_seg_tot, s));
+        HIPCHECK(ctx, launch_fill_u32(ws.msg_n.as<uint32_t>(), 0u, (size_t)4 * n_seg_tot, s));
+    }
+    HIPCHECK(ctx, launch_fill_u64(ws.phase_upd.as<unsigned long long>(), 0ull, max_ph + 1, s));
+    HIPCHECK(ctx, launch_fill_u64(ws.sig_upd.as<unsigned long long>(), 0ull, n_sig, s));
+    HIPCHECK(ctx, launch_fill_u32(ws.done.as<uint32_t>(), 0u, n_sig, s));
+    HIPCHECK(ctx, launch_fill_u32((uint32_t*)ws.sig_last.p, 0xffffffffu, n_sig, s));
+    HIPCHECK(ctx, launch_fill_u64((unsigned long long*)ws.counters.p, 0ull,
+                                  sizeof(Counters) / 8, s));
     // ---- 2. lambda --------------------------------------------------------
     std::vector<double> lmax(n_sig, 0.0);
     bool any_rel = false;
@@ -663,36 +749,18 @@ int solve_device_batch(dicod_ctx* ctx, int n_sig, const float* dX, const int64_t
                                                n_sig, nA, ws.thr.as<double>(),
                                                ws.lmax.as<unsigned long long>(), s));
         }
-        HIPCHECK(ctx, hipMemcpyAsync(bits.data(), ws.lmax.p, n_sig * sizeof(unsigned long long),
-                                     hipMemcpyDeviceToHost, s));
-        HIPCHECK(ctx, hipStreamSynchronize(s));
-        for (int i = 0; i < n_sig; ++i) {
-            double v;
-            std::memcpy(&v, &bits[i], sizeof v);
-            lmax[i] = v;
-            if (lam_in[i] < 0.0) {
-                pl.sig[i].lam = -lam_in[i] * v;
-                if (!(pl.sig[i].lam > 0.0))
-                    pl.sig[i].lam = 1e-300;  // X orthogonal to every atom: Z = 0
-            }
-        }
-        HIPCHECK(ctx, upload(ws.sig, pl.sig, s));
+        // lambda = |lambda_in| lambda_max, applied in the descriptors on the
+        // device (no host round trip); the host forms the same values for the
+        // statistics after the solve
+        std::vector<int> ids(n_sig);
+        for (int i = 0; i < n_sig; ++i)
+            ids[i] = i;
+        HIPCHECK(ctx, upload_cached(ws.slots, ids, ws.sh_slots, s));
+        HIPCHECK(ctx, upload_pinned(ws.lamin, lam_in, (size_t)n_sig * sizeof(double), pin_lam));
+        HIPCHECK(ctx, launch_apply_lambda(ws.sig.as<SigDesc>(), ws.slots.as<int>(),
+                                          ws.lamin.as<double>(),
+                                          ws.lmax.as<unsigned long long>(), n_sig, s));
     }
-    // ---- 3. descent state -------------------------------------------------
-    for (int i = 0; i < n_sig; ++i)
-        HIPCHECK(ctx, launch_fill_f64(dZ + pl.sig[i].z_off, 0.0,
-                                      (size_t)K * pl.sig[i].L, s));
-    HIPCHECK(ctx, launch_fill_u32(ws.dirty.as<uint32_t>(), 1u, n_seg_tot, s));
-    if (pl.dicod) {
-        HIPCHECK(ctx, launch_fill_u32(ws.dirty.as<uint32_t>() + n_seg_tot, 0u, n_seg_tot, s));
-        HIPCHECK(ctx, launch_fill_u32(ws.msg_n.as<uint32_t>(), 0u, (size_t)4 * n_seg_tot, s));
-    }
-    HIPCHECK(ctx, launch_fill_u64(ws.phase_upd.as<unsigned long long>(), 0ull, max_ph + 1, s));
-    HIPCHECK(ctx, launch_fill_u64(ws.sig_upd.as<unsigned long long>(), 0ull, n_sig, s));
-    HIPCHECK(ctx, launch_fill_u32(ws.done.as<uint32_t>(), 0u, n_sig, s));
-    HIPCHECK(ctx, launch_fill_u32((uint32_t*)ws.sig_last.p, 0xffffffffu, n_sig, s));
-    HIPCHECK(ctx, launch_fill_u64((unsigned long long*)ws.counters.p, 0ull,
-                                  sizeof(Counters) / 8, s));
     HIPCHECK(ctx, hipEventRecord(ev1, s));
 
     // Precision of the descent state: float (FP32 policy) until the double
@@ -738,7 +806,8 @@ int solve_device_batch(dicod_ctx* ctx, int n_sig, const float* dX, const int64_t
         a.inv_n2 = use64 ? ctx->inv64.p : ctx->inv32.p;
         for (int i = 0; i < n_sig; ++i)
             pl.sig[i].eps_stop = use64 ? eps : eps * cfg.inner_eps_factor;
-        return upload(ws.sig, pl.sig, s);
+        return launch_set_eps_stop(ws.sig.as<SigDesc>(), n_sig,
+                                   use64 ? eps : eps * cfg.inner_eps_factor, s);
     };
     HIPCHECK(ctx, set_state(cur64, in_lds));
 
@@ -752,62 +821,94 @@ int solve_device_batch(dicod_ctx* ctx, int n_sig, const float* dX, const int64_t
     int round_state[4] = {0, 0, 0, 0};
     std::vector<CheckResult> res(n_sig);
     std::vector<uint32_t> done(n_sig, 0u);
+    // phases queued past a round's convergence apply nothing: they are not
+    // counted in n_phases (round r starts at phase r_start[r]; r_over[r]
+    // overshoot phases ran before it)
+    std::vector<int64_t> r_start, r_over;
+    int64_t overshoot = 0;
 
     for (;;) {
         // ---- 3. coloured phases until C consecutive phases apply nothing
         HIPCHECK(ctx, hipEventRecord(ev2, s));
         const int64_t start = phase;
+        r_start.push_back(start);
+        r_over.push_back(overshoot);
         const int64_t launch0 = n_launch;
         const double kern0 = t_kernel;
         conv_phase = -1;
-        while (conv_phase < 0) {
-            if (phase >= max_ph) {
-                out_of_phases = true;
-                break;
-            }
-            // In float, rounding noise near the stop threshold can keep a few
-            // coordinates changing for ever; after a bounded number of phases
-            // the double-precision test decides instead.
-            if (!cur64 && phase - start >= kRoundPhaseLimit)
-                break;
-            const int64_t chunk = std::min<int64_t>(cfg.phases_per_poll, max_ph - phase);
-            size_t evi = 4;
-            for (int64_t c = 0; c < chunk; ++c, ++phase) {
-                const int par = (int)(phase % pl.colors);
-                a.list = ws.lists[par].as<int32_t>();
-                a.n_list = (int)pl.list[par].size();
-                a.phase = (int)phase;
-                if (a.n_list == 0)
-                    continue;
-                hipEvent_t e0 = nullptr, e1 = nullptr;
-                if (cfg.timing) {
-                    e0 = pool_event(ctx, evi++);
-                    e1 = pool_event(ctx, evi++);
-                    if (!e0 || !e1)
-                        return fail(ctx, DICOD_EDEVICE, "hipEventCreate failed");
-                    HIPCHECK(ctx, hipEventRecord(e0, s));
+        // Chunks of phases_per_poll phases; each chunk's update counts are
+        // copied to the host behind it.  Without per-launch timing the next
+        // chunk is queued before the host waits for the previous chunk's
+        // counts, so the device does not idle on the poll; phases queued after
+        // convergence find no dirty segment and apply nothing.
+        const bool overlap = !cfg.timing;
+        int64_t checked = start + pl.colors - 1;  // next phase whose quiet window is tested
+        int64_t copied = start;                   // counts copied (or queued) below this
+        int64_t known = start;                    // counts on the host below this
+        int64_t q_end[2] = {0, 0};                // queued chunks (FIFO of at most 2)
+        int q_head = 0, nq = 0;
+        size_t evi = 4;
+        bool limit = false;
+        for (;;) {
+            bool launched = false;
+            if (phase >= max_ph || (!cur64 && phase - start >= kRoundPhaseLimit)) {
+                // In float, rounding noise near the stop threshold can keep a
+                // few coordinates changing for ever; after a bounded number of
+                // phases the double-precision test decides instead.
+                limit = true;
+            } else {
+                const int64_t chunk = std::min<int64_t>(cfg.phases_per_poll, max_ph - phase);
+                evi = 4;
+                for (int64_t c = 0; c < chunk; ++c, ++phase) {
+                    const int par = (int)(phase % pl.colors);
+                    a.list = ws.lists[par].as<int32_t>();
+                    a.n_list = (int)pl.list[par].size();
+                    a.phase = (int)phase;
+                    if (a.n_list == 0)
+                        continue;
+                    hipEvent_t e0 = nullptr, e1 = nullptr;
+                    if (cfg.timing) {
+                        e0 = pool_event(ctx, evi++);
+                        e1 = pool_event(ctx, evi++);
+                        if (!e0 || !e1)
+                            return fail(ctx, DICOD_EDEVICE, "hipEventCreate failed");
+                        HIPCHECK(ctx, hipEventRecord(e0, s));
+                    }
+                    size_t lds = 0;
+                    hipError_t e = in_lds ? launch_lgcd_phase(a, cur64, &lds, s)
+                                          : launch_lgcd_phase_gm(a, cur64, &lds, s);
+                    if (e != hipSuccess)
+                        return fail(ctx, DICOD_EDEVICE,
+                                    "LGCD phase launch (%s state, %zu bytes LDS): %s",
+                                    in_lds ? "LDS" : "HBM", lds, hipGetErrorString(e));
+                    ++n_launch;
+                    if (cfg.timing)
+                        HIPCHECK(ctx, hipEventRecord(e1, s));
                 }
-                size_t lds = 0;
-                hipError_t e = in_lds ? launch_lgcd_phase(a, cur64, &lds, s)
-                                      : launch_lgcd_phase_gm(a, cur64, &lds, s);
-                if (e != hipSuccess)
-                    return fail(ctx, DICOD_EDEVICE, "LGCD phase launch (%s state, %zu bytes LDS): %s",
-                                in_lds ? "LDS" : "HBM", lds, hipGetErrorString(e));
-                ++n_launch;
-                if (cfg.timing)
-                    HIPCHECK(ctx, hipEventRecord(e1, s));
+                HIPCHECK(ctx, hipMemcpyAsync(ctx->h_upd + copied,
+                                             ws.phase_upd.as<unsigned long long>() + copied,
+                                             (size_t)(phase - copied) * sizeof(unsigned long long),
+                                             hipMemcpyDeviceToHost, s));
+                copied = phase;
+                const int tail = (q_head + nq) & 1;
+                q_end[tail] = copied;
+                HIPCHECK(ctx, hipEventRecord(ctx->ev_poll[tail], s));
+                ++nq;
+                launched = true;
             }
-            const int64_t from = std::max<int64_t>(start, phase - chunk - pl.colors);
-            HIPCHECK(ctx, hipMemcpyAsync(ctx->h_upd + from, ws.phase_upd.as<unsigned long long>() + from,
-                                         (size_t)(phase - from) * sizeof(unsigned long long),
-                                         hipMemcpyDeviceToHost, s));
-            HIPCHECK(ctx, hipStreamSynchronize(s));
-            if (cfg.timing)
-                for (size_t i = 4; i < evi; i += 2)
-                    t_kernel += elapsed_ms(ctx->ev_pool[i], ctx->ev_pool[i + 1]);
+            // wait for the oldest chunks, keeping one in flight while phases
+            // are still being queued
+            while (nq > (launched && overlap ? 1 : 0)) {
+                HIPCHECK(ctx, hipEventSynchronize(ctx->ev_poll[q_head]));
+                known = q_end[q_head];
+                q_head ^= 1;
+                --nq;
+                if (cfg.timing)
+                    for (size_t i = 4; i < evi; i += 2)
+                        t_kernel += elapsed_ms(ctx->ev_pool[i], ctx->ev_pool[i + 1]);
+            }
             // converged once `colors` consecutive phases applied nothing
-            for (int64_t p = std::max<int64_t>(start + pl.colors - 1, from + 1); p < phase;
-                 ++p) {
+            for (int64_t p = checked; p < known; ++p) {
                 bool quiet = true;
                 for (int c = 0; c < pl.colors; ++c)
                     quiet &= ctx->h_upd[p - c] == 0;
@@ -816,11 +917,18 @@ int solve_device_batch(dicod_ctx* ctx, int n_sig, const float* dX, const int64_t
                     break;
                 }
             }
+            checked = std::max(checked, known);
+            if (conv_phase >= 0 || (limit && nq == 0))
+                break;
         }
+        if (conv_phase < 0 && phase >= max_ph)
+            out_of_phases = true;
         HIPCHECK(ctx, hipEventRecord(ev3, s));
         HIPCHECK(ctx, hipEventSynchronize(ev3));
         const double t_round = elapsed_ms(ev2, ev3);
         t_cd += t_round;
+        if (conv_phase >= 0)
+            overshoot += phase - (conv_phase + 1);
         if (round < 4) {
             round_ms[round] = t_round;
             const int64_t last = conv_phase >= 0 ? conv_phase + 1 : phase;
@@ -889,7 +997,7 @@ int solve_device_batch(dicod_ctx* ctx, int n_sig, const float* dX, const int64_t
             any_hbm |= !in_lds;
         }
         HIPCHECK(ctx, set_state(cur64, in_lds));
-        HIPCHECK(ctx, upload(ws.done, done, s));
+        HIPCHECK(ctx, upload_pinned(ws.done, done.data(), (size_t)n_sig * sizeof(uint32_t), 0));
         while (phase % pl.colors)
             ++phase;
         if (pl.dicod) {
@@ -909,8 +1017,23 @@ int solve_device_batch(dicod_ctx* ctx, int n_sig, const float* dX, const int64_t
     HIPCHECK(ctx, hipMemcpyAsync(slast.data(), ws.sig_last.p, n_sig * sizeof(int),
                                  hipMemcpyDeviceToHost, s));
     HIPCHECK(ctx, hipMemcpyAsync(&cnt, ws.counters.p, sizeof cnt, hipMemcpyDeviceToHost, s));
+    std::vector<unsigned long long> lbits(n_sig, 0ull);
+    if (any_rel)
+        HIPCHECK(ctx, hipMemcpyAsync(lbits.data(), ws.lmax.p, n_sig * sizeof(unsigned long long),
+                                     hipMemcpyDeviceToHost, s));
     HIPCHECK(ctx, hipStreamSynchronize(s));
     ctx->last_trace_n = (int64_t)cnt.trace_n;
+    for (int i = 0; any_rel && i < n_sig; ++i) {
+        // the arithmetic of k_apply_lambda
+        double v;
+        std::memcpy(&v, &lbits[i], sizeof v);
+        lmax[i] = v;
+        if (lam_in[i] < 0.0) {
+            pl.sig[i].lam = -lam_in[i] * v;
+            if (!(pl.sig[i].lam > 0.0))
+                pl.sig[i].lam = 1e-300;  // X orthogonal to every atom: Z = 0
+        }
+    }
     const double t_init = elapsed_ms(ev0, ev1);
     const double t_total = now_ms() - t_call0;
     if (st) {
@@ -918,8 +1041,19 @@ int solve_device_batch(dicod_ctx* ctx, int n_sig, const float* dX, const int64_t
             dicod_stats& o = st[i];
             std::memset(&o, 0, sizeof o);
             o.n_updates = (int64_t)supd[i];
-            o.n_phases = n_sig == 1 ? (conv_phase >= 0 ? conv_phase + 1 : phase)
-                                    : std::min<int64_t>(phase, (int64_t)slast[i] + 3);
+            {
+                // phase index without the overshoot of earlier rounds
+                auto strip = [&](int64_t ph) {
+                    size_t r = 0;
+                    while (r + 1 < r_start.size() && r_start[r + 1] <= ph)
+                        ++r;
+                    return r < r_over.size() ? ph - r_over[r] : ph;
+                };
+                const int64_t last_ph = conv_phase >= 0 ? conv_phase + 1 : phase;
+                o.n_phases = n_sig == 1 ? strip(last_ph)
+                                        : std::min<int64_t>(strip(last_ph),
+                                                            strip((int64_t)slast[i]) + 3);
+            }
             o.n_phase_launches = n_launch;
             o.n_segment_runs = (int64_t)cnt.seg_runs;
             o.nnz = (int64_t)res[i].nnz;

@@ -200,6 +200,8 @@ hipError_t launch_absmax_f32(const float* beta, int K, const SigDesc* sig,
 // Serving: tab[slots[i]].lam = lam_in[i] (> 0) or -lam_in[i] * lambda_max[i].
 hipError_t launch_apply_lambda(SigDesc* tab, const int* slots, const double* lam_in,
                                const unsigned long long* lmax_bits, int n, hipStream_t s);
+// tab[0..n).eps_stop = eps (the stop threshold of the descent state).
+hipError_t launch_set_eps_stop(SigDesc* tab, int n, double eps, hipStream_t s);
 // Serving: ring[r][(start + c) % H] = 0 for r < rows, c < n.
 hipError_t launch_clear_ring(unsigned long long* ring, int rows, int H, int start, int n,
                              hipStream_t s);

@@ -2173,6 +2173,21 @@ hipError_t launch_apply_lambda(SigDesc* tab, const int* slots, const double* lam
     return hipGetLastError();
 }
 
+__global__ void k_set_eps_stop(SigDesc* tab, int n, double eps)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n)
+        tab[i].eps_stop = eps;
+}
+
+hipError_t launch_set_eps_stop(SigDesc* tab, int n, double eps, hipStream_t s)
+{
+    if (n <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_set_eps_stop, dim3((n + 255) / 256), dim3(256), 0, s, tab, n, eps);
+    return hipGetLastError();
+}
+
 __global__ void k_clear_ring(unsigned long long* ring, int rows, int H, int start, int n)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
