@@ -612,7 +612,14 @@ int solve_device_batch(dicod_ctx* ctx, int n_sig, const float* dX, const int64_t
     // by a synchronisation of the stream (the double check)
     const size_t pin_lam = ((size_t)n_sig * sizeof(uint32_t) + 255) & ~(size_t)255;
     const size_t pin_sig = pin_lam + (((size_t)n_sig * sizeof(double) + 255) & ~(size_t)255);
-    const size_t pin_need = pin_sig + (size_t)n_sig * sizeof(SigDesc);
+    auto al256 = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    // read-backs: check results, then the final statistics
+    const size_t pin_res = pin_sig + al256((size_t)n_sig * sizeof(SigDesc));
+    const size_t pin_supd = pin_res + al256((size_t)n_sig * sizeof(CheckResult));
+    const size_t pin_slast = pin_supd + al256((size_t)n_sig * sizeof(unsigned long long));
+    const size_t pin_lbits = pin_slast + al256((size_t)n_sig * sizeof(int));
+    const size_t pin_cnt = pin_lbits + al256((size_t)n_sig * sizeof(unsigned long long));
+    const size_t pin_need = pin_cnt + sizeof(Counters);
     if (pin_need > ctx->h_pin_cap) {
         if (ctx->h_pin)
             (void)hipHostFree(ctx->h_pin);
@@ -974,10 +981,11 @@ int solve_device_batch(dicod_ctx* ctx, int n_sig, const float* dX, const int64_t
                                         g_in, ws.part.as<double>(), s));
         HIPCHECK(ctx, launch_check_reduce(ws.part.as<double>(), ws.tilesC.as<int64_t>(), nC,
                                           n_kblk, n_sig, ws.results.as<CheckResult>(), s));
-        HIPCHECK(ctx, hipMemcpyAsync(res.data(), ws.results.p, n_sig * sizeof(CheckResult),
-                                     hipMemcpyDeviceToHost, s));
+        HIPCHECK(ctx, hipMemcpyAsync(ctx->h_pin + pin_res, ws.results.p,
+                                     n_sig * sizeof(CheckResult), hipMemcpyDeviceToHost, s));
         HIPCHECK(ctx, hipEventRecord(ev3, s));
         HIPCHECK(ctx, hipEventSynchronize(ev3));
+        std::memcpy(res.data(), ctx->h_pin + pin_res, n_sig * sizeof(CheckResult));
         t_verify += elapsed_ms(ev2, ev3);
         accepted = true;
         for (int i = 0; i < n_sig; ++i) {
@@ -1012,16 +1020,22 @@ int solve_device_batch(dicod_ctx* ctx, int n_sig, const float* dX, const int64_t
     std::vector<unsigned long long> supd(n_sig);
     std::vector<int> slast(n_sig);
     Counters cnt;
-    HIPCHECK(ctx, hipMemcpyAsync(supd.data(), ws.sig_upd.p, n_sig * sizeof(unsigned long long),
+    HIPCHECK(ctx, hipMemcpyAsync(ctx->h_pin + pin_supd, ws.sig_upd.p,
+                                 n_sig * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+    HIPCHECK(ctx, hipMemcpyAsync(ctx->h_pin + pin_slast, ws.sig_last.p, n_sig * sizeof(int),
                                  hipMemcpyDeviceToHost, s));
-    HIPCHECK(ctx, hipMemcpyAsync(slast.data(), ws.sig_last.p, n_sig * sizeof(int),
+    HIPCHECK(ctx, hipMemcpyAsync(ctx->h_pin + pin_cnt, ws.counters.p, sizeof cnt,
                                  hipMemcpyDeviceToHost, s));
-    HIPCHECK(ctx, hipMemcpyAsync(&cnt, ws.counters.p, sizeof cnt, hipMemcpyDeviceToHost, s));
     std::vector<unsigned long long> lbits(n_sig, 0ull);
     if (any_rel)
-        HIPCHECK(ctx, hipMemcpyAsync(lbits.data(), ws.lmax.p, n_sig * sizeof(unsigned long long),
-                                     hipMemcpyDeviceToHost, s));
+        HIPCHECK(ctx, hipMemcpyAsync(ctx->h_pin + pin_lbits, ws.lmax.p,
+                                     n_sig * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
     HIPCHECK(ctx, hipStreamSynchronize(s));
+    std::memcpy(supd.data(), ctx->h_pin + pin_supd, n_sig * sizeof(unsigned long long));
+    std::memcpy(slast.data(), ctx->h_pin + pin_slast, n_sig * sizeof(int));
+    std::memcpy(&cnt, ctx->h_pin + pin_cnt, sizeof cnt);
+    if (any_rel)
+        std::memcpy(lbits.data(), ctx->h_pin + pin_lbits, n_sig * sizeof(unsigned long long));
     ctx->last_trace_n = (int64_t)cnt.trace_n;
     for (int i = 0; any_rel && i < n_sig; ++i) {
         // the arithmetic of k_apply_lambda
