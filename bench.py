@@ -23,6 +23,7 @@ Three more workloads are measured beside it (skip with --no-long /
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -265,7 +266,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--cap", type=int, default=28, help="updates per segment per phase")
+    ap.add_argument("--cap", type=int, default=-1,
+                    help="updates per segment per phase (-1: the library's automatic cap)")
     ap.add_argument("--n-seg", type=int, default=0, help="0 = library default")
     ap.add_argument("--colors", type=int, default=3, help="phase classes of the schedule")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -388,7 +390,9 @@ def main():
         "config": {"workload": w.name, "P": P, "K": K, "W": W, "T": T, "rho": w.rho,
                    "sigma_noise": w.sigma_noise, "lambda": "0.1*lambda_max",
                    "eps": w.eps, "n_seg": s0["n_seg"], "seg_len": s0["seg_len"],
-                   "update_cap": args.cap, "precision": "FP32 descent, FP64 stop test",
+                   "update_cap": (args.cap if args.cap >= 0 else
+                                  max(4, int(math.floor(2.0 * math.sqrt(w.W) + 0.5)))),
+                   "precision": "FP32 descent, FP64 stop test",
                    "schedule": f"{args.colors}-colour phases", "seed": args.seed},
         "solve": {"n_updates": s0["n_updates"], "n_phases": s0["n_phases"],
                   "n_phase_launches": s0["n_phase_launches"], "n_refresh": s0["n_refresh"],

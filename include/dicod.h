@@ -80,7 +80,7 @@ extern "C" {
  *          neighbour is sent to it as (k0, t0, delta) and applied there at
  *          the start of the next phase.  Concurrent updates of adjacent
  *          segments may interfere (Sec. 3, Prop. A.2).  Segments must be
- *          >= W long and fit the on-chip kernel; update_cap in 1..1024 is
+ *          >= W long and fit the on-chip kernel; update_cap in 1..1024 (or -1) is
  *          the number of updates per segment and phase (1 keeps the message
  *          delay below one update time, hypothesis H3).  dicod_submit always
  *          uses the coloured schedule. */
@@ -93,7 +93,8 @@ typedef struct {
     int device;              /* HIP device ordinal                                  */
     int precision;           /* DICOD_PREC_*                                        */
     int schedule;            /* DICOD_SCHED_*                                       */
-    int update_cap;          /* max updates per segment per phase; 0 = no cap        */
+    int update_cap;          /* max updates per segment per phase; 0 = no cap;
+                              * -1 = automatic: max(4, round(2 sqrt(W)))            */
     int64_t max_phases;      /* watchdog: phases before DICOD_ENOTCONV              */
     int max_refresh;         /* double-precision verify-and-resume rounds (FP32)    */
     int phases_per_poll;     /* phases launched between convergence polls (>= 1)    */
@@ -158,7 +159,7 @@ typedef struct {
     double delta;     /* applied change of Z_{k0}[t0]         */
 } dicod_trace_rec;
 
-/* Fills *cfg with the defaults: device 0, FP32, coloured phases, update_cap 28,
+/* Fills *cfg with the defaults: device 0, FP32, coloured phases, update_cap -1,
  * max_phases 1e6, max_refresh 8, phases_per_poll 16, inner_eps_factor 0.5,
  * timing 0, no trace, state_in_lds 1, fp64_polish_after 1, colors 3,
  * verify_from_scratch 0.  Returns DICOD_OK, or DICOD_EINVAL if cfg is NULL. */

@@ -178,7 +178,7 @@ extern "C" int dicod_config_init(dicod_config* cfg)
     cfg->device = 0;
     cfg->precision = DICOD_PREC_FP32;
     cfg->schedule = DICOD_SCHED_EVENODD;
-    cfg->update_cap = 28;
+    cfg->update_cap = -1;
     cfg->max_phases = 1000000;
     cfg->max_refresh = 8;
     cfg->phases_per_poll = 16;
@@ -208,10 +208,11 @@ extern "C" int dicod_init(dicod_ctx** out, const dicod_config* cfg)
         return fail(nullptr, DICOD_EINVAL, "dicod_init: unknown precision %d", c.precision);
     if (c.schedule != DICOD_SCHED_EVENODD && c.schedule != DICOD_SCHED_DICOD)
         return fail(nullptr, DICOD_EINVAL, "dicod_init: unknown schedule %d", c.schedule);
-    if (c.schedule == DICOD_SCHED_DICOD && (c.update_cap < 1 || c.update_cap > 1024))
+    if (c.schedule == DICOD_SCHED_DICOD && c.update_cap != -1 &&
+        (c.update_cap < 1 || c.update_cap > 1024))
         return fail(nullptr, DICOD_EINVAL,
-                    "dicod_init: the DICOD schedule needs update_cap in 1..1024");
-    if (c.update_cap < 0 || c.max_phases < 2 || c.max_refresh < 0 ||
+                    "dicod_init: the DICOD schedule needs update_cap in 1..1024 or -1");
+    if (c.update_cap < -1 || c.max_phases < 2 || c.max_refresh < 0 ||
         c.phases_per_poll < 1 || !(c.inner_eps_factor > 0.0 && c.inner_eps_factor <= 1.0) ||
         c.trace_capacity < 0 || c.max_inflight < 1 || c.fp64_polish_after < 0 ||
         c.colors < 2 || c.colors > kMaxColors)
@@ -591,7 +592,7 @@ int solve_device_batch(dicod_ctx* ctx, int n_sig, const float* dX, const int64_t
     HIPCHECK(ctx, ensure(ws.beta0, pl.zext * sizeof(double)));
     HIPCHECK(ctx, ensure(ws.g, pl.zext * (fp64 ? sizeof(double) : sizeof(float))));
     HIPCHECK(ctx, ensure(ws.dirty, (pl.dicod ? 2 : 1) * n_seg_tot * sizeof(uint32_t)));
-    const int msg_cap = pl.dicod ? cfg.update_cap : 0;
+    const int msg_cap = pl.dicod ? effective_update_cap(cfg.update_cap, W) : 0;
     if (pl.dicod) {
         HIPCHECK(ctx, ensure(ws.msg, (size_t)4 * n_seg_tot * msg_cap * sizeof(DicodMsg)));
         HIPCHECK(ctx, ensure(ws.msg_n, (size_t)4 * n_seg_tot * sizeof(uint32_t)));
@@ -790,7 +791,7 @@ int solve_device_batch(dicod_ctx* ctx, int n_sig, const float* dX, const int64_t
     a.W = W;
     // update_cap 0 means "run each segment to local convergence"; a finite
     // bound still guarantees that every workgroup exits.
-    a.cap = cfg.update_cap > 0 ? cfg.update_cap : kRunUpdateBound;
+    a.cap = effective_update_cap(cfg.update_cap, W);
     a.dirty = ws.dirty.as<uint32_t>();
     a.phase_upd = ws.phase_upd.as<unsigned long long>();
     a.sig_upd = ws.sig_upd.as<unsigned long long>();
@@ -1304,5 +1305,13 @@ DictView ctx_dict(const dicod_ctx* ctx)
     return v;
 }
 int64_t min_segment_len(int W, int C) { return min_segment(W, C); }
+int effective_update_cap(int update_cap, int W)
+{
+    if (update_cap > 0)
+        return update_cap;
+    if (update_cap == 0)
+        return kRunUpdateBound;
+    return std::max(4, (int)std::lround(2.0 * std::sqrt((double)W)));
+}
 int auto_segment_count(int64_t L, int W, int C) { return auto_segments(L, W, C); }
 }  // namespace dicod

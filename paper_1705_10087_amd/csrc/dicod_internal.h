@@ -46,6 +46,11 @@ struct SegDesc {
     int32_t right;
 };
 
+// Updates per segment run: update_cap > 0 as given, 0 = no cap (a bound that
+// still ends every run), -1 = max(4, round(2 sqrt(W))) (measured: 28 at
+// W = 200, 16 at W = 64).
+int effective_update_cap(int update_cap, int W);
+
 // Per-signal results of the double-precision check, reduced from partials.
 struct CheckResult {
     double max_dz;

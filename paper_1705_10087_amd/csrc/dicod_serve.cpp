@@ -808,7 +808,7 @@ int Lane::iterate(int* admitted)
     a.sigs = v.dSig.as<SigDesc>();
     a.K = K;
     a.W = W;
-    a.cap = cfg.update_cap > 0 ? cfg.update_cap : kRunUpdateBound;
+    a.cap = effective_update_cap(cfg.update_cap, W);
     a.phase_stride = kRing;
     a.dirty = v.dDirty.as<uint32_t>();
     a.phase_upd = dRing.as<unsigned long long>();
