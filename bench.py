@@ -71,6 +71,11 @@ def cpu_baseline(X, D, lam, eps, M, cap, colors):
                       f"schedule ({colors} colours, M={M}, update cap {cap}), single thread"}
 
 
+def effective_cap(cap, W):
+    """The library's update cap: cap > 0 as given, 0 = none, -1 = max(4, round(2 sqrt(W)))."""
+    return cap if cap >= 0 else max(4, int(math.floor(2.0 * math.sqrt(W) + 0.5)))
+
+
 def ms_per_step_of(stats, wall, steps):
     return 1e3 * wall / steps
 
@@ -390,8 +395,7 @@ def main():
         "config": {"workload": w.name, "P": P, "K": K, "W": W, "T": T, "rho": w.rho,
                    "sigma_noise": w.sigma_noise, "lambda": "0.1*lambda_max",
                    "eps": w.eps, "n_seg": s0["n_seg"], "seg_len": s0["seg_len"],
-                   "update_cap": (args.cap if args.cap >= 0 else
-                                  max(4, int(math.floor(2.0 * math.sqrt(w.W) + 0.5)))),
+                   "update_cap": effective_cap(args.cap, w.W),
                    "precision": "FP32 descent, FP64 stop test",
                    "schedule": f"{args.colors}-colour phases", "seed": args.seed},
         "solve": {"n_updates": s0["n_updates"], "n_phases": s0["n_phases"],
@@ -488,7 +492,8 @@ def main():
         print(f"[bench] served done", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         lam = s0["lambda"]
-        out["cpu_baseline"] = cpu_baseline(X, D, lam, w.eps, s0["n_seg"], args.cap, args.colors)
+        out["cpu_baseline"] = cpu_baseline(X, D, lam, w.eps, s0["n_seg"], effective_cap(args.cap, w.W),
+                                           args.colors)
     print(json.dumps(out), flush=True)
 
 
