@@ -191,6 +191,12 @@ def test_paper_shaped_fp32_matches_oracle(dicod, paper_problem):
           f"refresh={st['n_refresh']}, cd={st['t_cd_ms']:.2f} ms", flush=True)
     assert st["n_seg"] == 749
     _check_solution(X, D, lam, Z, st, Zo)
+    # phases queued past a round's convergence apply nothing and are not
+    # counted: n_phases is the rounds' phases plus at most C - 1 alignment
+    # phases before each resumed round
+    rp = [p for p in st["round_phases"] if p > 0]
+    assert sum(rp) <= st["n_phases"] <= sum(rp) + 2 * (len(rp) - 1)
+    assert st["n_phase_launches"] >= sum(rp)
 
 
 @pytest.fixture(scope="module")
