@@ -997,12 +997,17 @@ k_lgcd_phase(PhaseArgs a)
         invl[k] = iv;
         linvl[k] = lam * iv;
     }
-    // own state in: [k][t] in HBM -> [j][k] in LDS, padding zeroed
+    // own state in: [k][t] in HBM -> [j][k] in LDS, padding zeroed (loads at
+    // clamped, valid atoms: unconditional, so that several are in flight)
+#pragma unroll 4
     for (int i = tid; i < KP * Lm; i += NT) {
         const int k = i / Lm;
         const int j = i - k * Lm;
-        g_l[j * KP + k] = k < K ? gs[(int64_t)k * L + b + j] : (G)0;
-        z_l[j * KP + k] = k < K ? (G)Zs[(int64_t)k * L + b + j] : (G)0;
+        const int kc = k < K ? k : K - 1;
+        const G gv = gs[(int64_t)kc * L + b + j];
+        const G zv = (G)Zs[(int64_t)kc * L + b + j];
+        g_l[j * KP + k] = k < K ? gv : (G)0;
+        z_l[j * KP + k] = k < K ? zv : (G)0;
     }
     __syncthreads();
     G n2r[KP], invr[KP], linvr[KP];
@@ -1076,7 +1081,8 @@ k_lgcd_phase(PhaseArgs a)
 #pragma unroll
                             for (int e = 0; e < Vec<G>::N; ++e) {
                                 const int k = (c0 + c) * Vec<G>::N + e;
-                                gv[c][e] = (c0 + c < KQ && k < K) ? gs[(int64_t)k * L + t] : (G)0;
+                                const G v = gs[(int64_t)(k < K ? k : K - 1) * L + t];
+                                gv[c][e] = (c0 + c < KQ && k < K) ? v : (G)0;
                             }
                         touched = true;
                     }
