@@ -1433,8 +1433,10 @@ struct ChunkBest {
     G d;
 };
 
-// Recompute chunk c (one position per lane): optional eq. (3) update of the
-// positions inside [wlo, whi], then the best candidate of the own positions.
+// Recompute chunk c (one position per lane): eq. (3) update of the positions
+// inside [wlo, whi] (none when the window is empty), then the best candidate
+// of the own positions.  Srow is always a valid row block of S; loads are at
+// clamped, valid indices and unconditional, their values selected afterwards.
 template <typename G, int KC>
 __device__ __forceinline__ void gm_chunk(int c, int K, int Kr, int W, int off, int Lm,
                                         int Lext, int ext_lo, int b, int64_t L,
@@ -1451,23 +1453,28 @@ __device__ __forceinline__ void gm_chunk(int c, int K, int Kr, int W, int off, i
     const int q = c * 64 + lane;
     const int j = q - off;
     const bool inq = q < Lext;
-    const bool upd = Srow && inq && q >= wlo && q <= whi;
+    const bool upd = inq && q >= wlo && q <= whi;
     const bool own = inq && j >= 0 && j < Lm;
     typename KO::T best = KO::null();
     G bd = (G)0;
     if (upd || own) {
         G* gp = gs + ext_lo + q;
-        const double* zp = Zs + b + j;
+        const double* zp = Zs + b + (j < 0 ? 0 : (j >= Lm ? Lm - 1 : j));
         const int dj = q - q0 + (W - 1);
+        const int djc = dj < 0 ? 0 : (dj >= nd ? nd - 1 : dj);
         for (int k0 = 0; k0 < K; k0 += 8) {
             G gv[8], sv[8];
             double zv[8];
 #pragma unroll
             for (int c8 = 0; c8 < 8; ++c8) {
                 const int k = k0 + c8;
-                gv[c8] = k < K ? gp[(int64_t)k * L] : (G)0;
-                sv[c8] = (upd && k < K) ? Srow[(int64_t)k * nd + dj] : (G)0;
-                zv[c8] = (own && k < K) ? zp[(int64_t)k * L] : 0.0;
+                const int kc = k < K ? k : K - 1;
+                const G gl = gp[(int64_t)kc * L];
+                const G sl = Srow[(int64_t)kc * nd + djc];
+                const double zl = zp[(int64_t)kc * L];
+                gv[c8] = k < K ? gl : (G)0;
+                sv[c8] = (upd && k < K) ? sl : (G)0;
+                zv[c8] = (own && k < K) ? zl : 0.0;
             }
             if (upd) {
 #pragma unroll
@@ -1551,8 +1558,8 @@ k_lgcd_phase_gm(PhaseArgs a)
     __syncthreads();
 
     for (int c = wave; c < nch; c += NW)
-        gm_chunk<G, KC>(c, K, a.K, W, off, Lm, Lext, ext_lo, b, L, gs, Zs, nullptr, (G)0, 0, 0,
-                        -1, n2l, invl, linvl, lam, cb);
+        gm_chunk<G, KC>(c, K, a.K, W, off, Lm, Lext, ext_lo, b, L, gs, Zs, S, (G)0, 0, 0,
+                        -1, n2l, invl, linvl, lam, cb);  // empty window: no update
     __syncthreads();
 
     int it = 0;
