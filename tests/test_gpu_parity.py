@@ -280,6 +280,10 @@ def test_lambda_at_lambda_max_gives_zero(dicod):
     (3, 4, 5, 333, 7),        # ragged segments (L = 329 = 7 * 47)
     (25, 7, 20, 5003, 13),    # K = 25 kernel, ragged tail
     (40, 2, 6, 900, 5),       # K > 32: two atom blocks in the check kernels
+    (64, 16, 16, 2000, 8),    # largest K of the LDS-state kernel, largest P
+    (66, 3, 8, 200, 1),       # K > 64: state in HBM for every precision
+    (4, 2, 700, 6000, 3),     # wide atoms: several tau passes, windows of 1399 positions
+    (3, 2, 1, 300, 5),        # W = 1: no coupling between positions
 ])
 def test_shapes_match_oracle(dicod, prec, K, P, W, T, M):
     print(f"\ncase: shape {prec} K={K} P={P} W={W} T={T} M={M}", flush=True)
@@ -290,6 +294,21 @@ def test_shapes_match_oracle(dicod, prec, K, P, W, T, M):
     with ctx_of(dicod, precision=p) as c:
         Z, st = c.solve(X, lam, EPS, n_seg=M, D=D)
     _check_solution(X, D, lam, Z, st, Zo)
+
+
+@pytest.mark.parametrize("prec", ["FP64", "FP32", "MIXED"])
+def test_zero_signal_gives_zero(dicod, prec):
+    # X = 0: lambda_max = 0, Z = 0 is the solution for every lambda >= 0 and
+    # the cost is 0; a relative lambda becomes 0, an absolute one stays.
+    _, D, _ = small(5)
+    X = np.zeros((D.shape[1], 3000), dtype=np.float32)
+    p = getattr(dicod, f"DICOD_PREC_{prec}")
+    for lam in (-0.1, 0.25):
+        print(f"\ncase: zero signal {prec} lam={lam}", flush=True)
+        with ctx_of(dicod, precision=p) as c:
+            Z, st = c.solve(X, lam, EPS, n_seg=6, D=D)
+        assert not Z.any() and st["n_updates"] == 0 and st["converged"] == 1
+        assert st["objective"] == 0.0 and st["lambda_max"] == 0.0
 
 
 @pytest.mark.parametrize("bad", ["lam0", "lamnan", "eps0", "short_segments", "T_lt_W",
