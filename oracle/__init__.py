@@ -65,6 +65,12 @@ def _load():
     global _lib
     if _lib is not None:
         return _lib
+    # ORACLE_LIB: a separately built copy (e.g. with sanitizers) instead of
+    # the library built here
+    other = os.environ.get("ORACLE_LIB")
+    if other:
+        _lib = load_library(other)
+        return _lib
     src = os.path.join(_HERE, "dicod_oracle.c")
     if (not os.path.exists(_LIB_PATH)
             or os.path.getmtime(_LIB_PATH) < os.path.getmtime(src)):
