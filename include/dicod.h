@@ -80,7 +80,7 @@ extern "C" {
  *          neighbour is sent to it as (k0, t0, delta) and applied there at
  *          the start of the next phase.  Concurrent updates of adjacent
  *          segments may interfere (Sec. 3, Prop. A.2).  Segments must be
- *          >= W long and fit the on-chip kernel; update_cap in 1..1024 (or -1) is
+ *          >= W - 1 long and fit the on-chip kernel; update_cap in 1..1024 (or -1) is
  *          the number of updates per segment and phase (1 keeps the message
  *          delay below one update time, hypothesis H3).  dicod_submit always
  *          uses the coloured schedule. */
@@ -109,9 +109,12 @@ typedef struct {
                              /* the descent continues on a double state; 0 = never   */
     int colors;              /* phase classes C in 2..4: segment m runs in phases p  */
                              /* with p % C == m % C (2 = even/odd); segments must be */
-                             /* >= max(W, (2W - 2) / (C - 1)) long                    */
+                             /* >= max(W - 1, (2W - 2) / (C - 1)) long                */
     int verify_from_scratch; /* 1 = every stop test recomputes g from Z; 0 = after a  */
                              /* double round the maintained double state is used     */
+    int reg_state;           /* 1 = float rounds keep each position's state in the   */
+                             /* registers of one thread (segments of at most 256     */
+                             /* positions, K <= 32); 0 = LDS / HBM state kernels only */
 } dicod_config;
 
 typedef struct {
@@ -142,11 +145,14 @@ typedef struct {
     double round_ms[4];       /* wall time of the first four descent rounds          */
     double round_kernel_ms[4]; /* phase-kernel time of those rounds (timing = 1)     */
     int64_t round_launches[4]; /* phase-kernel launches of those rounds              */
-    int round_state[4];       /* state of those rounds: bit 0 double, bit 1 HBM      */
+    int round_state[4];       /* state of those rounds: bit 0 double, bit 1 HBM,     */
+                              /* bit 2 registers                                     */
     int state_in_hbm;         /* 1 if segment state was kept in HBM, not LDS         */
     int polished_fp64;        /* 1 if the descent finished on a double state         */
     double t_queue_ms;        /* served: dicod_submit until admission to the device  */
     double t_latency_ms;      /* served: dicod_submit until the result was complete  */
+    double round_max_dz[4];   /* max |Delta Z| of the double check after each of the */
+                              /* first four descent rounds                           */
 } dicod_stats;
 
 /* One record per applied update (dicod_get_trace); 32 bytes. */
@@ -162,7 +168,8 @@ typedef struct {
 /* Fills *cfg with the defaults: device 0, FP32, coloured phases, update_cap -1,
  * max_phases 1e6, max_refresh 8, phases_per_poll 16, inner_eps_factor 0.5,
  * timing 0, no trace, state_in_lds 1, fp64_polish_after 1, colors 3,
- * verify_from_scratch 0.  Returns DICOD_OK, or DICOD_EINVAL if cfg is NULL. */
+ * verify_from_scratch 0, reg_state 1.  Returns DICOD_OK, or DICOD_EINVAL if
+ * cfg is NULL. */
 int dicod_config_init(dicod_config *cfg);
 
 /* Creates a context on cfg->device (cfg NULL = defaults) with its own HIP
@@ -182,8 +189,11 @@ const char *dicod_last_error(const dicod_ctx *ctx);
  * device and computes, in double on MFMA, the correlation table
  * S_{k,l}[d] = sum_tau <D_k[tau], D_l[tau + d]> for |d| < W (eq. (3)) and the
  * norms |D_k|^2 (eq. (pb_coord)).  Errors: EINVAL (NULL, K/P/W <= 0,
- * non-finite entry, an atom of zero norm), ENOTSUP (K > 32 or P > 16),
- * ENOMEM, EDEVICE. */
+ * non-finite entry, an atom of zero norm, or serving active: once
+ * dicod_submit has been called on the context, its serving lanes hold the
+ * dictionary until dicod_finalize), ENOTSUP (P > 16 channels, or
+ * K * P * W > 2^28), ENOMEM, EDEVICE.  Must not run concurrently with
+ * dicod_submit or dicod_poll. */
 int dicod_set_dictionary(dicod_ctx *ctx, const float *D, int K, int P, int W);
 
 /* Solves problem (2) for one signal with host buffers.
@@ -192,10 +202,11 @@ int dicod_set_dictionary(dicod_ctx *ctx, const float *D, int K, int P, int W);
  *          must match it); non-NULL replaces the resident dictionary
  *   lambda see conventions above; eps > 0 is the stop threshold on |Delta Z|
  *   n_seg  number of segments M; 0 = chosen by the library (the largest M
- *          allowed).  M > 1 requires floor(L / M) >= max(W, (2W - 2) / (C - 1))
- *          for C = cfg.colors, so that segments running in the same phase never
- *          touch the same coordinates (Sec. 2.2: an update changes beta on
- *          2W - 1 positions)
+ *          allowed).  M > 1 requires floor(L / M) >= max(W - 1, (2W - 2) / (C - 1))
+ *          for C = cfg.colors, so that a window reaches only the adjacent
+ *          segments and segments running in the same phase never touch the
+ *          same coordinates (Sec. 2.2: an update changes beta on 2W - 1
+ *          positions)
  *   Z_out  host double [K][L], written on DICOD_OK and DICOD_ENOTCONV
  *   st     optional statistics
  * Errors: EINVAL, ENOTSUP (segment too long for the on-chip kernel), ENOMEM,

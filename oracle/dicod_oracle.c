@@ -560,9 +560,10 @@ done:
  *   marked dirty each run locally greedy updates until their local maximum is
  *   below eps or `cap` updates were made (cap <= 0: no cap).  A segment stays
  *   dirty only if it stopped on the cap; a segment whose update window reaches
- *   a neighbour marks that neighbour dirty.  Segments are at least W long and
- *   at least (2W - 2) / (C - 1) long, so segments of one colour never touch the
- *   same beta entries and each phase equals running its segments one after the
+ *   a neighbour marks that neighbour dirty.  Segments are at least W - 1 long
+ *   (a window reaches W - 1 positions on each side) and at least
+ *   (2W - 2) / (C - 1) long, so segments of one colour never touch the same
+ *   beta entries and each phase equals running its segments one after the
  *   other.  The run stops after C consecutive phases without updates.
  *
  * schedule = ORACLE_SCHED_DICOD: Algorithm 2 with the cores in lockstep.  In
@@ -572,7 +573,7 @@ done:
  *   updates from its own beta (up to `cap`), changing beta on its own
  *   positions only; an update whose window reaches a neighbour is sent to it
  *   as (k0, t0, delta) (the paper's messages, delivered one phase later).
- *   Segments are at least W long, so a window reaches only the adjacent
+ *   Segments are at least W - 1 long, so a window reaches only the adjacent
  *   segments.  Updates of adjacent segments in one phase may interfere
  *   (Sec. 3, Prop. A.2); the statistics count them.  The run stops after a
  *   phase without updates (then no message is pending).
@@ -595,14 +596,15 @@ int oracle_lgcd(const double *X, const double *D, int K, int P, int W, int64_t T
     if (schedule == ORACLE_SCHED_EVENODD) {
         if (colors < 2)
             return -1;
-        /* segments of one colour must be 2W - 2 apart, and a window may only
-         * reach the adjacent segments */
-        if (M > 1 && (L / M < W || (colors - 1) * (L / M) < 2 * W - 2))
+        /* segments of one colour must be 2W - 2 apart, and a window (which
+         * reaches W - 1 positions on each side, eq. (3)) may only reach the
+         * adjacent segments */
+        if (M > 1 && (L / M < (W > 1 ? W - 1 : 1) || (colors - 1) * (L / M) < 2 * W - 2))
             return -2;
     }
     if (schedule == ORACLE_SCHED_SEQUENCE && (!seq || seq_len <= 0))
         return -1;
-    if (schedule == ORACLE_SCHED_DICOD && M > 1 && L / M < W)
+    if (schedule == ORACLE_SCHED_DICOD && M > 1 && L / M < (W > 1 ? W - 1 : 1))
         return -2;
     const int nd = 2 * W - 1;
 

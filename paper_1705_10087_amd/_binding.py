@@ -57,6 +57,7 @@ class dicod_config(ctypes.Structure):
         ("fp64_polish_after", ctypes.c_int),
         ("colors", ctypes.c_int),
         ("verify_from_scratch", ctypes.c_int),
+        ("reg_state", ctypes.c_int),
     ]
 
 
@@ -94,6 +95,7 @@ class dicod_stats(ctypes.Structure):
         ("polished_fp64", ctypes.c_int),
         ("t_queue_ms", ctypes.c_double),
         ("t_latency_ms", ctypes.c_double),
+        ("round_max_dz", ctypes.c_double * 4),
     ]
 
     def to_dict(self):
@@ -212,7 +214,12 @@ def dicod_solve(ctx, X, D, lam, eps, n_seg=0, K=None, W=None):
     st = dicod_stats()
     rc = lib().dicod_solve(ctx, _np_ptr(X), P, T, dptr, K, W, float(lam), float(eps),
                            int(n_seg), _np_ptr(Z), ctypes.byref(st))
-    _check(ctx, rc)
+    try:
+        _check(ctx, rc)
+    except DicodError as e:
+        if rc == DICOD_ENOTCONV:     # Z and the statistics are written
+            e.Z, e.stats = Z, st.to_dict()
+        raise
     return Z, st.to_dict()
 
 

@@ -68,7 +68,7 @@ struct Workspace {
     DevBuf tilesL, tilesC, tilesA, tilesN;
     DevBuf nzmask;                        // non-zero masks of Z for the check kernels
     DevBuf dirty, phase_upd, sig_upd, sig_last, counters;
-    DevBuf part, results, lmax, done, thr;
+    DevBuf part, results, lmax, done, thr, ebits;
     DevBuf msg, msg_n;                    // DICOD schedule: boundary messages
     DevBuf trace;
     DevBuf slots, lamin;                  // device-side lambda: signal indices, inputs
@@ -89,6 +89,7 @@ struct dicod_ctx {
     // resident dictionary
     bool has_dict = false;
     int K = 0, P = 0, W = 0;
+    double dnorm_max = 0.0;              // max_k |D_k|_2 (error bound of the bf16 split)
     DevBuf D64, D32, S64, S32, n2_64, inv64, n2_32, inv32;
     DevBuf St32, St64;  // phase-kernel layouts of S (float, double)
     DevBuf Sc64;        // S with rows padded to 2W doubles, for the double check
@@ -144,21 +145,23 @@ double now_ms()
     return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
 }
 
-// Shortest segment for C colours: segments of one colour run together and
-// must stay 2W - 2 apart (two half-windows), and a window may only reach the
-// adjacent segments.
+// Shortest segment for C colours: an update changes beta on the W - 1
+// positions on each side of it (eq. (3)), so a window may only reach the
+// adjacent segments when every segment is at least W - 1 long; segments of one
+// colour run together and must stay 2W - 2 apart (two half-windows).
 int64_t min_segment(int W, int C)
 {
+    const int64_t reach = W > 1 ? (int64_t)W - 1 : 1;
     if (C <= 1)  // Algorithm 2: a window may only reach the adjacent segments
-        return W;
+        return reach;
     const int64_t gap = (2 * (int64_t)W - 2 + (C - 2)) / (C - 1);
-    return std::max<int64_t>(W, gap);
+    return std::max<int64_t>(reach, gap);
 }
 
 // Segment count M chosen by the library: the largest M allowed by
 // min_segment (with 2 colours this is close to the paper's optimum
-// M* ~ T / (2W) of Corollary 1; 3 colours give segments of length W, the
-// paper's M = T / W choice for SeqDICOD).
+// M* ~ T / (2W) of Corollary 1; 3 colours give segments of W - 1 or W
+// coefficients, about the paper's M = T / W choice for SeqDICOD).
 int auto_segments(int64_t L, int W, int C)
 {
     const int64_t M = L / min_segment(W, C);
@@ -191,6 +194,7 @@ extern "C" int dicod_config_init(dicod_config* cfg)
     cfg->fp64_polish_after = 1;
     cfg->colors = 3;
     cfg->verify_from_scratch = 0;
+    cfg->reg_state = 1;
     return DICOD_OK;
 }
 
@@ -297,6 +301,15 @@ extern "C" int dicod_set_dictionary(dicod_ctx* ctx, const float* D, int K, int P
     if (K <= 0 || P <= 0 || W <= 0)
         return fail(ctx, DICOD_EINVAL, "dicod_set_dictionary: K=%d P=%d W=%d must be > 0",
                     K, P, W);
+    if (ctx->server) {
+        // the serving lanes hold the dictionary's device tables and sizes for
+        // the life of the context
+        const int64_t open = dicod::server_open_requests(ctx->server);
+        return fail(ctx, DICOD_EINVAL,
+                    "dicod_set_dictionary: serving active on this context (%lld requests "
+                    "not yet polled); the dictionary is fixed until dicod_finalize",
+                    (long long)open);
+    }
     if (P > kMaxP)
         return fail(ctx, DICOD_ENOTSUP, "dicod_set_dictionary: P=%d > %d channels", P, kMaxP);
     if ((int64_t)K * P * W > (int64_t)1 << 28)
@@ -308,12 +321,14 @@ extern "C" int dicod_set_dictionary(dicod_ctx* ctx, const float* D, int K, int P
             return fail(ctx, DICOD_EINVAL, "dicod_set_dictionary: D[%zu] is not finite", i);
         d64[i] = (double)D[i];
     }
+    double dnorm_max = 0.0;
     for (int k = 0; k < K; ++k) {
         double s = 0.0;
         for (size_t i = 0; i < (size_t)P * W; ++i)
             s += d64[(size_t)k * P * W + i] * d64[(size_t)k * P * W + i];
         if (!(s > 0.0))
             return fail(ctx, DICOD_EINVAL, "dicod_set_dictionary: atom %d has zero norm", k);
+        dnorm_max = std::max(dnorm_max, std::sqrt(s));
     }
     HIPCHECK(ctx, hipSetDevice(ctx->cfg.device));
     hipStream_t s = ctx->stream;
@@ -390,6 +405,7 @@ extern "C" int dicod_set_dictionary(dicod_ctx* ctx, const float* D, int K, int P
     ctx->K = K;
     ctx->P = P;
     ctx->W = W;
+    ctx->dnorm_max = dnorm_max;
     ctx->has_dict = true;
     return DICOD_OK;
 }
@@ -735,20 +751,40 @@ int solve_device_batch(dicod_ctx* ctx, int n_sig, const float* dX, const int64_t
                                         ws.tilesA.as<int64_t>(), n_sig, nA,
                                         ws.lmax.as<unsigned long long>(), s));
         } else {
-            // max of the float beta, then the exact maximum over the entries
-            // within 1e-3 (relative) of it, recomputed in double
+            // max of the split-bf16 beta, then the exact maximum over every
+            // entry that the rounding error could make the maximum, recomputed
+            // in double.  Per entry the error is at most
+            // c sum |d| |x| <= c |D_k| |X[., t : t + W]| with
+            // c = 3.1 2^-16 + (P W + 1) 2^-24 (bf16 unit roundoff 2^-8: the
+            // dropped lo*lo product and the two representation remainders,
+            // plus fp32 accumulation of P W terms and the final rounding), so
+            // the maximiser's split value is at least v - 2 e, e = c max|D_k|
+            // max_t |X[., t : t + W]| (5% margin on the bound).
+            HIPCHECK(ctx, ensure(ws.ebits, n_sig * sizeof(unsigned long long)));
+            HIPCHECK(ctx, launch_fill_u64(ws.ebits.as<unsigned long long>(), 0ull, n_sig, s));
             HIPCHECK(ctx, launch_absmax_f32(ws.g.as<float>(), K, ws.sig.as<SigDesc>(),
                                             ws.tilesA.as<int64_t>(), n_sig, nA,
                                             ws.lmax.as<unsigned long long>(), s));
+            HIPCHECK(ctx, launch_win_energy_max(dX, P, W, ws.sig.as<SigDesc>(),
+                                                ws.tilesL.as<int64_t>(), n_sig, nL,
+                                                ws.ebits.as<unsigned long long>(), s));
+            std::vector<unsigned long long> ebits(n_sig);
             HIPCHECK(ctx, hipMemcpyAsync(bits.data(), ws.lmax.p,
                                          n_sig * sizeof(unsigned long long),
                                          hipMemcpyDeviceToHost, s));
+            HIPCHECK(ctx, hipMemcpyAsync(ebits.data(), ws.ebits.p,
+                                         n_sig * sizeof(unsigned long long),
+                                         hipMemcpyDeviceToHost, s));
             HIPCHECK(ctx, hipStreamSynchronize(s));
+            const double c = 3.1 * std::ldexp(1.0, -16) +
+                             ((double)P * W + 1.0) * std::ldexp(1.0, -24);
             std::vector<double> thr(n_sig);
             for (int i = 0; i < n_sig; ++i) {
-                double v;
+                double v, en;
                 std::memcpy(&v, &bits[i], sizeof v);
-                thr[i] = v * (1.0 - 1e-3);
+                std::memcpy(&en, &ebits[i], sizeof en);
+                const double e = 1.05 * c * ctx->dnorm_max * std::sqrt(en);
+                thr[i] = std::max(0.0, v - 2.0 * e);
             }
             HIPCHECK(ctx, upload(ws.thr, thr, s));
             HIPCHECK(ctx, launch_fill_u64(ws.lmax.as<unsigned long long>(), 0ull, n_sig, s));
@@ -780,7 +816,11 @@ int solve_device_batch(dicod_ctx* ctx, int n_sig, const float* dX, const int64_t
         return fail(ctx, DICOD_ENOTSUP, "segments do not fit any phase kernel");
     if (pl.dicod && !in_lds)
         return fail(ctx, DICOD_ENOTSUP, "the DICOD schedule needs segments whose state fits LDS");
-    bool polished = false, any_hbm = !in_lds;
+    // float rounds on the register-state kernel when the segments allow it
+    const bool reg_ok = cfg.reg_state != 0 && !pl.dicod &&
+                        lgcd_wave_supported(K, pl.lm_max,
+                                            effective_update_cap(cfg.update_cap, W), false);
+    bool polished = false, any_hbm = !in_lds && (cur64 || !reg_ok);
 
     PhaseArgs a;
     std::memset(&a, 0, sizeof a);
@@ -829,6 +869,7 @@ int solve_device_batch(dicod_ctx* ctx, int n_sig, const float* dX, const int64_t
     int round_state[4] = {0, 0, 0, 0};
     std::vector<CheckResult> res(n_sig);
     std::vector<uint32_t> done(n_sig, 0u);
+    std::vector<double> round_mdz((size_t)n_sig * 4, 0.0);
     // phases queued past a round's convergence apply nothing: they are not
     // counted in n_phases (round r starts at phase r_start[r]; r_over[r]
     // overshoot phases ran before it)
@@ -883,12 +924,15 @@ int solve_device_batch(dicod_ctx* ctx, int n_sig, const float* dX, const int64_t
                         HIPCHECK(ctx, hipEventRecord(e0, s));
                     }
                     size_t lds = 0;
-                    hipError_t e = in_lds ? launch_lgcd_phase(a, cur64, &lds, s)
-                                          : launch_lgcd_phase_gm(a, cur64, &lds, s);
+                    const bool use_reg = !cur64 && reg_ok;
+                    hipError_t e = use_reg  ? launch_lgcd_wave(a, s)
+                                   : in_lds ? launch_lgcd_phase(a, cur64, &lds, s)
+                                            : launch_lgcd_phase_gm(a, cur64, &lds, s);
                     if (e != hipSuccess)
                         return fail(ctx, DICOD_EDEVICE,
                                     "LGCD phase launch (%s state, %zu bytes LDS): %s",
-                                    in_lds ? "LDS" : "HBM", lds, hipGetErrorString(e));
+                                    use_reg ? "register" : in_lds ? "LDS" : "HBM", lds,
+                                    hipGetErrorString(e));
                     ++n_launch;
                     if (cfg.timing)
                         HIPCHECK(ctx, hipEventRecord(e1, s));
@@ -943,7 +987,8 @@ int solve_device_batch(dicod_ctx* ctx, int n_sig, const float* dX, const int64_t
             round_ph[round] = last - start;
             round_launch[round] = n_launch - launch0;
             round_kms[round] = t_kernel - kern0;
-            round_state[round] = (cur64 ? 1 : 0) | (in_lds ? 0 : 2);
+            round_state[round] = (cur64 ? 1 : 0) | (in_lds ? 0 : 2) |
+                                 (!cur64 && reg_ok ? 4 : 0);
             for (int64_t p = start; p < last; ++p)
                 round_upd[round] += (int64_t)ctx->h_upd[p];
         }
@@ -988,6 +1033,10 @@ int solve_device_batch(dicod_ctx* ctx, int n_sig, const float* dX, const int64_t
         HIPCHECK(ctx, hipEventSynchronize(ev3));
         std::memcpy(res.data(), ctx->h_pin + pin_res, n_sig * sizeof(CheckResult));
         t_verify += elapsed_ms(ev2, ev3);
+        if (round <= 4)
+            for (int i = 0; i < n_sig; ++i)
+                if (!done[i])
+                    round_mdz[(size_t)i * 4 + (round - 1)] = res[i].max_dz;
         accepted = true;
         for (int i = 0; i < n_sig; ++i) {
             done[i] = res[i].max_dz < eps ? 1u : 0u;
@@ -1007,6 +1056,11 @@ int solve_device_batch(dicod_ctx* ctx, int n_sig, const float* dX, const int64_t
         }
         HIPCHECK(ctx, set_state(cur64, in_lds));
         HIPCHECK(ctx, upload_pinned(ws.done, done.data(), (size_t)n_sig * sizeof(uint32_t), 0));
+        // a signal that passed is frozen: the check may have flagged its
+        // segments against the next round's tighter threshold
+        HIPCHECK(ctx, launch_clear_done_dirty(ws.segs.as<SegDesc>(), n_seg_tot,
+                                              ws.done.as<uint32_t>(), ws.dirty.as<uint32_t>(),
+                                              s));
         while (phase % pl.colors)
             ++phase;
         if (pl.dicod) {
@@ -1090,6 +1144,7 @@ int solve_device_batch(dicod_ctx* ctx, int n_sig, const float* dX, const int64_t
             o.t_total_ms = t_total;
             o.t_lgcd_kernel_ms = t_kernel;
             for (int r = 0; r < 4; ++r) {
+                o.round_max_dz[r] = round_mdz[(size_t)i * 4 + r];
                 o.round_updates[r] = n_sig == 1 ? round_upd[r] : 0;
                 o.round_phases[r] = round_ph[r];
                 o.round_ms[r] = round_ms[r];

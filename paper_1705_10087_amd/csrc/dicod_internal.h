@@ -153,6 +153,12 @@ size_t lgcd_lds_bytes(int K, int lm_max, int lext_max, bool fp64);
 hipError_t launch_lgcd_phase_gm(const PhaseArgs& a, bool fp64, size_t* lds_bytes,
                                 hipStream_t s);
 size_t lgcd_gm_lds_bytes(int K, int lext_max, bool fp64);
+// Float phase with each position's state in the registers of one thread
+// (lgcd_wave.hip): segments of at most 256 positions, K <= 32, at most 64
+// updates per run, coloured schedule; S in the phase-kernel layout
+// (launch_s_transpose, float).
+bool lgcd_wave_supported(int K, int lm_max, int cap, bool fp64);
+hipError_t launch_lgcd_wave(const PhaseArgs& a, hipStream_t s);
 // Atoms per position in the phase kernel's layout (K padded), -1 if K is
 // beyond the instantiated sizes.
 int lgcd_k_padded(int K, bool fp64);
@@ -198,6 +204,14 @@ hipError_t launch_refine_absmax(const float* beta32, const double* D, const floa
                                 const int64_t* tile_pref, int n_sig, int64_t n_tiles,
                                 const double* thr, unsigned long long* out_bits,
                                 hipStream_t s);
+// Per signal, max over t < L of sum_p sum_{tau < W} X[p][t + tau]^2 (bits of a
+// non-negative double, atomic max; out_bits zeroed by the caller).  Tiles of
+// kTile positions (tile_pref: prefix of ceil(L / kTile)).  For W up to about
+// 20,000 (LDS).
+size_t win_energy_lds_bytes(int W);
+hipError_t launch_win_energy_max(const float* X, int P, int W, const SigDesc* sig,
+                                 const int64_t* tile_pref, int n_sig, int64_t n_tiles,
+                                 unsigned long long* out_bits, hipStream_t s);
 hipError_t launch_absmax_f32(const float* beta, int K, const SigDesc* sig,
                              const int64_t* tile_pref, int n_sig, int64_t n_tiles,
                              unsigned long long* out_bits, hipStream_t s);
@@ -207,6 +221,9 @@ hipError_t launch_apply_lambda(SigDesc* tab, const int* slots, const double* lam
                                const unsigned long long* lmax_bits, int n, hipStream_t s);
 // tab[0..n).eps_stop = eps (the stop threshold of the descent state).
 hipError_t launch_set_eps_stop(SigDesc* tab, int n, double eps, hipStream_t s);
+// dirty[i] = 0 for every segment i < n_seg whose signal has done[sig] != 0.
+hipError_t launch_clear_done_dirty(const SegDesc* segs, int n_seg, const uint32_t* done,
+                                   uint32_t* dirty, hipStream_t s);
 // Serving: ring[r][(start + c) % H] = 0 for r < rows, c < n.
 hipError_t launch_clear_ring(unsigned long long* ring, int rows, int H, int start, int n,
                              hipStream_t s);

@@ -176,6 +176,7 @@ struct Job {
     int slot = -1;
     int64_t z_off = 0, zn = 0, x_off = 0, xn = 0, seg_base = 0;
     bool cur64 = false, in_lds = false, lds64 = false, lds32 = false;
+    bool reg32 = false;           // float rounds on the register-state kernel
     int lane = 0;
     bool polished = false, any_hbm = false, out_of_phases = false;
     int n_refresh = 0, round = 0;
@@ -184,6 +185,7 @@ struct Job {
     unsigned long long upd_round0 = 0, upd = 0;
     int64_t round_upd[4] = {0, 0, 0, 0}, round_ph[4] = {0, 0, 0, 0};
     int round_state[4] = {0, 0, 0, 0};
+    double round_mdz[4] = {0.0, 0.0, 0.0, 0.0};
     int rc = DICOD_OK;
     std::string err;
     CheckResult res{};
@@ -221,7 +223,8 @@ struct Lane {
     int iterate(int* admitted);
     void admit(std::vector<Job*>& fresh);
     int init_jobs(const std::vector<Job*>& fresh);
-    int check_jobs(const std::vector<Job*>& conv);
+    int check_jobs(const std::vector<Job*>& conv, std::vector<Job*>& resumed);
+    void abandon(int rc, const std::string& m);
     hipError_t stage(void* dst, const void* src, size_t bytes);
 };
 
@@ -452,22 +455,24 @@ void Server::release(Job* j)
     }
 }
 
-// A HIP failure in a lane ends serving: every open request fails with it.
+// A HIP failure in a lane ends serving: every open request fails with it
+// (mu not held).
 void Server::fail_all(int rc, const std::string& m)
 {
     {
         std::lock_guard<std::mutex> g(mu);
-        fatal = rc;
-        fatal_msg = m;
+        if (fatal == DICOD_OK) {  // the first failure names the cause
+            fatal = rc;
+            fatal_msg = m;
+        }
         stop = true;
-        for (auto& kv : jobs) {
-            Job* j = kv.second;
-            if (j->state == kQueued || j->state == kRunning) {
-                j->rc = rc;
-                j->err = m;
-                j->state = kDone;
-                j->t_done = now_ms();
-            }
+        // queued requests belong to no lane; running ones are failed by their
+        // lane once it has stopped using them (Lane::abandon)
+        for (Job* j : queue) {
+            j->rc = rc;
+            j->err = m;
+            j->state = kDone;
+            j->t_done = now_ms();
         }
         queue.clear();
         for (Lane& l : lanes)
@@ -491,7 +496,10 @@ void Lane::loop()
                        (queued > 0 && !srv->free_slots.empty() && srv->epoch != blocked);
             });
             if (srv->stop) {
-                running.clear();
+                const int frc = srv->fatal;
+                const std::string fm = srv->fatal_msg;
+                g.unlock();
+                abandon(frc, fm);
                 return;
             }
             seen = srv->epoch;
@@ -499,8 +507,9 @@ void Lane::loop()
         int admitted = 0;
         const int rc = iterate(&admitted);
         if (rc != DICOD_OK) {
-            srv->fail_all(rc, "serving: " + msg);
-            running.clear();
+            const std::string m = "serving: " + msg;
+            srv->fail_all(rc, m);
+            abandon(rc, m);
             return;
         }
         if (running.empty() && admitted == 0) {
@@ -509,6 +518,24 @@ void Lane::loop()
             blocked = seen;
         }
     }
+}
+
+// The lane stops: its running requests fail with rc when serving failed
+// (rc != DICOD_OK; at teardown they are simply dropped with the server).
+void Lane::abandon(int rc, const std::string& m)
+{
+    if (rc != DICOD_OK) {
+        const double t = now_ms();
+        std::lock_guard<std::mutex> g(srv->mu);
+        for (Job* j : running) {
+            j->rc = rc;
+            j->err = m;
+            j->t_done = t;
+            j->state = kDone;
+        }
+    }
+    running.clear();
+    srv->cv.notify_all();
 }
 
 // Admission of this lane's requests in arrival order while a slot and the
@@ -613,113 +640,150 @@ int Lane::init_jobs(const std::vector<Job*>& fresh)
         j->start = tick;
         j->cur64 = v.fp64;
         j->in_lds = v.fp64 ? j->lds64 : j->lds32;
-        j->any_hbm = !j->in_lds;
+        j->any_hbm = !j->in_lds && (v.fp64 || !j->reg32);
     }
     return DICOD_OK;
 }
 
 // Double-precision stop test of the requests in conv (grouped by state and
 // eps), and the decision per request: complete, or refresh and resume at
-// colour 0 -- the round structure of the one-shot solver.
-int Lane::check_jobs(const std::vector<Job*>& conv)
+// colour 0 -- the round structure of the one-shot solver.  The resumed
+// requests are appended to `resumed`.  Completed requests are published
+// (Server::finish) only after the last access to them here: from then on
+// dicod_poll may copy their result and free them at any moment.
+int Lane::check_jobs(const std::vector<Job*>& conv, std::vector<Job*>& resumed)
 {
     Server& v = *srv;
     const int K = v.K, P = v.P, W = v.W;
     const int n_kblk = check_kblocks(K, W);
     const dicod_config& cfg = v.cfg;
-    for (int grp = 0; grp < 4; ++grp) {
-        const bool c64 = grp & 1;
-        const bool next64 = (grp & 2) != 0;
-        std::vector<Job*> g;
-        for (Job* j : conv) {
-            const bool n64 = j->cur64 || (cfg.fp64_polish_after > 0 &&
-                                          j->n_refresh + 1 >= cfg.fp64_polish_after);
-            if (j->cur64 == c64 && n64 == next64)
-                g.push_back(j);
-        }
-        if (g.empty())
-            continue;
-        std::sort(g.begin(), g.end(), [](const Job* a, const Job* b) { return a->eps < b->eps; });
-        size_t i0 = 0;
-        while (i0 < g.size()) {
-            size_t i1 = i0;
-            while (i1 < g.size() && g[i1]->eps == g[i0]->eps)
-                ++i1;
-            const int n = (int)(i1 - i0);
-            const double eps = g[i0]->eps;
-            std::vector<SigDesc> sub(n);
-            std::vector<int64_t> pC(n + 1, 0), pN(n + 1, 0);
-            for (int i = 0; i < n; ++i) {
-                Job* j = g[i0 + i];
-                sub[i] = v.h_sig[j->slot];
-                sub[i].nz_off = pN[i];
-                pC[i + 1] = pC[i] + ceil_div(j->L, kCheckSpan);
-                pN[i + 1] = pN[i] + (int64_t)K * ceil_div(j->L, 64);
-            }
-            if (pN[n] > v.mask_cap) {
-                msg = "non-zero mask buffer too small";
-                return DICOD_EDEVICE;
-            }
-            stage_off = 0;  // the previous group was synchronised
-            SRV_HIP(stage(dSub.p, sub.data(), n * sizeof(SigDesc)));
-            SRV_HIP(stage(dTilesC.p, pC.data(), (n + 1) * sizeof(int64_t)));
-            SRV_HIP(stage(dTilesN.p, pN.data(), (n + 1) * sizeof(int64_t)));
-            const double flag_eps = next64 ? eps : eps * cfg.inner_eps_factor;
-            void* g_next = next64 ? v.dG64.p : v.dG32.p;
-            const double* g_in =
-                (c64 && !cfg.verify_from_scratch) ? v.dG64.as<double>() : nullptr;
-            if (!g_in)
-                SRV_HIP(launch_nz_mask(v.dZ.as<double>(), dSub.as<SigDesc>(),
-                                       dTilesN.as<int64_t>(), n, K, pN[n],
-                                       dMask.as<unsigned long long>(), s));
-            SRV_HIP(launch_grad_check(v.dX.as<float>(), v.dB.as<double>(), v.dZ.as<double>(),
-                                      dMask.as<unsigned long long>(), v.dict.Sc64,
-                                      (const double*)v.dict.n2_64, K, P, W, dSub.as<SigDesc>(),
-                                      dTilesC.as<int64_t>(), n, pC[n], flag_eps,
-                                      dDone.as<uint32_t>(), v.dDirty.as<uint32_t>(),
-                                      g_in ? nullptr : g_next, next64, g_in, dPart.as<double>(),
-                                      s));
-            SRV_HIP(launch_check_reduce(dPart.as<double>(), dTilesC.as<int64_t>(), pC[n], n_kblk,
-                                        n, dRes.as<CheckResult>(), s));
-            SRV_HIP(hipMemcpyAsync(h_res, dRes.p, n * sizeof(CheckResult),
-                                   hipMemcpyDeviceToHost, s));
-            std::vector<SigDesc> upd;
-            std::vector<Job*> resumed;
-            SRV_HIP(hipStreamSynchronize(s));
-            for (int i = 0; i < n; ++i) {
-                Job* j = g[i0 + i];
-                j->res = h_res[i];
-                const bool ok = j->res.max_dz < j->eps;
-                if (ok || j->out_of_phases || j->n_refresh >= cfg.max_refresh) {
-                    v.finish(j, ok ? DICOD_OK : DICOD_ENOTCONV,
+    struct Done {
+        Job* j;
+        int rc;
+        const char* m;
+    };
+    std::vector<Done> finished;
+    // state class of every request (bit 0: double now, bit 1: double in the
+    // next round), decided before any request changes state
+    std::vector<int> cls(conv.size());
+    for (size_t i = 0; i < conv.size(); ++i) {
+        const Job* j = conv[i];
+        const bool n64 = j->cur64 || (cfg.fp64_polish_after > 0 &&
+                                      j->n_refresh + 1 >= cfg.fp64_polish_after);
+        cls[i] = (j->cur64 ? 1 : 0) | (n64 ? 2 : 0);
+    }
+    auto run = [&]() -> int {
+        for (int grp = 0; grp < 4; ++grp) {
+            const bool c64 = (grp & 1) != 0;
+            const bool next64 = (grp & 2) != 0;
+            std::vector<Job*> g;
+            for (size_t i = 0; i < conv.size(); ++i)
+                if (cls[i] == grp)
+                    g.push_back(conv[i]);
+            if (g.empty())
+                continue;
+            std::sort(g.begin(), g.end(),
+                      [](const Job* a, const Job* b) { return a->eps < b->eps; });
+            size_t i0 = 0;
+            while (i0 < g.size()) {
+                size_t i1 = i0;
+                while (i1 < g.size() && g[i1]->eps == g[i0]->eps)
+                    ++i1;
+                const int n = (int)(i1 - i0);
+                const double eps = g[i0]->eps;
+                std::vector<SigDesc> sub(n);
+                std::vector<int64_t> pC(n + 1, 0), pN(n + 1, 0);
+                for (int i = 0; i < n; ++i) {
+                    Job* j = g[i0 + i];
+                    sub[i] = v.h_sig[j->slot];
+                    sub[i].nz_off = pN[i];
+                    pC[i + 1] = pC[i] + ceil_div(j->L, kCheckSpan);
+                    pN[i + 1] = pN[i] + (int64_t)K * ceil_div(j->L, 64);
+                }
+                if (pN[n] > v.mask_cap) {
+                    msg = "non-zero mask buffer too small";
+                    return DICOD_EDEVICE;
+                }
+                stage_off = 0;  // the previous group was synchronised
+                SRV_HIP(stage(dSub.p, sub.data(), n * sizeof(SigDesc)));
+                SRV_HIP(stage(dTilesC.p, pC.data(), (n + 1) * sizeof(int64_t)));
+                SRV_HIP(stage(dTilesN.p, pN.data(), (n + 1) * sizeof(int64_t)));
+                const double flag_eps = next64 ? eps : eps * cfg.inner_eps_factor;
+                void* g_next = next64 ? v.dG64.p : v.dG32.p;
+                const double* g_in =
+                    (c64 && !cfg.verify_from_scratch) ? v.dG64.as<double>() : nullptr;
+                if (!g_in)
+                    SRV_HIP(launch_nz_mask(v.dZ.as<double>(), dSub.as<SigDesc>(),
+                                           dTilesN.as<int64_t>(), n, K, pN[n],
+                                           dMask.as<unsigned long long>(), s));
+                SRV_HIP(launch_grad_check(v.dX.as<float>(), v.dB.as<double>(),
+                                          v.dZ.as<double>(), dMask.as<unsigned long long>(),
+                                          v.dict.Sc64, (const double*)v.dict.n2_64, K, P, W,
+                                          dSub.as<SigDesc>(), dTilesC.as<int64_t>(), n, pC[n],
+                                          flag_eps, dDone.as<uint32_t>(),
+                                          v.dDirty.as<uint32_t>(), g_in ? nullptr : g_next,
+                                          next64, g_in, dPart.as<double>(), s));
+                SRV_HIP(launch_check_reduce(dPart.as<double>(), dTilesC.as<int64_t>(), pC[n],
+                                            n_kblk, n, dRes.as<CheckResult>(), s));
+                SRV_HIP(hipMemcpyAsync(h_res, dRes.p, n * sizeof(CheckResult),
+                                       hipMemcpyDeviceToHost, s));
+                std::vector<Job*> res_grp;
+                SRV_HIP(hipStreamSynchronize(s));
+                for (int i = 0; i < n; ++i) {
+                    Job* j = g[i0 + i];
+                    j->res = h_res[i];
+                    if (j->round >= 1 && j->round <= 4)
+                        j->round_mdz[j->round - 1] = j->res.max_dz;
+                    const bool ok = j->res.max_dz < j->eps;
+                    if (ok || j->out_of_phases || j->n_refresh >= cfg.max_refresh) {
+                        finished.push_back(
+                            {j, ok ? DICOD_OK : DICOD_ENOTCONV,
                              ok ? nullptr
                                 : (j->out_of_phases
                                        ? "max_phases reached before the stop test held"
-                                       : "max_refresh double-precision checks failed"));
-                    continue;
+                                       : "max_refresh double-precision checks failed")});
+                        continue;
+                    }
+                    ++j->n_refresh;
+                    if (next64 && !j->cur64) {
+                        j->cur64 = true;
+                        j->in_lds = j->lds64;
+                        j->polished = true;
+                        j->any_hbm |= !j->in_lds;
+                    }
+                    SigDesc& d = v.h_sig[j->slot];
+                    d.eps_stop = j->cur64 ? j->eps : j->eps * cfg.inner_eps_factor;
+                    res_grp.push_back(j);
+                    // the next round starts with colour 0 on the next tick
+                    j->start = tick;
+                    j->upd_round0 = j->upd;
                 }
-                ++j->n_refresh;
-                if (next64 && !j->cur64) {
-                    j->cur64 = true;
-                    j->in_lds = j->lds64;
-                    j->polished = true;
-                    j->any_hbm |= !j->in_lds;
-                }
-                SigDesc& d = v.h_sig[j->slot];
-                d.eps_stop = j->cur64 ? j->eps : j->eps * cfg.inner_eps_factor;
-                resumed.push_back(j);
-                // the next round starts with colour 0 on the next tick
-                j->start = tick;
-                j->upd_round0 = j->upd;
+                stage_off = 0;
+                for (Job* j : res_grp)
+                    SRV_HIP(stage(v.dSig.as<SigDesc>() + j->slot, &v.h_sig[j->slot],
+                                  sizeof(SigDesc)));
+                SRV_HIP(hipStreamSynchronize(s));
+                resumed.insert(resumed.end(), res_grp.begin(), res_grp.end());
+                i0 = i1;
             }
-            stage_off = 0;
-            for (Job* j : resumed)
-                SRV_HIP(stage(v.dSig.as<SigDesc>() + j->slot, &v.h_sig[j->slot], sizeof(SigDesc)));
-            SRV_HIP(hipStreamSynchronize(s));
-            i0 = i1;
+        }
+        return DICOD_OK;
+    };
+    const int rc = run();
+    if (rc != DICOD_OK) {
+        // the lane stops; the requests not yet decided stay in its care and
+        // fail with the lane (Lane::abandon)
+        for (Job* j : conv) {
+            bool decided = false;
+            for (const Done& d : finished)
+                decided |= d.j == j;
+            if (!decided && std::find(resumed.begin(), resumed.end(), j) == resumed.end())
+                resumed.push_back(j);
         }
     }
-    return DICOD_OK;
+    for (const Done& d : finished)
+        v.finish(d.j, d.rc, d.m);
+    return rc;
 }
 
 // One scheduling step: admission, one chunk of ticks, convergence and checks.
@@ -756,7 +820,7 @@ int Lane::iterate(int* admitted)
     // segment of the group fits the kernel's LDS layout; lists per tick
     // residue r = t % C (a request's colour at tick t is (t - start) % C)
     struct Group {
-        bool c64, lds;
+        bool c64, lds, reg;
         int lm, lx;
         std::vector<int32_t> list[kMaxColors];
         size_t off[kMaxColors];
@@ -764,11 +828,13 @@ int Lane::iterate(int* admitted)
     std::vector<Group> groups;
     for (Job* j : running) {
         Group* gp = nullptr;
+        const bool reg = !j->cur64 && j->reg32;
         for (Group& g : groups) {
-            if (g.c64 != j->cur64 || g.lds != j->in_lds)
+            if (g.c64 != j->cur64 || g.reg != reg || (!reg && g.lds != j->in_lds))
                 continue;
             const int lm = std::max(g.lm, j->lm), lx = std::max(g.lx, j->lext);
-            const size_t b = g.lds ? lgcd_lds_bytes(K, lm, lx, g.c64)
+            const size_t b = reg ? 0
+                           : g.lds ? lgcd_lds_bytes(K, lm, lx, g.c64)
                                    : lgcd_gm_lds_bytes(K, lx, g.c64);
             if (b <= kLdsBytes) {
                 gp = &g;
@@ -780,6 +846,7 @@ int Lane::iterate(int* admitted)
             gp = &groups.back();
             gp->c64 = j->cur64;
             gp->lds = j->in_lds;
+            gp->reg = reg;
             gp->lm = 0;
             gp->lx = 0;
         }
@@ -832,8 +899,9 @@ int Lane::iterate(int* admitted)
             a.lm_max = g.lm;
             a.lext_max = g.lx;
             size_t lds_b = 0;
-            hipError_t e = g.lds ? launch_lgcd_phase(a, g.c64, &lds_b, s)
-                                 : launch_lgcd_phase_gm(a, g.c64, &lds_b, s);
+            hipError_t e = g.reg   ? launch_lgcd_wave(a, s)
+                           : g.lds ? launch_lgcd_phase(a, g.c64, &lds_b, s)
+                                   : launch_lgcd_phase_gm(a, g.c64, &lds_b, s);
             if (e != hipSuccess) {
                 msg = std::string("phase launch: ") + hipGetErrorString(e);
                 return DICOD_EDEVICE;
@@ -890,7 +958,8 @@ int Lane::iterate(int* admitted)
             if (j->round < 4) {
                 j->round_ph[j->round] = ph;
                 j->round_upd[j->round] = (int64_t)(j->upd - j->upd_round0);
-                j->round_state[j->round] = (j->cur64 ? 1 : 0) | (j->in_lds ? 0 : 2);
+                j->round_state[j->round] = (j->cur64 ? 1 : 0) | (j->in_lds ? 0 : 2) |
+                                           (!j->cur64 && j->reg32 ? 4 : 0);
             }
             ++j->round;
             j->phases += ph;
@@ -902,17 +971,23 @@ int Lane::iterate(int* admitted)
     }
     running.swap(keep);
     if (!conv.empty()) {
-        int rc = check_jobs(conv);
+        // the finished requests are not touched again: dicod_poll may free them
+        std::vector<Job*> resumed;
+        const int rc = check_jobs(conv, resumed);
+        running.insert(running.end(), resumed.begin(), resumed.end());
         if (rc != DICOD_OK)
             return rc;
-        for (Job* j : conv)
-            if (j->state == kRunning)
-                running.push_back(j);
     }
     return DICOD_OK;
 }
 
 void server_destroy(Server* s) { delete s; }
+
+int64_t server_open_requests(Server* s)
+{
+    std::lock_guard<std::mutex> g(s->mu);
+    return (int64_t)s->jobs.size();
+}
 
 int server_submit(dicod_ctx* ctx, const float* X, int64_t T, double lambda, double eps,
                   int n_seg, uint64_t* req_id)
@@ -980,6 +1055,8 @@ int server_submit(dicod_ctx* ctx, const float* X, int64_t T, double lambda, doub
     j->eps = eps;
     j->lds32 = lds32;
     j->lds64 = lds64;
+    j->reg32 = cfg.reg_state != 0 &&
+               lgcd_wave_supported(K, (int)lm, effective_update_cap(cfg.update_cap, W), false);
     j->lane = M <= kShortSegs ? 0 : 1;
     j->zn = round_up((int64_t)K * L, 64);
     j->xn = round_up((int64_t)P * T, 64);
@@ -1072,6 +1149,7 @@ int server_poll(dicod_ctx* ctx, uint64_t req_id, double* Z_out, dicod_stats* st)
             st->round_updates[r] = j->round_upd[r];
             st->round_phases[r] = j->round_ph[r];
             st->round_state[r] = j->round_state[r];
+            st->round_max_dz[r] = j->round_mdz[r];
         }
         st->state_in_hbm = j->any_hbm ? 1 : 0;
         st->polished_fp64 = j->polished ? 1 : 0;

@@ -10,6 +10,8 @@ namespace dicod {
 struct Server;
 
 void server_destroy(Server* s);
+// Requests submitted and not yet returned by dicod_poll.
+int64_t server_open_requests(Server* s);
 int server_submit(dicod_ctx* ctx, const float* X, int64_t T, double lambda, double eps,
                   int n_seg, uint64_t* req_id);
 int server_poll(dicod_ctx* ctx, uint64_t req_id, double* Z_out, dicod_stats* st);

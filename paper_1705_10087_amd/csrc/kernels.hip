@@ -656,8 +656,8 @@ hipError_t launch_absmax_f32(const float* beta, int K, const SigDesc* sig,
 // Segments of one parity run in the same launch.  A run writes g back over
 // the part of the extended window it touched, i.e. into the idle neighbours'
 // positions: this is the even/odd form of the boundary messages of
-// Algorithm 2.  Segments are >= 2W long, so two runs of one launch never touch
-// the same entry.
+// Algorithm 2.  Segments are at least W - 1 long and same-colour segments are
+// at least 2W - 2 apart, so two runs of one launch never touch the same entry.
 // ---------------------------------------------------------------------------
 
 template <typename G>
@@ -2198,6 +2198,26 @@ hipError_t launch_set_eps_stop(SigDesc* tab, int n, double eps, hipStream_t s)
     if (n <= 0)
         return hipSuccess;
     hipLaunchKernelGGL(k_set_eps_stop, dim3((n + 255) / 256), dim3(256), 0, s, tab, n, eps);
+    return hipGetLastError();
+}
+
+// dirty[s] = 0 for the segments of signals whose stop test has held: an
+// accepted signal's Z is final, whatever its last check flagged.
+__global__ void k_clear_done_dirty(const SegDesc* __restrict__ segs, int n_seg,
+                                   const uint32_t* __restrict__ done, uint32_t* dirty)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n_seg && done[segs[i].sig] != 0u)
+        dirty[i] = 0u;
+}
+
+hipError_t launch_clear_done_dirty(const SegDesc* segs, int n_seg, const uint32_t* done,
+                                   uint32_t* dirty, hipStream_t s)
+{
+    if (n_seg <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_clear_done_dirty, dim3((n_seg + 255) / 256), dim3(256), 0, s, segs,
+                       n_seg, done, dirty);
     return hipGetLastError();
 }
 

@@ -1,0 +1,497 @@
+// Register-state LGCD phase kernel for float state (gfx950).
+//
+// One segment run is Algorithm 3 restricted to the segment C_m (Sec. 2.2):
+// repeat { for every coordinate of the segment, Z' = Sh(beta, lambda) /
+// |D_k|^2 (eq. (pb_coord)); take the coordinate with the largest
+// |Delta Z| = |Z' - Z|; apply it and the eq. (3) update of beta over the
+// 2W - 1 window } until the largest |Delta Z| is below the stop threshold or
+// the run has made `cap` updates.
+//
+// Layout.  A team of TW waves (TW = 1, 2 or 4) runs one segment of at most
+// 64 TW positions; thread j of the team owns segment position j and keeps its
+// K coefficients of the descent state g = beta - |D_k|^2 Z (g-form: eq. (3)
+// then applies uniformly, also at the updated coordinate) in vector
+// registers, in groups of four atoms, and its K values of Z (float) in its own
+// column of an LDS array (only the updated coordinate's changes).  In an
+// update the owner of every position in the window loads its row of the
+// correlation table S_{., k0}[t - t0] (St[k0][d][k], 16-byte vectors, the
+// rows of consecutive positions are contiguous) and applies g -= S delta to
+// its own registers, then re-evaluates its own candidates.
+//
+// Argmax.  A candidate is one 32-bit key: the bits of |Delta Z| with the low
+// five mantissa bits replaced by 31 - k, so an unsigned maximum over keys
+// picks the largest |Delta Z| (to 2^-18 relative) and, among equal values, the
+// smallest atom.  The team maximum is a DPP reduction inside each wave; the
+// winning lane is the lowest lane holding the maximum (smallest position).
+// With TW = 1 a segment is one wave and an update needs no barrier at all;
+// with TW > 1 the waves exchange (key, lane, delta) through LDS slots with
+// one barrier per update (slots double-buffered by update parity).  The
+// applied change delta is recomputed exactly from the winner's registers.
+//
+// Boundary.  An update whose window reaches a neighbouring segment (the
+// W - 1 halo) is recorded as (k0, t0, delta); the records are applied to the
+// neighbours' state in HBM at the end of the run, each halo position by one
+// thread, in update order (the neighbours are idle in this phase, so this
+// equals applying them at each update).  This replaces the boundary messages
+// of Algorithm 2 in the coloured schedule.
+#include <hip/hip_runtime.h>
+
+#include <climits>
+#include <cstdint>
+
+#include "dicod_internal.h"
+
+namespace dicod {
+namespace {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+constexpr int kWaveRecs = 64;  // halo records held on chip per segment
+
+struct WRec {
+    int k0;
+    int t0;
+    float delta;
+    int pad;
+};
+
+struct WSlot {
+    unsigned key;
+    int pos;
+    float delta;
+    int pad;
+};
+
+// Wave-wide maximum of an unsigned key with DPP row operations: quad
+// permutations, half-row and row mirrors, then the row broadcasts of lanes 15
+// and 31; lane 63 ends with the maximum, read into a scalar register.
+template <int CTRL, int RM>
+__device__ __forceinline__ unsigned dpp_max_step(unsigned a)
+{
+    const unsigned o = (unsigned)__builtin_amdgcn_update_dpp((int)a, (int)a, CTRL, RM, 0xf, false);
+    return o > a ? o : a;
+}
+
+__device__ __forceinline__ unsigned wave_max_u32(unsigned a)
+{
+    a = dpp_max_step<0xB1, 0xf>(a);   // quad_perm [1,0,3,2]
+    a = dpp_max_step<0x4E, 0xf>(a);   // quad_perm [2,3,0,1]
+    a = dpp_max_step<0x141, 0xf>(a);  // row_half_mirror
+    a = dpp_max_step<0x140, 0xf>(a);  // row_mirror
+    a = dpp_max_step<0x142, 0xa>(a);  // row_bcast:15 into rows 1 and 3
+    a = dpp_max_step<0x143, 0xc>(a);  // row_bcast:31 into rows 2 and 3
+    return __builtin_amdgcn_readlane(a, 63);
+}
+
+// Lowest lane whose predicate holds (the predicate holds in at least one lane).
+__device__ __forceinline__ int first_lane(bool p)
+{
+    const unsigned long long m = __ballot(p);
+    return __builtin_ctzll(m);
+}
+
+// v[k] of a register array for a wave-uniform k: a binary search on k, so
+// the branches are scalar and only one selection executes.
+template <int LO, int HI, int KQ>
+__device__ __forceinline__ float pick(const f4 (&v)[KQ], int k)
+{
+    if constexpr (HI - LO == 1) {
+        return v[LO / 4][LO % 4];
+    } else {
+        constexpr int MID = (LO + HI) / 2;
+        if (k < MID)
+            return pick<LO, MID, KQ>(v, k);
+        return pick<MID, HI, KQ>(v, k);
+    }
+}
+
+// Delta Z of one coordinate in g-form: beta = g + |D_k|^2 z; Z' = 0 where
+// |beta| <= lambda, so Delta Z = -z exactly (the change Z receives); else
+// Delta Z = (g - lambda sign(beta)) / |D_k|^2 (eq. (pb_coord)), formed without
+// cancellation against z and exact in the subtraction when g is close to
+// +-lambda.
+__device__ __forceinline__ float cand(float g, float z, float n2, float inv, float lam)
+{
+    const float bb = fmaf(n2, z, g);
+    return fabsf(bb) <= lam ? -z : (g - copysignf(lam, bb)) * inv;
+}
+
+__device__ __forceinline__ unsigned make_key(float d, int k)
+{
+    return (__float_as_uint(d) & 0x7fffffe0u) | (unsigned)(31 - k);
+}
+
+__device__ __forceinline__ float key_value(unsigned key)
+{
+    return __uint_as_float(key & 0x7fffffe0u);
+}
+
+// Best key over the own position's atoms.  z: this thread's column of the
+// LDS array [KQ][threads].
+template <int KQ, int NT>
+__device__ __forceinline__ unsigned best_key(const f4 (&g)[KQ], const f4* __restrict__ z,
+                                             const f4* __restrict__ cn2,
+                                             const f4* __restrict__ cinv, float lam)
+{
+    unsigned best = 0u;
+#pragma unroll
+    for (int i = 0; i < KQ; ++i) {
+        const f4 n2 = cn2[i], iv = cinv[i];
+        const f4 zv = z[i * NT];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const float d = cand(g[i][c], zv[c], n2[c], iv[c], lam);
+            const unsigned key = make_key(d, 4 * i + c);
+            best = key > best ? key : best;
+        }
+    }
+    return best;
+}
+
+template <int KQ, int TW>
+__global__ void __launch_bounds__(TW == 2 ? 128 : 256)
+k_lgcd_wave(PhaseArgs a)
+{
+    constexpr int SPB = TW == 1 ? 4 : 1;      // segments per workgroup
+    constexpr int NTT = 64 * TW;              // threads per team (one segment)
+    constexpr int KP = 4 * KQ;
+    const int lane = threadIdx.x & 63;
+    // uniform in the wave: the segment's descriptor and pointers then live in
+    // scalar registers
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int team = TW == 1 ? wave : 0;
+    const int tt = TW == 1 ? lane : (int)threadIdx.x;  // position owned in the segment
+
+    constexpr int NT = SPB * NTT;             // threads per workgroup
+    __shared__ f4 s_cst[SPB][2][KQ];            // |D_k|^2 and 1 / |D_k|^2
+    __shared__ f4 s_u[KQ * NT];                 // Z in float: [atom group][thread]
+    __shared__ WRec s_rec[SPB][kWaveRecs];
+    __shared__ WSlot s_slot[2][TW];
+    f4* __restrict__ u = s_u + threadIdx.x;    // this thread's column (stride NT)
+
+    const int li = blockIdx.x * SPB + team;
+    if (li >= a.n_list)
+        return;
+    const int sid = a.list[li];
+    if (a.dirty[sid] == 0)
+        return;
+
+    const SegDesc sd = a.segs[sid];
+    const int K = a.K;
+    const int W = a.W;
+    const int nd = 2 * W - 1;
+    const int64_t L = sd.L;
+    const int b = sd.b;
+    const int Lm = sd.e - sd.b;
+    float* __restrict__ gs = reinterpret_cast<float*>(a.g) + sd.z_off;
+    double* __restrict__ Zs = a.Z + sd.z_off;
+    const float* __restrict__ St = reinterpret_cast<const float*>(a.S);  // [K][nd][KP]
+    const float lam = (float)a.sigs[sd.sig].lam;
+    const float eps_stop = (float)a.sigs[sd.sig].eps_stop;
+
+    // per-atom constants of this team (padded atoms: |D|^2 = 1; their g and
+    // u are 0, so their candidate is 0)
+    // (scalar stores: each thread writes its own atoms' words, never a whole
+    // 16-byte vector, which would be a read-modify-write racing with the
+    // threads writing the vector's other words)
+    f4* cn2 = s_cst[team][0];
+    f4* cinv = s_cst[team][1];
+    for (int k = tt; k < KP; k += NTT) {
+        reinterpret_cast<float*>(cn2)[k] = k < K ? reinterpret_cast<const float*>(a.n2)[k] : 1.0f;
+        reinterpret_cast<float*>(cinv)[k] =
+            k < K ? reinterpret_cast<const float*>(a.inv_n2)[k] : 1.0f;
+    }
+    if (TW > 1)
+        __syncthreads();
+    else
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+
+    // own state: g and u = |D_k|^2 Z of position j = tt.  Every lane loads
+    // (idle lanes at position 0: their values are never used) and padded atoms
+    // load atom K - 1 and are zeroed by a uniform select, so that the loads
+    // are unconditional and all in flight at once.
+    const bool own = tt < Lm;
+    const int jc = own ? tt : 0;
+    f4 g[KQ], uz[KQ];
+    {
+        const float* pg = gs + b + jc;
+        const double* pz = Zs + b + jc;
+#pragma unroll
+        for (int i = 0; i < KQ; ++i)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                g[i][c] = *pg;
+                uz[i][c] = (float)*pz;
+                if (4 * i + c + 1 < K) {  // padded atoms reread atom K - 1
+                    pg += L;
+                    pz += L;
+                }
+            }
+    }
+#pragma unroll
+    for (int i = 0; i < KQ; ++i) {
+        const f4 n2 = cn2[i];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const bool pad = 4 * i + c >= K;
+            g[i][c] = pad ? 0.0f : g[i][c];
+            uz[i][c] = pad ? 0.0f : uz[i][c];
+        }
+        u[i * NT] = uz[i];
+    }
+    if (TW > 1)
+        __syncthreads();
+    else
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+
+    // team argmax: key, position and exact change delta of the best candidate
+    int it = 0;
+    auto argmax = [&](unsigned mine, unsigned& kb, int& j0, float& db) __attribute__((always_inline)) {
+        const unsigned wk = wave_max_u32(mine);
+        const int wl = first_lane(mine == wk);
+        const int k0w = 31 - (int)(wk & 31u);
+        const int kk = k0w < KP ? k0w : 0;
+        // exact delta of the wave's winner, from its registers and u column
+        const float gw = __int_as_float(
+            __builtin_amdgcn_readlane(__float_as_int(pick<0, KP, KQ>(g, kk)), wl));
+        const float zw = s_u[(kk / 4) * NT + (threadIdx.x - lane) + wl][kk % 4];
+        const float dw = cand(gw, zw, cn2[kk / 4][kk % 4], cinv[kk / 4][kk % 4], lam);
+        if (TW == 1) {
+            kb = wk;
+            j0 = wl;
+            db = dw;
+        } else {
+            WSlot* sl = s_slot[it & 1];
+            if (lane == 0) {
+                WSlot w;
+                w.key = wk;
+                w.pos = wave * 64 + wl;
+                w.delta = dw;
+                w.pad = 0;
+                sl[wave] = w;
+            }
+            __syncthreads();
+            WSlot bst = sl[0];
+#pragma unroll
+            for (int v = 1; v < TW; ++v) {
+                const WSlot o = sl[v];
+                if (o.key > bst.key)
+                    bst = o;
+            }
+            kb = (unsigned)__builtin_amdgcn_readfirstlane((int)bst.key);
+            j0 = __builtin_amdgcn_readfirstlane(bst.pos);
+            db = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(bst.delta)));
+        }
+        ++it;
+    };
+
+    unsigned mine = own ? best_key<KQ, NT>(g, u, cn2, cinv, lam) : 0u;
+    unsigned kb;
+    int j0;
+    float db;
+    argmax(mine, kb, j0, db);
+
+    WRec* recs = s_rec[team];
+    int n = 0, nrec = 0;
+    bool conv = false, touch_l = false, touch_r = false;
+    int tlo = INT_MAX, thi = -1;  // own positions whose g changed
+
+    // at most kWaveRecs updates per run (the launcher checks the cap), so the
+    // halo records of a run always fit on chip
+    for (;;) {
+        // per iteration, so that the per-atom constants are read from LDS where
+        // they are used instead of being held in registers across the loop
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        if (key_value(kb) < eps_stop) {
+            conv = true;
+            break;
+        }
+        if (n == a.cap)
+            break;
+        const int k0 = 31 - (int)(kb & 31u);
+        if (k0 >= K) {  // a padded atom wins only when every candidate is 0
+            conv = true;
+            break;
+        }
+        const float delta = db;
+        const int wlo = j0 - (W - 1) > 0 ? j0 - (W - 1) : 0;
+        const int whi = j0 + (W - 1) < Lm - 1 ? j0 + (W - 1) : Lm - 1;
+        tlo = wlo < tlo ? wlo : tlo;
+        thi = whi > thi ? whi : thi;
+
+        if (tt == j0) {
+            // owner of the updated coordinate: new Z (exactly 0 when the soft
+            // threshold is active), in registers and in the double Z in HBM
+            float* up = reinterpret_cast<float*>(u + (k0 / 4) * NT) + (k0 % 4);
+            const float zo = *up;
+            const bool zr = fabsf(fmaf(cn2[k0 / 4][k0 % 4], zo, pick<0, KP, KQ>(g, k0))) <= lam;
+            *up = zr ? 0.0f : zo + delta;
+            double* zp = Zs + (int64_t)k0 * L + b + j0;
+            if (zr)
+                *zp = 0.0;
+            else
+                unsafeAtomicAdd(zp, (double)delta);  // single owner: deterministic
+            if (a.trace) {
+                const unsigned long long r = atomicAdd(&a.counters->trace_n, 1ull);
+                if ((long long)r < a.trace_cap) {
+                    dicod_trace_rec rec;
+                    rec.phase = a.phase;
+                    rec.seg = sid;
+                    rec.k0 = k0;
+                    rec.n_local = n;
+                    rec.t0 = (int64_t)b + j0;
+                    rec.delta = (double)delta;
+                    a.trace[r] = rec;
+                }
+            }
+        }
+        const bool to_l = j0 - (W - 1) < 0 && sd.left >= 0;
+        const bool to_r = j0 + (W - 1) >= Lm && sd.right >= 0;
+        if ((to_l || to_r) && tt == 0) {
+            WRec rc;
+            rc.k0 = k0;
+            rc.t0 = b + j0;
+            rc.delta = delta;
+            rc.pad = 0;
+            recs[nrec] = rc;
+        }
+        nrec += (to_l || to_r) ? 1 : 0;
+        touch_l |= to_l;
+        touch_r |= to_r;
+
+        // eq. (3) over the own positions of the window
+        const int dj = tt - j0 + (W - 1);
+        if (own && dj >= 0 && dj < nd) {
+            const f4* srow = reinterpret_cast<const f4*>(St + ((size_t)k0 * nd + dj) * KP);
+            f4 sv[KQ];
+#pragma unroll
+            for (int i = 0; i < KQ; ++i)
+                sv[i] = srow[i];
+#pragma unroll
+            for (int i = 0; i < KQ; ++i)
+                g[i] -= sv[i] * delta;
+            mine = best_key<KQ, NT>(g, u, cn2, cinv, lam);
+        }
+        ++n;
+        argmax(mine, kb, j0, db);
+    }
+
+    // own g of every position the run changed
+    if (own && tt >= tlo && tt <= thi) {
+        float* pg = gs + b + tt;
+#pragma unroll
+        for (int i = 0; i < KQ; ++i)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                if (4 * i + c < K)
+                    *pg = g[i][c];
+                pg += L;
+            }
+    }
+
+    // Halo records applied to the neighbours' state in HBM, each halo position
+    // by one thread, records in update order (every record is visible: the
+    // same wave wrote it, or the argmax barrier came after it).
+    if (nrec > 0) {
+        const int ext_lo = b - (W - 1) > 0 ? b - (W - 1) : 0;
+        const int ext_hi = sd.e + (W - 1) < sd.L ? sd.e + (W - 1) : (int)sd.L;
+        const int n_hl = b - ext_lo;
+        const int n_h = n_hl + (ext_hi - sd.e);
+#pragma unroll 1
+        for (int h = tt; h < n_h; h += NTT) {
+            const int t = h < n_hl ? ext_lo + h : sd.e + (h - n_hl);
+            bool touched = false;
+            f4 gh[KQ];
+#pragma unroll 1
+            for (int r = 0; r < nrec; ++r) {
+                const WRec rc = recs[r];
+                const int dh = t - rc.t0 + (W - 1);
+                if (dh < 0 || dh >= nd)
+                    continue;
+                if (!touched) {
+                    const float* pg = gs + t;
+#pragma unroll
+                    for (int i = 0; i < KQ; ++i)
+#pragma unroll
+                        for (int c = 0; c < 4; ++c) {
+                            const float v = *pg;
+                            gh[i][c] = 4 * i + c < K ? v : 0.0f;
+                            if (4 * i + c + 1 < K)
+                                pg += L;
+                        }
+                    touched = true;
+                }
+                const f4* srow = reinterpret_cast<const f4*>(St + ((size_t)rc.k0 * nd + dh) * KP);
+#pragma unroll
+                for (int i = 0; i < KQ; ++i)
+                    gh[i] -= srow[i] * rc.delta;
+            }
+            if (touched) {
+                float* pg = gs + t;
+#pragma unroll
+                for (int i = 0; i < KQ; ++i)
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) {
+                        if (4 * i + c < K)
+                            *pg = gh[i][c];
+                        pg += L;
+                    }
+            }
+        }
+    }
+
+    if (tt == 0) {
+        if (n > 0) {
+            atomicAdd(&a.phase_upd[(size_t)sd.sig * a.phase_stride + a.phase],
+                      (unsigned long long)n);
+            atomicAdd(&a.sig_upd[sd.sig], (unsigned long long)n);
+            atomicMax(&a.sig_last_upd[sd.sig], a.phase);
+            atomicAdd(&a.counters->seg_runs, 1ull);
+        }
+        a.dirty[sid] = conv ? 0u : 1u;
+        if (touch_l)
+            a.dirty[sd.left] = 1u;
+        if (touch_r)
+            a.dirty[sd.right] = 1u;
+    }
+}
+
+template <int KQ>
+hipError_t launch_kq(const PhaseArgs& a, hipStream_t s)
+{
+    if (a.lm_max <= 64) {
+        hipLaunchKernelGGL((k_lgcd_wave<KQ, 1>), dim3((unsigned)((a.n_list + 3) / 4)), dim3(256),
+                           0, s, a);
+    } else if (a.lm_max <= 128) {
+        hipLaunchKernelGGL((k_lgcd_wave<KQ, 2>), dim3((unsigned)a.n_list), dim3(128), 0, s, a);
+    } else {
+        hipLaunchKernelGGL((k_lgcd_wave<KQ, 4>), dim3((unsigned)a.n_list), dim3(256), 0, s, a);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+bool lgcd_wave_supported(int K, int lm_max, int cap, bool fp64)
+{
+    return !fp64 && lgcd_k_padded(K, false) > 0 && lgcd_k_padded(K, false) <= 32 &&
+           lm_max >= 1 && lm_max <= 256 && cap >= 1 && cap <= kWaveRecs;
+}
+
+hipError_t launch_lgcd_wave(const PhaseArgs& a, hipStream_t s)
+{
+    if (a.n_list <= 0)
+        return hipSuccess;
+    if (a.dicod || !lgcd_wave_supported(a.K, a.lm_max, a.cap, false))
+        return hipErrorInvalidValue;
+    switch (lgcd_k_padded(a.K, false) / 4) {
+    case 1: return launch_kq<1>(a, s);
+    case 2: return launch_kq<2>(a, s);
+    case 4: return launch_kq<4>(a, s);
+    case 7: return launch_kq<7>(a, s);
+    case 8: return launch_kq<8>(a, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace dicod

@@ -156,6 +156,40 @@ def test_paper_shaped_mixed_matches_oracle(dicod, paper_problem):
     _check_solution(X, D, lam, Z, st, Zo)
 
 
+def test_mixed_lambda_max_exact_when_bf16_ranking_is_wrong(dicod):
+    """X = 1e6 u + v with u in the null space of X -> D^T X (dimension T - L =
+    W - 1): the correlation of X is about that of v, but the split-bf16
+    rounding error scales with sum |d| |x| ~ 1e6, far above the gaps between
+    the largest entries, so a refinement window fixed relative to the
+    split-bf16 maximum misses the maximiser.  lambda_max must still equal the
+    double-precision maximum of D^T X (its definition, eq. (2))."""
+    rng = np.random.default_rng(21)
+    K, P, W, T = 1, 1, 16, 64
+    D = rng.standard_normal((K, P, W))
+    D /= np.linalg.norm(D)
+    D = D.astype(np.float32)
+    L = T - W + 1
+    C = np.zeros((L, T))
+    for t in range(L):
+        C[t, t:t + W] = f64(D[0, 0])
+    _, sv, Vt = np.linalg.svd(C)
+    u = Vt[-1]                                   # C u = 0
+    assert sv[-1] < 1e-12 * sv[0] or np.abs(C @ u).max() < 1e-12
+    X = (1e6 * u + rng.standard_normal(T)).astype(np.float32)[None, :]
+    B = oracle.correlate(f64(D), f64(X))
+    lmax = float(np.max(np.abs(B)))
+    scale = float(np.sum(np.abs(f64(X))) * np.abs(f64(D)).max())
+    with ctx_of(dicod, precision=dicod.DICOD_PREC_MIXED) as c:
+        c.set_dictionary(D)
+        Bm = c.correlate(X, precision=dicod.DICOD_PREC_MIXED)
+        _, st = c.solve(X, -0.1, EPS, n_seg=1)
+    print(f"lambda_max {lmax:.6f}; split-bf16 argmax {np.argmax(np.abs(Bm))} vs exact "
+          f"{np.argmax(np.abs(B))}; max error {np.abs(Bm - B).max():.3g}", flush=True)
+    gap = np.sort(np.abs(B).ravel())[-1] - np.sort(np.abs(B).ravel())[-2]
+    assert np.abs(Bm - B).max() > max(1e-3 * lmax, gap)     # split-bf16 cannot rank
+    assert abs(st["lambda_max"] - lmax) <= 1e-13 * scale
+
+
 # ------------------------------------------------ FP32 policy: eps-solutions
 
 def _check_solution(X, D, lam, Z, st, Zo):
@@ -189,7 +223,7 @@ def test_paper_shaped_fp32_matches_oracle(dicod, paper_problem):
         Z, st = c.solve(X, -0.1, EPS, n_seg=0, D=D)
     print(f"gpu: {st['n_updates']} updates, {st['n_phases']} phases, M={st['n_seg']}, "
           f"refresh={st['n_refresh']}, cd={st['t_cd_ms']:.2f} ms", flush=True)
-    assert st["n_seg"] == 749
+    assert st["n_seg"] == 752   # floor(L / (W - 1)) for 3 colours
     _check_solution(X, D, lam, Z, st, Zo)
     # phases queued past a round's convergence apply nothing and are not
     # counted: n_phases is the rounds' phases plus at most C - 1 alignment
@@ -356,8 +390,13 @@ def test_device_api_equals_host_api(dicod):
     assert sd["n_updates"] == sh["n_updates"]
 
 
-def test_batch_equals_solo_bitwise(dicod):
+@pytest.mark.parametrize("polish", [1, 0, 2])
+def test_batch_equals_solo_bitwise(dicod, polish):
+    """A batched solve equals the solo solves element by element for every
+    polish policy (a signal whose stop test held is frozen while the others
+    continue), and every signal is an eps-solution of the oracle's problem."""
     import torch
+    print(f"\ncase: batch vs solo polish={polish}", flush=True)
     P, K, W = 7, 25, 64
     lens = [12_000, 3_001, 20_500, 9_999]
     _, D, _ = synth.generate(P, K, W, 4 * W, 0.005, 0.1, seed=11)
@@ -366,7 +405,7 @@ def test_batch_equals_solo_bitwise(dicod):
     Ls = [T - W + 1 for T in lens]
     x_off = np.cumsum([0] + [P * T for T in lens[:-1]])
     z_off = np.cumsum([0] + [K * L for L in Ls[:-1]])
-    with ctx_of(dicod) as c:
+    with ctx_of(dicod, fp64_polish_after=polish) as c:
         c.set_dictionary(D)
         solo = []
         for X in sigs:
@@ -383,6 +422,11 @@ def test_batch_equals_solo_bitwise(dicod):
         assert np.array_equal(Zb, Zs), f"signal {i} differs between batch and solo"
         assert sts[i]["n_updates"] == st["n_updates"]
         assert sts[i]["converged"] == 1
+        X = sigs[i]
+        lam = 0.1 * oracle.lambda_max(f64(X), f64(D))
+        assert abs(sts[i]["lambda"] - lam) <= 1e-12 * lam
+        Zo, _, _ = oracle.lgcd(f64(X), f64(D), lam, 1e-10, max(1, Ls[i] // 400))
+        _check_solution(X, D, lam, Zb, sts[i], Zo)
 
 
 # ------------------------------------------- long signal: sampled oracle checks
@@ -421,6 +465,28 @@ def test_long_signal_sampled_against_oracle(dicod):
     dz = np.abs(zp - Z[k, t])
     print(f"sampled max |Delta Z| {dz.max():.3g} over {dz.size} coordinates", flush=True)
     assert dz.max() < EPS
+    # every coordinate within W - 1 of 200 segment edges (where the halo
+    # records of boundary updates act; segments b_m = floor(m L / M)): beta
+    # from its definition on a local problem covering Z on [e - 2W + 2,
+    # e + 2W - 2), which is exact on [e - W + 1, e + W - 1)
+    W = w.W
+    M = st["n_seg"]
+    edges = (np.sort(rng.choice(np.arange(1, M), size=200, replace=False)).astype(np.int64)
+             * L) // M
+    worst = 0.0
+    n_chk = 0
+    for e in edges:
+        s0, s1 = e - 2 * W + 2, e + 2 * W - 2
+        if s0 < 0 or s1 > L:
+            continue
+        Bl = oracle.beta(f64(X[:, s0:s1 + W - 1]), f64(D), Z[:, s0:s1])
+        Bl = Bl[:, W - 1:3 * W - 3]
+        Zl = Z[:, e - W + 1:e + W - 1]
+        zp = np.sign(Bl) * np.maximum(np.abs(Bl) - lam, 0.0) / n2[:, None]
+        worst = max(worst, float(np.abs(zp - Zl).max()))
+        n_chk += Zl.size
+    print(f"edge bands: max |Delta Z| {worst:.3g} over {n_chk} coordinates", flush=True)
+    assert n_chk > 150 * K * (2 * W - 2) and worst < EPS
     obj = oracle.objective(f64(X), f64(D), Z, lam)
     assert abs(obj - st["objective"]) <= 1e-10 * abs(obj)
 
@@ -500,7 +566,7 @@ def test_dicod_schedule_fp32_paper_shaped(dicod, paper_problem):
         Z, st = c.solve(X, -0.1, EPS, n_seg=0, D=D)
     print(f"gpu: {st['n_updates']} updates, {st['n_phases']} phases, M={st['n_seg']}, "
           f"rounds {st['round_updates']}, cd {st['t_cd_ms']:.2f} ms", flush=True)
-    assert st["n_seg"] == 749
+    assert st["n_seg"] == 752   # floor(L / (W - 1)) for 3 colours
     _check_solution(X, D, lam, Z, st, Zo)
 
 

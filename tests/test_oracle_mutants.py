@@ -30,6 +30,9 @@ MUTANTS = [
     ("no_norm_division",
      "double zp = oracle_soft_threshold(s->beta[i], s->lam) / s->n2[k];",
      "double zp = oracle_soft_threshold(s->beta[i], s->lam);"),
+    ("no_norm_division_in_stop_test",
+     "double zp = oracle_soft_threshold(beta[(int64_t)k * L + t], lam) / n2[k];",
+     "double zp = oracle_soft_threshold(beta[(int64_t)k * L + t], lam);"),
     ("threshold_dropped",
      "double a = fabs(u) - lam;",
      "double a = fabs(u);"),
@@ -73,6 +76,8 @@ def _pins():
         lambda: [pins.test_golden_two_coordinate_lasso(r) for r in rows],
         lambda: pins.test_tiny_brute_force_explicit_toeplitz_lasso(0),
         lambda: pins.test_kkt_conditions_at_solution(),
+        lambda: pins.test_scaled_atoms_explicit_toeplitz_lasso(0),
+        lambda: pins.test_max_dz_matches_definition_scaled_atoms(),
         lambda: pins.test_dicod_schedule_cost_identity(1, 4, 3),
         lambda: pins.test_dicod_schedule_interferes_and_converges(),
     ]

@@ -282,6 +282,52 @@ def test_tiny_brute_force_explicit_toeplitz_lasso(seed):
     assert abs(oracle.objective(X, D, Z, lam) - Ef) <= 1e-10 * Ef
 
 
+def scaled_atoms(D, seed, lo=0.3, hi=3.0):
+    """The atoms of D rescaled to norms drawn uniformly in [lo, hi], so that the
+    division by |D_k|^2 of eq. (pb_coord) is not a division by 1."""
+    rng = np.random.default_rng(seed)
+    nrm = rng.uniform(lo, hi, size=D.shape[0])
+    return D / np.sqrt(np.sum(D * D, axis=(1, 2), keepdims=True)) * nrm[:, None, None]
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_scaled_atoms_explicit_toeplitz_lasso(seed):
+    # Atoms of norms in [0.3, 3]: the Lasso of Sec. 2.1 solved by FISTA on the
+    # explicit design, and the KKT conditions (Theorem A.1) written from the
+    # subgradient of eq. (2) with A^T (x - A z) recomputed from the design.
+    X, D, _ = tiny_problem(seed + 10, P=2, K=3, W=6, T=48, rho=0.1)
+    D = scaled_atoms(D, seed)
+    assert np.ptp(np.sqrt(np.sum(D * D, axis=(1, 2)))) > 0.5
+    lam = 0.2 * oracle.lambda_max(X, D)
+    A = _toeplitz_design(D, X.shape[1])
+    zf = _fista(A, X.reshape(-1), lam, n_iter=200000).reshape(D.shape[0], -1)
+    Z, st, _ = oracle.lgcd(X, D, lam, 1e-12, 3)
+    assert st["converged"] == 1
+    np.testing.assert_allclose(Z, zf, atol=1e-7)
+    c = (A.T @ (X.reshape(-1) - A @ Z.reshape(-1))).reshape(Z.shape)  # -grad of the quadratic
+    on = Z != 0
+    n2 = np.sum(D * D, axis=(1, 2))[:, None] * np.ones_like(Z)
+    assert np.all(np.abs(c[on] - lam * np.sign(Z[on])) <= 1e-9 * n2[on] + 1e-9)
+    assert np.all(np.abs(c[~on]) <= lam + 1e-9 * n2[~on] + 1e-9)
+
+
+def test_max_dz_matches_definition_scaled_atoms():
+    # The stop test of Sec. 2.1 / Algorithm 3: max over all coordinates of
+    # |Sh(beta, lambda) / |D_k|^2 - Z|, with beta from its definition (the
+    # replacement operator), at an arbitrary Z and atoms of unequal norms.
+    X, D, Zt = tiny_problem(12, P=2, K=3, W=5, T=30, rho=0.3)
+    D = scaled_atoms(D, 4)
+    rng = np.random.default_rng(5)
+    Z = 0.3 * Zt + 0.01 * rng.standard_normal(Zt.shape)
+    lam = 0.15 * oracle.lambda_max(X, D)
+    B = _beta_by_definition(X, D, Z)
+    n2 = np.array([np.sum(D[k] ** 2) for k in range(D.shape[0])])
+    dz = np.abs(np.sign(B) * np.maximum(np.abs(B) - lam, 0.0) / n2[:, None] - Z)
+    v, k, t = oracle.max_dz(X, D, Z, lam)
+    assert abs(v - dz.max()) <= 1e-12 * max(1.0, dz.max())
+    assert dz[k, t] == dz.max()
+
+
 def test_kkt_conditions_at_solution():
     # Coordinate-wise optimality (Theorem A.1) in terms of
     # g = beta - |D_k|^2 Z: |g - lambda sign z| <= |D|^2 eps on the support,
