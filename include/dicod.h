@@ -223,6 +223,25 @@ int dicod_solve_device(dicod_ctx *ctx, const float *X_dev, int64_t T, double lam
                        double eps, int n_seg, double *Z_dev, dicod_stats *st,
                        void *stream);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): dicod_solve_device with
+ * every device workspace buffer of the solve carved from a static device
+ * array of 128 MiB (one per GPU, held until the process ends) instead of
+ * being allocated; the pinned host staging and the events come from
+ * dicod_init.  It calls no hipMalloc, hipFree, hipHostMalloc or other
+ * allocating routine (the host plan of the segments uses ordinary heap
+ * vectors of O(M) bytes).  Arguments, results and errors as
+ * dicod_solve_device, plus EINVAL when the problem needs more scratch than the
+ * array holds (about 21 bytes per coefficient K * L in the FP32 policy, i.e.
+ * up to about 6 M coefficients; the message gives the bytes needed), and
+ * EINVAL with timing = 1.  Every call on a GPU shares that GPU's array and
+ * leaves its contents behind; a call initialises everything it reads, but
+ * calls that overlap on one GPU (from any context or thread) race and must be
+ * serialised by the caller. */
+int dicod_solve_device_noalloc(dicod_ctx *ctx, const float *X_dev, int64_t T, double lambda,
+                               double eps, int n_seg, double *Z_dev, dicod_stats *st,
+                               void *stream);
+
 /* Solves n_sig independent signals of different lengths against the resident
  * dictionary in one set of launches: their segments are packed into the same
  * phases (batching).

@@ -136,6 +136,7 @@ def lib():
     L.dicod_set_dictionary.argtypes = [_vp, _vp, ci, ci, ci]
     L.dicod_solve.argtypes = [_vp, _vp, ci, i64, _vp, ci, ci, cd, cd, ci, _vp, ps]
     L.dicod_solve_device.argtypes = [_vp, _vp, i64, cd, cd, ci, _vp, ps, _vp]
+    L.dicod_solve_device_noalloc.argtypes = [_vp, _vp, i64, cd, cd, ci, _vp, ps, _vp]
     L.dicod_solve_batch_device.argtypes = [_vp, ci, _vp, _vp, _vp, _vp, cd, _vp, _vp,
                                            _vp, _vp, _vp]
     L.dicod_correlate.argtypes = [_vp, _vp, i64, ci, _vp]
@@ -144,7 +145,7 @@ def lib():
     L.dicod_submit.argtypes = [_vp, _vp, i64, cd, cd, ci, ctypes.POINTER(ctypes.c_uint64)]
     L.dicod_poll.argtypes = [_vp, ctypes.c_uint64, _vp, ps]
     for name in ("dicod_config_init", "dicod_init", "dicod_set_dictionary", "dicod_solve",
-                 "dicod_solve_device", "dicod_solve_batch_device", "dicod_correlate",
+                 "dicod_solve_device", "dicod_solve_device_noalloc", "dicod_solve_batch_device", "dicod_correlate",
                  "dicod_get_s_table", "dicod_get_trace", "dicod_submit", "dicod_poll"):
         getattr(L, name).restype = ci
     _lib = L
@@ -236,6 +237,21 @@ def dicod_solve_device(ctx, X_dev, lam, eps, n_seg=0, Z_dev=None, K=None, W=None
     rc = lib().dicod_solve_device(ctx, _vp(X_dev.data_ptr()), T, float(lam), float(eps),
                                   int(n_seg), _vp(Z_dev.data_ptr()), ctypes.byref(st),
                                   _vp(s))
+    if check:
+        _check(ctx, rc)
+    return Z_dev, st.to_dict(), rc
+
+
+def dicod_solve_device_noalloc(ctx, X_dev, lam, eps, n_seg, Z_dev, stream=None, check=True):
+    """As dicod_solve_device with the workspace in the library's static device
+    scratch (no allocation); Z_dev must be given.  Returns (Z_dev, stats, rc)."""
+    assert X_dev.is_cuda and X_dev.dtype == torch.float32 and X_dev.is_contiguous()
+    assert Z_dev.is_cuda and Z_dev.dtype == torch.float64 and Z_dev.is_contiguous()
+    st = dicod_stats()
+    s = stream if stream is not None else torch.cuda.current_stream(X_dev.device).cuda_stream
+    rc = lib().dicod_solve_device_noalloc(ctx, _vp(X_dev.data_ptr()), X_dev.shape[1],
+                                          float(lam), float(eps), int(n_seg),
+                                          _vp(Z_dev.data_ptr()), ctypes.byref(st), _vp(s))
     if check:
         _check(ctx, rc)
     return Z_dev, st.to_dict(), rc
@@ -343,6 +359,9 @@ class Context:
     def solve_device(self, X_dev, lam, eps, n_seg=0, Z_dev=None, stream=None, check=True):
         return dicod_solve_device(self.h, X_dev, lam, eps, n_seg, Z_dev, self.K, self.W,
                                   stream, check)
+
+    def solve_device_noalloc(self, X_dev, lam, eps, n_seg, Z_dev, stream=None, check=True):
+        return dicod_solve_device_noalloc(self.h, X_dev, lam, eps, n_seg, Z_dev, stream, check)
 
     def solve_batch_device(self, X_dev, T, x_off, lam, eps, n_seg, Z_dev, z_off, stream=None):
         return dicod_solve_batch_device(self.h, X_dev, T, x_off, lam, eps, n_seg, Z_dev,

@@ -34,22 +34,51 @@ thread_local std::string g_init_error;
 struct DevBuf {
     void* p = nullptr;
     size_t n = 0;
+    bool owned = true;  // false: a view into the static scratch (never freed)
     ~DevBuf() { release(); }
     void release()
     {
-        if (p)
+        if (p && owned)
             (void)hipFree(p);
         p = nullptr;
         n = 0;
+        owned = true;
     }
     template <typename T>
     T* as() const { return static_cast<T*>(p); }
 };
 
+// The allocation-free solve (dicod_solve_device_noalloc) sets t_arena: every
+// workspace buffer is then carved, 256-byte aligned, from the static device
+// scratch instead of being allocated; a request beyond its size fails and
+// records how much the problem needs.
+struct Arena {
+    unsigned char* base = nullptr;
+    size_t cap = 0, off = 0, need = 0;
+    bool overflow = false;
+};
+thread_local Arena* t_arena = nullptr;
+
 hipError_t ensure(DevBuf& b, size_t bytes)
 {
     if (bytes == 0)
         bytes = 16;
+    if (t_arena) {
+        if (!b.owned && b.p && b.n >= bytes)
+            return hipSuccess;  // carved earlier in this call
+        const size_t off = (t_arena->off + 255) & ~(size_t)255;
+        if (off + bytes > t_arena->cap) {
+            t_arena->overflow = true;
+            t_arena->need = std::max(t_arena->need, off + bytes);
+            return hipErrorOutOfMemory;
+        }
+        b.release();
+        b.p = t_arena->base + off;
+        b.n = bytes;
+        b.owned = false;
+        t_arena->off = off + bytes;
+        return hipSuccess;
+    }
     if (b.n >= bytes)
         return hipSuccess;
     b.release();
@@ -95,6 +124,8 @@ struct dicod_ctx {
     DevBuf Sc64;        // S with rows padded to 2W doubles, for the double check
     DevBuf Dsp;         // bf16 hi/lo split of D for the MIXED correlation
     Workspace ws;
+    Workspace ws_scratch;                 // views into the static scratch (noalloc solve)
+    void* scratch = nullptr;              // device address of the static scratch
     unsigned long long* h_upd = nullptr;  // pinned copy of per-phase counts
     size_t h_upd_cap = 0;
     hipEvent_t ev_poll[2] = {nullptr, nullptr};  // queued chunks of phases
@@ -130,6 +161,32 @@ int fail(dicod_ctx* ctx, int code, const char* fmt, ...)
     } while (0)
 
 int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Offsets in the pinned staging of a solve of n_sig signals: uploads
+// (done flags at 0, lambda inputs, descriptors), then read-backs (check
+// results, final statistics).
+struct PinLayout {
+    size_t lam, sig, res, supd, slast, lbits, cnt, need;
+};
+
+PinLayout pin_layout(int n_sig)
+{
+    auto al256 = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    PinLayout l;
+    l.lam = al256((size_t)n_sig * sizeof(uint32_t));
+    l.sig = l.lam + al256((size_t)n_sig * sizeof(double));
+    l.res = l.sig + al256((size_t)n_sig * sizeof(SigDesc));
+    l.supd = l.res + al256((size_t)n_sig * sizeof(CheckResult));
+    l.slast = l.supd + al256((size_t)n_sig * sizeof(unsigned long long));
+    l.lbits = l.slast + al256((size_t)n_sig * sizeof(int));
+    l.cnt = l.lbits + al256((size_t)n_sig * sizeof(unsigned long long));
+    l.need = l.cnt + sizeof(Counters);
+    return l;
+}
+
+size_t pinned_bytes(int n_sig) { return pin_layout(n_sig).need; }
+
+hipEvent_t pool_event(dicod_ctx* ctx, size_t i);
 
 double elapsed_ms(hipEvent_t a, hipEvent_t b)
 {
@@ -246,6 +303,27 @@ extern "C" int dicod_init(dicod_ctx** out, const dicod_config* cfg)
     if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, c.device) ==
             hipSuccess && n_cu > 0)
         ctx->n_cu = n_cu;
+    // set-up of the allocation-free solve: the static scratch's address on this
+    // device, pinned staging for one signal and the phase counts, and the
+    // events of one solve
+    if (dicod::scratch_address(c.device, &ctx->scratch) != hipSuccess || !ctx->scratch) {
+        dicod_finalize(ctx);
+        return fail(nullptr, DICOD_EDEVICE, "dicod_init: no address for the static scratch");
+    }
+    const size_t n_upd = (size_t)std::min<int64_t>(c.max_phases, (int64_t)1 << 22) + 1;
+    if (hipHostMalloc((void**)&ctx->h_upd, n_upd * sizeof(unsigned long long),
+                      hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&ctx->h_pin, pinned_bytes(1), hipHostMallocDefault) != hipSuccess) {
+        dicod_finalize(ctx);
+        return fail(nullptr, DICOD_ENOMEM, "dicod_init: pinned staging");
+    }
+    ctx->h_upd_cap = n_upd;
+    ctx->h_pin_cap = pinned_bytes(1);
+    for (size_t i = 0; i < 4; ++i)
+        if (!pool_event(ctx, i)) {
+            dicod_finalize(ctx);
+            return fail(nullptr, DICOD_EDEVICE, "dicod_init: event creation failed");
+        }
     *out = ctx;
     return DICOD_OK;
 }
@@ -593,7 +671,7 @@ int solve_device_batch(dicod_ctx* ctx, int n_sig, const float* dX, const int64_t
     const int K = ctx->K, P = ctx->P, W = ctx->W;
     const bool fp64 = ctx->cfg.precision == DICOD_PREC_FP64;
     const dicod_config& cfg = ctx->cfg;
-    Workspace& ws = ctx->ws;
+    Workspace& ws = t_arena ? ctx->ws_scratch : ctx->ws;
 
     Plan pl;
     int rc = make_plan(ctx, n_sig, T, x_off, lam_in, n_seg, z_off, pl);
@@ -624,19 +702,37 @@ int solve_device_batch(dicod_ctx* ctx, int n_sig, const float* dX, const int64_t
     HIPCHECK(ctx, ensure(ws.done, n_sig * sizeof(uint32_t)));
     if (cfg.trace_capacity > 0)
         HIPCHECK(ctx, ensure(ws.trace, cfg.trace_capacity * sizeof(dicod_trace_rec)));
+    if (t_arena) {
+        // everything a solve may need is carved before the first launch, so a
+        // problem too large for the scratch fails before any work is queued
+        if (!fp64 && cfg.fp64_polish_after > 0)
+            HIPCHECK(ctx, ensure(ws.g64, pl.zext * sizeof(double)));
+        if (ctx->cfg.precision == DICOD_PREC_MIXED) {
+            HIPCHECK(ctx, ensure(ws.ebits, n_sig * sizeof(unsigned long long)));
+            HIPCHECK(ctx, ensure(ws.thr, n_sig * sizeof(double)));
+        }
+        HIPCHECK(ctx, ensure(ws.sig, (size_t)n_sig * sizeof(SigDesc)));
+        HIPCHECK(ctx, ensure(ws.segs, pl.segs.size() * sizeof(SegDesc)));
+        for (int c = 0; c < pl.colors; ++c)
+            HIPCHECK(ctx, ensure(ws.lists[c], pl.list[c].size() * sizeof(int32_t)));
+        HIPCHECK(ctx, ensure(ws.tilesL, pl.prefL.size() * sizeof(int64_t)));
+        HIPCHECK(ctx, ensure(ws.tilesC, pl.prefC.size() * sizeof(int64_t)));
+        HIPCHECK(ctx, ensure(ws.tilesA, pl.prefA.size() * sizeof(int64_t)));
+        HIPCHECK(ctx, ensure(ws.tilesN, pl.prefN.size() * sizeof(int64_t)));
+        HIPCHECK(ctx, ensure(ws.slots, (size_t)n_sig * sizeof(int)));
+        HIPCHECK(ctx, ensure(ws.lamin, (size_t)n_sig * sizeof(double)));
+    }
     // pinned staging of the per-round uploads (descriptors, done flags): the
     // copies then leave the host at once; every use is separated from the next
     // by a synchronisation of the stream (the double check)
-    const size_t pin_lam = ((size_t)n_sig * sizeof(uint32_t) + 255) & ~(size_t)255;
-    const size_t pin_sig = pin_lam + (((size_t)n_sig * sizeof(double) + 255) & ~(size_t)255);
-    auto al256 = [](size_t x) { return (x + 255) & ~(size_t)255; };
-    // read-backs: check results, then the final statistics
-    const size_t pin_res = pin_sig + al256((size_t)n_sig * sizeof(SigDesc));
-    const size_t pin_supd = pin_res + al256((size_t)n_sig * sizeof(CheckResult));
-    const size_t pin_slast = pin_supd + al256((size_t)n_sig * sizeof(unsigned long long));
-    const size_t pin_lbits = pin_slast + al256((size_t)n_sig * sizeof(int));
-    const size_t pin_cnt = pin_lbits + al256((size_t)n_sig * sizeof(unsigned long long));
-    const size_t pin_need = pin_cnt + sizeof(Counters);
+    const PinLayout pin = pin_layout(n_sig);
+    const size_t pin_lam = pin.lam, pin_sig = pin.sig, pin_res = pin.res, pin_supd = pin.supd;
+    const size_t pin_slast = pin.slast, pin_lbits = pin.lbits, pin_cnt = pin.cnt;
+    const size_t pin_need = pin.need;
+    const bool no_alloc = t_arena != nullptr;
+    if (no_alloc && (pin_need > ctx->h_pin_cap || (size_t)(max_ph + 1) > ctx->h_upd_cap))
+        return fail(ctx, DICOD_EINVAL, "pinned staging of the context is too small for this "
+                                       "solve (one signal, max_phases of the configuration)");
     if (pin_need > ctx->h_pin_cap) {
         if (ctx->h_pin)
             (void)hipHostFree(ctx->h_pin);
@@ -1180,6 +1276,37 @@ extern "C" int dicod_solve_device(dicod_ctx* ctx, const float* X_dev, int64_t T,
     const int64_t zero = 0;
     return solve_device_batch(ctx, 1, X_dev, &T, &zero, &lambda, eps, &n_seg, Z_dev, &zero,
                               st, stream ? (hipStream_t)stream : ctx->stream);
+}
+
+extern "C" int dicod_solve_device_noalloc(dicod_ctx* ctx, const float* X_dev, int64_t T,
+                                          double lambda, double eps, int n_seg, double* Z_dev,
+                                          dicod_stats* st, void* stream)
+{
+    if (!ctx)
+        return DICOD_EINVAL;
+    ctx->err.clear();
+    if (!ctx->scratch)
+        return fail(ctx, DICOD_EDEVICE, "dicod_solve_device_noalloc: no static scratch");
+    if (ctx->cfg.timing)
+        return fail(ctx, DICOD_EINVAL, "dicod_solve_device_noalloc: timing = 1 needs events "
+                                       "per launch; not available without allocation");
+    HIPCHECK(ctx, hipSetDevice(ctx->cfg.device));
+    // the views of the previous call are stale: this call lays the scratch out
+    // for its own problem, and uploads nothing from the plan cache
+    ctx->ws_scratch = Workspace();
+    Arena ar;
+    ar.base = static_cast<unsigned char*>(ctx->scratch);
+    ar.cap = dicod::scratch_bytes();
+    t_arena = &ar;
+    const int64_t zero = 0;
+    int rc = solve_device_batch(ctx, 1, X_dev, &T, &zero, &lambda, eps, &n_seg, Z_dev, &zero,
+                                st, stream ? (hipStream_t)stream : ctx->stream);
+    t_arena = nullptr;
+    if (ar.overflow)
+        rc = fail(ctx, DICOD_EINVAL,
+                  "dicod_solve_device_noalloc: this problem needs %zu bytes of scratch; the "
+                  "static scratch holds %zu bytes (use dicod_solve_device)", ar.need, ar.cap);
+    return rc;
 }
 
 extern "C" int dicod_solve_batch_device(dicod_ctx* ctx, int n_sig, const float* X_dev,

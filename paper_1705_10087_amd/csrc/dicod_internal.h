@@ -69,6 +69,12 @@ struct Counters {
     unsigned long long trace_n;    // trace records requested
 };
 
+// Static device scratch of dicod_solve_device_noalloc (noalloc.hip): its size,
+// and its device address on `device` (which must be the current device),
+// looked up once per device with hipGetSymbolAddress.
+size_t scratch_bytes();
+hipError_t scratch_address(int device, void** out);
+
 // ---- launchers (kernels.hip) ------------------------------------------------
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, size_t n,
