@@ -99,6 +99,7 @@ struct Workspace {
     DevBuf dirty, phase_upd, sig_upd, sig_last, counters;
     DevBuf part, results, lmax, done, thr, ebits;
     DevBuf msg, msg_n;                    // DICOD schedule: boundary messages
+    DevBuf box, box_n, z32;               // register kernel: mailboxes, float copy of Z
     DevBuf trace;
     DevBuf slots, lamin;                  // device-side lambda: signal indices, inputs
     // host copies of what the read-only plan tables hold on the device: an
@@ -683,8 +684,18 @@ int solve_device_batch(dicod_ctx* ctx, int n_sig, const float* dX, const int64_t
     const int n_kblk = check_kblocks(K, W);
     const int64_t max_ph = std::min<int64_t>(cfg.max_phases, (int64_t)1 << 22);
 
+    // float rounds on the register-state kernel when the segments allow it
+    const int cap_eff = effective_update_cap(cfg.update_cap, W);
+    const bool reg_ok = !fp64 && cfg.reg_state != 0 && !pl.dicod &&
+                        lgcd_wave_supported(K, pl.lm_max, cap_eff, false);
+    const int box_cap = reg_ok ? std::max(cap_eff, 1) : 0;
     HIPCHECK(ctx, ensure(ws.beta0, pl.zext * sizeof(double)));
     HIPCHECK(ctx, ensure(ws.g, pl.zext * (fp64 ? sizeof(double) : sizeof(float))));
+    if (reg_ok) {
+        HIPCHECK(ctx, ensure(ws.box, (size_t)2 * n_seg_tot * box_cap * sizeof(BoundaryRec)));
+        HIPCHECK(ctx, ensure(ws.box_n, (size_t)2 * n_seg_tot * sizeof(uint32_t)));
+        HIPCHECK(ctx, ensure(ws.z32, pl.zext * sizeof(float)));
+    }
     HIPCHECK(ctx, ensure(ws.dirty, (pl.dicod ? 2 : 1) * n_seg_tot * sizeof(uint32_t)));
     const int msg_cap = pl.dicod ? effective_update_cap(cfg.update_cap, W) : 0;
     if (pl.dicod) {
@@ -722,6 +733,7 @@ int solve_device_batch(dicod_ctx* ctx, int n_sig, const float* dX, const int64_t
         HIPCHECK(ctx, ensure(ws.slots, (size_t)n_sig * sizeof(int)));
         HIPCHECK(ctx, ensure(ws.lamin, (size_t)n_sig * sizeof(double)));
     }
+    (void)box_cap;
     // pinned staging of the per-round uploads (descriptors, done flags): the
     // copies then leave the host at once; every use is separated from the next
     // by a synchronisation of the stream (the double check)
@@ -817,6 +829,9 @@ int solve_device_batch(dicod_ctx* ctx, int n_sig, const float* dX, const int64_t
                 continue;
             }
             HIPCHECK(ctx, launch_fill_f64(dZ + lo, 0.0, (size_t)(hi - lo), s));
+            if (reg_ok)  // float 0.0 is the all-zero word
+                HIPCHECK(ctx, launch_fill_u32(ws.z32.as<uint32_t>() + lo, 0u,
+                                              (size_t)(hi - lo), s));
             if (i < n_sig) {
                 lo = zr[i].first;
                 hi = zr[i].second;
@@ -824,6 +839,8 @@ int solve_device_batch(dicod_ctx* ctx, int n_sig, const float* dX, const int64_t
         }
     }
     HIPCHECK(ctx, launch_fill_u32(ws.dirty.as<uint32_t>(), 1u, n_seg_tot, s));
+    if (reg_ok)
+        HIPCHECK(ctx, launch_fill_u32(ws.box_n.as<uint32_t>(), 0u, (size_t)2 * n_seg_tot, s));
     if (pl.dicod) {
         HIPCHECK(ctx, launch_fill_u32(ws.dirty.as<uint32_t>() + n_seg_tot, 0u, n_seg_tot, s));
         HIPCHECK(ctx, launch_fill_u32(ws.msg_n.as<uint32_t>(), 0u, (size_t)4 * n_seg_tot, s));
@@ -912,10 +929,6 @@ int solve_device_batch(dicod_ctx* ctx, int n_sig, const float* dX, const int64_t
         return fail(ctx, DICOD_ENOTSUP, "segments do not fit any phase kernel");
     if (pl.dicod && !in_lds)
         return fail(ctx, DICOD_ENOTSUP, "the DICOD schedule needs segments whose state fits LDS");
-    // float rounds on the register-state kernel when the segments allow it
-    const bool reg_ok = cfg.reg_state != 0 && !pl.dicod &&
-                        lgcd_wave_supported(K, pl.lm_max,
-                                            effective_update_cap(cfg.update_cap, W), false);
     bool polished = false, any_hbm = !in_lds && (cur64 || !reg_ok);
 
     PhaseArgs a;
@@ -942,6 +955,10 @@ int solve_device_batch(dicod_ctx* ctx, int n_sig, const float* dX, const int64_t
     a.msg_cap = msg_cap;
     a.msg = pl.dicod ? ws.msg.as<DicodMsg>() : nullptr;
     a.msg_n = pl.dicod ? ws.msg_n.as<uint32_t>() : nullptr;
+    a.box = reg_ok ? ws.box.as<BoundaryRec>() : nullptr;
+    a.box_n = reg_ok ? ws.box_n.as<uint32_t>() : nullptr;
+    a.box_cap = box_cap;
+    a.z32 = reg_ok ? ws.z32.as<float>() : nullptr;
     a.phase_stride = 0;
     auto set_state = [&](bool use64, bool lds) {
         a.g = use64 && !fp64 ? ws.g64.p : ws.g.p;
@@ -1120,7 +1137,9 @@ int solve_device_batch(dicod_ctx* ctx, int n_sig, const float* dX, const int64_t
                                         ws.sig.as<SigDesc>(), ws.tilesC.as<int64_t>(), n_sig, nC,
                                         flag_eps, ws.done.as<uint32_t>(),
                                         ws.dirty.as<uint32_t>(), g_in ? nullptr : g_next, next64,
-                                        g_in, ws.part.as<double>(), s));
+                                        g_in, ws.part.as<double>(),
+                                        reg_ok && !next64 && !g_in ? ws.z32.as<float>() : nullptr,
+                                        s));
         HIPCHECK(ctx, launch_check_reduce(ws.part.as<double>(), ws.tilesC.as<int64_t>(), nC,
                                           n_kblk, n_sig, ws.results.as<CheckResult>(), s));
         HIPCHECK(ctx, hipMemcpyAsync(ctx->h_pin + pin_res, ws.results.p,
@@ -1157,6 +1176,8 @@ int solve_device_batch(dicod_ctx* ctx, int n_sig, const float* dX, const int64_t
         HIPCHECK(ctx, launch_clear_done_dirty(ws.segs.as<SegDesc>(), n_seg_tot,
                                               ws.done.as<uint32_t>(), ws.dirty.as<uint32_t>(),
                                               s));
+        if (reg_ok)  // records of the last round are stale: g was refreshed
+            HIPCHECK(ctx, launch_fill_u32(ws.box_n.as<uint32_t>(), 0u, (size_t)2 * n_seg_tot, s));
         while (phase % pl.colors)
             ++phase;
         if (pl.dicod) {
@@ -1188,6 +1209,9 @@ int solve_device_batch(dicod_ctx* ctx, int n_sig, const float* dX, const int64_t
     if (any_rel)
         std::memcpy(lbits.data(), ctx->h_pin + pin_lbits, n_sig * sizeof(unsigned long long));
     ctx->last_trace_n = (int64_t)cnt.trace_n;
+    if (cnt.box_overflow)
+        return fail(ctx, DICOD_EDEVICE, "internal: %llu boundary records found a full mailbox",
+                    (unsigned long long)cnt.box_overflow);
     for (int i = 0; any_rel && i < n_sig; ++i) {
         // the arithmetic of k_apply_lambda
         double v;

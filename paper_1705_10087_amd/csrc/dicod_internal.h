@@ -67,6 +67,19 @@ struct CheckResult {
 struct Counters {
     unsigned long long seg_runs;   // segment runs that made at least one update
     unsigned long long trace_n;    // trace records requested
+    unsigned long long box_overflow;  // boundary records that found a full mailbox
+    unsigned long long pad;
+};
+
+// A boundary update of the coloured schedule with mailboxes (register-state
+// kernel): the update (k0, t0, delta) of a segment whose window reaches a
+// neighbour, applied by that neighbour when it next runs (the message of
+// Algorithm 2, delivered before the receiver's next run).
+struct BoundaryRec {
+    int32_t k0;
+    int32_t t0;     // position in the signal
+    float delta;
+    int32_t pad;
 };
 
 // Static device scratch of dicod_solve_device_noalloc (noalloc.hip): its size,
@@ -150,6 +163,14 @@ struct PhaseArgs {
     int msg_cap;            // messages per box (>= cap)
     DicodMsg* msg;          // [2 parity][n_seg][2: 0 leftwards, 1 rightwards][msg_cap]
     uint32_t* msg_n;        // [2 parity][n_seg][2]
+    // Register-state kernel: boundary mailboxes box[s][side][box_cap] with
+    // counts box_n[s][side] (side 0: records from the left neighbour, 1: from
+    // the right one), and a float copy of Z (z32, same layout as Z) from which
+    // the run loads its state.
+    BoundaryRec* box;
+    uint32_t* box_n;
+    int box_cap;
+    float* z32;
 };
 hipError_t launch_lgcd_phase(const PhaseArgs& a, bool fp64, size_t* lds_bytes,
                              hipStream_t s);
@@ -164,6 +185,8 @@ size_t lgcd_gm_lds_bytes(int K, int lext_max, bool fp64);
 // updates per run, coloured schedule; S in the phase-kernel layout
 // (launch_s_transpose, float).
 bool lgcd_wave_supported(int K, int lm_max, int cap, bool fp64);
+// Mailbox capacity (records per segment and side) the kernel needs: a.box_cap.
+int lgcd_wave_box_cap();
 hipError_t launch_lgcd_wave(const PhaseArgs& a, hipStream_t s);
 // Atoms per position in the phase kernel's layout (K padded), -1 if K is
 // beyond the instantiated sizes.
@@ -184,7 +207,7 @@ hipError_t launch_nz_mask(const double* Z, const SigDesc* sig, const int64_t* ma
 // objective partials |X|^2 and <beta0 + g, Z> (their difference is
 // |X - Z * D|^2), dirty flags for segments holding a coordinate with
 // |Delta Z| >= flag_eps, and an optional refresh of the state g (float or
-// double).  Tiles of kCheckSpan positions (tile_pref: prefix of
+// double) and of the float copy z32 of Z (when not NULL).  Tiles of kCheckSpan positions (tile_pref: prefix of
 // ceil(L / kCheckSpan)); part: [check_kblocks(K, W)][n_tiles][kCheckParts].
 // Sc: the padded copy of S described at check_s_elems.
 hipError_t launch_grad_check(const float* X, const double* beta0, const double* Z,
@@ -193,7 +216,7 @@ hipError_t launch_grad_check(const float* X, const double* beta0, const double* 
                              const int64_t* tile_pref, int n_sig, int64_t n_tiles,
                              double flag_eps, const uint32_t* sig_done, uint32_t* dirty,
                              void* g_state, bool state_fp64, const double* g_in,
-                             double* part, hipStream_t s);
+                             double* part, float* z32, hipStream_t s);
 // Atom blocks of the check (grid y); 0 when W is too large for it.
 int check_kblocks(int K, int W);
 int check_atoms_per_block(int K, int W);

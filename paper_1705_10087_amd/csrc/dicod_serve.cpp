@@ -252,6 +252,8 @@ struct Server {
     int chunk = 16;
     // shared device state, indexed by ranges and slots
     Mem dX, dZ, dB, dG32, dG64, dSig, dSeg, dDirty, dSigUpd, dSigLast, dCnt;
+    Mem dBox, dBoxN, dZ32;       // register kernel: mailboxes, float copy of Z
+    int box_cap = 0;
     SigDesc* h_sig = nullptr;    // host mirror, one entry per slot
     PinnedPool pool;
     Lane lanes[kLanes];
@@ -359,10 +361,11 @@ int Server::start(dicod_ctx* c)
         SRV_HIP(hipMemGetInfo(&fr, &tot));
         budget = std::min<size_t>((size_t)(0.8 * (double)fr), (size_t)16 << 30);
     }
-    // bytes per coefficient: Z, beta0 and the double g; the float g in FP32
+    // bytes per coefficient: Z, beta0 and the double g; the float g and the
+    // float copy of Z in FP32
     // (the lanes' non-zero masks, 1/8 byte per coefficient each, fit in the
     // 5% left over)
-    const int64_t bc = fp64 ? 24 : 28;
+    const int64_t bc = fp64 ? 24 : 32;
     const int64_t bs = 4;
     const double share = (double)(bc * K) / (double)(bc * K + bs * P);
     const int64_t n_coef = round_up((int64_t)(share * 0.95 * (double)budget) / bc, 64);
@@ -382,8 +385,13 @@ int Server::start(dicod_ctx* c)
     SRV_HIP(dZ.alloc((size_t)n_coef * sizeof(double)));
     SRV_HIP(dB.alloc((size_t)n_coef * sizeof(double)));
     SRV_HIP(dG64.alloc((size_t)n_coef * sizeof(double)));
-    if (!fp64)
+    if (!fp64) {
         SRV_HIP(dG32.alloc((size_t)n_coef * sizeof(float)));
+        SRV_HIP(dZ32.alloc((size_t)n_coef * sizeof(float)));
+        box_cap = std::max(effective_update_cap(cfg.update_cap, W), 1);
+        SRV_HIP(dBox.alloc((size_t)2 * seg_cap * box_cap * sizeof(BoundaryRec)));
+        SRV_HIP(dBoxN.alloc((size_t)2 * seg_cap * sizeof(uint32_t)));
+    }
     SRV_HIP(dSig.alloc((size_t)slots * sizeof(SigDesc)));
     SRV_HIP(dSeg.alloc((size_t)seg_cap * sizeof(SegDesc)));
     SRV_HIP(dDirty.alloc((size_t)seg_cap * sizeof(uint32_t)));
@@ -424,7 +432,7 @@ Server::~Server()
         delete kv.second;
     }
     for (Mem* m : {&dX, &dZ, &dB, &dG32, &dG64, &dSig, &dSeg, &dDirty, &dSigUpd, &dSigLast,
-                   &dCnt})
+                   &dCnt, &dBox, &dBoxN, &dZ32})
         m->release();
     if (h_sig)
         (void)hipHostFree(h_sig);
@@ -636,6 +644,11 @@ int Lane::init_jobs(const std::vector<Job*>& fresh)
     for (Job* j : fresh) {
         SRV_HIP(launch_fill_f64(v.dZ.as<double>() + j->z_off, 0.0, (size_t)K * j->L, s));
         SRV_HIP(launch_fill_u32(v.dDirty.as<uint32_t>() + j->seg_base, 1u, j->M, s));
+        if (!v.fp64) {
+            SRV_HIP(launch_fill_u32(v.dZ32.as<uint32_t>() + j->z_off, 0u, (size_t)K * j->L, s));
+            SRV_HIP(launch_fill_u32(v.dBoxN.as<uint32_t>() + 2 * j->seg_base, 0u,
+                                    (size_t)2 * j->M, s));
+        }
         SRV_HIP(launch_fill_u64(v.dSigUpd.as<unsigned long long>() + j->slot, 0ull, 1, s));
         j->start = tick;
         j->cur64 = v.fp64;
@@ -722,7 +735,8 @@ int Lane::check_jobs(const std::vector<Job*>& conv, std::vector<Job*>& resumed)
                                           dSub.as<SigDesc>(), dTilesC.as<int64_t>(), n, pC[n],
                                           flag_eps, dDone.as<uint32_t>(),
                                           v.dDirty.as<uint32_t>(), g_in ? nullptr : g_next,
-                                          next64, g_in, dPart.as<double>(), s));
+                                          next64, g_in, dPart.as<double>(),
+                                          !next64 && !g_in ? v.dZ32.as<float>() : nullptr, s));
                 SRV_HIP(launch_check_reduce(dPart.as<double>(), dTilesC.as<int64_t>(), pC[n],
                                             n_kblk, n, dRes.as<CheckResult>(), s));
                 SRV_HIP(hipMemcpyAsync(h_res, dRes.p, n * sizeof(CheckResult),
@@ -759,9 +773,13 @@ int Lane::check_jobs(const std::vector<Job*>& conv, std::vector<Job*>& resumed)
                     j->upd_round0 = j->upd;
                 }
                 stage_off = 0;
-                for (Job* j : res_grp)
+                for (Job* j : res_grp) {
                     SRV_HIP(stage(v.dSig.as<SigDesc>() + j->slot, &v.h_sig[j->slot],
                                   sizeof(SigDesc)));
+                    if (!v.fp64)  // records of the last round are stale: g was refreshed
+                        SRV_HIP(launch_fill_u32(v.dBoxN.as<uint32_t>() + 2 * j->seg_base, 0u,
+                                                (size_t)2 * j->M, s));
+                }
                 SRV_HIP(hipStreamSynchronize(s));
                 resumed.insert(resumed.end(), res_grp.begin(), res_grp.end());
                 i0 = i1;
@@ -882,6 +900,10 @@ int Lane::iterate(int* admitted)
     a.sig_upd = v.dSigUpd.as<unsigned long long>();
     a.sig_last_upd = v.dSigLast.as<int>();
     a.counters = v.dCnt.as<Counters>();
+    a.box = v.fp64 ? nullptr : v.dBox.as<BoundaryRec>();
+    a.box_n = v.fp64 ? nullptr : v.dBoxN.as<uint32_t>();
+    a.box_cap = v.box_cap;
+    a.z32 = v.fp64 ? nullptr : v.dZ32.as<float>();
     for (int64_t t = tick; t < tick + n; ++t) {
         const int r = (int)(t % C);
         for (const Group& g : groups) {

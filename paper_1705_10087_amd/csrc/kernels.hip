@@ -1690,26 +1690,51 @@ hipError_t launch_lgcd_phase_gm(const PhaseArgs& a, bool fp64, size_t* lds_bytes
 // ---------------------------------------------------------------------------
 
 // Non-zero masks: word w of a signal is bit i = (Z_k[64 b + i] != 0), with
-// w = k * ceil(L / 64) + b.  One wave per word.
+// w = k * ceil(L / 64) + b.  A wave handles kMaskWords consecutive words:
+// their signal, atom and block indices are scalar arithmetic (the signal is
+// looked up once per wave), and all their loads are issued before the first
+// ballot.
+constexpr int kMaskWords = 16;
+
 __global__ void __launch_bounds__(256)
 k_nz_mask(const double* __restrict__ Z, const SigDesc* __restrict__ sig,
           const int64_t* __restrict__ mask_pref, int n_sig, int K, int64_t n_words,
           unsigned long long* __restrict__ masks)
 {
     const int lane = threadIdx.x & 63;
-    const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
-    for (int64_t w = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); w < n_words;
-         w += nw) {
-        const int si = find_sig(mask_pref, n_sig, w);
-        const SigDesc sd = sig[si];
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int64_t w0 = ((int64_t)blockIdx.x * 4 + wv) * kMaskWords;
+    if (w0 >= n_words)
+        return;
+    int si = find_sig(mask_pref, n_sig, w0);
+    int64_t pref = mask_pref[si], pref_next = mask_pref[si + 1];
+    SigDesc sd = sig[si];
+    double z[kMaskWords];
+#pragma unroll
+    for (int i = 0; i < kMaskWords; ++i) {
+        const int64_t w = w0 + i;
+        z[i] = 0.0;
+        if (w >= n_words)
+            continue;
+        while (w >= pref_next) {  // next signal (every signal has at least one word)
+            ++si;
+            pref = pref_next;
+            pref_next = mask_pref[si + 1];
+            sd = sig[si];
+        }
         const int64_t nb = (sd.L + 63) / 64;
-        const int64_t loc = w - mask_pref[si];
+        const int64_t loc = w - pref;
         const int64_t k = loc / nb;
         const int64_t t = (loc - k * nb) * 64 + lane;
-        const double z = (k < K && t < sd.L) ? Z[sd.z_off + k * sd.L + t] : 0.0;
-        const unsigned long long m = __ballot(z != 0.0);
-        if (lane == 0)
-            masks[w] = m;
+        const int64_t tc = t < sd.L ? t : sd.L - 1;  // a valid address, selected below
+        const double v = Z[sd.z_off + (k < K ? k : K - 1) * sd.L + tc];
+        z[i] = (k < K && t < sd.L) ? v : 0.0;
+    }
+#pragma unroll
+    for (int i = 0; i < kMaskWords; ++i) {
+        const unsigned long long m = __ballot(z[i] != 0.0);
+        if (lane == 0 && w0 + i < n_words)
+            masks[w0 + i] = m;
     }
 }
 
@@ -1719,9 +1744,9 @@ hipError_t launch_nz_mask(const double* Z, const SigDesc* sig, const int64_t* ma
 {
     if (n_words <= 0)
         return hipSuccess;
-    const int64_t blocks = (n_words + 3) / 4;
-    hipLaunchKernelGGL(k_nz_mask, dim3((unsigned)(blocks < 65536 ? blocks : 65536)), dim3(256),
-                       0, s, Z, sig, mask_pref, n_sig, K, n_words, masks);
+    const int64_t blocks = (n_words + 4 * kMaskWords - 1) / (4 * kMaskWords);
+    hipLaunchKernelGGL(k_nz_mask, dim3((unsigned)blocks), dim3(256), 0, s, Z, sig, mask_pref,
+                       n_sig, K, n_words, masks);
     return hipGetLastError();
 }
 
@@ -1838,7 +1863,8 @@ k_grad_check(const float* __restrict__ X, const double* __restrict__ beta0,
              const int64_t* __restrict__ tile_pref, int n_sig, double flag_eps,
              const uint32_t* __restrict__ sig_done, uint32_t* __restrict__ dirty,
              float* __restrict__ g32, double* __restrict__ g64,
-             const double* __restrict__ g_in, double* __restrict__ part)
+             const double* __restrict__ g_in, double* __restrict__ part,
+             float* __restrict__ z32)
 {
     extern __shared__ __align__(16) double sst[];  // 2 x [kper][2W]: S_{kb+k,l}[d - W + 1]
     __shared__ int ls[kCheckList];                 // listed non-zeros (l, s, Z_l[s])
@@ -2033,6 +2059,8 @@ k_grad_check(const float* __restrict__ X, const double* __restrict__ beta0,
             }
             if (g32 && !frozen)
                 g32[o] = (float)g;
+            if (z32 && !frozen)
+                z32[o] = (float)z;
             if (g64 && !frozen)
                 g64[o] = g;
         }
@@ -2079,7 +2107,7 @@ hipError_t launch_grad_check(const float* X, const double* beta0, const double* 
                              const int64_t* tile_pref, int n_sig, int64_t n_tiles,
                              double flag_eps, const uint32_t* sig_done, uint32_t* dirty,
                              void* g_state, bool state_fp64, const double* g_in,
-                             double* part, hipStream_t s)
+                             double* part, float* z32, hipStream_t s)
 {
     const int kper = check_atoms_per_block(K, W);
     if (kper < 1)
@@ -2095,7 +2123,7 @@ hipError_t launch_grad_check(const float* X, const double* beta0, const double* 
                                   (int)lds);
         hipLaunchKernelGGL(kern, grid, dim3(256), lds, s, X, beta0, Z, masks, Sc, n2, K, P, W,
                            kper, sig, tile_pref, n_sig, flag_eps, sig_done, dirty, g32, g64,
-                           g_in, part);
+                           g_in, part, z32);
         return hipGetLastError();
     };
     static_assert(kCheckKB == 8, "instantiated atom counts");

@@ -29,11 +29,14 @@
 // applied change delta is recomputed exactly from the winner's registers.
 //
 // Boundary.  An update whose window reaches a neighbouring segment (the
-// W - 1 halo) is recorded as (k0, t0, delta); the records are applied to the
-// neighbours' state in HBM at the end of the run, each halo position by one
-// thread, in update order (the neighbours are idle in this phase, so this
-// equals applying them at each update).  This replaces the boundary messages
-// of Algorithm 2 in the coloured schedule.
+// W - 1 positions next to the edge) is sent to that neighbour as a record
+// (k0, t0, delta) in its mailbox in HBM -- the message of Algorithm 2 -- and
+// the neighbour applies its records, from the left neighbour first, each in
+// the order sent, when it next runs, before it picks a coordinate.  Under the
+// coloured schedule a segment that receives records is marked dirty and runs
+// before the sender runs again, so a mailbox holds at most one run's records,
+// and the result equals applying the records at once (up to the order of the
+// float additions).  A run therefore moves only its own state through HBM.
 #include <hip/hip_runtime.h>
 
 #include <climits>
@@ -46,14 +49,7 @@ namespace {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 
-constexpr int kWaveRecs = 64;  // halo records held on chip per segment
-
-struct WRec {
-    int k0;
-    int t0;
-    float delta;
-    int pad;
-};
+constexpr int kWaveRecs = 64;  // updates per run at most (mailbox capacity)
 
 struct WSlot {
     unsigned key;
@@ -165,8 +161,8 @@ k_lgcd_wave(PhaseArgs a)
     constexpr int NT = SPB * NTT;             // threads per workgroup
     __shared__ f4 s_cst[SPB][2][KQ];            // |D_k|^2 and 1 / |D_k|^2
     __shared__ f4 s_u[KQ * NT];                 // Z in float: [atom group][thread]
-    __shared__ WRec s_rec[SPB][kWaveRecs];
     __shared__ WSlot s_slot[2][TW];
+    __shared__ BoundaryRec s_in[SPB][2 * kWaveRecs];  // records received
     f4* __restrict__ u = s_u + threadIdx.x;    // this thread's column (stride NT)
 
     const int li = blockIdx.x * SPB + team;
@@ -185,6 +181,7 @@ k_lgcd_wave(PhaseArgs a)
     const int Lm = sd.e - sd.b;
     float* __restrict__ gs = reinterpret_cast<float*>(a.g) + sd.z_off;
     double* __restrict__ Zs = a.Z + sd.z_off;
+    float* __restrict__ zs32 = a.z32 + sd.z_off;
     const float* __restrict__ St = reinterpret_cast<const float*>(a.S);  // [K][nd][KP]
     const float lam = (float)a.sigs[sd.sig].lam;
     const float eps_stop = (float)a.sigs[sd.sig].eps_stop;
@@ -215,22 +212,28 @@ k_lgcd_wave(PhaseArgs a)
     f4 g[KQ], uz[KQ];
     {
         const float* pg = gs + b + jc;
-        const double* pz = Zs + b + jc;
+        const float* pz = zs32 + b + jc;
 #pragma unroll
         for (int i = 0; i < KQ; ++i)
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
                 g[i][c] = *pg;
-                uz[i][c] = (float)*pz;
+                uz[i][c] = *pz;
                 if (4 * i + c + 1 < K) {  // padded atoms reread atom K - 1
                     pg += L;
                     pz += L;
                 }
             }
     }
+    // mailbox counts: the records waiting for this segment, and where this
+    // run's records to the neighbours start (their boxes are emptied when they
+    // run, which under the coloured schedule is before this segment runs again)
+    uint32_t* __restrict__ bn = a.box_n;
+    const uint32_t in_l = bn[(size_t)sid * 2 + 0], in_r = bn[(size_t)sid * 2 + 1];
+    const uint32_t base_l = sd.left >= 0 ? bn[(size_t)sd.left * 2 + 1] : 0u;
+    const uint32_t base_r = sd.right >= 0 ? bn[(size_t)sd.right * 2 + 0] : 0u;
 #pragma unroll
     for (int i = 0; i < KQ; ++i) {
-        const f4 n2 = cn2[i];
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
             const bool pad = 4 * i + c >= K;
@@ -239,10 +242,53 @@ k_lgcd_wave(PhaseArgs a)
         }
         u[i * NT] = uz[i];
     }
+    int tlo = INT_MAX, thi = -1;  // own positions whose g changed (written back)
+    // records of the neighbours' last runs, from the left neighbour, then from
+    // the right one, each in the order sent: staged in LDS with one load per
+    // record, then applied two at a time (both S rows in flight; a record out
+    // of a position's reach reads a valid row and applies a zero change)
+    const int n_in = (int)(in_l + in_r);
+    BoundaryRec* rin = s_in[team];
+    for (int i = tt; i < n_in; i += NTT)
+        rin[i] = i < (int)in_l ? a.box[((size_t)sid * 2 + 0) * a.box_cap + i]
+                               : a.box[((size_t)sid * 2 + 1) * a.box_cap + (i - (int)in_l)];
     if (TW > 1)
         __syncthreads();
     else
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    for (int r = 0; r < n_in; r += 2) {
+        const BoundaryRec r0 = rin[r];
+        const BoundaryRec r1 = rin[r + 1 < n_in ? r + 1 : r];
+        const int j0a = r0.t0 - b, j0b = r1.t0 - b;
+        const int lo_a = j0a - (W - 1) > 0 ? j0a - (W - 1) : 0;
+        const int hi_a = j0a + (W - 1) < Lm - 1 ? j0a + (W - 1) : Lm - 1;
+        const int lo_b = j0b - (W - 1) > 0 ? j0b - (W - 1) : 0;
+        const int hi_b = j0b + (W - 1) < Lm - 1 ? j0b + (W - 1) : Lm - 1;
+        tlo = lo_a < tlo ? lo_a : tlo;
+        thi = hi_a > thi ? hi_a : thi;
+        tlo = lo_b < tlo ? lo_b : tlo;
+        thi = hi_b > thi ? hi_b : thi;
+        const int da = tt - j0a + (W - 1), db2 = tt - j0b + (W - 1);
+        const bool ina = own && da >= 0 && da < nd;
+        const bool inb = own && db2 >= 0 && db2 < nd && r + 1 < n_in;
+        const f4* sa = reinterpret_cast<const f4*>(
+            St + ((size_t)r0.k0 * nd + (ina ? da : 0)) * KP);
+        const f4* sb = reinterpret_cast<const f4*>(
+            St + ((size_t)r1.k0 * nd + (inb ? db2 : 0)) * KP);
+        f4 va[KQ], vb[KQ];
+#pragma unroll
+        for (int i = 0; i < KQ; ++i) {
+            va[i] = sa[i];
+            vb[i] = sb[i];
+        }
+        const float dla = ina ? r0.delta : 0.0f, dlb = inb ? r1.delta : 0.0f;
+#pragma unroll
+        for (int i = 0; i < KQ; ++i)
+            g[i] -= va[i] * dla;
+#pragma unroll
+        for (int i = 0; i < KQ; ++i)
+            g[i] -= vb[i] * dlb;
+    }
 
     // team argmax: key, position and exact change delta of the best candidate
     int it = 0;
@@ -290,14 +336,22 @@ k_lgcd_wave(PhaseArgs a)
     int j0;
     float db;
     argmax(mine, kb, j0, db);
+    // every thread has read the counts (the argmax synchronised the team):
+    // the waiting records are consumed
+    if (tt == 0 && (in_l | in_r)) {
+        bn[(size_t)sid * 2 + 0] = 0u;
+        bn[(size_t)sid * 2 + 1] = 0u;
+    }
 
-    WRec* recs = s_rec[team];
-    int n = 0, nrec = 0;
+    int n = 0;
+    uint32_t n_l = 0, n_r = 0;  // records sent to the left and right neighbours
     bool conv = false, touch_l = false, touch_r = false;
-    int tlo = INT_MAX, thi = -1;  // own positions whose g changed
+    BoundaryRec* __restrict__ box_l =
+        sd.left >= 0 ? a.box + ((size_t)sd.left * 2 + 1) * a.box_cap : nullptr;
+    BoundaryRec* __restrict__ box_r =
+        sd.right >= 0 ? a.box + ((size_t)sd.right * 2 + 0) * a.box_cap : nullptr;
 
-    // at most kWaveRecs updates per run (the launcher checks the cap), so the
-    // halo records of a run always fit on chip
+    // at most kWaveRecs updates per run (the launcher checks the cap)
     for (;;) {
         // per iteration, so that the per-atom constants are read from LDS where
         // they are used instead of being held in registers across the loop
@@ -325,7 +379,9 @@ k_lgcd_wave(PhaseArgs a)
             float* up = reinterpret_cast<float*>(u + (k0 / 4) * NT) + (k0 % 4);
             const float zo = *up;
             const bool zr = fabsf(fmaf(cn2[k0 / 4][k0 % 4], zo, pick<0, KP, KQ>(g, k0))) <= lam;
-            *up = zr ? 0.0f : zo + delta;
+            const float zn = zr ? 0.0f : zo + delta;
+            *up = zn;
+            zs32[(int64_t)k0 * L + b + j0] = zn;
             double* zp = Zs + (int64_t)k0 * L + b + j0;
             if (zr)
                 *zp = 0.0;
@@ -348,14 +404,26 @@ k_lgcd_wave(PhaseArgs a)
         const bool to_l = j0 - (W - 1) < 0 && sd.left >= 0;
         const bool to_r = j0 + (W - 1) >= Lm && sd.right >= 0;
         if ((to_l || to_r) && tt == 0) {
-            WRec rc;
+            BoundaryRec rc;
             rc.k0 = k0;
             rc.t0 = b + j0;
             rc.delta = delta;
             rc.pad = 0;
-            recs[nrec] = rc;
+            if (to_l) {
+                if (base_l + n_l < (uint32_t)a.box_cap)
+                    box_l[base_l + n_l] = rc;
+                else
+                    atomicAdd(&a.counters->box_overflow, 1ull);
+            }
+            if (to_r) {
+                if (base_r + n_r < (uint32_t)a.box_cap)
+                    box_r[base_r + n_r] = rc;
+                else
+                    atomicAdd(&a.counters->box_overflow, 1ull);
+            }
         }
-        nrec += (to_l || to_r) ? 1 : 0;
+        n_l += to_l ? 1u : 0u;
+        n_r += to_r ? 1u : 0u;
         touch_l |= to_l;
         touch_r |= to_r;
 
@@ -389,57 +457,6 @@ k_lgcd_wave(PhaseArgs a)
             }
     }
 
-    // Halo records applied to the neighbours' state in HBM, each halo position
-    // by one thread, records in update order (every record is visible: the
-    // same wave wrote it, or the argmax barrier came after it).
-    if (nrec > 0) {
-        const int ext_lo = b - (W - 1) > 0 ? b - (W - 1) : 0;
-        const int ext_hi = sd.e + (W - 1) < sd.L ? sd.e + (W - 1) : (int)sd.L;
-        const int n_hl = b - ext_lo;
-        const int n_h = n_hl + (ext_hi - sd.e);
-#pragma unroll 1
-        for (int h = tt; h < n_h; h += NTT) {
-            const int t = h < n_hl ? ext_lo + h : sd.e + (h - n_hl);
-            bool touched = false;
-            f4 gh[KQ];
-#pragma unroll 1
-            for (int r = 0; r < nrec; ++r) {
-                const WRec rc = recs[r];
-                const int dh = t - rc.t0 + (W - 1);
-                if (dh < 0 || dh >= nd)
-                    continue;
-                if (!touched) {
-                    const float* pg = gs + t;
-#pragma unroll
-                    for (int i = 0; i < KQ; ++i)
-#pragma unroll
-                        for (int c = 0; c < 4; ++c) {
-                            const float v = *pg;
-                            gh[i][c] = 4 * i + c < K ? v : 0.0f;
-                            if (4 * i + c + 1 < K)
-                                pg += L;
-                        }
-                    touched = true;
-                }
-                const f4* srow = reinterpret_cast<const f4*>(St + ((size_t)rc.k0 * nd + dh) * KP);
-#pragma unroll
-                for (int i = 0; i < KQ; ++i)
-                    gh[i] -= srow[i] * rc.delta;
-            }
-            if (touched) {
-                float* pg = gs + t;
-#pragma unroll
-                for (int i = 0; i < KQ; ++i)
-#pragma unroll
-                    for (int c = 0; c < 4; ++c) {
-                        if (4 * i + c < K)
-                            *pg = gh[i][c];
-                        pg += L;
-                    }
-            }
-        }
-    }
-
     if (tt == 0) {
         if (n > 0) {
             atomicAdd(&a.phase_upd[(size_t)sd.sig * a.phase_stride + a.phase],
@@ -449,10 +466,16 @@ k_lgcd_wave(PhaseArgs a)
             atomicAdd(&a.counters->seg_runs, 1ull);
         }
         a.dirty[sid] = conv ? 0u : 1u;
-        if (touch_l)
+        if (touch_l) {
             a.dirty[sd.left] = 1u;
-        if (touch_r)
+            bn[(size_t)sd.left * 2 + 1] = base_l + n_l < (uint32_t)a.box_cap
+                                              ? base_l + n_l : (uint32_t)a.box_cap;
+        }
+        if (touch_r) {
             a.dirty[sd.right] = 1u;
+            bn[(size_t)sd.right * 2 + 0] = base_r + n_r < (uint32_t)a.box_cap
+                                               ? base_r + n_r : (uint32_t)a.box_cap;
+        }
     }
 }
 
@@ -472,6 +495,8 @@ hipError_t launch_kq(const PhaseArgs& a, hipStream_t s)
 
 }  // namespace
 
+int lgcd_wave_box_cap() { return kWaveRecs; }
+
 bool lgcd_wave_supported(int K, int lm_max, int cap, bool fp64)
 {
     return !fp64 && lgcd_k_padded(K, false) > 0 && lgcd_k_padded(K, false) <= 32 &&
@@ -482,7 +507,8 @@ hipError_t launch_lgcd_wave(const PhaseArgs& a, hipStream_t s)
 {
     if (a.n_list <= 0)
         return hipSuccess;
-    if (a.dicod || !lgcd_wave_supported(a.K, a.lm_max, a.cap, false))
+    if (a.dicod || !lgcd_wave_supported(a.K, a.lm_max, a.cap, false) || !a.box || !a.box_n ||
+        !a.z32 || a.box_cap < a.cap || a.box_cap > kWaveRecs)
         return hipErrorInvalidValue;
     switch (lgcd_k_padded(a.K, false) / 4) {
     case 1: return launch_kq<1>(a, s);
