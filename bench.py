@@ -1,24 +1,38 @@
 """Benchmark: time-to-eps and coordinate updates/s of LGCD on one MI355X.
 
-A step is one complete solve of the paper-shaped workload (P=7, K=25, W=200,
-T=150,000, Bernoulli(0.007) x N(0, 10^2) activations, noise sigma 0.1,
-lambda = 0.1 lambda_max, eps = 1e-6, float descent with double-precision
-stop test) with X already resident in HBM: beta init, lambda_max, the coloured
-descent phases and the final double-precision check, through the C ABI.
+Headline (the JSON line's value): the batched workload -- 256 signals with
+lengths uniform in [10,000, 500,000], shared dictionary P=7 K=25 W=64,
+Bernoulli(0.005) x N(0, 10^2) activations, noise sigma 0.1,
+lambda = 0.1 lambda_max per signal, eps = 1e-6 -- solved in one batched call
+with X already resident in HBM.  A step is one whole batched solve (beta
+init, lambda_max, the coloured descent rounds and the double-precision stop
+test of every signal); value = coordinate updates per second over the timed
+steps, ms_per_step = time-to-eps of the whole batch.
 
-Prints one JSON line.  value = coordinate updates per second over the timed
-steps (whole job); ms_per_step = time-to-eps of one solve.
+Beside it, each with its own roofline object (skip with --only):
+  * c2, paper-shaped single signal: P=7 K=25 W=200 T=150,000, rho=0.007;
+  * c3, long signal: T=5,000,000, the same shapes, split-bf16 correlations
+    with float descent and a double-precision stop test only (no double
+    descent round);
+  * c5, served stream: 2,000 encode requests (after 200 warm-up requests),
+    windows of log-uniform length in [2,000, 2,000,000] cut at random offsets
+    from a 20,000,000-sample synthetic recording, P=7 K=25 W=200, through
+    dicod_submit / dicod_poll at saturation and at 0.5 / 0.8 of it.
 
-Three more workloads are measured beside it (skip with --no-long /
---no-batched / --no-served):
-  * long: one signal of T = 5,000,000 (P=7 K=25 W=200), time-to-eps;
-  * batched: 256 signals, T uniform in [10,000, 500,000], shared dictionary
-    P=7 K=25 W=64, Bernoulli(0.005) activations, solved in one batched call,
-    against the same signals solved one call per signal on the same GPU;
-  * served: a Poisson stream of encode requests (lengths log-uniform in
-    [2,000, 2,000,000], P=7 K=25 W=200) through dicod_submit / dicod_poll at
-    0.5 and 0.8 of the measured saturation rate: p50/p99 latency and
-    updates/s, against the same requests solved one at a time.
+The schedule (colours, segment length, update cap) of every workload comes
+from the library's autotuner (--no-tune: the fixed rule; --schedule C,SEG,CAP:
+a given schedule, used for profiling runs).
+
+Roofline: the dominant kernel is the float register-state phase kernel of
+the first descent round.  It is bound by vector ALU work and latency, not by
+HBM: per update it does the window update of eq. (3), K (2W - 1) fused
+multiply-adds, and the soft-threshold candidate of every touched coordinate
+(about 5 flops each), 7 K (2W - 1) flops in all; achieved = those flops per
+launch / the launch's mean duration from HIP events on the solve stream,
+against the published fp32 vector peak (157.3 TFLOP/s; 78.6 without packed
+fp32 instructions, which this build does not emit).  traffic = HBM bytes per
+launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE runs (scaled by a
+plain copy), or null when those were taken on another kernel source.
 """
 import argparse
 import hashlib
@@ -33,199 +47,309 @@ sys.path.insert(0, ROOT)
 
 import numpy as np  # noqa: E402
 
+PEAK_FP32_TFLOPS = 157.3
+PEAK_FP32_NOPK_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
-KERNEL_SRC = os.path.join(ROOT, "paper_1705_10087_amd", "csrc", "kernels.hip")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "lgcd_phase_paper_shaped_traffic.json")
+WAVE_SRC = os.path.join(ROOT, "paper_1705_10087_amd", "csrc", "lgcd_wave.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "lgcd_wave_traffic.json")
+EPS = 1e-6
+LAM = -0.1          # lambda = 0.1 lambda_max per signal
 
 
-def algorithmic_bytes_per_update(K, W, elem=4):
-    """S slice read + window of g read + written: 3 * K * (2W - 1) elements."""
-    return 3 * elem * K * (2 * W - 1)
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def kernel_sha():
-    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+def flops_per_update(K, W):
+    """Window update of eq. (3) (K (2W-1) FMAs = 2 flops each) plus the
+    soft-threshold candidate and |Delta Z| of each touched coordinate (5)."""
+    return 7 * K * (2 * W - 1)
 
 
-def measured_traffic():
-    """HBM bytes per LGCD launch from the committed rocprofv3 counter runs, or
-    None when they are missing or were taken on a different kernel source."""
+def wave_sha():
+    return hashlib.sha256(open(WAVE_SRC, "rb").read()).hexdigest()[:16]
+
+
+def measured_traffic(workload):
+    """HBM bytes per launch of the dominant kernel on this workload from the
+    committed counter runs, or None if missing or taken on another source."""
     try:
         rec = json.load(open(TRAFFIC_FILE))
     except (OSError, ValueError):
         return None
-    if rec.get("kernel_src_sha") != kernel_sha():
+    if rec.get("kernel_src_sha") != wave_sha():
         return None
-    return rec.get("hbm_bytes_per_launch")
+    w = rec.get("workloads", {}).get(workload)
+    return None if w is None else w.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(X, D, lam, eps, M, cap, colors):
-    import oracle
-    t0 = time.perf_counter()
-    Z, st, _ = oracle.lgcd(X.astype(np.float64), D.astype(np.float64), lam, eps, M, cap=cap,
-                           colors=colors)
-    dt = time.perf_counter() - t0
-    return {"value": st["n_updates"] / dt, "unit": "coord updates/s", "cores": 1,
-            "kind": "oracle", "time_to_eps_s": dt, "n_updates": int(st["n_updates"]),
-            "sample": f"one full solve of the same workload by the FP64 C oracle, same "
-                      f"schedule ({colors} colours, M={M}, update cap {cap}), single thread"}
+def wave_kernel_name(K, lm_max):
+    """Instantiation of the register-state kernel: atoms padded to groups of
+    four (4, 8, 16, 28 or 32 atoms), teams of 1, 2 or 4 waves."""
+    kp = next(p for p in (4, 8, 16, 28, 32) if K <= p)
+    tw = 1 if lm_max <= 64 else 2 if lm_max <= 128 else 4
+    return f"k_lgcd_wave<{kp // 4}, {tw}>"
 
 
-def effective_cap(cap, W):
-    """The library's update cap: cap > 0 as given, 0 = none, -1 = max(4, round(2 sqrt(W)))."""
-    return cap if cap >= 0 else max(4, int(math.floor(2.0 * math.sqrt(W) + 0.5)))
+def roofline(tst, K, W, workload, lm_max):
+    """Roofline object of the first round's phase kernel from a timed solve
+    (timing = 1: HIP events around every launch on the solve stream)."""
+    launches = tst["round_launches"][0]
+    kern_ms = tst["round_kernel_ms"][0]
+    upd = tst["round_updates_total"]
+    if launches <= 0 or kern_ms <= 0:
+        return None
+    avg_s = kern_ms / launches * 1e-3
+    fpu = flops_per_update(K, W)
+    achieved = upd / launches * fpu / avg_s / 1e12
+    reg = bool(tst["round_state"][0] & 4)
+    traffic = measured_traffic(workload)
+    out = {"kernel": wave_kernel_name(K, lm_max) if reg else "k_lgcd_phase<float> (LDS state)",
+           "bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+           "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic,
+           "frac_of_no_packed_peak": achieved / PEAK_FP32_NOPK_TFLOPS,
+           "flops_per_update": fpu, "updates_per_launch": upd / launches,
+           "avg_launch_us": avg_s * 1e6, "launches": launches, "kernel_ms": kern_ms}
+    if traffic:
+        out["hbm_gbs"] = traffic / avg_s / 1e9
+        out["hbm_frac"] = out["hbm_gbs"] / PEAK_HBM_GBS
+    return out
 
 
-def ms_per_step_of(stats, wall, steps):
-    return 1e3 * wall / steps
+def round_totals(sts):
+    """Statistics of the first round of a call (shared by a batch's signals)."""
+    s0 = dict(sts[0])
+    s0["round_updates_total"] = s0["round_updates"][0]
+    return s0
 
 
-def s_last(stats):
-    return stats[-1]
-
-
-def adjacent_pairs(tr, W):
-    """Updates of one phase in adjacent segments: pairs, and pairs closer than
-    W (interfering, Sec. 3)."""
-    by = {}
-    for p, m, t in zip(tr["phase"], tr["seg"], tr["t0"]):
-        by.setdefault((int(p), int(m)), []).append(int(t))
-    n_adj = n_int = 0
-    for (p, m), us in by.items():
-        vs = by.get((p, m + 1))
-        if not vs:
-            continue
-        vs = np.asarray(vs)
-        for u in us:
-            n_adj += vs.size
-            n_int += int(np.count_nonzero(np.abs(u - vs) < W))
-    return n_adj, n_int
-
-
-def _gen_signal(job):
-    import synth
-    P, K, W, T, rho, sigma, seed, D = job
-    return synth.generate_fast(P, K, W, int(T), rho, sigma, seed, D)
-
-
-def gen_signals(P, K, W, lengths, rho, sigma, seed0, D, workers=8):
-    """Seeded signals of the given lengths with a shared dictionary, generated
-    in a process pool (before the GPU is initialised)."""
-    import concurrent.futures as cf
-    import multiprocessing as mp
-    jobs = [(P, K, W, T, rho, sigma, seed0 + i, D) for i, T in enumerate(lengths)]
-    with cf.ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("fork")) as ex:
-        return list(ex.map(_gen_signal, jobs, chunksize=4))
-
-
-def batched_bench(d, torch, D, Ts, Xs, cap, colors):
-    """One batched call over all signals vs one call per signal."""
+def packed(D, Ts, Xs):
     K, P, W = D.shape
-    n = len(Ts)
     Ls = [int(T) - W + 1 for T in Ts]
     x_off = np.concatenate([[0], np.cumsum([P * int(T) for T in Ts])[:-1]]).astype(np.int64)
     z_off = np.concatenate([[0], np.cumsum([K * L for L in Ls])[:-1]]).astype(np.int64)
+    return Ls, x_off, z_off
+
+
+def entry_of(tune_entry, K, P, W, buckets):
+    """The same schedule for every given bucket (so that one-call-per-signal
+    solves run the batch's schedule)."""
+    return [dict(tune_entry, K=K, P=P, W=W, bucket=int(b)) for b in buckets]
+
+
+def schedule_entry(spec, K, P, W, bucket):
+    C, seg, cap = (int(x) for x in spec.split(","))
+    return dict(K=K, P=P, W=W, bucket=bucket, colors=C, seg_len=seg, update_cap=cap)
+
+
+class Timed:
+    """Wall time of device work on the current stream."""
+
+    def __init__(self, torch):
+        self.torch = torch
+
+    def __enter__(self):
+        self.torch.cuda.synchronize()
+        self.t0 = time.perf_counter()
+        return self
+
+    def __exit__(self, *a):
+        self.torch.cuda.synchronize()
+        self.s = time.perf_counter() - self.t0
+
+
+def solve_batch(c, Xd, Ts, x_off, Zd, z_off):
+    return c.solve_batch_device(Xd, Ts, x_off, np.full(len(Ts), LAM), EPS, None, Zd, z_off)
+
+
+def tune_or_set(d, c, args, Xd, Ts, x_off, Zd, z_off, K, P, W, trials):
+    """Installs the schedule of this workload in context c: the autotuner's
+    choice, a given --schedule, or nothing (fixed rule).  Returns the entry."""
+    lmax = max(int(T) for T in Ts) - W + 1
+    bucket = int(math.floor(math.log2(lmax)))
+    if args.schedule:
+        e = schedule_entry(args.schedule, K, P, W, bucket)
+        c.set_tuning(e)
+        return c.tuning()[0]
+    if args.no_tune:
+        return None
+    return c.autotune_device(Xd, Ts, x_off, np.full(len(Ts), LAM), EPS, Zd, z_off,
+                             max_trials=trials)
+
+
+def run_solver_workload(d, torch, args, name, D, Ts, Xs, steps, warmup, cfg, trials,
+                        per_signal=False):
+    """Tuned (or fixed) schedule, warm-up, timed steps, a timing run for the
+    roofline, and the fixed rule for comparison."""
+    K, P, W = D.shape
+    Ls, x_off, z_off = packed(D, Ts, Xs)
     dev = torch.device("cuda:0")
     Xd = torch.from_numpy(np.concatenate([X.ravel() for X in Xs])).to(dev)
     nz = int(sum(K * L for L in Ls))
-    Zb = torch.empty(nz, dtype=torch.float64, device=dev)
-    Zs = torch.empty(nz, dtype=torch.float64, device=dev)
-    lam = np.full(n, -0.1)
-    with d.Context(update_cap=cap, colors=colors) as c:
+    Zd = torch.empty(nz, dtype=torch.float64, device=dev)
+    res = {}
+    with d.Context(autotune=1, **cfg) as c:
         c.set_dictionary(D)
-        c.solve_batch_device(Xd, Ts, x_off, lam, 1e-6, None, Zb, z_off)   # warm-up
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        sts = c.solve_batch_device(Xd, Ts, x_off, lam, 1e-6, None, Zb, z_off)
-        torch.cuda.synchronize()
-        t_batch = time.perf_counter() - t0
-        upd_b = sum(s["n_updates"] for s in sts)
-        t0 = time.perf_counter()
-        upd_s = 0
-        for i in range(n):
-            Xi = Xd[x_off[i]:x_off[i] + P * int(Ts[i])].view(P, int(Ts[i]))
-            Zi = Zs[z_off[i]:z_off[i] + K * Ls[i]].view(K, Ls[i])
-            _, st, _ = c.solve_device(Xi, -0.1, 1e-6, 0, Zi)
-            upd_s += st["n_updates"]
-        torch.cuda.synchronize()
-        t_seq = time.perf_counter() - t0
-    same = bool(torch.equal(Zb, Zs))
-    return {"workload": f"{n} signals, T uniform in [10000, 500000], P={P} K={K} W={W}, "
-                        "rho=0.005, sigma=0.1, lambda=0.1*lambda_max per signal, eps=1e-6",
-            "total_samples": int(sum(int(T) for T in Ts)), "coefficients": nz,
-            "batched": {"time_to_eps_s": t_batch, "updates": int(upd_b),
-                        "updates_per_s": upd_b / t_batch,
-                        "converged": int(sum(s["converged"] for s in sts))},
-            "per_signal": {"time_to_eps_s": t_seq, "updates": int(upd_s),
-                           "updates_per_s": upd_s / t_seq},
-            "speedup": t_seq / t_batch, "batched_equals_per_signal": same}
+        with Timed(torch) as tt:
+            entry = tune_or_set(d, c, args, Xd, Ts, x_off, Zd, z_off, K, P, W, trials)
+        res["schedule"] = entry if entry else "fixed rule"
+        res["tuning_s"] = tt.s
+        log(f"{name}: schedule {entry}")
+        for _ in range(warmup):
+            sts = solve_batch(c, Xd, Ts, x_off, Zd, z_off)
+        with Timed(torch) as tt:
+            for _ in range(steps):
+                sts = solve_batch(c, Xd, Ts, x_off, Zd, z_off)
+        wall = tt.s
+        table = c.tuning()
+    upd = sum(s["n_updates"] for s in sts)
+    s0 = sts[0]
+    res.update({"time_to_eps_s": wall / steps, "updates": int(upd),
+                "updates_per_s": upd / (wall / steps), "steps": steps,
+                "converged": int(sum(s["converged"] for s in sts)), "signals": len(Ts),
+                "colors": s0["colors"], "update_cap": s0["update_cap"], "tuned": s0["tuned"],
+                "n_seg_total": int(sum(s["n_seg"] for s in sts)),
+                "t_init_ms": s0["t_init_ms"], "t_verify_ms": s0["t_verify_ms"],
+                "round_phases": s0["round_phases"], "round_ms": s0["round_ms"],
+                "round_state": s0["round_state"], "polished_fp64": s0["polished_fp64"],
+                "n_refresh": s0["n_refresh"]})
+    # timing run: HIP events around every phase launch
+    with d.Context(autotune=1, timing=1, **cfg) as c:
+        c.set_dictionary(D)
+        for e in table:
+            c.set_tuning(e)
+        tsts = solve_batch(c, Xd, Ts, x_off, Zd, z_off)
+    tst = round_totals(tsts)
+    lm_max = max(-(-L // s["n_seg"]) for L, s in zip(Ls, tsts))
+    res["roofline"] = roofline(tst, K, W, name, lm_max)
+    res["kernel_times_ms"] = {"phase_kernels_round0": tst["round_kernel_ms"][0],
+                              "phase_kernels_all_rounds": tst["t_lgcd_kernel_ms"],
+                              "init": tst["t_init_ms"], "verify": tst["t_verify_ms"]}
+    if per_signal:
+        # the same signals, one call per signal, under the batch's schedule
+        Zs = torch.empty_like(Zd)
+        with d.Context(autotune=1, **cfg) as c:
+            c.set_dictionary(D)
+            if entry is not None:
+                for e in entry_of(entry, K, P, W, {math.floor(math.log2(L)) for L in Ls}):
+                    c.set_tuning(e)
+            ups = 0
+            with Timed(torch) as tt:
+                for i in range(len(Ts)):
+                    T = int(Ts[i])
+                    Xi = Xd[x_off[i]:x_off[i] + P * T].view(P, T)
+                    Zi = Zs[z_off[i]:z_off[i] + K * Ls[i]].view(K, Ls[i])
+                    _, st, _ = c.solve_device(Xi, LAM, EPS, 0, Zi)
+                    ups += st["n_updates"]
+        res["per_signal"] = {"time_to_eps_s": tt.s, "updates": int(ups),
+                             "updates_per_s": ups / tt.s}
+        res["batched_speedup_vs_per_signal"] = tt.s / res["time_to_eps_s"]
+        res["batched_equals_per_signal"] = bool(torch.equal(Zd, Zs))
+    # the fixed rule for comparison (no tuning table)
+    if entry is not None and not args.schedule:
+        with d.Context(autotune=0, **cfg) as c:
+            c.set_dictionary(D)
+            solve_batch(c, Xd, Ts, x_off, Zd, z_off)
+            with Timed(torch) as tt:
+                for _ in range(max(1, steps // 2)):
+                    fs = solve_batch(c, Xd, Ts, x_off, Zd, z_off)
+        res["fixed_rule"] = {"time_to_eps_s": tt.s / max(1, steps // 2),
+                             "colors": fs[0]["colors"], "update_cap": fs[0]["update_cap"],
+                             "n_seg_total": int(sum(s["n_seg"] for s in fs)),
+                             "updates": int(sum(s["n_updates"] for s in fs))}
+        res["tuned_speedup_vs_fixed_rule"] = res["fixed_rule"]["time_to_eps_s"] / \
+            res["time_to_eps_s"]
+    return res, (Xd, Zd, Ls, x_off, z_off)
 
 
-def long_bench(d, torch, D, X, cap, colors, steps=2):
-    """Long single signal (T = 5,000,000): time-to-eps on the device."""
+def cpu_baseline_batch(D, Ts, Xs, sched, budget_s=12.0):
+    """The FP64 C oracle, single thread, on the first signals of the batch
+    (one after another) until about budget_s seconds of work."""
+    import oracle
     K, P, W = D.shape
-    dev = torch.device("cuda:0")
-    Xd = torch.from_numpy(X).to(dev)
-    Zd = torch.empty((K, X.shape[1] - W + 1), dtype=torch.float64, device=dev)
-    with d.Context(update_cap=cap, colors=colors) as c:
-        c.set_dictionary(D)
-        c.solve_device(Xd, -0.1, 1e-6, 0, Zd)
-        torch.cuda.synchronize()
+    C, cap = sched["colors"], sched["update_cap"]
+    t_all, upd, n = 0.0, 0, 0
+    for X, T in zip(Xs, Ts):
+        L = int(T) - W + 1
+        M = sched["n_seg"](L)
+        X64, D64 = X.astype(np.float64), D.astype(np.float64)
         t0 = time.perf_counter()
-        for _ in range(steps):
-            _, st, _ = c.solve_device(Xd, -0.1, 1e-6, 0, Zd)
-        torch.cuda.synchronize()
-        t = (time.perf_counter() - t0) / steps
-    return {"workload": f"single signal P={P} K={K} W={W} T={X.shape[1]}, rho=0.007, "
-                        "sigma=0.1, lambda=0.1*lambda_max, eps=1e-6",
-            "precision": "FP32 descent, FP64 beta init and stop test",
-            "time_to_eps_s": t, "updates": st["n_updates"], "updates_per_s": st["n_updates"] / t,
-            "n_seg": st["n_seg"], "n_phases": st["n_phases"], "t_init_ms": st["t_init_ms"],
-            "t_cd_ms": st["t_cd_ms"], "t_verify_ms": st["t_verify_ms"],
-            "round_updates": st["round_updates"], "round_ms": st["round_ms"],
-            "converged": st["converged"]}
+        lam = 0.1 * oracle.lambda_max(X64, D64)
+        _, st, _ = oracle.lgcd(X64, D64, lam, EPS, M, cap=cap, colors=C)
+        t_all += time.perf_counter() - t0
+        upd += st["n_updates"]
+        n += 1
+        if t_all >= budget_s:
+            break
+    return {"value": upd / t_all, "unit": "coord updates/s", "cores": 1, "kind": "oracle",
+            "time_s": t_all, "n_updates": int(upd),
+            "sample": f"the first {n} of the {len(Ts)} signals of the same batch "
+                      f"({int(sum(Ts[:n]))} samples), lambda_max and the full solve to "
+                      f"eps = 1e-6 each, by the FP64 C oracle on one host thread under the "
+                      f"GPU run's schedule ({C} colours, cap {cap}, same segment counts)"}
 
 
-def served_bench(d, torch, D, pool_T, pool_X, n_req, cap, colors, seed):
-    """Poisson stream through dicod_submit / dicod_poll vs requests solved alone."""
+def seg_rule(W, entry):
+    def min_segment(C):
+        return max(max(W - 1, 1), (2 * W - 2 + C - 2) // (C - 1))
+    if entry is None:
+        return lambda L: max(1, L // min_segment(3))
+
+    def f(L):
+        M = max(1, min(-(-L // entry["seg_len"]), L))
+        if M > 1 and L // M < min_segment(entry["colors"]):
+            M = max(1, L // min_segment(entry["colors"]))
+        return M
+    return f
+
+
+def served_bench(d, torch, args, D, base, cfg):
+    """Poisson stream of windows of a long recording through submit / poll."""
     import threading
     import synth
     K, P, W = D.shape
-    Lmax = max(int(T) for T in pool_T) - W + 1
-    out_buf = torch.empty(K * Lmax, dtype=torch.float64, pin_memory=True).numpy()
-    npool = len(pool_X)
-    res = {"workload": f"requests drawn from {npool} signals with T log-uniform in [2000, "
-                       f"2000000], P={P} K={K} W={W}, rho=0.007, sigma=0.1, "
-                       "lambda=0.1*lambda_max, eps=1e-6",
-           "requests": n_req}
+    n_req, n_warm = args.served_requests, args.served_warmup
+    n_all = n_req + n_warm
+    rng = np.random.Generator(np.random.PCG64(args.seed + 23))
+    Ts = synth.served_lengths(n_all, 2_000, 2_000_000, args.seed + 22)
+    offs = [int(rng.integers(0, base.shape[1] - int(T) + 1)) for T in Ts]
 
-    def run_stream(c, rate):
-        """Submits n_req requests (closed batch if rate is None) and polls
-        them; returns (makespan s, client latencies ms, server latencies ms,
-        updates)."""
-        arrivals = (np.zeros(n_req) if rate is None else
-                    synth.poisson_arrivals(n_req, rate, seed + int(rate or 0)))
-        t_sub = [0.0] * n_req
-        ids = [None] * n_req
-        done = {}
+    def req(i):
+        return np.ascontiguousarray(base[:, offs[i]:offs[i] + int(Ts[i])])
+
+    Lmax = int(Ts.max()) - W + 1
+    out_buf = torch.empty(K * Lmax, dtype=torch.float64, pin_memory=True).numpy()
+    res = {"workload": f"{n_req} requests after {n_warm} warm-up requests: windows of "
+                       f"log-uniform length in [2000, 2000000] at random offsets of a "
+                       f"{base.shape[1]}-sample recording, P={P} K={K} W={W}, rho=0.007, "
+                       "sigma=0.1, lambda=0.1*lambda_max, eps=1e-6",
+           "requests": n_req, "warmup_requests": n_warm,
+           "distinct_lengths": int(len(set(int(t) for t in Ts[n_warm:])))}
+
+    def run_stream(c, idx, rate, seed):
+        arrivals = (np.zeros(len(idx)) if rate is None else
+                    synth.poisson_arrivals(len(idx), rate, seed))
+        t_sub = {}
+        ids = {}
         start = time.perf_counter()
 
         def submitter():
-            for i in range(n_req):
-                dt = start + arrivals[i] - time.perf_counter()
+            for a, i in zip(arrivals, idx):
+                X = req(i)
+                dt = start + a - time.perf_counter()
                 if dt > 0:
                     time.sleep(dt)
                 t_sub[i] = time.perf_counter()
-                ids[i] = c.submit(pool_X[i % npool], -0.1, 1e-6)
+                ids[i] = c.submit(X, LAM, EPS)
 
         th = threading.Thread(target=submitter)
         th.start()
-        lat_c, lat_s, upd = [], [], 0
-        while len(done) < n_req:
-            for i in range(n_req):
-                if i in done or ids[i] is None:
+        done, lat_c, lat_s, upd = {}, [], [], 0
+        while len(done) < len(idx):
+            for i in idx:
+                if i in done or i not in ids:
                     continue
-                ok, _, st = c.poll(ids[i], int(pool_T[i % npool]), out_buf)
+                ok, _, st = c.poll(ids[i], int(Ts[i]), out_buf)
                 if ok:
                     done[i] = time.perf_counter()
                     lat_c.append(1e3 * (done[i] - t_sub[i]))
@@ -235,265 +359,204 @@ def served_bench(d, torch, D, pool_T, pool_X, n_req, cap, colors, seed):
         th.join()
         return max(done.values()) - start, np.array(lat_c), np.array(lat_s), upd
 
-    with d.Context(update_cap=cap, colors=colors) as c:
+    warm = list(range(n_warm))
+    timed = list(range(n_warm, n_all))
+    with d.Context(autotune=0, **cfg) as c:
         c.set_dictionary(D)
-        # alone: every distinct request solved by itself
+        # served requests run the config's schedule (3 colours, the fixed
+        # segment rule); the one-shot "alone" solves below use the same
+        res["schedule"] = "fixed rule (3 colours, automatic cap)"
+        # alone: a sample of the timed requests solved one at a time
         alone, upd_alone = [], 0
-        for i in range(min(n_req, npool)):
+        for i in timed[:args.served_alone]:
+            X = req(i)
             t0 = time.perf_counter()
-            _, st = c.solve(pool_X[i], -0.1, 1e-6)
+            _, st = c.solve(X, LAM, EPS)
             alone.append(1e3 * (time.perf_counter() - t0))
             upd_alone += st["n_updates"]
         alone = np.array(alone)
-        res["alone"] = {"p50_ms": float(np.percentile(alone, 50)),
+        res["alone"] = {"requests": len(alone), "p50_ms": float(np.percentile(alone, 50)),
                         "p99_ms": float(np.percentile(alone, 99)),
-                        "requests_per_s": 1e3 / alone.mean(),
                         "updates_per_s": upd_alone / (alone.sum() / 1e3)}
-        run_stream(c, None)  # warm-up of the serving path
-        mk, lc, ls, upd = run_stream(c, None)
+        log("served: alone done")
+        run_stream(c, warm, None, 0)
+        mk, lc, ls, upd = run_stream(c, timed, None, 0)
         sat = n_req / mk
         res["saturation"] = {"requests_per_s": sat, "updates_per_s": upd / mk,
-                             "makespan_s": mk}
+                             "makespan_s": mk, "p50_ms": float(np.percentile(lc, 50)),
+                             "p99_ms": float(np.percentile(lc, 99))}
+        log(f"served: saturation {sat:.1f} req/s")
         for frac in (0.5, 0.8):
-            mk, lc, ls, upd = run_stream(c, frac * sat)
+            mk, lc, ls, upd = run_stream(c, timed, frac * sat, args.seed + int(100 * frac))
             res[f"rate_{frac}"] = {"rate_per_s": frac * sat,
                                    "p50_ms": float(np.percentile(lc, 50)),
                                    "p99_ms": float(np.percentile(lc, 99)),
                                    "server_p50_ms": float(np.percentile(ls, 50)),
                                    "server_p99_ms": float(np.percentile(ls, 99)),
                                    "updates_per_s": upd / mk}
+            log(f"served: rate {frac} done")
+        table = c.tuning()
+    # roofline of the served kernels: the largest request of the stream solved
+    # one-shot under the same table with kernel timing (the serving loop
+    # launches the same phase kernel)
+    big = max(timed, key=lambda i: int(Ts[i]))
+    dev = torch.device("cuda:0")
+    Xb = torch.from_numpy(req(big)).to(dev).reshape(-1)
+    Lb = int(Ts[big]) - W + 1
+    Zb = torch.empty(K * Lb, dtype=torch.float64, device=dev)
+    with d.Context(autotune=0, timing=1, **cfg) as c:
+        c.set_dictionary(D)
+        for e in table:
+            c.set_tuning(e)
+        sts = c.solve_batch_device(Xb, [int(Ts[big])], [0], [LAM], EPS, None, Zb, [0])
+    tst = round_totals(sts)
+    res["roofline"] = roofline(tst, K, W, "c5", -(-Lb // sts[0]["n_seg"]))
+    if res["roofline"]:
+        res["roofline"]["measured_on"] = (f"the stream's longest request (T={int(Ts[big])}) "
+                                          "solved one-shot under the serving schedule")
     return res
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--cap", type=int, default=-1,
-                    help="updates per segment per phase (-1: the library's automatic cap)")
-    ap.add_argument("--n-seg", type=int, default=0, help="0 = library default")
-    ap.add_argument("--colors", type=int, default=3, help="phase classes of the schedule")
+    ap.add_argument("--only", default="all", help="all, or a comma list of c2,c3,c4,c5")
+    ap.add_argument("--no-tune", action="store_true", help="fixed segment rule, no autotuner")
+    ap.add_argument("--schedule", default="", metavar="C,SEG,CAP",
+                    help="a given schedule for every workload (profiling runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-sweep", action="store_true")
+    ap.add_argument("--no-per-signal", action="store_true")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="first run one plain device copy of MIB MiB (counter calibration)")
-    ap.add_argument("--no-batched", action="store_true")
-    ap.add_argument("--no-served", action="store_true")
-    ap.add_argument("--no-long", action="store_true")
     ap.add_argument("--batch-signals", type=int, default=256)
-    ap.add_argument("--served-requests", type=int, default=200)
+    ap.add_argument("--served-requests", type=int, default=2000)
+    ap.add_argument("--served-warmup", type=int, default=200)
+    ap.add_argument("--served-alone", type=int, default=200)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; --gpus "
-                                   f"{args.gpus} is not supported (multi-GPU sharding is "
-                                   "a design only)"}))
+                                   f"{args.gpus} is not supported (sharding across GPUs "
+                                   "is a design only)"}))
         sys.exit(2)
+    only = set(["c2", "c3", "c4", "c5"] if args.only == "all" else args.only.split(","))
 
     import torch
     import synth
     import paper_1705_10087_amd as d
 
-    # inputs of the batched and served workloads, drawn before the GPU starts
-    batch_data = served_data = long_data = None
-    if not args.no_batched:
-        a = synth.BATCH_ATOM
-        Db = synth.dictionary(np.random.Generator(np.random.PCG64(args.seed + 11)),
-                              a["K"], a["P"], a["W"]).astype(np.float32)
-        Tb = synth.batch_lengths(args.batch_signals, 10_000, 500_000, args.seed + 12)
-        Xb = gen_signals(a["P"], a["K"], a["W"], Tb, a["rho"], a["sigma_noise"],
-                         args.seed + 1000, Db)
-        batch_data = (Db, Tb, Xb)
-        print(f"[bench] batched inputs: {len(Tb)} signals, {int(Tb.sum())} samples",
-              file=sys.stderr, flush=True)
-    if not args.no_long:
+    # ---- inputs, drawn before the GPU starts -------------------------------
+    a = synth.BATCH_ATOM
+    Db = synth.dictionary(np.random.Generator(np.random.PCG64(args.seed + 11)),
+                          a["K"], a["P"], a["W"]).astype(np.float32)
+    Tb = synth.batch_lengths(args.batch_signals, 10_000, 500_000, args.seed + 12)
+    if "c4" in only:
+        Xb = [synth.generate_conv(a["P"], a["K"], a["W"], int(T), a["rho"], a["sigma_noise"],
+                                  args.seed + 1000 + i, Db) for i, T in enumerate(Tb)]
+        log(f"c4 inputs: {len(Tb)} signals, {int(Tb.sum())} samples")
+    if "c2" in only:
+        X2, D2, _ = synth.workload(synth.PAPER, args.seed)
+    if "c3" in only:
         w = synth.LONG
-        Dl = synth.dictionary(np.random.Generator(np.random.PCG64(args.seed + 31)),
+        D3 = synth.dictionary(np.random.Generator(np.random.PCG64(args.seed + 31)),
                               w.K, w.P, w.W).astype(np.float32)
-        long_data = (Dl, synth.generate_fast(w.P, w.K, w.W, w.T, w.rho, w.sigma_noise,
-                                             args.seed + 32, Dl))
-        print(f"[bench] long input: T={w.T}", file=sys.stderr, flush=True)
-    if not args.no_served:
-        Ds = synth.dictionary(np.random.Generator(np.random.PCG64(args.seed + 21)),
+        X3 = synth.generate_conv(w.P, w.K, w.W, w.T, w.rho, w.sigma_noise, args.seed + 32, D3)
+        log("c3 input ready")
+    if "c5" in only:
+        D5 = synth.dictionary(np.random.Generator(np.random.PCG64(args.seed + 21)),
                               25, 7, 200).astype(np.float32)
-        Ts = synth.served_lengths(min(64, args.served_requests), 2_000, 2_000_000,
-                                  args.seed + 22)
-        Xs = gen_signals(7, 25, 200, Ts, 0.007, 0.1, args.seed + 5000, Ds)
-        served_data = (Ds, Ts, Xs)
-        print(f"[bench] served inputs: {len(Ts)} signals, {int(Ts.sum())} samples",
-              file=sys.stderr, flush=True)
+        base5 = synth.generate_conv(7, 25, 200, 20_000_000, 0.007, 0.1, args.seed + 5000, D5)
+        log("c5 recording ready")
 
-    w = synth.PAPER
-    X, D, _ = synth.workload(w, args.seed)
-    K, P, W = D.shape
-    T = X.shape[1]
-    L = T - W + 1
     dev = torch.device("cuda:0")
-    Xd = torch.from_numpy(X).to(dev)
-    Zd = torch.empty((K, L), dtype=torch.float64, device=dev)
-    stream = torch.cuda.current_stream(dev).cuda_stream
     if args.copy_calib > 0:
         # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE readings
-        # convert the counters of the LGCD kernels into bytes
+        # convert the counters of the phase kernel into bytes
         n = args.copy_calib * (1 << 20) // 4
-        a = torch.ones(n, dtype=torch.float32, device=dev)
-        b = torch.empty_like(a)
+        x = torch.ones(n, dtype=torch.float32, device=dev)
+        y = torch.empty_like(x)
         torch.cuda.synchronize()
-        b.copy_(a)
+        y.copy_(x)
         torch.cuda.synchronize()
-        del a, b
-    print(f"[bench] workload {w.name}; steps={args.steps} warmup={args.warmup}",
-          file=sys.stderr, flush=True)
+        del x, y
 
-    with d.Context(update_cap=args.cap, colors=args.colors) as c:
-        c.set_dictionary(D)
-        for i in range(args.warmup):
-            _, st, _ = c.solve_device(Xd, -w.lam_rel, w.eps, args.n_seg, Zd, stream)
-        torch.cuda.synchronize()
-        stats = []
-        t0 = time.perf_counter()
-        for i in range(args.steps):
-            _, st, _ = c.solve_device(Xd, -w.lam_rel, w.eps, args.n_seg, Zd, stream)
-            stats.append(st)
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        print(f"[bench] timed {args.steps} solves in {wall:.3f} s", file=sys.stderr, flush=True)
+    fp32 = dict(precision=d.DICOD_PREC_FP32, fp64_polish_after=2, max_phases=200_000)
+    mixed = dict(precision=d.DICOD_PREC_MIXED, fp64_polish_after=0, max_phases=200_000)
+    configs = {}
+    head = None
+    if "c4" in only:
+        log("c4: batched")
+        res, _ = run_solver_workload(d, torch, args, "c4", Db, Tb, Xb, args.steps, args.warmup,
+                                     fp32, trials=12, per_signal=not args.no_per_signal)
+        res["workload"] = (f"{len(Tb)} signals, T uniform in [10000, 500000], P=7 K=25 W=64, "
+                           "rho=0.005, sigma=0.1, lambda=0.1*lambda_max per signal, eps=1e-6, "
+                           "one batched call")
+        res["precision"] = ("FP32 descent rounds from the double beta (FP64 MFMA), a double-"
+                            "state finish round after two failed double checks, double "
+                            "stop test")
+        head = res
+        log(f"c4: {res['time_to_eps_s']:.4f} s per batch")
+    if "c2" in only:
+        log("c2: paper-shaped")
+        res, _ = run_solver_workload(d, torch, args, "c2", D2, [X2.shape[1]], [X2],
+                                     max(args.steps, 10), 2, dict(fp32, fp64_polish_after=1),
+                                     trials=12)
+        res["workload"] = synth.PAPER.name + ", rho=0.007, sigma=0.1, lambda=0.1*lambda_max"
+        res["precision"] = ("FP32 descent from the double beta, a double-state finish "
+                            "round after the first failed double check, double stop test")
+        configs["c2"] = res
+    if "c3" in only:
+        log("c3: long, split-bf16")
+        res, _ = run_solver_workload(d, torch, args, "c3", D3, [X3.shape[1]], [X3],
+                                     max(2, args.steps), 1, mixed, trials=8)
+        res["workload"] = synth.LONG.name + ", rho=0.007, sigma=0.1, lambda=0.1*lambda_max"
+        res["precision"] = ("split-bf16 MFMA beta with fp32 accumulation, FP32 descent with "
+                            "refresh from the double check, no double descent round; "
+                            "lambda_max exact (near-maximal entries recomputed in double)")
+        configs["c3"] = res
+    if "c5" in only:
+        log("c5: served")
+        configs["c5"] = served_bench(d, torch, args, D5, base5, dict(fp32, fp64_polish_after=1))
+        configs["c5"]["precision"] = ("FP32 descent from the double beta, a double finish "
+                                      "round after the first failed check, double stop test")
 
-    with d.Context(update_cap=args.cap, timing=1, colors=args.colors) as c:
-        c.set_dictionary(D)
-        _, tst, _ = c.solve_device(Xd, -w.lam_rel, w.eps, args.n_seg, Zd, stream)
-        torch.cuda.synchronize()
-
-    n_upd = sum(s["n_updates"] for s in stats)
-    ms_per_step = 1e3 * wall / args.steps
-    bpu = algorithmic_bytes_per_update(K, W)
-    # dominant kernel: the float LDS-state phase kernel of the first round
-    # (the double finish round, if any, runs the HBM-state kernel)
-    assert tst["round_state"][0] == 0, "first round expected on the float LDS-state kernel"
-    launches = tst["round_launches"][0]
-    kern_ms = tst["round_kernel_ms"][0]
-    upd0 = tst["round_updates"][0]
-    achieved = (upd0 * bpu / launches) / (kern_ms / launches * 1e-3) / 1e9
-    traffic = measured_traffic()
-    s0 = stats[-1]
+    if head is None:
+        key = sorted(configs)[0]
+        head = configs.pop(key)
+        head_name = key
+    else:
+        head_name = "c4"
     out = {
         "metric": "time-to-eps (s) & coord updates/s on 1 MI355X; p50/p99 solve latency "
                   "(served)",
-        "value": n_upd / wall,
+        "value": head.get("updates_per_s", head.get("saturation", {}).get("updates_per_s")),
         "unit": "coord updates/s",
         "n_gpus": 1,
-        "steps": args.steps,
+        "steps": head.get("steps", args.steps),
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
-        "time_to_eps_s": ms_per_step / 1e3,
+        "ms_per_step": 1e3 * head.get("time_to_eps_s", 0.0),
+        "time_to_eps_s": head.get("time_to_eps_s"),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": w.name, "P": P, "K": K, "W": W, "T": T, "rho": w.rho,
-                   "sigma_noise": w.sigma_noise, "lambda": "0.1*lambda_max",
-                   "eps": w.eps, "n_seg": s0["n_seg"], "seg_len": s0["seg_len"],
-                   "update_cap": effective_cap(args.cap, w.W),
-                   "precision": "FP32 descent, FP64 stop test",
-                   "schedule": f"{args.colors}-colour phases", "seed": args.seed},
-        "solve": {"n_updates": s0["n_updates"], "n_phases": s0["n_phases"],
-                  "n_phase_launches": s0["n_phase_launches"], "n_refresh": s0["n_refresh"],
-                  "nnz": s0["nnz"], "objective": s0["objective"], "max_dz": s0["max_dz"],
-                  "converged": s0["converged"], "t_init_ms": s0["t_init_ms"],
-                  "t_cd_ms": s0["t_cd_ms"], "t_verify_ms": s0["t_verify_ms"],
-                  "round_updates": s0["round_updates"], "round_phases": s0["round_phases"],
-                  "round_ms": s0["round_ms"],
-                  "polished_fp64": s0["polished_fp64"]},
-        "roofline": {"kernel": "k_lgcd_phase<float> (LDS state)", "bound": "hbm",
-                     "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
-                     "bytes_per_update": bpu,
-                     "updates_per_launch": upd0 / launches,
-                     "avg_launch_us": 1e3 * kern_ms / launches,
-                     "launches": launches, "kernel_ms": kern_ms},
+        "config": {"workload": head_name + ": " + head.get("workload", ""),
+                   "precision": head.get("precision"), "seed": args.seed,
+                   "schedule": head.get("schedule")},
+        "roofline": head.get("roofline"),
+        "result": {k: v for k, v in head.items() if k not in ("roofline", "workload",
+                                                              "precision", "schedule")},
+        "configs": configs,
     }
-    if tst["round_launches"][1] > 0:
-        l1, k1, u1 = tst["round_launches"][1], tst["round_kernel_ms"][1], tst["round_updates"][1]
-        out["finish_round"] = {"state": "double, HBM" if tst["round_state"][1] & 2
-                               else "double, LDS", "launches": l1, "kernel_ms": k1,
-                               "updates": u1, "avg_launch_us": 1e3 * k1 / l1}
-    # the same solve under each precision policy (time-to-eps, 5 solves each)
-    variants = {}
-    for name, prec in (("FP64", d.DICOD_PREC_FP64), ("FP32", d.DICOD_PREC_FP32),
-                       ("MIXED", d.DICOD_PREC_MIXED)):
-        with d.Context(update_cap=args.cap, colors=args.colors, precision=prec) as c:
-            c.set_dictionary(D)
-            c.solve_device(Xd, -w.lam_rel, w.eps, args.n_seg, Zd, stream)
-            torch.cuda.synchronize()
-            t1 = time.perf_counter()
-            for _ in range(5):
-                _, st, _ = c.solve_device(Xd, -w.lam_rel, w.eps, args.n_seg, Zd, stream)
-            torch.cuda.synchronize()
-            variants[name] = {"time_to_eps_ms": 1e3 * (time.perf_counter() - t1) / 5,
-                              "n_updates": st["n_updates"], "t_init_ms": st["t_init_ms"],
-                              "round_updates": st["round_updates"][:3],
-                              "objective": st["objective"]}
-    out["precision_variants"] = variants
-    # Algorithm 2 in lockstep (DICOD schedule) against the coloured schedule:
-    # time-to-eps, and the interference rate from a traced solve
-    sched = {"coloured": {"time_to_eps_ms": ms_per_step_of(stats, wall, args.steps),
-                          "n_updates": s_last(stats)["n_updates"],
-                          "n_phases": s_last(stats)["n_phases"]}}
-    with d.Context(schedule=d.DICOD_SCHED_DICOD, update_cap=1) as c:
-        c.set_dictionary(D)
-        c.solve_device(Xd, -w.lam_rel, w.eps, args.n_seg, Zd, stream)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        for _ in range(5):
-            _, st, _ = c.solve_device(Xd, -w.lam_rel, w.eps, args.n_seg, Zd, stream)
-        torch.cuda.synchronize()
-        t_dicod = 1e3 * (time.perf_counter() - t1) / 5
-    with d.Context(schedule=d.DICOD_SCHED_DICOD, update_cap=1, trace_capacity=400_000) as c:
-        c.set_dictionary(D)
-        _, stt, _ = c.solve_device(Xd, -w.lam_rel, w.eps, args.n_seg, Zd, stream)
-        torch.cuda.synchronize()
-        tr = c.trace()
-    first = tr[tr["phase"] < stt["round_phases"][0]]   # first (float) round
-    n_adj, n_int = adjacent_pairs(first, W)
-    Lm = (T - W + 1) / stt["n_seg"]
-    sched["dicod_lockstep"] = {
-        "time_to_eps_ms": t_dicod, "n_updates": st["n_updates"], "n_phases": st["n_phases"],
-        "update_cap": 1, "n_seg": stt["n_seg"],
-        "first_round": {"adjacent_concurrent_pairs": n_adj, "interfering_pairs": n_int,
-                        "interference_rate": n_int / max(n_adj, 1),
-                        "model_paper_(MW/T)^2": min(1.0, (W / Lm) ** 2),
-                        "model_uniform_W^2/(2 L_M^2)": min(1.0, W * W / (2 * Lm * Lm))}}
-    out["schedules"] = sched
-    if not args.no_sweep:
-        sweep = []
-        with d.Context(update_cap=args.cap, colors=args.colors) as c:
-            c.set_dictionary(D)
-            for M in (8, 16, 32, 64, 128, 256, 374, 512, 749):
-                try:
-                    t1 = time.perf_counter()
-                    _, st, _ = c.solve_device(Xd, -w.lam_rel, w.eps, M, Zd, stream)
-                    torch.cuda.synchronize()
-                    sweep.append({"n_seg": M, "time_to_eps_s": time.perf_counter() - t1,
-                                  "n_updates": st["n_updates"], "n_phases": st["n_phases"]})
-                except d.DicodError as e:
-                    sweep.append({"n_seg": M, "error": str(e)[:120]})
-        out["segment_sweep"] = sweep
-    if long_data is not None:
-        out["long"] = long_bench(d, torch, *long_data, args.cap, args.colors)
-        print(f"[bench] long done", file=sys.stderr, flush=True)
-    if batch_data is not None:
-        out["batched"] = batched_bench(d, torch, *batch_data, args.cap, args.colors)
-        print(f"[bench] batched done", file=sys.stderr, flush=True)
-    if served_data is not None:
-        out["served"] = served_bench(d, torch, *served_data, args.served_requests, args.cap,
-                                     args.colors, args.seed)
-        print(f"[bench] served done", file=sys.stderr, flush=True)
-    if not args.no_cpu_baseline:
-        lam = s0["lambda"]
-        out["cpu_baseline"] = cpu_baseline(X, D, lam, w.eps, s0["n_seg"], effective_cap(args.cap, w.W),
-                                           args.colors)
+    if not args.no_cpu_baseline and head_name == "c4":
+        log("cpu baseline (oracle)")
+        sched = {"colors": head["colors"], "update_cap": head["update_cap"],
+                 "n_seg": seg_rule(Db.shape[2], head["schedule"]
+                                   if isinstance(head["schedule"], dict) else None)}
+        out["cpu_baseline"] = cpu_baseline_batch(Db, Tb, Xb, sched)
     print(json.dumps(out), flush=True)
 
 

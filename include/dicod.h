@@ -115,6 +115,11 @@ typedef struct {
     int reg_state;           /* 1 = float rounds keep each position's state in the   */
                              /* registers of one thread (segments of at most 256     */
                              /* positions, K <= 32); 0 = LDS / HBM state kernels only */
+    int autotune;            /* 1 = solves with n_seg = 0 take colours, update cap   */
+                             /* and segment length from the tuning table entry of    */
+                             /* their length bucket when one exists                  */
+                             /* (dicod_autotune_device); served requests keep the    */
+                             /* config's schedule                                    */
 } dicod_config;
 
 typedef struct {
@@ -140,7 +145,8 @@ typedef struct {
     double t_verify_ms;       /* double-precision checks and refreshes              */
     double t_total_ms;        /* whole call                                         */
     double t_lgcd_kernel_ms;  /* sum of LGCD kernel durations (timing = 1)          */
-    int64_t round_updates[4]; /* updates of the first four descent rounds            */
+    int64_t round_updates[4]; /* updates of the first four descent rounds (of the     */
+                              /* whole call: a batch's signals share the rounds)     */
     int64_t round_phases[4];  /* phases of the first four descent rounds             */
     double round_ms[4];       /* wall time of the first four descent rounds          */
     double round_kernel_ms[4]; /* phase-kernel time of those rounds (timing = 1)     */
@@ -153,7 +159,30 @@ typedef struct {
     double t_latency_ms;      /* served: dicod_submit until the result was complete  */
     double round_max_dz[4];   /* max |Delta Z| of the double check after each of the */
                               /* first four descent rounds                           */
+    int colors;               /* phase classes C the solve ran with                  */
+    int update_cap;           /* updates per segment per phase it ran with (0: none) */
+    int tuned;                /* 1 if colours, cap and M came from the tuning table   */
+    int pad_;
 } dicod_stats;
+
+/* One entry of the autotuner's table: the schedule chosen for the signals of
+ * one length bucket with one dictionary shape. */
+typedef struct {
+    int K, P, W;       /* dictionary shape the entry was tuned for              */
+    int bucket;        /* floor(log2(L)) of the longest signal of the call       */
+    int colors;        /* phase classes C in 2..4                                */
+    int seg_len;       /* longest segment: M = ceil(L / seg_len), raised to the
+                        * fewest segments of at least the minimum length for C   */
+    int update_cap;    /* updates per segment per phase, 1..1024                 */
+    int team_threads;  /* threads per segment of the register-state kernel that
+                        * segments of seg_len positions take (64, 128 or 256;
+                        * 0 = LDS / HBM state kernels); informational            */
+    int trials;        /* configurations timed                                   */
+    int pad_;
+    double ms;         /* best time-to-eps of the chosen schedule while tuning   */
+    double ms_prior;   /* time-to-eps of the starting point: 2 colours, segments
+                        * of 2W (M = L / (2W), Corollary 1), the automatic cap  */
+} dicod_tune_entry;
 
 /* One record per applied update (dicod_get_trace); 32 bytes. */
 typedef struct {
@@ -168,7 +197,7 @@ typedef struct {
 /* Fills *cfg with the defaults: device 0, FP32, coloured phases, update_cap -1,
  * max_phases 1e6, max_refresh 8, phases_per_poll 16, inner_eps_factor 0.5,
  * timing 0, no trace, state_in_lds 1, fp64_polish_after 1, colors 3,
- * verify_from_scratch 0, reg_state 1.  Returns DICOD_OK, or DICOD_EINVAL if
+ * verify_from_scratch 0, reg_state 1, autotune 0.  Returns DICOD_OK, or DICOD_EINVAL if
  * cfg is NULL. */
 int dicod_config_init(dicod_config *cfg);
 
@@ -257,6 +286,40 @@ int dicod_solve_batch_device(dicod_ctx *ctx, int n_sig, const float *X_dev,
                              const double *lambda, double eps, const int *n_seg,
                              double *Z_dev, const int64_t *z_off, dicod_stats *st,
                              void *stream);
+
+/* ---- autotuning of the schedule ---------------------------------------- */
+/* Times complete solves of the given signals (arguments as
+ * dicod_solve_batch_device; Z_dev is overwritten by every trial) under
+ * candidate schedules -- colours C, longest segment length (which also picks
+ * the threads per segment of the register-state kernel) and update cap --
+ * starting from 2 colours with segments of 2W, the optimum M* ~ T / (2W) of
+ * Corollary 1 (Sec. 3), and moving to the neighbouring candidate that is more
+ * than 2% faster (best of two timed solves each) until none is or max_trials
+ * (1..64) schedules have been timed.  The choice is stored in the context's
+ * tuning table under the length bucket floor(log2(max L)) and written to *out
+ * (may be NULL); Z_dev then holds the solution under the chosen schedule.
+ * A solve whose schedule comes from the table depends only on the table and
+ * the length of its longest signal.  Served requests (dicod_submit) do not
+ * use the table: they run the config's colours and cap with the fixed
+ * segment rule (a served pair of tuned requests stopped making progress in
+ * testing, cause not found; that path is switched off).
+ * Errors: EINVAL (as the batch solve; also DICOD schedule, or serving active),
+ * ENOMEM, EDEVICE, ENOTCONV (no candidate converged). */
+int dicod_autotune_device(dicod_ctx *ctx, int n_sig, const float *X_dev,
+                          const int64_t *T, const int64_t *x_off, const double *lambda,
+                          double eps, double *Z_dev, const int64_t *z_off, int max_trials,
+                          dicod_tune_entry *out);
+
+/* Copies up to cap entries of the tuning table (ascending bucket) into out and
+ * their number into *n (out may be NULL with cap 0).  Errors: EINVAL. */
+int dicod_get_tuning(dicod_ctx *ctx, dicod_tune_entry *out, int cap, int *n);
+
+/* Stores one entry (e.g. a cached choice from an earlier process) in the
+ * tuning table, replacing the entry of its bucket; e NULL empties the table.
+ * Errors: EINVAL (shape differs from the resident dictionary, colours outside
+ * 2..4, seg_len below the minimum segment for its colours, update_cap outside
+ * 1..1024, or serving active). */
+int dicod_set_tuning(dicod_ctx *ctx, const dicod_tune_entry *e);
 
 /* Correlation with the resident dictionary, out[k][t] = sum_{p,tau}
  * D_k[p][tau] X[p][t + tau] for t < L (beta at Z = 0, Algorithm 1 init),

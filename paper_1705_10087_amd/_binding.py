@@ -58,6 +58,7 @@ class dicod_config(ctypes.Structure):
         ("colors", ctypes.c_int),
         ("verify_from_scratch", ctypes.c_int),
         ("reg_state", ctypes.c_int),
+        ("autotune", ctypes.c_int),
     ]
 
 
@@ -96,6 +97,10 @@ class dicod_stats(ctypes.Structure):
         ("t_queue_ms", ctypes.c_double),
         ("t_latency_ms", ctypes.c_double),
         ("round_max_dz", ctypes.c_double * 4),
+        ("colors", ctypes.c_int),
+        ("update_cap", ctypes.c_int),
+        ("tuned", ctypes.c_int),
+        ("pad_", ctypes.c_int),
     ]
 
     def to_dict(self):
@@ -105,6 +110,36 @@ class dicod_stats(ctypes.Structure):
             d[name] = list(v) if isinstance(v, ctypes.Array) else v
         d["lambda"] = d.pop("lambda_")
         return d
+
+
+class dicod_tune_entry(ctypes.Structure):
+    _fields_ = [
+        ("K", ctypes.c_int),
+        ("P", ctypes.c_int),
+        ("W", ctypes.c_int),
+        ("bucket", ctypes.c_int),
+        ("colors", ctypes.c_int),
+        ("seg_len", ctypes.c_int),
+        ("update_cap", ctypes.c_int),
+        ("team_threads", ctypes.c_int),
+        ("trials", ctypes.c_int),
+        ("pad_", ctypes.c_int),
+        ("ms", ctypes.c_double),
+        ("ms_prior", ctypes.c_double),
+    ]
+
+    def to_dict(self):
+        d = {name: getattr(self, name) for name, _ in self._fields_}
+        d.pop("pad_")
+        return d
+
+    @classmethod
+    def from_dict(cls, d):
+        e = cls()
+        for name, _ in cls._fields_:
+            if name in d:
+                setattr(e, name, d[name])
+        return e
 
 
 TRACE_DTYPE = np.dtype([("phase", np.int32), ("seg", np.int32), ("k0", np.int32),
@@ -144,9 +179,14 @@ def lib():
     L.dicod_get_trace.argtypes = [_vp, _vp, i64, ctypes.POINTER(i64)]
     L.dicod_submit.argtypes = [_vp, _vp, i64, cd, cd, ci, ctypes.POINTER(ctypes.c_uint64)]
     L.dicod_poll.argtypes = [_vp, ctypes.c_uint64, _vp, ps]
+    pe = ctypes.POINTER(dicod_tune_entry)
+    L.dicod_autotune_device.argtypes = [_vp, ci, _vp, _vp, _vp, _vp, cd, _vp, _vp, ci, pe]
+    L.dicod_get_tuning.argtypes = [_vp, pe, ci, ctypes.POINTER(ci)]
+    L.dicod_set_tuning.argtypes = [_vp, pe]
     for name in ("dicod_config_init", "dicod_init", "dicod_set_dictionary", "dicod_solve",
-                 "dicod_solve_device", "dicod_solve_device_noalloc", "dicod_solve_batch_device", "dicod_correlate",
-                 "dicod_get_s_table", "dicod_get_trace", "dicod_submit", "dicod_poll"):
+                 "dicod_solve_device", "dicod_solve_device_noalloc", "dicod_solve_batch_device",
+                 "dicod_correlate", "dicod_get_s_table", "dicod_get_trace", "dicod_submit",
+                 "dicod_poll", "dicod_autotune_device", "dicod_get_tuning", "dicod_set_tuning"):
         getattr(L, name).restype = ci
     _lib = L
     return L
@@ -276,6 +316,38 @@ def dicod_solve_batch_device(ctx, X_dev, T, x_off, lam, eps, n_seg, Z_dev, z_off
     return [st[i].to_dict() for i in range(n)]
 
 
+def dicod_autotune_device(ctx, X_dev, T, x_off, lam, eps, Z_dev, z_off, max_trials=16):
+    """Tunes the schedule on packed device signals (layout as the batch solve);
+    returns the chosen entry as a dict.  Runs on the context's stream, after
+    the current torch stream has finished writing X_dev."""
+    n = len(T)
+    T = np.ascontiguousarray(T, dtype=np.int64)
+    x_off = np.ascontiguousarray(x_off, dtype=np.int64)
+    z_off = np.ascontiguousarray(z_off, dtype=np.int64)
+    lam = np.ascontiguousarray(lam, dtype=np.float64)
+    torch.cuda.current_stream(X_dev.device).synchronize()
+    e = dicod_tune_entry()
+    rc = lib().dicod_autotune_device(ctx, n, _vp(X_dev.data_ptr()), _np_ptr(T), _np_ptr(x_off),
+                                     _np_ptr(lam), float(eps), _vp(Z_dev.data_ptr()),
+                                     _np_ptr(z_off), int(max_trials), ctypes.byref(e))
+    _check(ctx, rc)
+    return e.to_dict()
+
+
+def dicod_get_tuning(ctx):
+    n = ctypes.c_int(0)
+    _check(ctx, lib().dicod_get_tuning(ctx, None, 0, ctypes.byref(n)))
+    arr = (dicod_tune_entry * max(n.value, 1))()
+    _check(ctx, lib().dicod_get_tuning(ctx, arr, n.value, ctypes.byref(n)))
+    return [arr[i].to_dict() for i in range(n.value)]
+
+
+def dicod_set_tuning(ctx, entry):
+    """entry: dict of dicod_tune_entry fields, or None to empty the table."""
+    e = None if entry is None else ctypes.byref(dicod_tune_entry.from_dict(entry))
+    _check(ctx, lib().dicod_set_tuning(ctx, e))
+
+
 def dicod_correlate(ctx, X, K, W, precision=DICOD_PREC_FP64):
     X = np.ascontiguousarray(X, dtype=np.float32)
     P, T = X.shape
@@ -366,6 +438,29 @@ class Context:
     def solve_batch_device(self, X_dev, T, x_off, lam, eps, n_seg, Z_dev, z_off, stream=None):
         return dicod_solve_batch_device(self.h, X_dev, T, x_off, lam, eps, n_seg, Z_dev,
                                         z_off, stream)
+
+    def autotune_device(self, X_dev, T, x_off, lam, eps, Z_dev, z_off, max_trials=16):
+        return dicod_autotune_device(self.h, X_dev, T, x_off, lam, eps, Z_dev, z_off,
+                                     max_trials)
+
+    def tuning(self):
+        return dicod_get_tuning(self.h)
+
+    def set_tuning(self, entry):
+        dicod_set_tuning(self.h, entry)
+
+    def save_tuning(self, path):
+        """Writes the tuning table to a JSON file (the cache of chosen schedules)."""
+        import json
+        with open(path, "w") as f:
+            json.dump(self.tuning(), f, indent=1)
+
+    def load_tuning(self, path):
+        """Loads a tuning table written by save_tuning into this context."""
+        import json
+        with open(path) as f:
+            for e in json.load(f):
+                self.set_tuning(e)
 
     def correlate(self, X, precision=DICOD_PREC_FP64):
         return dicod_correlate(self.h, X, self.K, self.W, precision)

@@ -19,6 +19,8 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <limits>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -135,6 +137,10 @@ struct dicod_ctx {
     std::vector<hipEvent_t> ev_pool;
     int64_t last_trace_n = 0;
     dicod::Server* server = nullptr;
+    // autotuner: chosen schedule per length bucket, and the schedule forced on
+    // the solves of a tuning trial
+    std::map<int, dicod_tune_entry> tuning;
+    const dicod_tune_entry* sched_force = nullptr;
 };
 
 namespace {
@@ -226,6 +232,31 @@ int auto_segments(int64_t L, int W, int C)
     return M < 1 ? 1 : (int)std::min<int64_t>(M, INT32_MAX);
 }
 
+// Length bucket of the tuning table: floor(log2(L)).
+int length_bucket(int64_t L)
+{
+    int b = 0;
+    while (L > 1) {
+        L >>= 1;
+        ++b;
+    }
+    return b;
+}
+
+// Segment count for a longest segment of seg_len positions: ceil(L / seg_len),
+// lowered to the largest count that keeps every segment at least
+// min_segment(W, C) long.
+int tuned_segments(int64_t L, int W, int C, int seg_len)
+{
+    int64_t M = (L + seg_len - 1) / std::max(seg_len, 1);
+    M = std::max<int64_t>(1, std::min<int64_t>(M, L));
+    if (M > 1 && L / M < min_segment(W, C))
+        M = auto_segments(L, W, C);
+    return (int)std::min<int64_t>(M, INT32_MAX);
+}
+
+bool find_tuning(const dicod_ctx* ctx, int bucket, dicod_tune_entry* e);
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -253,6 +284,7 @@ extern "C" int dicod_config_init(dicod_config* cfg)
     cfg->colors = 3;
     cfg->verify_from_scratch = 0;
     cfg->reg_state = 1;
+    cfg->autotune = 0;
     return DICOD_OK;
 }
 
@@ -277,7 +309,7 @@ extern "C" int dicod_init(dicod_ctx** out, const dicod_config* cfg)
     if (c.update_cap < -1 || c.max_phases < 2 || c.max_refresh < 0 ||
         c.phases_per_poll < 1 || !(c.inner_eps_factor > 0.0 && c.inner_eps_factor <= 1.0) ||
         c.trace_capacity < 0 || c.max_inflight < 1 || c.fp64_polish_after < 0 ||
-        c.colors < 2 || c.colors > kMaxColors)
+        c.colors < 2 || c.colors > kMaxColors || c.autotune < 0 || c.autotune > 1)
         return fail(nullptr, DICOD_EINVAL, "dicod_init: invalid configuration field");
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0)
@@ -536,7 +568,7 @@ bool state_fits(const Plan& pl, int K, bool fp64, bool allow_lds, bool* in_lds)
     return lgcd_gm_lds_bytes(K, pl.lext_max, fp64) <= kLdsBytes;
 }
 
-int make_plan(dicod_ctx* ctx, int n_sig, const int64_t* T, const int64_t* x_off,
+int make_plan(dicod_ctx* ctx, int colors, int n_sig, const int64_t* T, const int64_t* x_off,
               const double* lam, const int* n_seg, const int64_t* z_off, Plan& pl)
 {
     const int K = ctx->K, W = ctx->W;
@@ -544,7 +576,7 @@ int make_plan(dicod_ctx* ctx, int n_sig, const int64_t* T, const int64_t* x_off,
     if (check_kblocks(K, W) < 1)
         return fail(ctx, DICOD_ENOTSUP, "W=%d: one row of S does not fit the check kernel", W);
     pl.dicod = ctx->cfg.schedule == DICOD_SCHED_DICOD;
-    pl.colors = pl.dicod ? 1 : ctx->cfg.colors;
+    pl.colors = pl.dicod ? 1 : colors;
     pl.sig.resize(n_sig);
     pl.prefL.assign(n_sig + 1, 0);
     pl.prefC.assign(n_sig + 1, 0);
@@ -671,11 +703,39 @@ int solve_device_batch(dicod_ctx* ctx, int n_sig, const float* dX, const int64_t
         return fail(ctx, DICOD_EINVAL, "solve: eps must be finite and > 0");
     const int K = ctx->K, P = ctx->P, W = ctx->W;
     const bool fp64 = ctx->cfg.precision == DICOD_PREC_FP64;
-    const dicod_config& cfg = ctx->cfg;
+    dicod_config cfg = ctx->cfg;  // colours and cap may come from the tuning table
     Workspace& ws = t_arena ? ctx->ws_scratch : ctx->ws;
 
+    std::vector<int> m_tuned;
+    int tuned = 0;
+    {
+        bool all_auto = true;
+        for (int i = 0; n_seg && i < n_sig; ++i)
+            all_auto = all_auto && n_seg[i] == 0;
+        dicod_tune_entry e;
+        bool have = false;
+        if (ctx->sched_force) {
+            e = *ctx->sched_force;
+            have = true;
+        } else if (cfg.autotune && all_auto && cfg.schedule == DICOD_SCHED_EVENODD) {
+            int64_t lmax = 0;
+            for (int i = 0; i < n_sig; ++i)
+                lmax = std::max(lmax, T[i] - W + 1);
+            have = find_tuning(ctx, length_bucket(lmax), &e);
+        }
+        if (have) {
+            cfg.colors = e.colors;
+            cfg.update_cap = e.update_cap;
+            m_tuned.resize(n_sig);
+            for (int i = 0; i < n_sig; ++i)
+                m_tuned[i] = T[i] >= W ? tuned_segments(T[i] - W + 1, W, e.colors, e.seg_len) : 0;
+            n_seg = m_tuned.data();
+            tuned = 1;
+        }
+    }
+
     Plan pl;
-    int rc = make_plan(ctx, n_sig, T, x_off, lam_in, n_seg, z_off, pl);
+    int rc = make_plan(ctx, cfg.colors, n_sig, T, x_off, lam_in, n_seg, z_off, pl);
     if (rc != DICOD_OK)
         return rc;
     const int n_seg_tot = (int)pl.segs.size();
@@ -1265,7 +1325,7 @@ int solve_device_batch(dicod_ctx* ctx, int n_sig, const float* dX, const int64_t
             o.t_lgcd_kernel_ms = t_kernel;
             for (int r = 0; r < 4; ++r) {
                 o.round_max_dz[r] = round_mdz[(size_t)i * 4 + r];
-                o.round_updates[r] = n_sig == 1 ? round_upd[r] : 0;
+                o.round_updates[r] = round_upd[r];
                 o.round_phases[r] = round_ph[r];
                 o.round_ms[r] = round_ms[r];
                 o.round_kernel_ms[r] = round_kms[r];
@@ -1274,6 +1334,9 @@ int solve_device_batch(dicod_ctx* ctx, int n_sig, const float* dX, const int64_t
             }
             o.state_in_hbm = any_hbm ? 1 : 0;
             o.polished_fp64 = polished ? 1 : 0;
+            o.colors = pl.colors;
+            o.update_cap = cfg.update_cap == 0 ? 0 : effective_update_cap(cfg.update_cap, W);
+            o.tuned = tuned;
         }
     }
     if (!accepted)
@@ -1483,8 +1546,241 @@ extern "C" int dicod_poll(dicod_ctx* ctx, uint64_t req_id, double* Z_out, dicod_
     return dicod::server_poll(ctx, req_id, Z_out, st);
 }
 
+// ---------------------------------------------------------------------------
+// autotuner
+// ---------------------------------------------------------------------------
+namespace {
+
+bool find_tuning(const dicod_ctx* ctx, int bucket, dicod_tune_entry* e)
+{
+    auto it = ctx->tuning.find(bucket);
+    if (it == ctx->tuning.end() || it->second.K != ctx->K || it->second.P != ctx->P ||
+        it->second.W != ctx->W)
+        return false;
+    *e = it->second;
+    return true;
+}
+
+int team_threads_for(int K, int seg_len, int cap)
+{
+    if (!lgcd_wave_supported(K, seg_len, cap, false))
+        return 0;
+    return seg_len <= 64 ? 64 : seg_len <= 128 ? 128 : 256;
+}
+
+// Candidate longest-segment lengths for C colours: the shortest legal one,
+// the register kernel's team boundaries, and multiples of W.
+std::vector<int> seg_ladder(int W, int C, int64_t lmax)
+{
+    const int lo = (int)min_segment(W, C);
+    std::vector<int> v = {lo, 64, 96, 128, 192, 256, 2 * W, 3 * W, 4 * W, 8 * W};
+    std::vector<int> out;
+    for (int x : v)
+        if (x >= lo && x <= lmax)
+            out.push_back(x);
+    if (out.empty())
+        out.push_back((int)std::min<int64_t>(lmax, INT32_MAX));
+    std::sort(out.begin(), out.end());
+    out.erase(std::unique(out.begin(), out.end()), out.end());
+    return out;
+}
+
+}  // namespace
+
+extern "C" int dicod_autotune_device(dicod_ctx* ctx, int n_sig, const float* X_dev,
+                                     const int64_t* T, const int64_t* x_off,
+                                     const double* lambda, double eps, double* Z_dev,
+                                     const int64_t* z_off, int max_trials,
+                                     dicod_tune_entry* out)
+{
+    if (!ctx)
+        return DICOD_EINVAL;
+    ctx->err.clear();
+    if (!ctx->has_dict)
+        return fail(ctx, DICOD_EINVAL, "autotune: no resident dictionary");
+    if (n_sig <= 0 || !X_dev || !T || !x_off || !lambda || !Z_dev || !z_off)
+        return fail(ctx, DICOD_EINVAL, "autotune: NULL argument or n_sig <= 0");
+    if (max_trials < 1 || max_trials > 64)
+        return fail(ctx, DICOD_EINVAL, "autotune: max_trials must be in 1..64");
+    if (ctx->cfg.schedule != DICOD_SCHED_EVENODD)
+        return fail(ctx, DICOD_EINVAL, "autotune: only the coloured schedule is tuned");
+    if (ctx->server)
+        return fail(ctx, DICOD_EINVAL, "autotune: serving active on this context (the "
+                                       "tuning table is fixed until dicod_finalize)");
+    HIPCHECK(ctx, hipSetDevice(ctx->cfg.device));
+    const int K = ctx->K, W = ctx->W;
+    int64_t lmax = 0;
+    for (int i = 0; i < n_sig; ++i) {
+        if (T[i] < W)
+            return fail(ctx, DICOD_EINVAL, "autotune: signal %d: T < W", i);
+        lmax = std::max(lmax, T[i] - W + 1);
+    }
+    const int bucket = length_bucket(lmax);
+    std::vector<dicod_stats> st(n_sig);
+    std::map<std::vector<int>, double> seen;
+    int trials = 0;
+    const double inf = std::numeric_limits<double>::infinity();
+    int hard_rc = DICOD_OK;
+    std::string hard_msg;
+
+    auto make = [&](int C, int seg, int cap) {
+        dicod_tune_entry e;
+        std::memset(&e, 0, sizeof e);
+        e.K = K;
+        e.P = ctx->P;
+        e.W = W;
+        e.bucket = bucket;
+        e.colors = C;
+        e.seg_len = seg;
+        e.update_cap = std::min(std::max(cap, 1), 1024);
+        e.team_threads = team_threads_for(K, seg, e.update_cap);
+        return e;
+    };
+    // best of two timed solves; failures to converge count as infinitely slow
+    auto eval = [&](const dicod_tune_entry& e) -> double {
+        const std::vector<int> key = {e.colors, e.seg_len, e.update_cap};
+        auto it = seen.find(key);
+        if (it != seen.end())
+            return it->second;
+        if (trials >= max_trials || hard_rc != DICOD_OK)
+            return inf;
+        ++trials;
+        double best = inf;
+        ctx->sched_force = &e;
+        for (int rep = 0; rep < 2; ++rep) {
+            const double t0 = now_ms();
+            const int rc = dicod::solve_device_batch(ctx, n_sig, X_dev, T, x_off, lambda, eps,
+                                                     nullptr, Z_dev, z_off, st.data(),
+                                                     ctx->stream);
+            const double t = now_ms() - t0;
+            if (rc == DICOD_ENOTCONV || rc == DICOD_EINVAL || rc == DICOD_ENOTSUP)
+                break;  // this schedule is not usable here
+            if (rc != DICOD_OK) {
+                hard_rc = rc;
+                hard_msg = ctx->err;
+                break;
+            }
+            best = std::min(best, t);
+        }
+        ctx->sched_force = nullptr;
+        ctx->err.clear();
+        seen[key] = best;
+        return best;
+    };
+
+    const int cap0 = effective_update_cap(-1, W);
+    std::vector<int> lad2 = seg_ladder(W, 2, lmax);
+    int seg0 = lad2.back();
+    for (int x : lad2)  // the ladder entry nearest 2W from above
+        if (x >= 2 * W) {
+            seg0 = x;
+            break;
+        }
+    dicod_tune_entry best = make(2, seg0, cap0);
+    double tb = eval(best);
+    const double t_prior = tb;
+    for (bool moved = true; moved && trials < max_trials && hard_rc == DICOD_OK;) {
+        moved = false;
+        std::vector<dicod_tune_entry> nb;
+        for (int C = 2; C <= 4; ++C) {
+            if (C == best.colors)
+                continue;
+            const int lo = (int)min_segment(W, C);
+            nb.push_back(make(C, std::max(best.seg_len, lo), best.update_cap));
+            nb.push_back(make(C, seg_ladder(W, C, lmax).front(), best.update_cap));
+        }
+        const std::vector<int> lad = seg_ladder(W, best.colors, lmax);
+        const size_t pos = std::lower_bound(lad.begin(), lad.end(), best.seg_len) - lad.begin();
+        if (pos > 0)
+            nb.push_back(make(best.colors, lad[pos - 1], best.update_cap));
+        if (pos + 1 < lad.size())
+            nb.push_back(make(best.colors, lad[pos + 1], best.update_cap));
+        nb.push_back(make(best.colors, best.seg_len, best.update_cap * 2));
+        if (best.update_cap > 1)
+            nb.push_back(make(best.colors, best.seg_len, best.update_cap / 2));
+        for (const dicod_tune_entry& e : nb) {
+            const double t = eval(e);
+            if (t < 0.98 * tb) {
+                best = e;
+                tb = t;
+                moved = true;
+                break;
+            }
+        }
+    }
+    if (hard_rc != DICOD_OK)
+        return fail(ctx, hard_rc, "autotune: %s", hard_msg.c_str());
+    if (!(tb < inf))
+        return fail(ctx, DICOD_ENOTCONV, "autotune: no candidate schedule converged");
+    best.trials = trials;
+    best.ms = tb;
+    best.ms_prior = t_prior;
+    ctx->tuning[bucket] = best;
+    // leave the chosen schedule's solution in Z_dev
+    ctx->sched_force = &best;
+    const int rc = dicod::solve_device_batch(ctx, n_sig, X_dev, T, x_off, lambda, eps, nullptr,
+                                             Z_dev, z_off, st.data(), ctx->stream);
+    ctx->sched_force = nullptr;
+    if (out)
+        *out = best;
+    return rc;
+}
+
+extern "C" int dicod_get_tuning(dicod_ctx* ctx, dicod_tune_entry* out, int cap, int* n)
+{
+    if (!ctx || !n || cap < 0 || (cap > 0 && !out))
+        return DICOD_EINVAL;
+    int i = 0;
+    for (const auto& kv : ctx->tuning) {
+        if (i < cap)
+            out[i] = kv.second;
+        ++i;
+    }
+    *n = i;
+    return DICOD_OK;
+}
+
+extern "C" int dicod_set_tuning(dicod_ctx* ctx, const dicod_tune_entry* e)
+{
+    if (!ctx)
+        return DICOD_EINVAL;
+    ctx->err.clear();
+    if (ctx->server)
+        return fail(ctx, DICOD_EINVAL, "set_tuning: serving active on this context (the "
+                                       "tuning table is fixed until dicod_finalize)");
+    if (!e) {
+        ctx->tuning.clear();
+        return DICOD_OK;
+    }
+    if (!ctx->has_dict || e->K != ctx->K || e->P != ctx->P || e->W != ctx->W)
+        return fail(ctx, DICOD_EINVAL, "set_tuning: entry shape differs from the dictionary");
+    if (e->colors < 2 || e->colors > kMaxColors || e->update_cap < 1 || e->update_cap > 1024 ||
+        e->bucket < 0 || e->bucket > 62 || e->seg_len < min_segment(ctx->W, e->colors))
+        return fail(ctx, DICOD_EINVAL, "set_tuning: invalid entry");
+    dicod_tune_entry c = *e;
+    c.team_threads = team_threads_for(ctx->K, c.seg_len, c.update_cap);
+    ctx->tuning[c.bucket] = c;
+    return DICOD_OK;
+}
+
 // Accessors used by the serving module.
 namespace dicod {
+// Colours and update cap of a server on this context: the config's.  (Served
+// requests do not take their schedule from the tuning table: a served pair of
+// tuned requests stopped making progress in testing and the cause is not
+// known, so that path is switched off.)
+void ctx_serve_schedule(const dicod_ctx* ctx, int* colors, int* update_cap)
+{
+    *colors = ctx->cfg.colors;
+    *update_cap = ctx->cfg.update_cap;
+}
+// Segment count of a served request of L coefficients under C colours: the
+// fixed rule (see ctx_serve_schedule).
+int ctx_serve_segments(const dicod_ctx* ctx, int64_t L, int C, int* tuned)
+{
+    *tuned = 0;
+    return auto_segments(L, ctx->W, C);
+}
 dicod::Server*& ctx_server(dicod_ctx* ctx) { return ctx->server; }
 const dicod_config& ctx_config(const dicod_ctx* ctx) { return ctx->cfg; }
 int ctx_dims(const dicod_ctx* ctx, int* K, int* P, int* W)

@@ -177,6 +177,7 @@ struct Job {
     int64_t z_off = 0, zn = 0, x_off = 0, xn = 0, seg_base = 0;
     bool cur64 = false, in_lds = false, lds64 = false, lds32 = false;
     bool reg32 = false;           // float rounds on the register-state kernel
+    int tuned = 0;                // segment count from the tuning table
     int lane = 0;
     bool polished = false, any_hbm = false, out_of_phases = false;
     int n_refresh = 0, round = 0;
@@ -348,6 +349,7 @@ int Server::start(dicod_ctx* c)
     ctx = c;
     cfg = ctx_config(c);
     ctx_dims(c, &K, &P, &W);
+    ctx_serve_schedule(c, &cfg.colors, &cfg.update_cap);
     C = cfg.colors;
     fp64 = cfg.precision == DICOD_PREC_FP64;
     dict = ctx_dict(c);
@@ -1028,13 +1030,21 @@ int server_submit(dicod_ctx* ctx, const float* X, int64_t T, double lambda, doub
         return ctx_fail(ctx, DICOD_EINVAL, "dicod_submit: lambda must be finite and non-zero");
     if (!(eps > 0.0) || !std::isfinite(eps))
         return ctx_fail(ctx, DICOD_EINVAL, "dicod_submit: eps must be finite and > 0");
-    const int C = cfg.colors;
+    // the server's colours and cap (fixed when it starts)
+    Server*& srv = ctx_server(ctx);
+    int C = 0, cap_cfg = 0;
+    if (srv) {
+        C = srv->C;
+        cap_cfg = srv->cfg.update_cap;
+    } else {
+        ctx_serve_schedule(ctx, &C, &cap_cfg);
+    }
     const int64_t L = T - W + 1;
-    int M = n_seg;
+    int M = n_seg, tuned = 0;
     if (M < 0)
         return ctx_fail(ctx, DICOD_EINVAL, "dicod_submit: n_seg < 0");
     if (M == 0)
-        M = auto_segment_count(L, W, C);
+        M = ctx_serve_segments(ctx, L, C, &tuned);
     if (M > L)
         return ctx_fail(ctx, DICOD_EINVAL, "dicod_submit: n_seg > L");
     if (M > 1 && L / M < min_segment_len(W, C))
@@ -1056,7 +1066,6 @@ int server_submit(dicod_ctx* ctx, const float* X, int64_t T, double lambda, doub
     if ((!fp64 && !fits(false, &lds32)) || !fits(true, &lds64))
         return ctx_fail(ctx, DICOD_ENOTSUP, "dicod_submit: segments too long for the phase "
                                             "kernels; use more segments");
-    Server*& srv = ctx_server(ctx);
     if (!srv) {
         Server* ns = new Server();
         const int rc = ns->start(ctx);
@@ -1077,8 +1086,9 @@ int server_submit(dicod_ctx* ctx, const float* X, int64_t T, double lambda, doub
     j->eps = eps;
     j->lds32 = lds32;
     j->lds64 = lds64;
+    j->tuned = tuned;
     j->reg32 = cfg.reg_state != 0 &&
-               lgcd_wave_supported(K, (int)lm, effective_update_cap(cfg.update_cap, W), false);
+               lgcd_wave_supported(K, (int)lm, effective_update_cap(cap_cfg, W), false);
     j->lane = M <= kShortSegs ? 0 : 1;
     j->zn = round_up((int64_t)K * L, 64);
     j->xn = round_up((int64_t)P * T, 64);
@@ -1156,6 +1166,10 @@ int server_poll(dicod_ctx* ctx, uint64_t req_id, double* Z_out, dicod_stats* st)
         st->nnz = (int64_t)j->res.nnz;
         st->n_seg = j->M;
         st->seg_len = (int)(j->L / j->M);
+        st->colors = srv->C;
+        st->update_cap = srv->cfg.update_cap == 0 ? 0
+                                                  : effective_update_cap(srv->cfg.update_cap, srv->W);
+        st->tuned = j->tuned;
         st->converged = j->res.max_dz < j->eps ? 1 : 0;
         st->n_refresh = j->n_refresh;
         st->lambda = j->lam;

@@ -37,5 +37,9 @@ int ctx_fail(dicod_ctx* ctx, int code, const char* msg);
 // Segment-length rules shared with the one-shot solver.
 int64_t min_segment_len(int W, int C);
 int auto_segment_count(int64_t L, int W, int C);
+// Schedule of a server from the tuning table (autotune on) or the config.
+void ctx_serve_schedule(const dicod_ctx* ctx, int* colors, int* update_cap);
+// Segment count of a request of L coefficients under C colours.
+int ctx_serve_segments(const dicod_ctx* ctx, int64_t L, int C, int* tuned);
 
 }  // namespace dicod

@@ -144,8 +144,14 @@ __device__ __forceinline__ unsigned best_key(const f4 (&g)[KQ], const f4* __rest
     return best;
 }
 
+// Occupancy: the register budget is capped at four waves per SIMD (128
+// registers), which the LDS footprint allows for every instantiation but
+// <8, 1>; without the cap the compiler spends up to 131 registers on keeping
+// loads in flight and three waves per SIMD remain, which hides less of the
+// latency of the per-update chain (argmax, S-row loads, window update).
 template <int KQ, int TW>
 __global__ void __launch_bounds__(TW == 2 ? 128 : 256)
+__attribute__((amdgpu_waves_per_eu(KQ == 8 && TW == 1 ? 3 : 4)))
 k_lgcd_wave(PhaseArgs a)
 {
     constexpr int SPB = TW == 1 ? 4 : 1;      // segments per workgroup

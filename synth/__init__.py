@@ -123,6 +123,26 @@ def generate_fast(P, K, W, T, rho, sigma_noise, seed, D, sigma_z=10.0):
     return X.astype(np.float32)
 
 
+def generate_conv(P, K, W, T, rho, sigma_noise, seed, D, sigma_z=10.0):
+    """The draws of ``generate_fast`` (same seed, same Z and noise) with the
+    sum of convolutions formed by one transposed convolution in float32 on the
+    CPU (torch): seconds for millions of samples, for the largest benchmark
+    workloads.  Differs from ``generate_fast`` by float32 rounding only.
+    Returns X float32 [P, T]."""
+    import torch
+    rng = np.random.Generator(np.random.PCG64(seed))
+    L = T - W + 1
+    mask = rng.random((K, L), dtype=np.float32) < rho
+    ks, ts = np.nonzero(mask)
+    vals = rng.standard_normal(ks.size) * sigma_z
+    Z = torch.zeros(1, K, L, dtype=torch.float32)
+    Z[0, torch.from_numpy(ks), torch.from_numpy(ts)] = torch.from_numpy(vals.astype(np.float32))
+    X = torch.nn.functional.conv_transpose1d(
+        Z, torch.from_numpy(np.ascontiguousarray(D, dtype=np.float32)))[0].numpy()
+    X += sigma_noise * rng.standard_normal((P, T), dtype=np.float32)
+    return np.ascontiguousarray(X, dtype=np.float32)
+
+
 def workload(w: Workload, seed: int):
     return generate(w.P, w.K, w.W, w.T, w.rho, w.sigma_noise, seed, w.sigma_z)
 

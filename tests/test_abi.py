@@ -42,7 +42,8 @@ def test_library_has_gfx950_code_and_no_cpu_fallback_symbols():
 
 
 @pytest.mark.parametrize("struct,cname", [("dicod_config", "dicod_config"),
-                                          ("dicod_stats", "dicod_stats")])
+                                          ("dicod_stats", "dicod_stats"),
+                                          ("dicod_tune_entry", "dicod_tune_entry")])
 def test_struct_layout_matches_header(tmp_path, struct, cname):
     import paper_1705_10087_amd as d
     cls = getattr(d, struct)

@@ -25,13 +25,39 @@ def test_more_than_one_gpu_exits_with_a_message():
         assert "one GPU" in msg["error"] and f"--gpus {n}" in msg["error"]
 
 
-def test_effective_update_cap():
+def test_flops_and_kernel_names():
     b = load_bench()
-    # automatic cap max(4, round(2 sqrt(W))): 28 at the paper's W = 200, 16 at W = 64
-    assert b.effective_cap(-1, 200) == 28
-    assert b.effective_cap(-1, 64) == 16
-    assert b.effective_cap(-1, 1) == 4 and b.effective_cap(-1, 4) == 4
-    assert b.effective_cap(-1, 5) == 4   # 2 sqrt(5) = 4.47
-    assert b.effective_cap(-1, 7) == 5   # 2 sqrt(7) = 5.29
-    # explicit caps pass through; 0 means no cap
-    assert b.effective_cap(9, 200) == 9 and b.effective_cap(0, 200) == 0
+    # eq. (3): K (2W - 1) FMAs plus ~5 flops of candidate per touched coordinate
+    assert b.flops_per_update(25, 64) == 7 * 25 * 127
+    assert b.flops_per_update(25, 200) == 7 * 25 * 399
+    assert b.wave_kernel_name(25, 64) == "k_lgcd_wave<7, 1>"
+    assert b.wave_kernel_name(25, 126) == "k_lgcd_wave<7, 2>"
+    assert b.wave_kernel_name(25, 199) == "k_lgcd_wave<7, 4>"
+    assert b.wave_kernel_name(5, 40) == "k_lgcd_wave<2, 1>"
+    assert b.wave_kernel_name(13, 200) == "k_lgcd_wave<4, 4>"
+    assert b.wave_kernel_name(32, 10) == "k_lgcd_wave<8, 1>"
+
+
+def test_roofline_arithmetic():
+    b = load_bench()
+    st = {"round_launches": [10, 0, 0, 0], "round_kernel_ms": [2.0, 0, 0, 0],
+          "round_updates_total": 1_000_000, "round_state": [4, 0, 0, 0]}
+    r = b.roofline(st, 25, 64, "nowhere", 63)
+    # 1e5 updates per launch of 200 us: 1e5 * 22225 flops / 2e-4 s = 11.1125 TFLOP/s
+    assert abs(r["achieved"] - 11.1125) < 1e-9
+    assert r["bound"] == "alu" and r["unit"] == "TFLOP/s" and r["peak"] == 157.3
+    assert abs(r["frac"] - 11.1125 / 157.3) < 1e-12
+    assert r["traffic"] is None and r["kernel"] == "k_lgcd_wave<7, 1>"
+    assert abs(r["avg_launch_us"] - 200.0) < 1e-9
+
+
+def test_segment_rule_mirrors_the_library():
+    """The bench's copy of the tuned segment rule: ceil(L / seg_len), lowered
+    to keep segments at least max(W - 1, (2W - 2) / (C - 1)) long; the fixed
+    rule is floor(L / min_segment(W, 3))."""
+    b = load_bench()
+    f = b.seg_rule(64, {"seg_len": 128, "colors": 2})
+    assert f(1280) == 10 and f(1281) == 10   # 11 segments of 116 < 126 -> 10
+    assert f(100) == 1
+    g = b.seg_rule(64, None)
+    assert g(6300) == 100 and g(62) == 1
