@@ -83,9 +83,25 @@ extern "C" {
  *          >= W - 1 long and fit the on-chip kernel; update_cap in 1..1024 (or -1) is
  *          the number of updates per segment and phase (1 keeps the message
  *          delay below one update time, hypothesis H3).  dicod_submit always
- *          uses the coloured schedule. */
+ *          uses the coloured schedule.
+ * ASYNC:   Algorithm 2 without phase barriers: float rounds run persistent
+ *          teams that loop over the segments, each segment picking and
+ *          applying its own updates as soon as it has work and applying its
+ *          neighbours' records whenever it runs, with no wait for any other
+ *          segment; concurrent updates of adjacent segments may interfere
+ *          (Prop. A.2; convergence under H1, see dicod_check_h1).  A round
+ *          ends after a launch that applies no update; the double-precision
+ *          check and any double round follow the coloured schedule with
+ *          cfg.colors.  Needs the register-state kernel (FP32 or MIXED,
+ *          reg_state 1, segments of at most 256 positions, K <= 32,
+ *          update_cap in 1..64): ENOTSUP otherwise.  With a trace, update
+ *          records carry their number in selection order in n_local, and
+ *          every application of a neighbour's record is logged with
+ *          k0 = -1 - atom, n_local = that update's number and t0 = the
+ *          number of updates selected when it was applied. */
 #define DICOD_SCHED_EVENODD 0
 #define DICOD_SCHED_DICOD 1
+#define DICOD_SCHED_ASYNC 2
 
 typedef struct dicod_ctx dicod_ctx;
 
@@ -152,7 +168,7 @@ typedef struct {
     double round_kernel_ms[4]; /* phase-kernel time of those rounds (timing = 1)     */
     int64_t round_launches[4]; /* phase-kernel launches of those rounds              */
     int round_state[4];       /* state of those rounds: bit 0 double, bit 1 HBM,     */
-                              /* bit 2 registers                                     */
+                              /* bit 2 registers, bit 3 free-running schedule        */
     int state_in_hbm;         /* 1 if segment state was kept in HBM, not LDS         */
     int polished_fp64;        /* 1 if the descent finished on a double state         */
     double t_queue_ms;        /* served: dicod_submit until admission to the device  */
@@ -334,6 +350,14 @@ int dicod_correlate(dicod_ctx *ctx, const float *X, int64_t T, int precision,
  * l applies, eq. (3)), and the norms to host double [K] (either may be NULL).
  * Errors: EINVAL (no dictionary). */
 int dicod_get_s_table(dicod_ctx *ctx, double *S_out, double *norms_out);
+
+/* Hypothesis H1 of Theorem 1 (Sec. 3) for the resident dictionary: *ratio
+ * gets the largest |S_{k,l}[d]| / (|D_k|_2 |D_l|_2) over atoms k, l and shifts
+ * d != 0, in double from the resident correlation table (at most 1 by
+ * Cauchy-Schwarz).  Algorithm 2 (schedules DICOD and ASYNC) converges when it
+ * is below 1; *holds (may be NULL) gets 1 then, else 0.  Errors: EINVAL (NULL
+ * ctx or ratio, no dictionary), EDEVICE. */
+int dicod_check_h1(dicod_ctx *ctx, double *ratio, int *holds);
 
 /* Copies up to cap update records of the last solve (in the order they were
  * recorded; segments of one phase interleave) into out and the number

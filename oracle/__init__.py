@@ -98,6 +98,8 @@ def load_library(path):
     lib.oracle_soft_threshold.argtypes = [ctypes.c_double, ctypes.c_double]
     lib.oracle_norms.argtypes = [dp, ci, ci, ci, dp]
     lib.oracle_s_table.argtypes = [dp, ci, ci, ci, dp]
+    lib.oracle_h1_ratio.argtypes = [dp, ci, ci, ci]
+    lib.oracle_h1_ratio.restype = ctypes.c_double
     lib.oracle_correlate.argtypes = [dp, ci, ci, ci, dp, i64, dp]
     lib.oracle_reconstruct.argtypes = [dp, dp, ci, ci, ci, i64, dp]
     lib.oracle_objective.restype = ctypes.c_double
@@ -148,6 +150,14 @@ def s_table(D):
     out = np.empty((K, K, 2 * W - 1))
     _load().oracle_s_table(_ptr(D), K, P, W, _ptr(out))
     return out
+
+
+def h1_ratio(D):
+    """max over atoms k, l and shifts d != 0 of |S_{k,l}[d]| / (|D_k| |D_l|):
+    hypothesis H1 of Theorem 1 (Sec. 3) holds when it is below 1."""
+    D = _f64(D)
+    K, P, W = D.shape
+    return float(_load().oracle_h1_ratio(_ptr(D), K, P, W))
 
 
 def correlate(D, Y):

@@ -89,6 +89,37 @@ void oracle_s_table(const double *D, int K, int P, int W, double *S)
             }
 }
 
+/* Hypothesis H1 (Sec. 3, Theorem 1): for every pair of coordinates at
+ * different positions, |S_{k0,k1}[t0 - t1]| / (|D_k0|_2 |D_k1|_2) < 1.  Returns
+ * the largest such ratio over atoms k, l and shifts d != 0 (0 when W = 1);
+ * H1 holds when it is below 1.  By Cauchy-Schwarz it is at most 1. */
+double oracle_h1_ratio(const double *D, int K, int P, int W)
+{
+    const int nd = 2 * W - 1;
+    double *S = (double *)malloc(sizeof(double) * (size_t)K * K * nd);
+    double *n2 = (double *)malloc(sizeof(double) * (size_t)K);
+    if (!S || !n2) {
+        free(S);
+        free(n2);
+        return -1.0;
+    }
+    oracle_s_table(D, K, P, W, S);
+    oracle_norms(D, K, P, W, n2);
+    double worst = 0.0;
+    for (int k = 0; k < K; ++k)
+        for (int l = 0; l < K; ++l)
+            for (int d = -(W - 1); d <= W - 1; ++d) {
+                if (d == 0)
+                    continue;
+                double r = fabs(S[IDX3(k, l, d + W - 1, K, nd)]) / sqrt(n2[k] * n2[l]);
+                if (r > worst)
+                    worst = r;
+            }
+    free(S);
+    free(n2);
+    return worst;
+}
+
 /* out_k[t] = sum_p sum_tau D_k[p][tau] Y[p][t + tau], t in [0, T - W + 1).
  * At Z = 0 this is the initial beta of Algorithm 1 (D~_k * X, reading R1). */
 void oracle_correlate(const double *D, int K, int P, int W, const double *Y,

@@ -29,6 +29,7 @@ DICOD_PREC_FP32 = 1
 DICOD_PREC_MIXED = 2
 DICOD_SCHED_EVENODD = 0
 DICOD_SCHED_DICOD = 1
+DICOD_SCHED_ASYNC = 2
 
 _CODES = {v: k for k, v in dict(globals()).items() if k.startswith("DICOD_E")}
 
@@ -183,10 +184,12 @@ def lib():
     L.dicod_autotune_device.argtypes = [_vp, ci, _vp, _vp, _vp, _vp, cd, _vp, _vp, ci, pe]
     L.dicod_get_tuning.argtypes = [_vp, pe, ci, ctypes.POINTER(ci)]
     L.dicod_set_tuning.argtypes = [_vp, pe]
+    L.dicod_check_h1.argtypes = [_vp, ctypes.POINTER(cd), ctypes.POINTER(ci)]
     for name in ("dicod_config_init", "dicod_init", "dicod_set_dictionary", "dicod_solve",
                  "dicod_solve_device", "dicod_solve_device_noalloc", "dicod_solve_batch_device",
                  "dicod_correlate", "dicod_get_s_table", "dicod_get_trace", "dicod_submit",
-                 "dicod_poll", "dicod_autotune_device", "dicod_get_tuning", "dicod_set_tuning"):
+                 "dicod_poll", "dicod_autotune_device", "dicod_get_tuning", "dicod_set_tuning",
+                 "dicod_check_h1"):
         getattr(L, name).restype = ci
     _lib = L
     return L
@@ -348,6 +351,13 @@ def dicod_set_tuning(ctx, entry):
     _check(ctx, lib().dicod_set_tuning(ctx, e))
 
 
+def dicod_check_h1(ctx):
+    """(ratio, holds): the H1 quantity of the resident dictionary."""
+    r, h = ctypes.c_double(0.0), ctypes.c_int(0)
+    _check(ctx, lib().dicod_check_h1(ctx, ctypes.byref(r), ctypes.byref(h)))
+    return r.value, bool(h.value)
+
+
 def dicod_correlate(ctx, X, K, W, precision=DICOD_PREC_FP64):
     X = np.ascontiguousarray(X, dtype=np.float32)
     P, T = X.shape
@@ -461,6 +471,9 @@ class Context:
         with open(path) as f:
             for e in json.load(f):
                 self.set_tuning(e)
+
+    def check_h1(self):
+        return dicod_check_h1(self.h)
 
     def correlate(self, X, precision=DICOD_PREC_FP64):
         return dicod_correlate(self.h, X, self.K, self.W, precision)

@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdicod.so")
-SOURCES = ["kernels.hip", "lgcd_wave.hip", "lambda_bound.hip", "noalloc.hip", "dicod_api.cpp", "dicod_serve.cpp"]
+SOURCES = ["kernels.hip", "lgcd_wave.hip", "lgcd_async.hip", "lambda_bound.hip", "noalloc.hip", "dicod_api.cpp", "dicod_serve.cpp"]
 ARCH = os.environ.get("DICOD_ARCH", "gfx950")
 
 

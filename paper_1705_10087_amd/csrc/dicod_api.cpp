@@ -102,6 +102,7 @@ struct Workspace {
     DevBuf part, results, lmax, done, thr, ebits;
     DevBuf msg, msg_n;                    // DICOD schedule: boundary messages
     DevBuf box, box_n, z32;               // register kernel: mailboxes, float copy of Z
+    DevBuf ring, ring_wr;                 // free-running schedule: rings and their counters
     DevBuf trace;
     DevBuf slots, lamin;                  // device-side lambda: signal indices, inputs
     // host copies of what the read-only plan tables hold on the device: an
@@ -300,7 +301,8 @@ extern "C" int dicod_init(dicod_ctx** out, const dicod_config* cfg)
         dicod_config_init(&c);
     if (c.precision < DICOD_PREC_FP64 || c.precision > DICOD_PREC_MIXED)
         return fail(nullptr, DICOD_EINVAL, "dicod_init: unknown precision %d", c.precision);
-    if (c.schedule != DICOD_SCHED_EVENODD && c.schedule != DICOD_SCHED_DICOD)
+    if (c.schedule != DICOD_SCHED_EVENODD && c.schedule != DICOD_SCHED_DICOD &&
+        c.schedule != DICOD_SCHED_ASYNC)
         return fail(nullptr, DICOD_EINVAL, "dicod_init: unknown schedule %d", c.schedule);
     if (c.schedule == DICOD_SCHED_DICOD && c.update_cap != -1 &&
         (c.update_cap < 1 || c.update_cap > 1024))
@@ -537,6 +539,35 @@ extern "C" int dicod_get_s_table(dicod_ctx* ctx, double* S_out, double* norms_ou
     return DICOD_OK;
 }
 
+extern "C" int dicod_check_h1(dicod_ctx* ctx, double* ratio, int* holds)
+{
+    if (!ctx || !ratio)
+        return DICOD_EINVAL;
+    ctx->err.clear();
+    if (!ctx->has_dict)
+        return fail(ctx, DICOD_EINVAL, "dicod_check_h1: no resident dictionary");
+    const int K = ctx->K, W = ctx->W, nd = 2 * W - 1;
+    std::vector<double> S((size_t)K * K * nd), n2(K);
+    const int rc = dicod_get_s_table(ctx, S.data(), n2.data());
+    if (rc != DICOD_OK)
+        return rc;
+    // S[l][k][d + W - 1] = S_{k,l}[d]; every (k, l) pair and shift d != 0
+    double worst = 0.0;
+    for (int l = 0; l < K; ++l)
+        for (int k = 0; k < K; ++k)
+            for (int j = 0; j < nd; ++j) {
+                if (j == W - 1)
+                    continue;
+                const double r = std::fabs(S[((size_t)l * K + k) * nd + j]) /
+                                 std::sqrt(n2[k] * n2[l]);
+                worst = std::max(worst, r);
+            }
+    *ratio = worst;
+    if (holds)
+        *holds = worst < 1.0 ? 1 : 0;
+    return DICOD_OK;
+}
+
 // ---------------------------------------------------------------------------
 // the solver
 // ---------------------------------------------------------------------------
@@ -749,6 +780,24 @@ int solve_device_batch(dicod_ctx* ctx, int n_sig, const float* dX, const int64_t
     const bool reg_ok = !fp64 && cfg.reg_state != 0 && !pl.dicod &&
                         lgcd_wave_supported(K, pl.lm_max, cap_eff, false);
     const int box_cap = reg_ok ? std::max(cap_eff, 1) : 0;
+    // free-running schedule: float rounds only, on the register-state kernel
+    const bool async = cfg.schedule == DICOD_SCHED_ASYNC;
+    if (async && (fp64 || !reg_ok))
+        return fail(ctx, DICOD_ENOTSUP,
+                    "the free-running schedule needs float rounds on the register-state kernel "
+                    "(FP32 or MIXED, reg_state 1, segments of at most 256 positions, K <= 32, "
+                    "update_cap in 1..64)");
+    AsyncArgs ax;
+    std::memset(&ax, 0, sizeof ax);
+    if (async) {
+        ax.sweeps = kAsyncSweeps;
+        ax.ring_cap = lgcd_async_ring_cap(cap_eff, kAsyncSweeps);
+        ax.n_teams = lgcd_async_teams(K, pl.lm_max, n_seg_tot, ctx->n_cu);
+        if (ax.n_teams < 1)
+            return fail(ctx, DICOD_ENOTSUP, "free-running schedule: no team fits the device");
+        HIPCHECK(ctx, ensure(ws.ring, (size_t)2 * n_seg_tot * ax.ring_cap * sizeof(BoundaryRec)));
+        HIPCHECK(ctx, ensure(ws.ring_wr, (size_t)4 * n_seg_tot * sizeof(uint32_t)));
+    }
     HIPCHECK(ctx, ensure(ws.beta0, pl.zext * sizeof(double)));
     HIPCHECK(ctx, ensure(ws.g, pl.zext * (fp64 ? sizeof(double) : sizeof(float))));
     if (reg_ok) {
@@ -901,6 +950,8 @@ int solve_device_batch(dicod_ctx* ctx, int n_sig, const float* dX, const int64_t
     HIPCHECK(ctx, launch_fill_u32(ws.dirty.as<uint32_t>(), 1u, n_seg_tot, s));
     if (reg_ok)
         HIPCHECK(ctx, launch_fill_u32(ws.box_n.as<uint32_t>(), 0u, (size_t)2 * n_seg_tot, s));
+    if (async)
+        HIPCHECK(ctx, launch_fill_u32(ws.ring_wr.as<uint32_t>(), 0u, (size_t)4 * n_seg_tot, s));
     if (pl.dicod) {
         HIPCHECK(ctx, launch_fill_u32(ws.dirty.as<uint32_t>() + n_seg_tot, 0u, n_seg_tot, s));
         HIPCHECK(ctx, launch_fill_u32(ws.msg_n.as<uint32_t>(), 0u, (size_t)4 * n_seg_tot, s));
@@ -1020,6 +1071,11 @@ int solve_device_batch(dicod_ctx* ctx, int n_sig, const float* dX, const int64_t
     a.box_cap = box_cap;
     a.z32 = reg_ok ? ws.z32.as<float>() : nullptr;
     a.phase_stride = 0;
+    if (async) {
+        ax.ring = ws.ring.as<BoundaryRec>();
+        ax.ring_w = ws.ring_wr.as<uint32_t>();
+        ax.ring_r = ws.ring_wr.as<uint32_t>() + (size_t)2 * n_seg_tot;
+    }
     auto set_state = [&](bool use64, bool lds) {
         a.g = use64 && !fp64 ? ws.g64.p : ws.g.p;
         a.S = use64 ? (lds ? ctx->St64.p : ctx->S64.p) : (lds ? ctx->St32.p : ctx->S32.p);
@@ -1064,7 +1120,12 @@ int solve_device_batch(dicod_ctx* ctx, int n_sig, const float* dX, const int64_t
         // counts, so the device does not idle on the poll; phases queued after
         // convergence find no dirty segment and apply nothing.
         const bool overlap = !cfg.timing;
-        int64_t checked = start + pl.colors - 1;  // next phase whose quiet window is tested
+        // a free-running float round: every launch runs all segments, and one
+        // launch that applies nothing ends the round (no record is left: a
+        // segment with records waiting runs and applies them)
+        const bool async_round = async && !cur64;
+        const int quiet_n = async_round ? 1 : pl.colors;
+        int64_t checked = start + quiet_n - 1;    // next phase whose quiet window is tested
         int64_t copied = start;                   // counts copied (or queued) below this
         int64_t known = start;                    // counts on the host below this
         int64_t q_end[2] = {0, 0};                // queued chunks (FIFO of at most 2)
@@ -1079,14 +1140,16 @@ int solve_device_batch(dicod_ctx* ctx, int n_sig, const float* dX, const int64_t
                 // phases the double-precision test decides instead.
                 limit = true;
             } else {
-                const int64_t chunk = std::min<int64_t>(cfg.phases_per_poll, max_ph - phase);
+                const int64_t chunk = std::min<int64_t>(
+                    async_round ? std::min(cfg.phases_per_poll, 2) : cfg.phases_per_poll,
+                    max_ph - phase);
                 evi = 4;
                 for (int64_t c = 0; c < chunk; ++c, ++phase) {
                     const int par = (int)(phase % pl.colors);
                     a.list = ws.lists[par].as<int32_t>();
                     a.n_list = (int)pl.list[par].size();
                     a.phase = (int)phase;
-                    if (a.n_list == 0)
+                    if (a.n_list == 0 && !async_round)
                         continue;
                     hipEvent_t e0 = nullptr, e1 = nullptr;
                     if (cfg.timing) {
@@ -1098,9 +1161,10 @@ int solve_device_batch(dicod_ctx* ctx, int n_sig, const float* dX, const int64_t
                     }
                     size_t lds = 0;
                     const bool use_reg = !cur64 && reg_ok;
-                    hipError_t e = use_reg  ? launch_lgcd_wave(a, s)
-                                   : in_lds ? launch_lgcd_phase(a, cur64, &lds, s)
-                                            : launch_lgcd_phase_gm(a, cur64, &lds, s);
+                    hipError_t e = async_round ? launch_lgcd_async(a, ax, s)
+                                   : use_reg   ? launch_lgcd_wave(a, s)
+                                   : in_lds    ? launch_lgcd_phase(a, cur64, &lds, s)
+                                               : launch_lgcd_phase_gm(a, cur64, &lds, s);
                     if (e != hipSuccess)
                         return fail(ctx, DICOD_EDEVICE,
                                     "LGCD phase launch (%s state, %zu bytes LDS): %s",
@@ -1135,7 +1199,7 @@ int solve_device_batch(dicod_ctx* ctx, int n_sig, const float* dX, const int64_t
             // converged once `colors` consecutive phases applied nothing
             for (int64_t p = checked; p < known; ++p) {
                 bool quiet = true;
-                for (int c = 0; c < pl.colors; ++c)
+                for (int c = 0; c < quiet_n; ++c)
                     quiet &= ctx->h_upd[p - c] == 0;
                 if (quiet) {
                     conv_phase = p;
@@ -1161,7 +1225,7 @@ int solve_device_batch(dicod_ctx* ctx, int n_sig, const float* dX, const int64_t
             round_launch[round] = n_launch - launch0;
             round_kms[round] = t_kernel - kern0;
             round_state[round] = (cur64 ? 1 : 0) | (in_lds ? 0 : 2) |
-                                 (!cur64 && reg_ok ? 4 : 0);
+                                 (!cur64 && reg_ok ? 4 : 0) | (async_round ? 8 : 0);
             for (int64_t p = start; p < last; ++p)
                 round_upd[round] += (int64_t)ctx->h_upd[p];
         }
@@ -1238,6 +1302,9 @@ int solve_device_batch(dicod_ctx* ctx, int n_sig, const float* dX, const int64_t
                                               s));
         if (reg_ok)  // records of the last round are stale: g was refreshed
             HIPCHECK(ctx, launch_fill_u32(ws.box_n.as<uint32_t>(), 0u, (size_t)2 * n_seg_tot, s));
+        if (async)
+            HIPCHECK(ctx, launch_fill_u32(ws.ring_wr.as<uint32_t>(), 0u, (size_t)4 * n_seg_tot,
+                                          s));
         while (phase % pl.colors)
             ++phase;
         if (pl.dicod) {
@@ -1270,7 +1337,8 @@ int solve_device_batch(dicod_ctx* ctx, int n_sig, const float* dX, const int64_t
         std::memcpy(lbits.data(), ctx->h_pin + pin_lbits, n_sig * sizeof(unsigned long long));
     ctx->last_trace_n = (int64_t)cnt.trace_n;
     if (cnt.box_overflow)
-        return fail(ctx, DICOD_EDEVICE, "internal: %llu boundary records found a full mailbox",
+        return fail(ctx, DICOD_EDEVICE,
+                    "internal: %llu boundary records found a full mailbox or ring",
                     (unsigned long long)cnt.box_overflow);
     for (int i = 0; any_rel && i < n_sig; ++i) {
         // the arithmetic of k_apply_lambda

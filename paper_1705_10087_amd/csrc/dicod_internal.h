@@ -67,8 +67,8 @@ struct CheckResult {
 struct Counters {
     unsigned long long seg_runs;   // segment runs that made at least one update
     unsigned long long trace_n;    // trace records requested
-    unsigned long long box_overflow;  // boundary records that found a full mailbox
-    unsigned long long pad;
+    unsigned long long box_overflow;  // boundary records that found a full mailbox or ring
+    unsigned long long upd_seq;    // free-running schedule: updates numbered in selection order
 };
 
 // A boundary update of the coloured schedule with mailboxes (register-state
@@ -79,7 +79,7 @@ struct BoundaryRec {
     int32_t k0;
     int32_t t0;     // position in the signal
     float delta;
-    int32_t pad;
+    int32_t seq;    // free-running schedule with a trace: the update's number; else 0
 };
 
 // Static device scratch of dicod_solve_device_noalloc (noalloc.hip): its size,
@@ -188,6 +188,31 @@ bool lgcd_wave_supported(int K, int lm_max, int cap, bool fp64);
 // Mailbox capacity (records per segment and side) the kernel needs: a.box_cap.
 int lgcd_wave_box_cap();
 hipError_t launch_lgcd_wave(const PhaseArgs& a, hipStream_t s);
+
+// Free-running schedule (Algorithm 2 without phase barriers, lgcd_async.hip):
+// persistent teams, each looping over the segments sid = team, team +
+// n_teams, ... for up to `sweeps` passes; a segment runs when it has work
+// (dirty) or records waiting, and boundary records travel through
+// single-producer rings ring[s][side][ring_cap] with monotone counters
+// ring_w (records written, advanced by the neighbour with release order) and
+// ring_r (records applied, advanced by the owner).  A team stops early after
+// a pass in which none of its segments ran.  No team ever waits for another.
+constexpr int kAsyncSweeps = 4;  // passes over the segments per free-running launch
+struct AsyncArgs {
+    BoundaryRec* ring;
+    uint32_t* ring_w;     // [n_seg][2]
+    uint32_t* ring_r;     // [n_seg][2]
+    int ring_cap;
+    int sweeps;
+    int n_teams;
+};
+// Ring capacity for a given update cap and sweeps per launch: records of one
+// launch plus those left from the previous one.
+int lgcd_async_ring_cap(int cap, int sweeps);
+// Teams of the free-running launch for these segments (at most the resident
+// capacity of the device).
+int lgcd_async_teams(int K, int lm_max, int n_seg, int n_cu);
+hipError_t launch_lgcd_async(const PhaseArgs& a, const AsyncArgs& x, hipStream_t s);
 // Atoms per position in the phase kernel's layout (K padded), -1 if K is
 // beyond the instantiated sizes.
 int lgcd_k_padded(int K, bool fp64);

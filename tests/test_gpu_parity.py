@@ -431,26 +431,40 @@ def test_batch_equals_solo_bitwise(dicod, polish):
 
 # ------------------------------------------- long signal: sampled oracle checks
 
-def test_long_signal_sampled_against_oracle(dicod):
+@pytest.mark.parametrize("policy", ["fp32", "mixed_float_only"])
+def test_long_signal_sampled_against_oracle(dicod, policy):
     """T = 5,000,000 (P=7, K=25, W=200): too long for an oracle solve, so the
     oracle recomputes beta from its definition at sampled coordinates (random
     non-zeros of Z and random coordinates) and the objective of the returned
     Z; every sampled |Delta Z| must be below eps (the stop test of Sec. 2.1)
-    and the objective must agree with the library's double-precision value."""
+    and the objective must agree with the library's double-precision value.
+    Policies: FP32 (double beta, a double finish round after a failed check),
+    and the long workload's own: split-bf16 correlations, float descent only
+    (fp64_polish_after = 0), segments of at most 256 positions from a tuning
+    entry."""
     import torch
     w = synth.LONG
-    print(f"\ncase: long signal T={w.T}", flush=True)
+    print(f"\ncase: long signal T={w.T} policy={policy}", flush=True)
     D = synth.dictionary(np.random.Generator(np.random.PCG64(31)), w.K, w.P, w.W).astype(np.float32)
     X = synth.generate_fast(w.P, w.K, w.W, w.T, w.rho, w.sigma_noise, 32, D)
     print("inputs ready", flush=True)
-    with ctx_of(dicod) as c:
+    cfg = {} if policy == "fp32" else dict(precision=dicod.DICOD_PREC_MIXED,
+                                           fp64_polish_after=0, autotune=1)
+    with ctx_of(dicod, **cfg) as c:
         c.set_dictionary(D)
+        if policy != "fp32":
+            c.set_tuning(dict(K=w.K, P=w.P, W=w.W, bucket=22, colors=3, seg_len=256,
+                              update_cap=28))
         Xd = torch.from_numpy(X).cuda()
         Zd, st, _ = c.solve_device(Xd, -w.lam_rel, EPS)
         Z = Zd.cpu().numpy()
     print(f"gpu: {st['n_updates']} updates, {st['n_phases']} phases, M={st['n_seg']}, "
-          f"time {st['t_total_ms']:.1f} ms, max_dz {st['max_dz']:.3g}", flush=True)
+          f"time {st['t_total_ms']:.1f} ms, max_dz {st['max_dz']:.3g}, rounds "
+          f"{st['round_state']}", flush=True)
     assert st["converged"] == 1 and st["max_dz"] < EPS
+    if policy != "fp32":
+        assert st["tuned"] == 1 and st["polished_fp64"] == 0
+        assert all(s & 1 == 0 for s in st["round_state"])   # no double descent round
     assert st["lambda"] == pytest.approx(w.lam_rel * st["lambda_max"], rel=1e-15)
     K, L = Z.shape
     rng = np.random.default_rng(5)

@@ -54,6 +54,12 @@ MUTANTS = [
     ("interference_lag_reversed",
      "st->interf_sum += s->S[IDX3(u->k0, v->k0, dt + W - 1, K, nd)] *",
      "st->interf_sum += s->S[IDX3(u->k0, v->k0, -dt + W - 1, K, nd)] *"),
+    ("h1_includes_zero_shift",
+     "if (d == 0)\n                    continue;\n                double r",
+     "if (0)\n                    continue;\n                double r"),
+    ("h1_unnormalised",
+     "/ sqrt(n2[k] * n2[l]);",
+     "/ 1.0;"),
     ("message_sent_to_wrong_side",
      "out[((size_t)(m + 1) * 2) * per + n_out[2 * (m + 1)]++] = msg;",
      "out[((size_t)(m + 1) * 2 + 1) * per + n_out[2 * (m + 1)]++] = msg;"),
@@ -80,6 +86,8 @@ def _pins():
         lambda: pins.test_max_dz_matches_definition_scaled_atoms(),
         lambda: pins.test_dicod_schedule_cost_identity(1, 4, 3),
         lambda: pins.test_dicod_schedule_interferes_and_converges(),
+        lambda: pins.test_h1_ratio_closed_forms(),
+        lambda: pins.test_h1_ratio_matches_numpy_definition(),
     ]
 
 

@@ -378,6 +378,39 @@ def test_h1_coherence_of_generated_dictionaries():
         assert np.max(np.abs(C)) < 1.0
 
 
+def test_h1_ratio_closed_forms():
+    """The H1 quantity of Theorem 1 (Sec. 3) on dictionaries with known values:
+    one atom [1, 1] / sqrt(2) has S[+-1] = 1/2; an atom and its one-sample shift
+    reach the Cauchy-Schwarz bound 1 (H1 fails); two 2-channel atoms whose
+    shifted cross-correlations are 1 with squared norms 2 give 1/2."""
+    D = np.array([[[1.0, 1.0]]]) / np.sqrt(2.0)
+    assert abs(oracle.h1_ratio(D) - 0.5) <= 1e-15
+    a, b = 0.6, -0.8
+    D = np.array([[[a, b, 0.0]], [[0.0, a, b]]])
+    assert abs(oracle.h1_ratio(D) - 1.0) <= 1e-15
+    D = np.array([[[1.0, 0.0], [0.0, 1.0]], [[0.0, 1.0], [1.0, 0.0]]])
+    assert abs(oracle.h1_ratio(D) - 0.5) <= 1e-15
+    assert oracle.h1_ratio(np.array([[[2.0]]])) == 0.0      # W = 1: no shift
+
+
+def test_h1_ratio_matches_numpy_definition():
+    """max over k, l, d != 0 of |sum_p sum_tau D_k[p][tau] D_l[p][tau + d]| /
+    (|D_k| |D_l|), formed with numpy.correlate per channel."""
+    rng = np.random.default_rng(8)
+    for K, P, W in ((3, 2, 5), (4, 1, 7), (2, 3, 1)):
+        D = rng.standard_normal((K, P, W))
+        best = 0.0
+        for k in range(K):
+            for l in range(K):
+                # numpy.correlate(a, v, 'full')[n] = sum_m a[m + n - (W - 1)] v[m]
+                c = sum(np.correlate(D[l, p], D[k, p], "full") for p in range(P))
+                nk, nl = np.linalg.norm(D[k]), np.linalg.norm(D[l])
+                for d in range(-(W - 1), W):
+                    if d != 0:
+                        best = max(best, abs(c[d + W - 1]) / (nk * nl))
+        assert abs(oracle.h1_ratio(D) - best) <= 1e-13 * max(best, 1e-300) + 1e-300
+
+
 def test_bad_arguments_rejected():
     X, D, _ = tiny_problem(0)
     with pytest.raises(ValueError):
