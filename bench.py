@@ -262,6 +262,100 @@ def run_solver_workload(d, torch, args, name, D, Ts, Xs, steps, warmup, cfg, tri
     return res, (Xd, Zd, Ls, x_off, z_off)
 
 
+def interference(tr, W):
+    """From a free-running trace: updates, and the pairs (u, v) where v, in
+    the segment that received u's record, was selected after u and before that
+    segment applied the record, with |t_u - t_v| < W (interfering, Sec. 3)."""
+    import bisect
+    upd = tr[tr["k0"] >= 0]
+    app = tr[tr["k0"] < 0]
+    t_of = {int(r["n_local"]): int(r["t0"]) for r in upd}
+    per_seg = {}
+    for r in upd:
+        per_seg.setdefault(int(r["seg"]), []).append((int(r["n_local"]), int(r["t0"])))
+    keys = {}
+    for m, v in per_seg.items():
+        v.sort()
+        keys[m] = [q for q, _ in v]
+    n_int = 0
+    for a in app:
+        tu = t_of.get(int(a["n_local"]))
+        m = int(a["seg"])
+        if tu is None or m not in per_seg:
+            continue
+        lo = bisect.bisect_right(keys[m], int(a["n_local"]))
+        hi = bisect.bisect_left(keys[m], int(a["t0"]))
+        n_int += sum(1 for _, tv in per_seg[m][lo:hi] if abs(tv - tu) < W)
+    return len(upd), len(app), n_int
+
+
+def schedules_bench(d, torch, D, X, steps=5):
+    """Time-to-eps of the coloured schedule against Algorithm 2 in lockstep and
+    free-running (the same segments, M = L / (W - 1)); interference counts from
+    traced free-running solves at the automatic update cap and at cap 1."""
+    K, P, W = D.shape
+    T = X.shape[1]
+    L = T - W + 1
+    dev = torch.device("cuda:0")
+    Xd = torch.from_numpy(X).to(dev)
+    Zd = torch.empty((K, L), dtype=torch.float64, device=dev)
+    out = {}
+    base = dict(max_phases=200_000)
+    for name, cfg in (("coloured", dict(base)),
+                      ("dicod_lockstep", dict(base, schedule=d.DICOD_SCHED_DICOD, update_cap=1)),
+                      ("free_running", dict(base, schedule=d.DICOD_SCHED_ASYNC)),
+                      ("free_running_cap1", dict(base, schedule=d.DICOD_SCHED_ASYNC,
+                                                 update_cap=1))):
+        with d.Context(**cfg) as c:
+            c.set_dictionary(D)
+            c.solve_device(Xd, LAM, EPS, 0, Zd)
+            with Timed(torch) as tt:
+                for _ in range(steps):
+                    _, st, _ = c.solve_device(Xd, LAM, EPS, 0, Zd)
+        out[name] = {"time_to_eps_ms": 1e3 * tt.s / steps, "n_updates": st["n_updates"],
+                     "n_phases": st["n_phases"], "n_seg": st["n_seg"],
+                     "update_cap": st["update_cap"], "round_state": st["round_state"]}
+    Lm = L / out["free_running"]["n_seg"]
+    for name, cap in (("free_running", -1), ("free_running_cap1", 1)):
+        with d.Context(schedule=d.DICOD_SCHED_ASYNC, update_cap=cap, max_phases=200_000,
+                       trace_capacity=4_000_000, fp64_polish_after=0) as c:
+            c.set_dictionary(D)
+            _, st, _ = c.solve_device(Xd, LAM, EPS, 0, Zd)
+            tr = c.trace()
+        n_upd, n_app, n_int = interference(tr, W)
+        out[name]["trace"] = {"updates": n_upd, "records_applied": n_app,
+                              "interfering_pairs": n_int,
+                              "interfering_pairs_per_update": n_int / max(n_upd, 1),
+                              "model_(MW/T)^2": min(1.0, (W / Lm) ** 2)}
+    return out
+
+
+def screening_report(d, torch, D, X, cfg, entry):
+    """One solve with the Gap Safe count (screen = 1) beside one without: the
+    duality gap of the returned Z, the coordinates proved zero, and the cost
+    of the extra double pass that counts them."""
+    K, P, W = D.shape
+    L = X.shape[1] - W + 1
+    dev = torch.device("cuda:0")
+    Xd = torch.from_numpy(X).to(dev)
+    Zd = torch.empty((K, L), dtype=torch.float64, device=dev)
+    out = {}
+    for scr in (0, 1):
+        with d.Context(autotune=1, screen=scr, **cfg) as c:
+            c.set_dictionary(D)
+            if isinstance(entry, dict):
+                c.set_tuning(entry)
+            c.solve_device(Xd, LAM, EPS, 0, Zd)
+            with Timed(torch) as tt:
+                _, st, _ = c.solve_device(Xd, LAM, EPS, 0, Zd)
+        out[f"screen_{scr}"] = {"time_to_eps_ms": 1e3 * tt.s, "duality_gap": st["duality_gap"],
+                                "n_screened": st["n_screened"], "nnz": st["nnz"]}
+    s1 = out["screen_1"]
+    out["coordinates"] = K * L
+    out["screened_fraction_of_zeros"] = s1["n_screened"] / max(1, K * L - s1["nnz"])
+    return out
+
+
 def cpu_baseline_batch(D, Ts, Xs, sched, budget_s=12.0):
     """The FP64 C oracle, single thread, on the first signals of the batch
     (one after another) until about budget_s seconds of work."""
@@ -506,6 +600,8 @@ def main():
         res["workload"] = synth.PAPER.name + ", rho=0.007, sigma=0.1, lambda=0.1*lambda_max"
         res["precision"] = ("FP32 descent from the double beta, a double-state finish "
                             "round after the first failed double check, double stop test")
+        log("c2: schedules")
+        res["schedules"] = schedules_bench(d, torch, D2, X2)
         configs["c2"] = res
     if "c3" in only:
         log("c3: long, split-bf16")
@@ -515,6 +611,8 @@ def main():
         res["precision"] = ("split-bf16 MFMA beta with fp32 accumulation, FP32 descent with "
                             "refresh from the double check, no double descent round; "
                             "lambda_max exact (near-maximal entries recomputed in double)")
+        log("c3: screening")
+        res["screening"] = screening_report(d, torch, D3, X3, mixed, res["schedule"])
         configs["c3"] = res
     if "c5" in only:
         log("c5: served")

@@ -136,6 +136,8 @@ typedef struct {
                              /* their length bucket when one exists                  */
                              /* (dicod_autotune_device); served requests keep the    */
                              /* config's schedule                                    */
+    int screen;              /* 1 = after the solve, count the coordinates the Gap    */
+                             /* Safe rule proves zero (one more double check pass)   */
 } dicod_config;
 
 typedef struct {
@@ -179,6 +181,10 @@ typedef struct {
     int update_cap;           /* updates per segment per phase it ran with (0: none) */
     int tuned;                /* 1 if colours, cap and M came from the tuning table   */
     int pad_;
+    double duality_gap;       /* E(Z) - Dual(theta) >= E(Z) - E(Z*) at the returned Z, */
+                              /* theta = R / max(lambda, max |D^T R|) (safe screening) */
+    int64_t n_screened;       /* coordinates the Gap Safe sphere rule proves zero     */
+                              /* (screen = 1; else -1)                                */
 } dicod_stats;
 
 /* One entry of the autotuner's table: the schedule chosen for the signals of
@@ -213,7 +219,7 @@ typedef struct {
 /* Fills *cfg with the defaults: device 0, FP32, coloured phases, update_cap -1,
  * max_phases 1e6, max_refresh 8, phases_per_poll 16, inner_eps_factor 0.5,
  * timing 0, no trace, state_in_lds 1, fp64_polish_after 1, colors 3,
- * verify_from_scratch 0, reg_state 1, autotune 0.  Returns DICOD_OK, or DICOD_EINVAL if
+ * verify_from_scratch 0, reg_state 1, autotune 0, screen 0.  Returns DICOD_OK, or DICOD_EINVAL if
  * cfg is NULL. */
 int dicod_config_init(dicod_config *cfg);
 

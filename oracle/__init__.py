@@ -98,6 +98,9 @@ def load_library(path):
     lib.oracle_soft_threshold.argtypes = [ctypes.c_double, ctypes.c_double]
     lib.oracle_norms.argtypes = [dp, ci, ci, ci, dp]
     lib.oracle_s_table.argtypes = [dp, ci, ci, ci, dp]
+    lib.oracle_gap_safe.argtypes = [dp, dp, dp, ci, ci, ci, i64, ctypes.c_double, dp, dp,
+                                    ctypes.c_void_p]
+    lib.oracle_gap_safe.restype = i64
     lib.oracle_h1_ratio.argtypes = [dp, ci, ci, ci]
     lib.oracle_h1_ratio.restype = ctypes.c_double
     lib.oracle_correlate.argtypes = [dp, ci, ci, ci, dp, i64, dp]
@@ -150,6 +153,20 @@ def s_table(D):
     out = np.empty((K, K, 2 * W - 1))
     _load().oracle_s_table(_ptr(D), K, P, W, _ptr(out))
     return out
+
+
+def gap_safe(X, D, Z, lam):
+    """(gap, radius, screened bool [K, L]) of the Gap Safe sphere rule at Z:
+    screened coordinates are zero in every solution of (2)."""
+    X, D, Z = _f64(X), _f64(D), _f64(Z)
+    K, P, W = D.shape
+    g, r = ctypes.c_double(0.0), ctypes.c_double(0.0)
+    out = np.zeros(Z.shape, dtype=np.uint8)
+    n = _load().oracle_gap_safe(_ptr(X), _ptr(D), _ptr(Z), K, P, W, X.shape[1], float(lam),
+                                ctypes.byref(g), ctypes.byref(r), out.ctypes.data)
+    if n < 0:
+        raise MemoryError("oracle_gap_safe: out of memory")
+    return g.value, r.value, out.astype(bool)
 
 
 def h1_ratio(D):

@@ -175,6 +175,76 @@ double oracle_objective(const double *X, const double *D, const double *Z, int K
     return 0.5 * quad + lam * l1;
 }
 
+/* Safe screening (Sec. 2.4 names screening as a complement to the
+ * greedy selection; this is the Gap Safe sphere rule of Fercoq, Gramfort and
+ * Salmon, 2015, for the Lasso (2) written out in the convolutional case).
+ * With R = X - sum_k Z_k * D_k and c_k[t] = sum_p sum_tau D_k[p][tau] R[p][t + tau]
+ * (the correlation D^T R), the rescaled residual theta = R / max(lambda,
+ * max |c|) is dual feasible (|D^T theta| <= 1); the dual objective is
+ * Dual(theta) = 1/2 |X|^2 - lambda^2 / 2 |theta - X / lambda|^2, the gap
+ * G = E(Z) - Dual(theta) >= 0, and every coordinate with
+ * |c_k[t]| / max(lambda, max |c|) + sqrt(2 G) / lambda |D_k|_2 < 1 is zero in
+ * every solution of (2).  Writes the gap, the sphere radius sqrt(2 G) / lambda
+ * and screened[k * L + t] (1 = proved zero); returns the number screened, or
+ * -1 when out of memory. */
+int64_t oracle_gap_safe(const double *X, const double *D, const double *Z, int K, int P,
+                        int W, int64_t T, double lam, double *gap, double *radius,
+                        unsigned char *screened)
+{
+    const int64_t L = T - W + 1;
+    double *R = (double *)malloc(sizeof(double) * (size_t)P * (size_t)T);
+    double *c = (double *)malloc(sizeof(double) * (size_t)K * (size_t)L);
+    double *n2 = (double *)malloc(sizeof(double) * (size_t)K);
+    if (!R || !c || !n2) {
+        free(R);
+        free(c);
+        free(n2);
+        return -1;
+    }
+    oracle_reconstruct(D, Z, K, P, W, T, R);
+    double rr = 0.0, xx = 0.0;
+    for (int64_t i = 0; i < (int64_t)P * T; ++i) {
+        R[i] = X[i] - R[i];
+        rr += R[i] * R[i];
+        xx += X[i] * X[i];
+    }
+    oracle_correlate(D, K, P, W, R, T, c);
+    oracle_norms(D, K, P, W, n2);
+    double cmax = 0.0, l1 = 0.0;
+    for (int64_t i = 0; i < (int64_t)K * L; ++i) {
+        if (fabs(c[i]) > cmax)
+            cmax = fabs(c[i]);
+        l1 += fabs(Z[i]);
+    }
+    const double sc = cmax > lam ? cmax : lam;
+    const double primal = 0.5 * rr + lam * l1;
+    /* |theta - X / lambda|^2 with theta = R / sc */
+    double dd = 0.0;
+    for (int64_t i = 0; i < (int64_t)P * T; ++i) {
+        double v = R[i] / sc - X[i] / lam;
+        dd += v * v;
+    }
+    const double dual = 0.5 * xx - 0.5 * lam * lam * dd;
+    double G = primal - dual;
+    if (G < 0.0)
+        G = 0.0;
+    const double r = sqrt(2.0 * G) / lam;
+    int64_t n = 0;
+    for (int k = 0; k < K; ++k)
+        for (int64_t t = 0; t < L; ++t) {
+            const int64_t i = (int64_t)k * L + t;
+            const int z = fabs(c[i]) / sc + r * sqrt(n2[k]) < 1.0;
+            screened[i] = (unsigned char)z;
+            n += z;
+        }
+    *gap = G;
+    *radius = r;
+    free(R);
+    free(c);
+    free(n2);
+    return n;
+}
+
 /* beta from its definition (Sec. 2.1): the correlation of D_k with the
  * residual in which Z_k[t] alone is set to zero (reading R1). */
 int oracle_beta(const double *X, const double *D, const double *Z, int K, int P,

@@ -60,6 +60,7 @@ class dicod_config(ctypes.Structure):
         ("verify_from_scratch", ctypes.c_int),
         ("reg_state", ctypes.c_int),
         ("autotune", ctypes.c_int),
+        ("screen", ctypes.c_int),
     ]
 
 
@@ -102,6 +103,8 @@ class dicod_stats(ctypes.Structure):
         ("update_cap", ctypes.c_int),
         ("tuned", ctypes.c_int),
         ("pad_", ctypes.c_int),
+        ("duality_gap", ctypes.c_double),
+        ("n_screened", ctypes.c_int64),
     ]
 
     def to_dict(self):

@@ -286,6 +286,7 @@ extern "C" int dicod_config_init(dicod_config* cfg)
     cfg->verify_from_scratch = 0;
     cfg->reg_state = 1;
     cfg->autotune = 0;
+    cfg->screen = 0;
     return DICOD_OK;
 }
 
@@ -311,7 +312,8 @@ extern "C" int dicod_init(dicod_ctx** out, const dicod_config* cfg)
     if (c.update_cap < -1 || c.max_phases < 2 || c.max_refresh < 0 ||
         c.phases_per_poll < 1 || !(c.inner_eps_factor > 0.0 && c.inner_eps_factor <= 1.0) ||
         c.trace_capacity < 0 || c.max_inflight < 1 || c.fp64_polish_after < 0 ||
-        c.colors < 2 || c.colors > kMaxColors || c.autotune < 0 || c.autotune > 1)
+        c.colors < 2 || c.colors > kMaxColors || c.autotune < 0 || c.autotune > 1 ||
+        c.screen < 0 || c.screen > 1)
         return fail(nullptr, DICOD_EINVAL, "dicod_init: invalid configuration field");
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0)
@@ -1351,6 +1353,46 @@ int solve_device_batch(dicod_ctx* ctx, int n_sig, const float* dX, const int64_t
                 pl.sig[i].lam = 1e-300;  // X orthogonal to every atom: Z = 0
         }
     }
+    // Duality gap of the returned Z (Gap Safe rule): theta = R / max(lambda,
+    // max |D^T R|) is dual feasible, gap = E(Z) - Dual(theta) with
+    // Dual(theta) = -lambda^2 |R|^2 / (2 s^2) + lambda <R, X> / s and
+    // <R, X> = |X|^2 - <beta0, Z>.  With screen = 1 the coordinates the
+    // sphere rule proves zero are counted from g recomputed in double.
+    std::vector<double> gap(n_sig, 0.0), rule(2 * (size_t)n_sig, 0.0);
+    std::vector<unsigned long long> n_scr(n_sig, 0ull);
+    for (int i = 0; i < n_sig; ++i) {
+        const double lam = pl.sig[i].lam;
+        const double sc = std::max(lam, res[i].gmax);
+        const double primal = 0.5 * res[i].sum_r2 + lam * res[i].l1;
+        const double dual =
+            -lam * lam * res[i].sum_r2 / (2.0 * sc * sc) + lam * (res[i].x2 - res[i].bx) / sc;
+        gap[i] = std::max(primal - dual, 0.0);
+        rule[2 * i] = 1.0 / sc;
+        rule[2 * i + 1] = std::sqrt(2.0 * gap[i]) / lam;
+    }
+    if (cfg.screen) {
+        if (!fp64)
+            HIPCHECK(ctx, ensure(ws.g64, pl.zext * sizeof(double)));
+        void* gs = fp64 ? ws.g.p : ws.g64.p;
+        HIPCHECK(ctx, launch_nz_mask(dZ, ws.sig.as<SigDesc>(), ws.tilesN.as<int64_t>(), n_sig, K,
+                                     nN, ws.nzmask.as<unsigned long long>(), s));
+        HIPCHECK(ctx, launch_grad_check(dX, ws.beta0.as<double>(), dZ,
+                                        ws.nzmask.as<unsigned long long>(),
+                                        ctx->Sc64.as<double>(), ctx->n2_64.as<double>(), K, P, W,
+                                        ws.sig.as<SigDesc>(), ws.tilesC.as<int64_t>(), n_sig, nC,
+                                        eps, nullptr, nullptr, gs, true, nullptr,
+                                        ws.part.as<double>(), nullptr, s));
+        HIPCHECK(ctx, upload(ws.thr, rule, s));
+        HIPCHECK(ctx, ensure(ws.ebits, n_sig * sizeof(unsigned long long)));
+        HIPCHECK(ctx, launch_fill_u64(ws.ebits.as<unsigned long long>(), 0ull, n_sig, s));
+        HIPCHECK(ctx, launch_screen_count(gs, true, ctx->n2_64.as<double>(), K,
+                                          ws.sig.as<SigDesc>(), ws.tilesA.as<int64_t>(), n_sig,
+                                          nA, ws.thr.as<double>(),
+                                          ws.ebits.as<unsigned long long>(), s));
+        HIPCHECK(ctx, hipMemcpyAsync(n_scr.data(), ws.ebits.p, n_sig * sizeof(unsigned long long),
+                                     hipMemcpyDeviceToHost, s));
+        HIPCHECK(ctx, hipStreamSynchronize(s));
+    }
     const double t_init = elapsed_ms(ev0, ev1);
     const double t_total = now_ms() - t_call0;
     if (st) {
@@ -1402,6 +1444,8 @@ int solve_device_batch(dicod_ctx* ctx, int n_sig, const float* dX, const int64_t
             }
             o.state_in_hbm = any_hbm ? 1 : 0;
             o.polished_fp64 = polished ? 1 : 0;
+            o.duality_gap = gap[i];
+            o.n_screened = cfg.screen ? (int64_t)n_scr[i] : -1;
             o.colors = pl.colors;
             o.update_cap = cfg.update_cap == 0 ? 0 : effective_update_cap(cfg.update_cap, W);
             o.tuned = tuned;

@@ -12,7 +12,7 @@ namespace dicod {
 
 constexpr int kCheckKB = 8;      // most atoms of one block of the double check
 constexpr int kCheckSpan = 1024; // positions of one tile of the double check
-constexpr int kCheckParts = 8;   // partials per check tile
+constexpr int kCheckParts = 10;  // partials per check tile
 constexpr int kMaxP = 16;        // channels accepted (the correlation kernels stage P rows)
 constexpr int kPhaseThreads = 512;
 constexpr int kPhaseThreadsMax = 1024;
@@ -60,6 +60,9 @@ struct CheckResult {
     double sum_r2;
     double max_abs_z;
     double nnz;
+    double bx;         // <beta0, Z> = <X, sum_k Z_k * D_k>
+    double gmax;       // max |g| = max |D^T R| over the coordinates
+    double x2;         // |X|^2
     double pad;
 };
 
@@ -266,6 +269,13 @@ size_t win_energy_lds_bytes(int W);
 hipError_t launch_win_energy_max(const float* X, int P, int W, const SigDesc* sig,
                                  const int64_t* tile_pref, int n_sig, int64_t n_tiles,
                                  unsigned long long* out_bits, hipStream_t s);
+// Coordinates proved zero by the Gap Safe rule (kernels.hip): g float or
+// double [K][L] per signal, rule[2 i] = 1 / max(lambda, max|g|) and
+// rule[2 i + 1] = sqrt(2 gap) / lambda; count per signal (accumulated).
+hipError_t launch_screen_count(const void* g, bool fp64, const double* n2, int K,
+                               const SigDesc* sig, const int64_t* tile_pref, int n_sig,
+                               int64_t n_tiles, const double* rule, unsigned long long* count,
+                               hipStream_t s);
 hipError_t launch_absmax_f32(const float* beta, int K, const SigDesc* sig,
                              const int64_t* tile_pref, int n_sig, int64_t n_tiles,
                              unsigned long long* out_bits, hipStream_t s);

@@ -1170,6 +1170,16 @@ int server_poll(dicod_ctx* ctx, uint64_t req_id, double* Z_out, dicod_stats* st)
         st->update_cap = srv->cfg.update_cap == 0 ? 0
                                                   : effective_update_cap(srv->cfg.update_cap, srv->W);
         st->tuned = j->tuned;
+        {
+            // duality gap of the returned Z (as in the one-shot solve)
+            const double lam = j->lam;
+            const double sc = std::max(lam, j->res.gmax);
+            const double primal = 0.5 * j->res.sum_r2 + lam * j->res.l1;
+            const double dual = -lam * lam * j->res.sum_r2 / (2.0 * sc * sc) +
+                                lam * (j->res.x2 - j->res.bx) / sc;
+            st->duality_gap = std::max(primal - dual, 0.0);
+            st->n_screened = -1;
+        }
         st->converged = j->res.max_dz < j->eps ? 1 : 0;
         st->n_refresh = j->n_refresh;
         st->lambda = j->lam;

@@ -628,6 +628,56 @@ hipError_t launch_absmax(const double* beta, int K, const SigDesc* sig,
     return hipGetLastError();
 }
 
+// Gap Safe sphere rule at the current Z (safe screening): coordinate (k, t)
+// is zero in every solution when |g_k[t]| / s + r |D_k| < 1, with g = D^T R,
+// s = max(lambda, max |g|) and r = sqrt(2 gap) / lambda per signal
+// (rule[2 si] = 1 / s, rule[2 si + 1] = r).  A float g is enlarged by 2^-22
+// of itself first, so rounding never screens a coordinate the double value
+// would keep.  count[si] gets the screened coordinates.
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_screen_count(const T* __restrict__ g, const double* __restrict__ n2, int K,
+               const SigDesc* __restrict__ sig, const int64_t* __restrict__ tile_pref,
+               int n_sig, const double* __restrict__ rule,
+               unsigned long long* __restrict__ count)
+{
+    __shared__ unsigned long long red[4];
+    const int64_t tile = blockIdx.x;
+    const int si = find_sig(tile_pref, n_sig, tile);
+    const SigDesc sd = sig[si];
+    const int64_t n = (int64_t)K * sd.L;
+    const int64_t i0 = (tile - tile_pref[si]) * kAbsChunk;
+    const double inv_s = rule[2 * si], r = rule[2 * si + 1];
+    const double slack = sizeof(T) == 4 ? 2.384185791015625e-7 : 0.0;  // 2^-22
+    unsigned long long c = 0;
+    for (int64_t i = i0 + threadIdx.x; i < n && i < i0 + kAbsChunk; i += 256) {
+        const int k = (int)(i / sd.L);
+        const double a = fabs((double)g[sd.z_off + i]);
+        c += (a + slack * a) * inv_s + r * sqrt(n2[k]) < 1.0 ? 1ull : 0ull;
+    }
+    for (int o = 32; o > 0; o >>= 1)
+        c += __shfl_xor(c, o);
+    if ((threadIdx.x & 63) == 0)
+        red[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        atomicAdd(&count[si], red[0] + red[1] + red[2] + red[3]);
+}
+
+hipError_t launch_screen_count(const void* g, bool fp64, const double* n2, int K,
+                               const SigDesc* sig, const int64_t* tile_pref, int n_sig,
+                               int64_t n_tiles, const double* rule, unsigned long long* count,
+                               hipStream_t s)
+{
+    if (fp64)
+        hipLaunchKernelGGL(k_screen_count<double>, dim3((unsigned)n_tiles), dim3(256), 0, s,
+                           (const double*)g, n2, K, sig, tile_pref, n_sig, rule, count);
+    else
+        hipLaunchKernelGGL(k_screen_count<float>, dim3((unsigned)n_tiles), dim3(256), 0, s,
+                           (const float*)g, n2, K, sig, tile_pref, n_sig, rule, count);
+    return hipGetLastError();
+}
+
 hipError_t launch_absmax_f32(const float* beta, int K, const SigDesc* sig,
                              const int64_t* tile_pref, int n_sig, int64_t n_tiles,
                              unsigned long long* out_bits, hipStream_t s)
@@ -2018,6 +2068,7 @@ k_grad_check(const float* __restrict__ X, const double* __restrict__ beta0,
     }
 
     double mdz = 0.0, kon = 0.0, koff = 0.0, l1 = 0.0, mz = 0.0, nnz = 0.0, x2 = 0.0, bz = 0.0;
+    double bx = 0.0, gm = 0.0;
     const double lam = sd.lam;
 #pragma unroll
     for (int j = 0; j < J; ++j) {
@@ -2046,6 +2097,7 @@ k_grad_check(const float* __restrict__ X, const double* __restrict__ beta0,
             const double zp = ab > 0.0 ? (bb > 0.0 ? ab : -ab) / n2 : 0.0;
             const double dz = fabs(zp - z);
             mdz = fmax(mdz, dz);
+            gm = fmax(gm, fabs(g));
             if (dz >= flag_eps)
                 flag = true;
             if (z != 0.0) {
@@ -2053,7 +2105,9 @@ k_grad_check(const float* __restrict__ X, const double* __restrict__ beta0,
                 l1 += fabs(z);
                 mz = fmax(mz, fabs(z));
                 nnz += 1.0;
-                bz += (beta0[o] + g) * z;
+                const double b0 = beta0[o];
+                bz += (b0 + g) * z;
+                bx += b0 * z;
             } else {
                 koff = fmax(koff, fmax(fabs(g) - lam, 0.0) / n2);
             }
@@ -2088,6 +2142,8 @@ k_grad_check(const float* __restrict__ X, const double* __restrict__ beta0,
     nnz = block_sum256(nnz, red);
     x2 = block_sum256(x2, red);
     bz = block_sum256(bz, red);
+    bx = block_sum256(bx, red);
+    gm = block_max256(gm, red);
     if (tid == 0) {
         double* o = part + ((int64_t)blockIdx.y * gridDim.x + tile) * kCheckParts;
         o[0] = mdz;
@@ -2098,6 +2154,8 @@ k_grad_check(const float* __restrict__ X, const double* __restrict__ beta0,
         o[5] = nnz;
         o[6] = x2;
         o[7] = bz;
+        o[8] = bx;
+        o[9] = gm;
     }
 }
 
@@ -2144,6 +2202,7 @@ k_check_reduce(const double* __restrict__ part, const int64_t* __restrict__ pref
     __shared__ double red[4];
     const int si = blockIdx.x;
     double mdz = 0.0, kon = 0.0, koff = 0.0, l1 = 0.0, mz = 0.0, nnz = 0.0, x2 = 0.0, bz = 0.0;
+    double bx = 0.0, gm = 0.0;
     for (int kbk = 0; kbk < n_kblk; ++kbk)
         for (int64_t i = pref[si] + threadIdx.x; i < pref[si + 1]; i += 256) {
             const double* p = part + ((int64_t)kbk * n_tiles + i) * kCheckParts;
@@ -2155,6 +2214,8 @@ k_check_reduce(const double* __restrict__ part, const int64_t* __restrict__ pref
             nnz += p[5];
             x2 += p[6];
             bz += p[7];
+            bx += p[8];
+            gm = fmax(gm, p[9]);
         }
     mdz = block_max256(mdz, red);
     kon = block_max256(kon, red);
@@ -2164,6 +2225,8 @@ k_check_reduce(const double* __restrict__ part, const int64_t* __restrict__ pref
     nnz = block_sum256(nnz, red);
     x2 = block_sum256(x2, red);
     bz = block_sum256(bz, red);
+    bx = block_sum256(bx, red);
+    gm = block_max256(gm, red);
     if (threadIdx.x == 0) {
         CheckResult c;
         c.max_dz = mdz;
@@ -2173,6 +2236,9 @@ k_check_reduce(const double* __restrict__ part, const int64_t* __restrict__ pref
         c.sum_r2 = fmax(x2 - bz, 0.0);  // rounding could leave an exact fit just below 0
         c.max_abs_z = mz;
         c.nnz = nnz;
+        c.bx = bx;
+        c.gmax = gm;
+        c.x2 = x2;
         c.pad = 0.0;
         out[si] = c;
     }

@@ -60,6 +60,15 @@ MUTANTS = [
     ("h1_unnormalised",
      "/ sqrt(n2[k] * n2[l]);",
      "/ 1.0;"),
+    ("gap_safe_theta_not_rescaled",
+     "const double sc = cmax > lam ? cmax : lam;",
+     "const double sc = lam;"),
+    ("gap_safe_radius_halved",
+     "const double r = sqrt(2.0 * G) / lam;",
+     "const double r = sqrt(0.5 * G) / lam;"),
+    ("gap_safe_atom_norm_dropped",
+     "fabs(c[i]) / sc + r * sqrt(n2[k]) < 1.0",
+     "fabs(c[i]) / sc + r < 1.0"),
     ("message_sent_to_wrong_side",
      "out[((size_t)(m + 1) * 2) * per + n_out[2 * (m + 1)]++] = msg;",
      "out[((size_t)(m + 1) * 2 + 1) * per + n_out[2 * (m + 1)]++] = msg;"),
@@ -88,6 +97,9 @@ def _pins():
         lambda: pins.test_dicod_schedule_interferes_and_converges(),
         lambda: pins.test_h1_ratio_closed_forms(),
         lambda: pins.test_h1_ratio_matches_numpy_definition(),
+        lambda: pins.test_gap_safe_closed_form_at_zero(),
+        lambda: pins.test_gap_safe_is_safe_and_bounds_the_objective(0),
+        lambda: pins.test_gap_safe_mask_is_the_sphere_test(),
     ]
 
 

@@ -411,6 +411,130 @@ def test_h1_ratio_matches_numpy_definition():
         assert abs(oracle.h1_ratio(D) - best) <= 1e-13 * max(best, 1e-300) + 1e-300
 
 
+# ------------------------------------------------- safe screening (Gap Safe)
+
+def _scaled(D, seed, lo=0.3, hi=3.0):
+    rng = np.random.default_rng(seed)
+    Dn = D / np.sqrt(np.sum(D ** 2, axis=(1, 2), keepdims=True))
+    return Dn * rng.uniform(lo, hi, size=D.shape[0])[:, None, None]
+
+
+def test_gap_safe_closed_form_at_zero():
+    """At Z = 0 the residual is X and theta = X / max(lambda, lambda_max):
+    gap = |X|^2 / 2 (1 - lambda / lambda_max)^2 for lambda < lambda_max, 0 above;
+    above lambda_max every coordinate with |beta| < lambda is screened."""
+    X, D, _ = tiny_problem(4)
+    D = _scaled(D, 4)
+    Z = np.zeros((D.shape[0], X.shape[1] - D.shape[2] + 1))
+    lmax = oracle.lambda_max(X, D)
+    xx = float(np.sum(X ** 2))
+    for f in (0.1, 0.5, 0.9):
+        g, r, sc = oracle.gap_safe(X, D, Z, f * lmax)
+        ref = 0.5 * xx * (1.0 - f) ** 2
+        assert abs(g - ref) <= 1e-12 * xx, (g, ref)
+        assert abs(r - np.sqrt(2.0 * ref) / (f * lmax)) <= 1e-9 * r
+    g, r, sc = oracle.gap_safe(X, D, Z, 1.5 * lmax)
+    assert g <= 1e-12 * xx
+    B = oracle.correlate(D, X)
+    assert np.array_equal(sc, np.abs(B) / (1.5 * lmax) + r * np.sqrt(oracle.norms(D))[:, None] < 1)
+    assert sc.all()
+
+
+def _numpy_corr(D, R):
+    """c_k[t] = sum_p sum_tau D_k[p][tau] R[p][t + tau] with numpy.correlate."""
+    K, P, W = D.shape
+    return np.array([sum(np.correlate(R[p], D[k, p], "valid") for p in range(P))
+                     for k in range(K)])
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_gap_safe_is_safe_and_bounds_the_objective(seed):
+    """At iterates of every accuracy: the dual point is feasible (numpy),
+    E(Z) - E(Z*) <= gap (weak duality), and every screened coordinate is zero
+    in the reference solution (eps_ref = 1e-10) and in the explicit Toeplitz
+    Lasso solved by ISTA; atoms of unequal norms."""
+    X, D, _ = tiny_problem(10 + seed, P=2, K=3, W=6, T=60, rho=0.06)
+    D = _scaled(D, seed)
+    K, P, W = D.shape
+    L = X.shape[1] - W + 1
+    lam = 0.2 * oracle.lambda_max(X, D)
+    Zref, st, _ = oracle.lgcd(X, D, lam, 1e-10, 1)
+    assert st["converged"] == 1
+    Eref = oracle.objective(X, D, Zref, lam)
+    # explicit Toeplitz Lasso: columns are the shifted atoms
+    A = np.zeros((P * X.shape[1], K * L))
+    for k in range(K):
+        for t in range(L):
+            col = np.zeros((P, X.shape[1]))
+            col[:, t:t + W] = D[k]
+            A[:, k * L + t] = col.ravel()
+    step = 1.0 / np.linalg.norm(A, 2) ** 2
+    z = np.zeros(K * L)
+    for _ in range(20000):
+        v = z - step * (A.T @ (A @ z - X.ravel()))
+        z = np.sign(v) * np.maximum(np.abs(v) - step * lam, 0.0)
+    Zista = z.reshape(K, L)
+    rng = np.random.default_rng(seed)
+    n_total = 0
+    for eps in (1e-1, 1e-3, 1e-6):
+        Z, _, _ = oracle.lgcd(X, D, lam, eps, 1)
+        for Zi in (Z, Z + 0.01 * rng.standard_normal(Z.shape) * (Z != 0)):
+            g, r, sc = oracle.gap_safe(X, D, Zi, lam)
+            R = X - oracle.reconstruct(D, Zi, X.shape[1])
+            c = _numpy_corr(D, R)
+            sc_ = max(lam, np.abs(c).max())
+            assert np.abs(c / sc_).max() <= 1.0 + 1e-12
+            assert oracle.objective(X, D, Zi, lam) - Eref <= g * (1 + 1e-9) + 1e-12
+            assert not np.any(Zref[sc] != 0)
+            assert np.all(np.abs(Zista[sc]) <= 1e-8)
+            n_total += int(sc.sum())
+    assert n_total > 0
+
+
+def test_gap_safe_mask_is_the_sphere_test():
+    """The screened set is exactly the set of coordinates whose shifted atom
+    a (a column of the explicit Toeplitz matrix) keeps |<a, theta'>| < 1 over
+    the whole ball around theta of radius sqrt(2 gap) / lambda: the maximum
+    over that ball is attained at theta' = theta + r a / |a| (or its mirror),
+    evaluated here explicitly; theta, the primal and the dual objectives are
+    formed with numpy.  Atoms of unequal norms, iterates of several accuracies."""
+    X, D, _ = tiny_problem(21, P=2, K=3, W=6, T=60, rho=0.06)
+    D = _scaled(D, 21)
+    K, P, W = D.shape
+    T = X.shape[1]
+    L = T - W + 1
+    lam = 0.2 * oracle.lambda_max(X, D)
+    A = np.zeros((P * T, K * L))
+    for k in range(K):
+        for t in range(L):
+            col = np.zeros((P, T))
+            col[:, t:t + W] = D[k]
+            A[:, k * L + t] = col.ravel()
+    x = X.ravel()
+    n_diff_norm = 0
+    for eps in (3e-1, 1e-1, 1e-2, 1e-4):
+        Z, _, _ = oracle.lgcd(X, D, lam, eps, 1)
+        z = Z.ravel()
+        res = x - A @ z
+        c = A.T @ res
+        sc = max(lam, np.abs(c).max())
+        theta = res / sc
+        primal = 0.5 * res @ res + lam * np.abs(z).sum()
+        dual = 0.5 * x @ x - 0.5 * lam ** 2 * np.sum((theta - x / lam) ** 2)
+        r = np.sqrt(2.0 * max(primal - dual, 0.0)) / lam
+        g, r_o, mask = oracle.gap_safe(X, D, Z, lam)
+        assert abs(g - (primal - dual)) <= 1e-9 * max(1.0, primal)
+        for j in range(K * L):
+            a = A[:, j]
+            na = np.linalg.norm(a)
+            top = max(abs(a @ (theta + r * a / na)), abs(a @ (theta - r * a / na)))
+            if abs(top - 1.0) < 1e-9:
+                continue                      # on the boundary: rounding decides
+            assert mask.ravel()[j] == (top < 1.0), (eps, j, top)
+            n_diff_norm += (abs(a @ theta) + r < 1.0) != (top < 1.0)
+    assert n_diff_norm > 0    # the atom norm changed the decision somewhere
+
+
 def test_bad_arguments_rejected():
     X, D, _ = tiny_problem(0)
     with pytest.raises(ValueError):
