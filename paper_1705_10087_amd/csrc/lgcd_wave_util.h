@@ -75,18 +75,6 @@ __device__ __forceinline__ float cand(float g, float z, float n2, float inv, flo
     return fabsf(bb) <= lam ? -z : (g - copysignf(lam, bb)) * inv;
 }
 
-// The same change for the selection key only: the soft threshold as
-// beta - clamp(beta, -lambda, lambda), so Delta Z = (g - clamp(beta)) / |D_k|^2
-// in four operations.  It equals cand() where |beta| > lambda; where the
-// threshold is active it is -z up to one rounding of beta, below the float
-// resolution 2^-24 lambda / |D_k|^2 of the state.  The winner's change itself
-// comes from cand().
-__device__ __forceinline__ float cand_key(float g, float z, float n2, float inv, float lam)
-{
-    const float bb = fmaf(n2, z, g);
-    return (g - __builtin_amdgcn_fmed3f(bb, -lam, lam)) * inv;
-}
-
 __device__ __forceinline__ unsigned make_key(float d, int k)
 {
     return (__float_as_uint(d) & 0x7fffffe0u) | (unsigned)(31 - k);
@@ -100,7 +88,8 @@ __device__ __forceinline__ float key_value(unsigned key)
 // Best key over the own position's atoms.  z: this thread's column of the
 // LDS array [KQ][threads].  Padded atoms (g = z = 0) give a zero key; they
 // run unconditionally, which costs fewer instructions than branching around
-// them.
+// them.  (A four-operation form of the soft threshold through a clamp of
+// beta measured slower here than the compare-and-select of cand().)
 template <int KQ, int NT>
 __device__ __forceinline__ unsigned best_key(const f4 (&g)[KQ], const f4* __restrict__ z,
                                              const f4* __restrict__ cn2,
@@ -113,7 +102,7 @@ __device__ __forceinline__ unsigned best_key(const f4 (&g)[KQ], const f4* __rest
         const f4 zv = z[i * NT];
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
-            const float d = cand_key(g[i][c], zv[c], n2[c], iv[c], lam);
+            const float d = cand(g[i][c], zv[c], n2[c], iv[c], lam);
             const unsigned key = make_key(d, 4 * i + c);
             best = key > best ? key : best;
         }
