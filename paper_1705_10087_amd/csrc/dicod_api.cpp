@@ -103,6 +103,7 @@ struct Workspace {
     DevBuf msg, msg_n;                    // DICOD schedule: boundary messages
     DevBuf box, box_n, z32;               // register kernel: mailboxes, float copy of Z
     DevBuf ring, ring_wr;                 // free-running schedule: rings and their counters
+    DevBuf changed;                       // per segment: Z changed since the last check
     DevBuf trace;
     DevBuf slots, lamin;                  // device-side lambda: signal indices, inputs
     // host copies of what the read-only plan tables hold on the device: an
@@ -808,6 +809,7 @@ int solve_device_batch(dicod_ctx* ctx, int n_sig, const float* dX, const int64_t
         HIPCHECK(ctx, ensure(ws.z32, pl.zext * sizeof(float)));
     }
     HIPCHECK(ctx, ensure(ws.dirty, (pl.dicod ? 2 : 1) * n_seg_tot * sizeof(uint32_t)));
+    HIPCHECK(ctx, ensure(ws.changed, (size_t)n_seg_tot * sizeof(uint32_t)));
     const int msg_cap = pl.dicod ? effective_update_cap(cfg.update_cap, W) : 0;
     if (pl.dicod) {
         HIPCHECK(ctx, ensure(ws.msg, (size_t)4 * n_seg_tot * msg_cap * sizeof(DicodMsg)));
@@ -950,6 +952,7 @@ int solve_device_batch(dicod_ctx* ctx, int n_sig, const float* dX, const int64_t
         }
     }
     HIPCHECK(ctx, launch_fill_u32(ws.dirty.as<uint32_t>(), 1u, n_seg_tot, s));
+    HIPCHECK(ctx, launch_fill_u32(ws.changed.as<uint32_t>(), 1u, n_seg_tot, s));
     if (reg_ok)
         HIPCHECK(ctx, launch_fill_u32(ws.box_n.as<uint32_t>(), 0u, (size_t)2 * n_seg_tot, s));
     if (async)
@@ -1072,6 +1075,7 @@ int solve_device_batch(dicod_ctx* ctx, int n_sig, const float* dX, const int64_t
     a.box_n = reg_ok ? ws.box_n.as<uint32_t>() : nullptr;
     a.box_cap = box_cap;
     a.z32 = reg_ok ? ws.z32.as<float>() : nullptr;
+    a.changed = ws.changed.as<uint32_t>();
     a.phase_stride = 0;
     if (async) {
         ax.ring = ws.ring.as<BoundaryRec>();
@@ -1092,6 +1096,7 @@ int solve_device_batch(dicod_ctx* ctx, int n_sig, const float* dX, const int64_t
 
     int64_t phase = 0, n_launch = 0, conv_phase = -1;
     int n_refresh = 0, round = 0;
+    int n_checks = 0, last_out = 0;  // checks run; state buffer the last refresh wrote
     bool accepted = false, out_of_phases = false;
     double t_cd = 0.0, t_verify = 0.0, t_kernel = 0.0;
     int64_t round_upd[4] = {0, 0, 0, 0}, round_ph[4] = {0, 0, 0, 0};
@@ -1254,6 +1259,12 @@ int solve_device_batch(dicod_ctx* ctx, int n_sig, const float* dX, const int64_t
         const double* g_in = (cur64 && !cfg.verify_from_scratch)
                                  ? (fp64 ? ws.g.as<double>() : ws.g64.as<double>())
                                  : nullptr;
+        // Only the tiles within reach of a segment whose Z changed since the
+        // last check are recomputed when that check wrote the same state
+        // buffer, or this one writes none (the check of a maintained double
+        // state after a double round, which changed few segments).
+        const int out_kind = g_in ? 0 : next64 ? 2 : 1;
+        const bool skip_tiles = n_checks > 0 && (out_kind == 0 || out_kind == last_out);
         if (!g_in)
             HIPCHECK(ctx, launch_nz_mask(dZ, ws.sig.as<SigDesc>(), ws.tilesN.as<int64_t>(), n_sig,
                                          K, nN, ws.nzmask.as<unsigned long long>(), s));
@@ -1265,7 +1276,11 @@ int solve_device_batch(dicod_ctx* ctx, int n_sig, const float* dX, const int64_t
                                         ws.dirty.as<uint32_t>(), g_in ? nullptr : g_next, next64,
                                         g_in, ws.part.as<double>(),
                                         reg_ok && !next64 && !g_in ? ws.z32.as<float>() : nullptr,
-                                        s));
+                                        skip_tiles ? ws.changed.as<uint32_t>() : nullptr, s));
+        HIPCHECK(ctx, launch_fill_u32(ws.changed.as<uint32_t>(), 0u, n_seg_tot, s));
+        ++n_checks;
+        if (out_kind != 0)
+            last_out = out_kind;
         HIPCHECK(ctx, launch_check_reduce(ws.part.as<double>(), ws.tilesC.as<int64_t>(), nC,
                                           n_kblk, n_sig, ws.results.as<CheckResult>(), s));
         HIPCHECK(ctx, hipMemcpyAsync(ctx->h_pin + pin_res, ws.results.p,
@@ -1381,7 +1396,7 @@ int solve_device_batch(dicod_ctx* ctx, int n_sig, const float* dX, const int64_t
                                         ctx->Sc64.as<double>(), ctx->n2_64.as<double>(), K, P, W,
                                         ws.sig.as<SigDesc>(), ws.tilesC.as<int64_t>(), n_sig, nC,
                                         eps, nullptr, nullptr, gs, true, nullptr,
-                                        ws.part.as<double>(), nullptr, s));
+                                        ws.part.as<double>(), nullptr, nullptr, s));
         HIPCHECK(ctx, upload(ws.thr, rule, s));
         HIPCHECK(ctx, ensure(ws.ebits, n_sig * sizeof(unsigned long long)));
         HIPCHECK(ctx, launch_fill_u64(ws.ebits.as<unsigned long long>(), 0ull, n_sig, s));

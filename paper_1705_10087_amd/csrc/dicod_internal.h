@@ -174,6 +174,9 @@ struct PhaseArgs {
     uint32_t* box_n;
     int box_cap;
     float* z32;
+    // Set to 1 for every segment whose Z a run changed (the double check
+    // recomputes only the tiles within reach of such segments); may be null.
+    uint32_t* changed;
 };
 hipError_t launch_lgcd_phase(const PhaseArgs& a, bool fp64, size_t* lds_bytes,
                              hipStream_t s);
@@ -244,7 +247,11 @@ hipError_t launch_grad_check(const float* X, const double* beta0, const double* 
                              const int64_t* tile_pref, int n_sig, int64_t n_tiles,
                              double flag_eps, const uint32_t* sig_done, uint32_t* dirty,
                              void* g_state, bool state_fp64, const double* g_in,
-                             double* part, float* z32, hipStream_t s);
+                             double* part, float* z32, const uint32_t* changed, hipStream_t s);
+// (changed, when not NULL: per-segment flags of Z changed since the last
+// check; a tile whose reach holds no changed segment keeps its partials and
+// refreshed state from that check, which must have run on the same tiles with
+// the same state output, and only re-marks its segments dirty.)
 // Atom blocks of the check (grid y); 0 when W is too large for it.
 int check_kblocks(int K, int W);
 int check_atoms_per_block(int K, int W);

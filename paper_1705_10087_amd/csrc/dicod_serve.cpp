@@ -738,7 +738,8 @@ int Lane::check_jobs(const std::vector<Job*>& conv, std::vector<Job*>& resumed)
                                           flag_eps, dDone.as<uint32_t>(),
                                           v.dDirty.as<uint32_t>(), g_in ? nullptr : g_next,
                                           next64, g_in, dPart.as<double>(),
-                                          !next64 && !g_in ? v.dZ32.as<float>() : nullptr, s));
+                                          !next64 && !g_in ? v.dZ32.as<float>() : nullptr,
+                                          nullptr, s));
                 SRV_HIP(launch_check_reduce(dPart.as<double>(), dTilesC.as<int64_t>(), pC[n],
                                             n_kblk, n, dRes.as<CheckResult>(), s));
                 SRV_HIP(hipMemcpyAsync(h_res, dRes.p, n * sizeof(CheckResult),

@@ -1297,6 +1297,8 @@ k_lgcd_phase(PhaseArgs a)
             atomicAdd(&a.sig_upd[sd.sig], (unsigned long long)n);
             atomicMax(&a.sig_last_upd[sd.sig], a.phase);
             atomicAdd(&a.counters->seg_runs, 1ull);
+            if (a.changed)
+                a.changed[sid] = 1u;
         }
     }
     if (tid == 0) {
@@ -1690,6 +1692,8 @@ k_lgcd_phase_gm(PhaseArgs a)
         atomicAdd(&a.sig_upd[sd.sig], (unsigned long long)n);
         atomicMax(&a.sig_last_upd[sd.sig], a.phase);
         atomicAdd(&a.counters->seg_runs, 1ull);
+        if (a.changed)
+            a.changed[sid] = 1u;
     }
     if (tid == 0) {
         a.dirty[sid] = conv ? 0u : 1u;
@@ -1914,7 +1918,7 @@ k_grad_check(const float* __restrict__ X, const double* __restrict__ beta0,
              const uint32_t* __restrict__ sig_done, uint32_t* __restrict__ dirty,
              float* __restrict__ g32, double* __restrict__ g64,
              const double* __restrict__ g_in, double* __restrict__ part,
-             float* __restrict__ z32)
+             float* __restrict__ z32, const uint32_t* __restrict__ changed)
 {
     extern __shared__ __align__(16) double sst[];  // 2 x [kper][2W]: S_{kb+k,l}[d - W + 1]
     __shared__ int ls[kCheckList];                 // listed non-zeros (l, s, Z_l[s])
@@ -1937,6 +1941,32 @@ k_grad_check(const float* __restrict__ X, const double* __restrict__ beta0,
     const double* __restrict__ Zs = Z + sd.z_off;
     // accepted signals are only measured: no refresh, no new dirty segments
     const bool frozen = sig_done && sig_done[si] != 0u;
+
+    // With change flags: a tile none of whose reach [t_a - W + 1,
+    // t_a + span + W - 1) lies in a segment whose Z changed since the last
+    // check keeps its partials and its refreshed state from that check; it
+    // only marks its segments dirty again when its largest |Delta Z| still
+    // reaches flag_eps.
+    if (changed) {
+        const int64_t lo = t_a - (W - 1) > 0 ? t_a - (W - 1) : 0;
+        const int64_t hi = t_a + 256 * J + (W - 1) < L ? t_a + 256 * J + (W - 1) : L;
+        const int64_t m0 = ((lo + 1) * (int64_t)sd.M - 1) / L;
+        const int64_t m1 = (hi * (int64_t)sd.M - 1) / L;
+        bool any = false;
+        for (int64_t m = m0; m <= m1; ++m)
+            any = any || changed[sd.seg_base + m] != 0u;
+        if (!any) {
+            const double* o = part + ((int64_t)blockIdx.y * gridDim.x + tile) * kCheckParts;
+            if (tid == 0 && dirty && !frozen && o[0] >= flag_eps) {
+                const int64_t e = t_a + 256 * J < L ? t_a + 256 * J : L;
+                const int64_t q0 = ((t_a + 1) * (int64_t)sd.M - 1) / L;
+                const int64_t q1 = (e * (int64_t)sd.M - 1) / L;
+                for (int64_t m = q0; m <= q1; ++m)
+                    dirty[sd.seg_base + m] = 1u;
+            }
+            return;
+        }
+    }
 
     // loads at clamped (valid) indices, unconditional so that they are all in
     // flight together; the values past the ends are never used
@@ -2165,7 +2195,7 @@ hipError_t launch_grad_check(const float* X, const double* beta0, const double* 
                              const int64_t* tile_pref, int n_sig, int64_t n_tiles,
                              double flag_eps, const uint32_t* sig_done, uint32_t* dirty,
                              void* g_state, bool state_fp64, const double* g_in,
-                             double* part, float* z32, hipStream_t s)
+                             double* part, float* z32, const uint32_t* changed, hipStream_t s)
 {
     const int kper = check_atoms_per_block(K, W);
     if (kper < 1)
@@ -2181,7 +2211,7 @@ hipError_t launch_grad_check(const float* X, const double* beta0, const double* 
                                   (int)lds);
         hipLaunchKernelGGL(kern, grid, dim3(256), lds, s, X, beta0, Z, masks, Sc, n2, K, P, W,
                            kper, sig, tile_pref, n_sig, flag_eps, sig_done, dirty, g32, g64,
-                           g_in, part, z32);
+                           g_in, part, z32, changed);
         return hipGetLastError();
     };
     static_assert(kCheckKB == 8, "instantiated atom counts");

@@ -426,6 +426,8 @@ k_lgcd_async(PhaseArgs a, AsyncArgs x)
                     atomicAdd(&a.sig_upd[sd.sig], (unsigned long long)n);
                     atomicMax(&a.sig_last_upd[sd.sig], a.phase);
                     atomicAdd(&a.counters->seg_runs, 1ull);
+                    if (a.changed)
+                        a.changed[sid] = 1u;
                 }
                 a.dirty[sid] = conv ? 0u : 1u;
             }
