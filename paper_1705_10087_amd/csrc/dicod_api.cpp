@@ -905,12 +905,20 @@ int solve_device_batch(dicod_ctx* ctx, int n_sig, const float* dX, const int64_t
     // cheaper float beta; the double beta0, needed only by the first
     // double-precision check, runs on a side stream meanwhile.
     const bool fast_init = ctx->cfg.precision == DICOD_PREC_MIXED;
+    bool any_rel = false;
+    for (int i = 0; i < n_sig; ++i)
+        any_rel |= lam_in[i] < 0.0;
     if (!fast_init) {
+        // the same pass zeroes Z (and its float copy) and takes lambda_max
+        if (any_rel)
+            HIPCHECK(ctx, launch_fill_u64(ws.lmax.as<unsigned long long>(), 0ull, n_sig, s));
         HIPCHECK(ctx, launch_corr_f64_x32(ctx->D64.as<double>(), K, P, W, dX,
                                           ws.sig.as<SigDesc>(), ws.tilesL.as<int64_t>(), n_sig,
                                           nL, ws.beta0.as<double>(),
                                           fp64 ? nullptr : ws.g.as<float>(),
-                                          fp64 ? ws.g.as<double>() : nullptr, s));
+                                          fp64 ? ws.g.as<double>() : nullptr, s, dZ,
+                                          reg_ok ? ws.z32.as<float>() : nullptr,
+                                          any_rel ? ws.lmax.as<unsigned long long>() : nullptr));
     } else {
         // the float start first; the double beta0 then runs beside the
         // descent (it is needed after the first float round only)
@@ -928,9 +936,9 @@ int solve_device_batch(dicod_ctx* ctx, int n_sig, const float* dX, const int64_t
     bool beta_waited = !fast_init;
     // ---- descent state (queued behind the correlation, before the lambda
     // read-back, so that these small launches do not wait for the host) ----
-    {
+    if (fast_init) {
         // Z = 0 over the union of the signals' [K][L] ranges (one launch per
-        // contiguous run)
+        // contiguous run; the double correlation does it otherwise)
         std::vector<std::pair<int64_t, int64_t>> zr(n_sig);
         for (int i = 0; i < n_sig; ++i)
             zr[i] = {pl.sig[i].z_off, pl.sig[i].z_off + (int64_t)K * pl.sig[i].L};
@@ -969,17 +977,10 @@ int solve_device_batch(dicod_ctx* ctx, int n_sig, const float* dX, const int64_t
                                   sizeof(Counters) / 8, s));
     // ---- 2. lambda --------------------------------------------------------
     std::vector<double> lmax(n_sig, 0.0);
-    bool any_rel = false;
-    for (int i = 0; i < n_sig; ++i)
-        any_rel |= lam_in[i] < 0.0;
     if (any_rel) {
         std::vector<unsigned long long> bits(n_sig);
-        HIPCHECK(ctx, launch_fill_u64(ws.lmax.as<unsigned long long>(), 0ull, n_sig, s));
-        if (!fast_init) {
-            HIPCHECK(ctx, launch_absmax(ws.beta0.as<double>(), K, ws.sig.as<SigDesc>(),
-                                        ws.tilesA.as<int64_t>(), n_sig, nA,
-                                        ws.lmax.as<unsigned long long>(), s));
-        } else {
+        if (fast_init) {
+            HIPCHECK(ctx, launch_fill_u64(ws.lmax.as<unsigned long long>(), 0ull, n_sig, s));
             // max of the split-bf16 beta, then the exact maximum over every
             // entry that the rounding error could make the maximum, recomputed
             // in double.  Per entry the error is at most

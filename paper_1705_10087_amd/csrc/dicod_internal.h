@@ -99,10 +99,14 @@ hipError_t launch_fill_f64(double* p, double v, size_t n, hipStream_t s);
 
 // out[b][k][t] = sum_{p,tau} D[k][p][tau] Y_b[p][t + tau] in double on MFMA
 // (f64 16x16x4).  Signals/tiles are described by sig[] and tile_pref[].
+// z0 / z32_0 (may be NULL): zeroed at every output coordinate (the descent's
+// Z and its float copy); amax_bits (may be NULL): per signal, atomic maximum
+// of the bits of max |out| (the caller zeroes it first).
 hipError_t launch_corr_f64_x32(const double* D, int K, int P, int W, const float* Y,
                                const SigDesc* sig, const int64_t* tile_pref,
                                int n_sig, int64_t n_tiles, double* out64,
-                               float* g32, double* g64, hipStream_t s);
+                               float* g32, double* g64, hipStream_t s, double* z0 = nullptr,
+                               float* z32_0 = nullptr, unsigned long long* amax_bits = nullptr);
 hipError_t launch_corr_f64_x64(const double* D, int K, int P, int W,
                                const double* Y, const SigDesc* sig,
                                const int64_t* tile_pref, int n_sig,

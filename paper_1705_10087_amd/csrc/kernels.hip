@@ -124,7 +124,8 @@ k_corr_f64(const double* __restrict__ D, int K, int P, int W,
            const TY* __restrict__ Y, const SigDesc* __restrict__ sig,
            const int64_t* __restrict__ tile_pref, int n_sig,
            double* __restrict__ out64, float* __restrict__ g32,
-           double* __restrict__ g64)
+           double* __restrict__ g64, double* __restrict__ z0, float* __restrict__ z32_0,
+           unsigned long long* __restrict__ amax_bits)
 {
     extern __shared__ double lds[];
     const int ystride = kTile + ((W + 3) & ~3);          // window + padded taus
@@ -216,6 +217,9 @@ k_corr_f64(const double* __restrict__ D, int K, int P, int W,
 
     // C[i][j] of a 16x16 f64 MFMA tile sits in lane (i % 4) * 16 + j, item i / 4
     // (measured on gfx950; the f32/bf16 tiles use lane (i / 4) * 16 + j, item i % 4).
+    // Optionally the same pass zeroes the descent's Z (and its float copy) at
+    // these coordinates and takes max |beta| (lambda_max, eq. 2) per signal.
+    double amax = 0.0;
 #pragma unroll
     for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
@@ -232,8 +236,19 @@ k_corr_f64(const double* __restrict__ D, int K, int P, int W,
                         g32[o] = (float)val;
                     if (g64)
                         g64[o] = val;
+                    if (z0)
+                        z0[o] = 0.0;
+                    if (z32_0)
+                        z32_0[o] = 0.0f;
+                    amax = fmax(amax, fabs(val));
                 }
             }
+    if (amax_bits) {
+        for (int o = 32; o > 0; o >>= 1)
+            amax = fmax(amax, __shfl_xor(amax, o));
+        if ((threadIdx.x & 63) == 0)  // non-negative doubles order as their bits
+            atomicMax(&amax_bits[si], (unsigned long long)__double_as_longlong(amax));
+    }
 }
 
 static size_t corr_lds(int P, int W)
@@ -244,7 +259,8 @@ static size_t corr_lds(int P, int W)
 hipError_t launch_corr_f64_x32(const double* D, int K, int P, int W, const float* Y,
                                const SigDesc* sig, const int64_t* tile_pref,
                                int n_sig, int64_t n_tiles, double* out64,
-                               float* g32, double* g64, hipStream_t s)
+                               float* g32, double* g64, hipStream_t s, double* z0,
+                               float* z32_0, unsigned long long* amax_bits)
 {
     size_t lds = corr_lds(P, W);
     if (lds > kLdsBytes)
@@ -255,7 +271,7 @@ hipError_t launch_corr_f64_x32(const double* D, int K, int P, int W, const float
         return hipSuccess;
     dim3 grid((unsigned)n_tiles, (unsigned)((K + 31) / 32));
     hipLaunchKernelGGL(k_corr_f64<float>, grid, dim3(256), lds, s, D, K, P, W, Y,
-                       sig, tile_pref, n_sig, out64, g32, g64);
+                       sig, tile_pref, n_sig, out64, g32, g64, z0, z32_0, amax_bits);
     return hipGetLastError();
 }
 
@@ -274,7 +290,8 @@ hipError_t launch_corr_f64_x64(const double* D, int K, int P, int W,
     dim3 grid((unsigned)n_tiles, (unsigned)((K + 31) / 32));
     hipLaunchKernelGGL(k_corr_f64<double>, grid, dim3(256), lds, s, D, K, P, W, Y,
                        sig, tile_pref, n_sig, out64, (float*)nullptr,
-                       (double*)nullptr);
+                       (double*)nullptr, (double*)nullptr, (float*)nullptr,
+                       (unsigned long long*)nullptr);
     return hipGetLastError();
 }
 
