@@ -1947,7 +1947,7 @@ k_grad_check(const float* __restrict__ X, const double* __restrict__ beta0,
     const int ndp = 2 * W;  // padded row: 16-byte multiple
     const int tid = threadIdx.x;
     const int lane = tid & 63;
-    const int wave = tid >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int64_t tile = blockIdx.x;
     const int si = find_sig(tile_pref, n_sig, tile);
     const SigDesc sd = sig[si];
@@ -2088,11 +2088,17 @@ k_grad_check(const float* __restrict__ X, const double* __restrict__ beta0,
                     const double* __restrict__ rows = sst + (size_t)cb * bstride + tid;
                     for (int q = e; q < e1; ++q) {
                         // lag of position t_a + tid + 256 j: d0 + tid + 256 j (32-bit:
-                        // positions are below 2^31)
-                        const int d0 = (int)(t_a - ls[q]) + (W - 1);
+                        // positions are below 2^31); d0 is the same in every lane
+                        const int d0 = __builtin_amdgcn_readfirstlane(
+                            (int)(t_a - ls[q]) + (W - 1));
                         const double z = lz[q];
 #pragma unroll
                         for (int j = 0; j < J; ++j) {
+                            // this wave's 64 lags for j: a scalar test skips the
+                            // strips the window of the non-zero does not reach
+                            const int dw = d0 + wave * 64 + 256 * j;
+                            if (dw + 63 < 0 || dw >= nd)
+                                continue;
                             const int d = d0 + tid + 256 * j;
                             if ((unsigned)d < (unsigned)nd && tid + 256 * j < n_own) {
                                 const double* __restrict__ sr = rows + (d0 + 256 * j);
