@@ -85,10 +85,14 @@ def measured_traffic(workload):
 
 def wave_kernel_name(K, lm_max):
     """Instantiation of the register-state kernel: atoms padded to groups of
-    four (4, 8, 16, 28 or 32 atoms), teams of 1, 2 or 4 waves."""
+    four (4, 8, 16, 28 or 32 atoms), the real atoms of the last group when only
+    that group is padded (else 4), teams of 1, 2 or 4 waves."""
     kp = next(p for p in (4, 8, 16, 28, 32) if K <= p)
+    kq = kp // 4
+    r = K - 4 * (kq - 1)
+    kl = r if 1 <= r <= 4 else 4
     tw = 1 if lm_max <= 64 else 2 if lm_max <= 128 else 4
-    return f"k_lgcd_wave<{kp // 4}, {tw}>"
+    return f"k_lgcd_wave<{kq}, {kl}, {tw}>"
 
 
 def roofline(tst, K, W, workload, lm_max):

@@ -65,9 +65,9 @@ __device__ __forceinline__ void team_sync()
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 }
 
-template <int KQ, int TW>
+template <int KQ, int KL, int TW>
 __global__ void __launch_bounds__(TW == 2 ? 128 : 256)
-__attribute__((amdgpu_waves_per_eu(KQ == 8 && TW == 1 ? 3 : 4)))
+__attribute__((amdgpu_waves_per_eu(KQ == 8 ? (TW == 1 ? 3 : 4) : (TW == 1 ? 4 : 5))))
 k_lgcd_async(PhaseArgs a, AsyncArgs x)
 {
     constexpr int SPB = TW == 1 ? 4 : 1;      // teams per workgroup
@@ -218,38 +218,23 @@ k_lgcd_async(PhaseArgs a, AsyncArgs x)
                         }
                     }
                 }
-                for (int r = 0; r < cn; r += 2) {
+                for (int r = 0; r < cn; ++r) {
                     const BoundaryRec r0 = rin[r];
-                    const BoundaryRec r1 = rin[r + 1 < cn ? r + 1 : r];
-                    const int j0a = r0.t0 - b, j0b = r1.t0 - b;
+                    const int j0a = r0.t0 - b;
                     const int lo_a = j0a - (W - 1) > 0 ? j0a - (W - 1) : 0;
                     const int hi_a = j0a + (W - 1) < Lm - 1 ? j0a + (W - 1) : Lm - 1;
-                    const int lo_b = j0b - (W - 1) > 0 ? j0b - (W - 1) : 0;
-                    const int hi_b = j0b + (W - 1) < Lm - 1 ? j0b + (W - 1) : Lm - 1;
                     tlo = lo_a < tlo ? lo_a : tlo;
                     thi = hi_a > thi ? hi_a : thi;
-                    tlo = lo_b < tlo ? lo_b : tlo;
-                    thi = hi_b > thi ? hi_b : thi;
-                    const int da = tt - j0a + (W - 1), db2 = tt - j0b + (W - 1);
+                    const int da = tt - j0a + (W - 1);
                     const bool ina = own && da >= 0 && da < nd;
-                    const bool inb = own && db2 >= 0 && db2 < nd && r + 1 < cn;
                     const f4* sa = reinterpret_cast<const f4*>(
                         St + ((size_t)r0.k0 * nd + (ina ? da : 0)) * KP);
-                    const f4* sb = reinterpret_cast<const f4*>(
-                        St + ((size_t)r1.k0 * nd + (inb ? db2 : 0)) * KP);
-                    f4 va[KQ], vb[KQ];
+                    f4 va[KQ];
 #pragma unroll
-                    for (int i = 0; i < KQ; ++i) {
+                    for (int i = 0; i < KQ; ++i)
                         va[i] = sa[i];
-                        vb[i] = sb[i];
-                    }
-                    const float dla = ina ? r0.delta : 0.0f, dlb = inb ? r1.delta : 0.0f;
-#pragma unroll
-                    for (int i = 0; i < KQ; ++i)
-                        g[i] -= va[i] * dla;
-#pragma unroll
-                    for (int i = 0; i < KQ; ++i)
-                        g[i] -= vb[i] * dlb;
+                    __builtin_amdgcn_sched_barrier(0);  // the row in flight at once
+                    axpy_state<KQ, KL>(g, va, ina ? r0.delta : 0.0f);
                 }
                 team_sync<TW>();  // the staged records are consumed
             }
@@ -300,7 +285,7 @@ k_lgcd_async(PhaseArgs a, AsyncArgs x)
                 ++it;
             };
 
-            unsigned mine = own ? best_key<KQ, NT>(g, u, cn2, cinv, lam) : 0u;
+            unsigned mine = own ? best_key<KQ, KL, NT>(g, u, cn2, cinv, lam) : 0u;
             unsigned kb;
             int j0;
             float db;
@@ -399,10 +384,11 @@ k_lgcd_async(PhaseArgs a, AsyncArgs x)
 #pragma unroll
                     for (int i = 0; i < KQ; ++i)
                         sv[i] = srow[i];
-#pragma unroll
-                    for (int i = 0; i < KQ; ++i)
-                        g[i] -= sv[i] * delta;
-                    mine = best_key<KQ, NT>(g, u, cn2, cinv, lam);
+                    // all rows in flight before the first use (the scheduler would
+                    // otherwise trade them for registers and wait for each in turn)
+                    __builtin_amdgcn_sched_barrier(0);
+                    axpy_state<KQ, KL>(g, sv, delta);
+                    mine = best_key<KQ, KL, NT>(g, u, cn2, cinv, lam);
                 }
                 ++n;
                 argmax(mine, kb, j0, db);
@@ -437,12 +423,12 @@ k_lgcd_async(PhaseArgs a, AsyncArgs x)
     }
 }
 
-template <int KQ, int TW>
+template <int KQ, int KL, int TW>
 int teams_of(int n_seg, int n_cu)
 {
     constexpr int SPB = TW == 1 ? 4 : 1;
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)k_lgcd_async<KQ, TW>,
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)k_lgcd_async<KQ, KL, TW>,
                                                      TW == 2 ? 128 : 256, 0) != hipSuccess ||
         nb < 1)
         nb = 1;
@@ -450,30 +436,52 @@ int teams_of(int n_seg, int n_cu)
     return (int)(n_seg < cap ? n_seg : cap);
 }
 
-template <int KQ>
-int teams_kq(int lm_max, int n_seg, int n_cu)
+template <int KQ, int KL>
+int teams_kl(int lm_max, int n_seg, int n_cu)
 {
     if (lm_max <= 64)
-        return teams_of<KQ, 1>(n_seg, n_cu);
+        return teams_of<KQ, KL, 1>(n_seg, n_cu);
     if (lm_max <= 128)
-        return teams_of<KQ, 2>(n_seg, n_cu);
-    return teams_of<KQ, 4>(n_seg, n_cu);
+        return teams_of<KQ, KL, 2>(n_seg, n_cu);
+    return teams_of<KQ, KL, 4>(n_seg, n_cu);
+}
+
+template <int KQ>
+int teams_kq(int K, int lm_max, int n_seg, int n_cu)
+{
+    switch (wave_last_group(K, KQ)) {
+    case 1: return teams_kl<KQ, 1>(lm_max, n_seg, n_cu);
+    case 2: return teams_kl<KQ, 2>(lm_max, n_seg, n_cu);
+    case 3: return teams_kl<KQ, 3>(lm_max, n_seg, n_cu);
+    default: return teams_kl<KQ, 4>(lm_max, n_seg, n_cu);
+    }
+}
+
+template <int KQ, int KL>
+hipError_t launch_kl(const PhaseArgs& a, const AsyncArgs& x, hipStream_t s)
+{
+    if (a.lm_max <= 64) {
+        hipLaunchKernelGGL((k_lgcd_async<KQ, KL, 1>), dim3((unsigned)((x.n_teams + 3) / 4)),
+                           dim3(256), 0, s, a, x);
+    } else if (a.lm_max <= 128) {
+        hipLaunchKernelGGL((k_lgcd_async<KQ, KL, 2>), dim3((unsigned)x.n_teams), dim3(128), 0,
+                           s, a, x);
+    } else {
+        hipLaunchKernelGGL((k_lgcd_async<KQ, KL, 4>), dim3((unsigned)x.n_teams), dim3(256), 0,
+                           s, a, x);
+    }
+    return hipGetLastError();
 }
 
 template <int KQ>
 hipError_t launch_kq(const PhaseArgs& a, const AsyncArgs& x, hipStream_t s)
 {
-    if (a.lm_max <= 64) {
-        hipLaunchKernelGGL((k_lgcd_async<KQ, 1>), dim3((unsigned)((x.n_teams + 3) / 4)),
-                           dim3(256), 0, s, a, x);
-    } else if (a.lm_max <= 128) {
-        hipLaunchKernelGGL((k_lgcd_async<KQ, 2>), dim3((unsigned)x.n_teams), dim3(128), 0, s,
-                           a, x);
-    } else {
-        hipLaunchKernelGGL((k_lgcd_async<KQ, 4>), dim3((unsigned)x.n_teams), dim3(256), 0, s,
-                           a, x);
+    switch (wave_last_group(a.K, KQ)) {
+    case 1: return launch_kl<KQ, 1>(a, x, s);
+    case 2: return launch_kl<KQ, 2>(a, x, s);
+    case 3: return launch_kl<KQ, 3>(a, x, s);
+    default: return launch_kl<KQ, 4>(a, x, s);
     }
-    return hipGetLastError();
 }
 
 }  // namespace
@@ -483,11 +491,11 @@ int lgcd_async_ring_cap(int cap, int sweeps) { return 2 * cap * sweeps; }
 int lgcd_async_teams(int K, int lm_max, int n_seg, int n_cu)
 {
     switch (lgcd_k_padded(K, false) / 4) {
-    case 1: return teams_kq<1>(lm_max, n_seg, n_cu);
-    case 2: return teams_kq<2>(lm_max, n_seg, n_cu);
-    case 4: return teams_kq<4>(lm_max, n_seg, n_cu);
-    case 7: return teams_kq<7>(lm_max, n_seg, n_cu);
-    case 8: return teams_kq<8>(lm_max, n_seg, n_cu);
+    case 1: return teams_kq<1>(K, lm_max, n_seg, n_cu);
+    case 2: return teams_kq<2>(K, lm_max, n_seg, n_cu);
+    case 4: return teams_kq<4>(K, lm_max, n_seg, n_cu);
+    case 7: return teams_kq<7>(K, lm_max, n_seg, n_cu);
+    case 8: return teams_kq<8>(K, lm_max, n_seg, n_cu);
     default: return 0;
     }
 }

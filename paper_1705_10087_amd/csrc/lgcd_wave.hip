@@ -48,14 +48,18 @@
 namespace dicod {
 namespace {
 
-// Occupancy: the register budget is capped at four waves per SIMD (128
-// registers), which the LDS footprint allows for every instantiation but
-// <8, 1>; without the cap the compiler spends up to 131 registers on keeping
-// loads in flight and three waves per SIMD remain, which hides less of the
-// latency of the per-update chain (argmax, S-row loads, window update).
-template <int KQ, int TW>
+// Occupancy: the kernel is bound by the latency of its per-update chain
+// (argmax, S-row loads, window update), which more resident waves hide.  The
+// register budget asks for the waves the LDS footprint allows: four per SIMD
+// for one-wave teams (four segments of 28 KB of z per workgroup), five for
+// larger teams (up to 96 registers), one less for 32 atoms.  Without a cap the
+// compiler spends up to 131 registers and three waves remain.  The S rows of
+// an update are pinned in flight together by a scheduling barrier: under the
+// register cap the scheduler would otherwise reuse one register quad and wait
+// for each row in turn (measured 15-30% slower).
+template <int KQ, int KL, int TW>
 __global__ void __launch_bounds__(TW == 2 ? 128 : 256)
-__attribute__((amdgpu_waves_per_eu(KQ == 8 && TW == 1 ? 3 : 4)))
+__attribute__((amdgpu_waves_per_eu(KQ == 8 ? (TW == 1 ? 3 : 4) : (TW == 1 ? 4 : 5))))
 k_lgcd_wave(PhaseArgs a)
 {
     constexpr int SPB = TW == 1 ? 4 : 1;      // segments per workgroup
@@ -155,8 +159,8 @@ k_lgcd_wave(PhaseArgs a)
     int tlo = INT_MAX, thi = -1;  // own positions whose g changed (written back)
     // records of the neighbours' last runs, from the left neighbour, then from
     // the right one, each in the order sent: staged in LDS with one load per
-    // record, then applied two at a time (both S rows in flight; a record out
-    // of a position's reach reads a valid row and applies a zero change)
+    // record, then applied one at a time (a record out of a position's reach
+    // reads a valid row and applies a zero change)
     const int n_in = (int)(in_l + in_r);
     BoundaryRec* rin = s_in[team];
     for (int i = tt; i < n_in; i += NTT)
@@ -166,38 +170,23 @@ k_lgcd_wave(PhaseArgs a)
         __syncthreads();
     else
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    for (int r = 0; r < n_in; r += 2) {
+    for (int r = 0; r < n_in; ++r) {
         const BoundaryRec r0 = rin[r];
-        const BoundaryRec r1 = rin[r + 1 < n_in ? r + 1 : r];
-        const int j0a = r0.t0 - b, j0b = r1.t0 - b;
+        const int j0a = r0.t0 - b;
         const int lo_a = j0a - (W - 1) > 0 ? j0a - (W - 1) : 0;
         const int hi_a = j0a + (W - 1) < Lm - 1 ? j0a + (W - 1) : Lm - 1;
-        const int lo_b = j0b - (W - 1) > 0 ? j0b - (W - 1) : 0;
-        const int hi_b = j0b + (W - 1) < Lm - 1 ? j0b + (W - 1) : Lm - 1;
         tlo = lo_a < tlo ? lo_a : tlo;
         thi = hi_a > thi ? hi_a : thi;
-        tlo = lo_b < tlo ? lo_b : tlo;
-        thi = hi_b > thi ? hi_b : thi;
-        const int da = tt - j0a + (W - 1), db2 = tt - j0b + (W - 1);
+        const int da = tt - j0a + (W - 1);
         const bool ina = own && da >= 0 && da < nd;
-        const bool inb = own && db2 >= 0 && db2 < nd && r + 1 < n_in;
         const f4* sa = reinterpret_cast<const f4*>(
             St + ((size_t)r0.k0 * nd + (ina ? da : 0)) * KP);
-        const f4* sb = reinterpret_cast<const f4*>(
-            St + ((size_t)r1.k0 * nd + (inb ? db2 : 0)) * KP);
-        f4 va[KQ], vb[KQ];
+        f4 va[KQ];
 #pragma unroll
-        for (int i = 0; i < KQ; ++i) {
+        for (int i = 0; i < KQ; ++i)
             va[i] = sa[i];
-            vb[i] = sb[i];
-        }
-        const float dla = ina ? r0.delta : 0.0f, dlb = inb ? r1.delta : 0.0f;
-#pragma unroll
-        for (int i = 0; i < KQ; ++i)
-            g[i] -= va[i] * dla;
-#pragma unroll
-        for (int i = 0; i < KQ; ++i)
-            g[i] -= vb[i] * dlb;
+        __builtin_amdgcn_sched_barrier(0);  // the row in flight at once
+        axpy_state<KQ, KL>(g, va, ina ? r0.delta : 0.0f);
     }
 
     // team argmax: key, position and exact change delta of the best candidate
@@ -241,7 +230,7 @@ k_lgcd_wave(PhaseArgs a)
         ++it;
     };
 
-    unsigned mine = own ? best_key<KQ, NT>(g, u, cn2, cinv, lam) : 0u;
+    unsigned mine = own ? best_key<KQ, KL, NT>(g, u, cn2, cinv, lam) : 0u;
     unsigned kb;
     int j0;
     float db;
@@ -345,10 +334,11 @@ k_lgcd_wave(PhaseArgs a)
 #pragma unroll
             for (int i = 0; i < KQ; ++i)
                 sv[i] = srow[i];
-#pragma unroll
-            for (int i = 0; i < KQ; ++i)
-                g[i] -= sv[i] * delta;
-            mine = best_key<KQ, NT>(g, u, cn2, cinv, lam);
+            // all rows in flight before the first use (the scheduler would
+            // otherwise trade them for registers and wait for each in turn)
+            __builtin_amdgcn_sched_barrier(0);
+            axpy_state<KQ, KL>(g, sv, delta);
+            mine = best_key<KQ, KL, NT>(g, u, cn2, cinv, lam);
         }
         ++n;
         argmax(mine, kb, j0, db);
@@ -391,18 +381,33 @@ k_lgcd_wave(PhaseArgs a)
     }
 }
 
+template <int KQ, int KL>
+hipError_t launch_kl(const PhaseArgs& a, hipStream_t s)
+{
+    if (a.lm_max <= 64) {
+        hipLaunchKernelGGL((k_lgcd_wave<KQ, KL, 1>), dim3((unsigned)((a.n_list + 3) / 4)),
+                           dim3(256), 0, s, a);
+    } else if (a.lm_max <= 128) {
+        hipLaunchKernelGGL((k_lgcd_wave<KQ, KL, 2>), dim3((unsigned)a.n_list), dim3(128), 0, s,
+                           a);
+    } else {
+        hipLaunchKernelGGL((k_lgcd_wave<KQ, KL, 4>), dim3((unsigned)a.n_list), dim3(256), 0, s,
+                           a);
+    }
+    return hipGetLastError();
+}
+
+// KL: real atoms in the last group of four when only that group is padded;
+// otherwise the padded atoms are carried as zeros (KL = 4)
 template <int KQ>
 hipError_t launch_kq(const PhaseArgs& a, hipStream_t s)
 {
-    if (a.lm_max <= 64) {
-        hipLaunchKernelGGL((k_lgcd_wave<KQ, 1>), dim3((unsigned)((a.n_list + 3) / 4)), dim3(256),
-                           0, s, a);
-    } else if (a.lm_max <= 128) {
-        hipLaunchKernelGGL((k_lgcd_wave<KQ, 2>), dim3((unsigned)a.n_list), dim3(128), 0, s, a);
-    } else {
-        hipLaunchKernelGGL((k_lgcd_wave<KQ, 4>), dim3((unsigned)a.n_list), dim3(256), 0, s, a);
+    switch (wave_last_group(a.K, KQ)) {
+    case 1: return launch_kl<KQ, 1>(a, s);
+    case 2: return launch_kl<KQ, 2>(a, s);
+    case 3: return launch_kl<KQ, 3>(a, s);
+    default: return launch_kl<KQ, 4>(a, s);
     }
-    return hipGetLastError();
 }
 
 }  // namespace

@@ -27,7 +27,9 @@ struct WSlot {
 template <int CTRL, int RM>
 __device__ __forceinline__ unsigned dpp_max_step(unsigned a)
 {
-    const unsigned o = (unsigned)__builtin_amdgcn_update_dpp((int)a, (int)a, CTRL, RM, 0xf, false);
+    // lanes the row mask leaves out read 0, the identity of the maximum, so
+    // that the move folds into one v_max_u32 with a DPP source
+    const unsigned o = (unsigned)__builtin_amdgcn_update_dpp(0, (int)a, CTRL, RM, 0xf, false);
     return o > a ? o : a;
 }
 
@@ -85,12 +87,20 @@ __device__ __forceinline__ float key_value(unsigned key)
     return __uint_as_float(key & 0x7fffffe0u);
 }
 
+// Key of one coordinate: |Delta Z| of cand() with the atom in the low bits.
+__device__ __forceinline__ unsigned cand_key(float g, float z, float n2, float inv, float lam,
+                                             int k)
+{
+    return make_key(cand(g, z, n2, inv, lam), k);
+}
+
 // Best key over the own position's atoms.  z: this thread's column of the
-// LDS array [KQ][threads].  Padded atoms (g = z = 0) give a zero key; they
-// run unconditionally, which costs fewer instructions than branching around
-// them.  (A four-operation form of the soft threshold through a clamp of
-// beta measured slower here than the compare-and-select of cand().)
-template <int KQ, int NT>
+// LDS array [KQ][threads].  KL atoms of the last group of four are real (the
+// rest pad the group and are skipped).  (Two other forms of the soft
+// threshold measured slower here than the compare-and-select of cand(): a
+// clamp of beta, and the median of g - lambda, g + lambda and -|D_k|^2 z,
+// which needs no beta and one instruction less.)
+template <int KQ, int KL, int NT>
 __device__ __forceinline__ unsigned best_key(const f4 (&g)[KQ], const f4* __restrict__ z,
                                              const f4* __restrict__ cn2,
                                              const f4* __restrict__ cinv, float lam)
@@ -101,13 +111,32 @@ __device__ __forceinline__ unsigned best_key(const f4 (&g)[KQ], const f4* __rest
         const f4 n2 = cn2[i], iv = cinv[i];
         const f4 zv = z[i * NT];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const float d = cand(g[i][c], zv[c], n2[c], iv[c], lam);
-            const unsigned key = make_key(d, 4 * i + c);
+        for (int c = 0; c < (i == KQ - 1 ? KL : 4); ++c) {
+            const unsigned key = cand_key(g[i][c], zv[c], n2[c], iv[c], lam, 4 * i + c);
             best = key > best ? key : best;
         }
     }
     return best;
+}
+
+// Real atoms in the last of KQ groups of four when K fills all but that
+// group's tail, else 4 (the padded atoms are then carried as zeros).
+inline int wave_last_group(int K, int KQ)
+{
+    const int r = K - 4 * (KQ - 1);
+    return r >= 1 && r <= 4 ? r : 4;
+}
+
+// g -= s delta over the real atoms.
+template <int KQ, int KL>
+__device__ __forceinline__ void axpy_state(f4 (&g)[KQ], const f4 (&s)[KQ], float delta)
+{
+#pragma unroll
+    for (int i = 0; i < KQ - 1; ++i)
+        g[i] -= s[i] * delta;
+#pragma unroll
+    for (int c = 0; c < KL; ++c)
+        g[KQ - 1][c] -= s[KQ - 1][c] * delta;
 }
 
 }  // namespace

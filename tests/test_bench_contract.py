@@ -30,12 +30,14 @@ def test_flops_and_kernel_names():
     # eq. (3): K (2W - 1) FMAs plus ~5 flops of candidate per touched coordinate
     assert b.flops_per_update(25, 64) == 7 * 25 * 127
     assert b.flops_per_update(25, 200) == 7 * 25 * 399
-    assert b.wave_kernel_name(25, 64) == "k_lgcd_wave<7, 1>"
-    assert b.wave_kernel_name(25, 126) == "k_lgcd_wave<7, 2>"
-    assert b.wave_kernel_name(25, 199) == "k_lgcd_wave<7, 4>"
-    assert b.wave_kernel_name(5, 40) == "k_lgcd_wave<2, 1>"
-    assert b.wave_kernel_name(13, 200) == "k_lgcd_wave<4, 4>"
-    assert b.wave_kernel_name(32, 10) == "k_lgcd_wave<8, 1>"
+    assert b.wave_kernel_name(25, 64) == "k_lgcd_wave<7, 1, 1>"
+    assert b.wave_kernel_name(25, 126) == "k_lgcd_wave<7, 1, 2>"
+    assert b.wave_kernel_name(25, 199) == "k_lgcd_wave<7, 1, 4>"
+    assert b.wave_kernel_name(5, 40) == "k_lgcd_wave<2, 1, 1>"
+    assert b.wave_kernel_name(13, 200) == "k_lgcd_wave<4, 1, 4>"
+    assert b.wave_kernel_name(32, 10) == "k_lgcd_wave<8, 4, 1>"
+    assert b.wave_kernel_name(20, 100) == "k_lgcd_wave<7, 4, 2>"   # two padded groups
+    assert b.wave_kernel_name(27, 100) == "k_lgcd_wave<7, 3, 2>"
 
 
 def test_roofline_arithmetic():
@@ -47,7 +49,7 @@ def test_roofline_arithmetic():
     assert abs(r["achieved"] - 11.1125) < 1e-9
     assert r["bound"] == "alu" and r["unit"] == "TFLOP/s" and r["peak"] == 157.3
     assert abs(r["frac"] - 11.1125 / 157.3) < 1e-12
-    assert r["traffic"] is None and r["kernel"] == "k_lgcd_wave<7, 1>"
+    assert r["traffic"] is None and r["kernel"] == "k_lgcd_wave<7, 1, 1>"
     assert abs(r["avg_launch_us"] - 200.0) < 1e-9
 
 
