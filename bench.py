@@ -533,6 +533,9 @@ def main():
     ap.add_argument("--served-requests", type=int, default=2000)
     ap.add_argument("--served-warmup", type=int, default=200)
     ap.add_argument("--served-alone", type=int, default=200)
+    ap.add_argument("--served-precision", choices=("mixed", "fp32"), default="mixed",
+                    help="policy of the served stream: split-bf16 start (mixed) or the "
+                         "double beta (fp32)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; --gpus "
@@ -620,9 +623,18 @@ def main():
         configs["c3"] = res
     if "c5" in only:
         log("c5: served")
-        configs["c5"] = served_bench(d, torch, args, D5, base5, dict(fp32, fp64_polish_after=1))
-        configs["c5"]["precision"] = ("FP32 descent from the double beta, a double finish "
-                                      "round after the first failed check, double stop test")
+        if args.served_precision == "mixed":
+            configs["c5"] = served_bench(d, torch, args, D5, base5,
+                                         dict(mixed, fp64_polish_after=1))
+            configs["c5"]["precision"] = (
+                "split-bf16 MFMA beta with fp32 accumulation (lambda_max exact), FP32 descent, "
+                "the double beta0 on a second stream, a double finish round after the first "
+                "failed check, double stop test")
+        else:
+            configs["c5"] = served_bench(d, torch, args, D5, base5,
+                                         dict(fp32, fp64_polish_after=1))
+            configs["c5"]["precision"] = ("FP32 descent from the double beta, a double finish "
+                                          "round after the first failed check, double stop test")
 
     if head is None:
         key = sorted(configs)[0]

@@ -64,8 +64,7 @@ extern "C" {
  *       accumulation (three products hi*hi + hi*lo + lo*hi); lambda_max is
  *       made exact by recomputing the near-maximal entries in double, and the
  *       double beta of the check is computed on a second stream during the
- *       first descent round.  Served requests (dicod_submit) start from the
- *       double beta in every policy.                                         */
+ *       first descent round (served requests: a second stream per lane).    */
 #define DICOD_PREC_FP64 0
 #define DICOD_PREC_FP32 1
 #define DICOD_PREC_MIXED 2

@@ -978,7 +978,6 @@ int solve_device_batch(dicod_ctx* ctx, int n_sig, const float* dX, const int64_t
     // ---- 2. lambda --------------------------------------------------------
     std::vector<double> lmax(n_sig, 0.0);
     if (any_rel) {
-        std::vector<unsigned long long> bits(n_sig);
         if (fast_init) {
             HIPCHECK(ctx, launch_fill_u64(ws.lmax.as<unsigned long long>(), 0ull, n_sig, s));
             // max of the split-bf16 beta, then the exact maximum over every
@@ -991,6 +990,7 @@ int solve_device_batch(dicod_ctx* ctx, int n_sig, const float* dX, const int64_t
             // the maximiser's split value is at least v - 2 e, e = c max|D_k|
             // max_t |X[., t : t + W]| (5% margin on the bound).
             HIPCHECK(ctx, ensure(ws.ebits, n_sig * sizeof(unsigned long long)));
+            HIPCHECK(ctx, ensure(ws.thr, n_sig * sizeof(double)));
             HIPCHECK(ctx, launch_fill_u64(ws.ebits.as<unsigned long long>(), 0ull, n_sig, s));
             HIPCHECK(ctx, launch_absmax_f32(ws.g.as<float>(), K, ws.sig.as<SigDesc>(),
                                             ws.tilesA.as<int64_t>(), n_sig, nA,
@@ -998,25 +998,10 @@ int solve_device_batch(dicod_ctx* ctx, int n_sig, const float* dX, const int64_t
             HIPCHECK(ctx, launch_win_energy_max(dX, P, W, ws.sig.as<SigDesc>(),
                                                 ws.tilesL.as<int64_t>(), n_sig, nL,
                                                 ws.ebits.as<unsigned long long>(), s));
-            std::vector<unsigned long long> ebits(n_sig);
-            HIPCHECK(ctx, hipMemcpyAsync(bits.data(), ws.lmax.p,
-                                         n_sig * sizeof(unsigned long long),
-                                         hipMemcpyDeviceToHost, s));
-            HIPCHECK(ctx, hipMemcpyAsync(ebits.data(), ws.ebits.p,
-                                         n_sig * sizeof(unsigned long long),
-                                         hipMemcpyDeviceToHost, s));
-            HIPCHECK(ctx, hipStreamSynchronize(s));
-            const double c = 3.1 * std::ldexp(1.0, -16) +
-                             ((double)P * W + 1.0) * std::ldexp(1.0, -24);
-            std::vector<double> thr(n_sig);
-            for (int i = 0; i < n_sig; ++i) {
-                double v, en;
-                std::memcpy(&v, &bits[i], sizeof v);
-                std::memcpy(&en, &ebits[i], sizeof en);
-                const double e = 1.05 * c * ctx->dnorm_max * std::sqrt(en);
-                thr[i] = std::max(0.0, v - 2.0 * e);
-            }
-            HIPCHECK(ctx, upload(ws.thr, thr, s));
+            HIPCHECK(ctx, launch_refine_threshold(ws.lmax.as<unsigned long long>(),
+                                                  ws.ebits.as<unsigned long long>(), n_sig,
+                                                  refine_coef(P, W, ctx->dnorm_max),
+                                                  ws.thr.as<double>(), s));
             HIPCHECK(ctx, launch_fill_u64(ws.lmax.as<unsigned long long>(), 0ull, n_sig, s));
             HIPCHECK(ctx, launch_refine_absmax(ws.g.as<float>(), ctx->D64.as<double>(), dX, K, P,
                                                W, ws.sig.as<SigDesc>(), ws.tilesA.as<int64_t>(),
@@ -1932,6 +1917,8 @@ DictView ctx_dict(const dicod_ctx* ctx)
     v.inv32 = ctx->inv32.p;
     v.n2_64 = ctx->n2_64.p;
     v.inv64 = ctx->inv64.p;
+    v.Dsp = ctx->Dsp.as<unsigned short>();
+    v.dnorm_max = ctx->dnorm_max;
     return v;
 }
 int64_t min_segment_len(int W, int C) { return min_segment(W, C); }

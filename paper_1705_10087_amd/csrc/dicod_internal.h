@@ -287,6 +287,14 @@ hipError_t launch_screen_count(const void* g, bool fp64, const double* n2, int K
                                const SigDesc* sig, const int64_t* tile_pref, int n_sig,
                                int64_t n_tiles, const double* rule, unsigned long long* count,
                                hipStream_t s);
+// Candidate threshold of the refinement per signal (lambda_bound.hip):
+// thr[i] = max(0, v_i - 2 coef sqrt(e_i)) from the bits of the largest split
+// |beta| v_i and the largest window energy e_i; coef = refine_coef(P, W,
+// max_k |D_k|) = 1.05 (3.1 2^-16 + (P W + 1) 2^-24) max_k |D_k|.
+double refine_coef(int P, int W, double dnorm_max);
+hipError_t launch_refine_threshold(const unsigned long long* vbits,
+                                   const unsigned long long* ebits, int n, double coef,
+                                   double* thr, hipStream_t s);
 hipError_t launch_absmax_f32(const float* beta, int K, const SigDesc* sig,
                              const int64_t* tile_pref, int n_sig, int64_t n_tiles,
                              unsigned long long* out_bits, hipStream_t s);

@@ -211,6 +211,12 @@ struct Lane {
     std::string msg;            // last HIP failure
     Mem dRing, dLists, dSub, dTilesL, dTilesC, dTilesA, dTilesN, dPart, dRes, dLmax,
         dDone, dSlots, dLamIn, dMask;
+    // MIXED policy: the double beta0 of admitted requests runs on a side
+    // stream beside the descent; ev_b marks the last one queued
+    hipStream_t side = nullptr;
+    hipEvent_t ev_x = nullptr, ev_b = nullptr;
+    bool beta_pending = false;
+    Mem dEbits, dThr;
     unsigned long long* h_ring = nullptr;
     unsigned long long* h_sigupd = nullptr;
     unsigned long long* h_lmax = nullptr;
@@ -234,6 +240,7 @@ struct Server {
     dicod_config cfg{};
     int K = 0, P = 0, W = 0, C = 2;
     bool fp64 = false;
+    bool mixed = false;          // split-bf16 float start (MIXED policy)
     DictView dict{};
     hipStream_t cs = nullptr;    // result copies (dicod_poll)
     std::mutex mu;               // queue, jobs, allocators, slots, lane counters
@@ -307,6 +314,13 @@ int Lane::start()
     SRV_HIP(dSlots.alloc((size_t)slots * sizeof(int)));
     SRV_HIP(dLamIn.alloc((size_t)slots * sizeof(double)));
     SRV_HIP(launch_fill_u32(dDone.as<uint32_t>(), 0u, slots, s));
+    if (srv->mixed) {
+        SRV_HIP(hipStreamCreateWithFlags(&side, hipStreamNonBlocking));
+        SRV_HIP(hipEventCreateWithFlags(&ev_x, hipEventDisableTiming));
+        SRV_HIP(hipEventCreateWithFlags(&ev_b, hipEventDisableTiming));
+        SRV_HIP(dEbits.alloc((size_t)slots * sizeof(unsigned long long)));
+        SRV_HIP(dThr.alloc((size_t)slots * sizeof(double)));
+    }
     stage_cap = (size_t)srv->seg_cap * sizeof(int32_t) +
                 2 * (size_t)srv->seg_cap * sizeof(SegDesc) +
                 8 * (size_t)(slots + 1) * (sizeof(SigDesc) + 3 * sizeof(int64_t) + 16) +
@@ -331,9 +345,19 @@ void Lane::teardown()
         th.join();
     if (s)
         (void)hipStreamSynchronize(s);
+    if (side)
+        (void)hipStreamSynchronize(side);
     for (Mem* m : {&dRing, &dLists, &dSub, &dTilesL, &dTilesC, &dTilesA, &dTilesN, &dPart,
-                   &dRes, &dLmax, &dDone, &dSlots, &dLamIn, &dMask})
+                   &dRes, &dLmax, &dDone, &dSlots, &dLamIn, &dMask, &dEbits, &dThr})
         m->release();
+    for (hipEvent_t* e : {&ev_x, &ev_b})
+        if (*e) {
+            (void)hipEventDestroy(*e);
+            *e = nullptr;
+        }
+    if (side)
+        (void)hipStreamDestroy(side);
+    side = nullptr;
     for (void* p : {(void*)h_stage, (void*)h_ring, (void*)h_sigupd, (void*)h_lmax,
                     (void*)h_res})
         if (p)
@@ -352,6 +376,7 @@ int Server::start(dicod_ctx* c)
     ctx_serve_schedule(c, &cfg.colors, &cfg.update_cap);
     C = cfg.colors;
     fp64 = cfg.precision == DICOD_PREC_FP64;
+    mixed = cfg.precision == DICOD_PREC_MIXED;
     dict = ctx_dict(c);
     slots = cfg.max_inflight;
     chunk = std::min(std::max(cfg.phases_per_poll, 1), kMaxChunk);
@@ -534,6 +559,8 @@ void Lane::loop()
 // (rc != DICOD_OK; at teardown they are simply dropped with the server).
 void Lane::abandon(int rc, const std::string& m)
 {
+    if (side)  // no double beta0 left writing into ranges about to be freed
+        (void)hipStreamSynchronize(side);
     if (rc != DICOD_OK) {
         const double t = now_ms();
         std::lock_guard<std::mutex> g(srv->mu);
@@ -585,11 +612,19 @@ void Lane::admit(std::vector<Job*>& fresh)
 }
 
 // beta0 and g on MFMA, lambda on the device, Z = 0, every segment dirty.
+// MIXED: g starts from the split-bf16 correlation, lambda_max is made exact
+// by the double recomputation of every entry the split's error bound could
+// make the maximum (as in the one-shot solver), and the double beta0, read
+// only by the requests' first check, runs on the side stream.
 int Lane::init_jobs(const std::vector<Job*>& fresh)
 {
     Server& v = *srv;
     const int K = v.K, P = v.P, W = v.W;
     const int n = (int)fresh.size();
+    // the descriptors staged below are read by the previous side-stream
+    // correlation until it ends
+    if (beta_pending)
+        SRV_HIP(hipStreamWaitEvent(s, ev_b, 0));
     std::vector<SigDesc> sub(n);
     std::vector<int64_t> pL(n + 1, 0), pA(n + 1, 0);
     std::vector<int> sl(n);
@@ -632,13 +667,41 @@ int Lane::init_jobs(const std::vector<Job*>& fresh)
     SRV_HIP(stage(dTilesA.p, pA.data(), (n + 1) * sizeof(int64_t)));
     SRV_HIP(stage(dSlots.p, sl.data(), n * sizeof(int)));
     SRV_HIP(stage(dLamIn.p, lin.data(), n * sizeof(double)));
-    SRV_HIP(launch_corr_f64_x32(v.dict.D64, K, P, W, v.dX.as<float>(), dSub.as<SigDesc>(),
-                                dTilesL.as<int64_t>(), n, pL[n], v.dB.as<double>(),
-                                v.fp64 ? nullptr : v.dG32.as<float>(),
-                                v.fp64 ? v.dG64.as<double>() : nullptr, s));
-    SRV_HIP(launch_fill_u64(dLmax.as<unsigned long long>(), 0ull, n, s));
-    SRV_HIP(launch_absmax(v.dB.as<double>(), K, dSub.as<SigDesc>(), dTilesA.as<int64_t>(), n,
-                          pA[n], dLmax.as<unsigned long long>(), s));
+    if (v.mixed) {
+        const float* dX = v.dX.as<float>();
+        unsigned long long* lmax = dLmax.as<unsigned long long>();
+        SRV_HIP(launch_corr_bf16x3(v.dict.Dsp, K, P, W, dX, dSub.as<SigDesc>(),
+                                   dTilesL.as<int64_t>(), n, pL[n], v.dG32.as<float>(), s));
+        SRV_HIP(launch_fill_u64(lmax, 0ull, n, s));
+        SRV_HIP(launch_fill_u64(dEbits.as<unsigned long long>(), 0ull, n, s));
+        SRV_HIP(launch_absmax_f32(v.dG32.as<float>(), K, dSub.as<SigDesc>(),
+                                  dTilesA.as<int64_t>(), n, pA[n], lmax, s));
+        SRV_HIP(launch_win_energy_max(dX, P, W, dSub.as<SigDesc>(), dTilesL.as<int64_t>(), n,
+                                      pL[n], dEbits.as<unsigned long long>(), s));
+        SRV_HIP(launch_refine_threshold(lmax, dEbits.as<unsigned long long>(), n,
+                                        refine_coef(P, W, v.dict.dnorm_max), dThr.as<double>(),
+                                        s));
+        SRV_HIP(launch_fill_u64(lmax, 0ull, n, s));
+        SRV_HIP(launch_refine_absmax(v.dG32.as<float>(), v.dict.D64, dX, K, P, W,
+                                     dSub.as<SigDesc>(), dTilesA.as<int64_t>(), n, pA[n],
+                                     dThr.as<double>(), lmax, s));
+        SRV_HIP(hipEventRecord(ev_x, s));
+        SRV_HIP(hipStreamWaitEvent(side, ev_x, 0));
+        SRV_HIP(launch_corr_f64_x32(v.dict.D64, K, P, W, dX, dSub.as<SigDesc>(),
+                                    dTilesL.as<int64_t>(), n, pL[n], v.dB.as<double>(), nullptr,
+                                    nullptr, side));
+        SRV_HIP(hipEventRecord(ev_b, side));
+        beta_pending = true;
+    } else {
+        SRV_HIP(launch_corr_f64_x32(v.dict.D64, K, P, W, v.dX.as<float>(), dSub.as<SigDesc>(),
+                                    dTilesL.as<int64_t>(), n, pL[n], v.dB.as<double>(),
+                                    v.fp64 ? nullptr : v.dG32.as<float>(),
+                                    v.fp64 ? v.dG64.as<double>() : nullptr, s));
+        SRV_HIP(launch_fill_u64(dLmax.as<unsigned long long>(), 0ull, n, s));
+        SRV_HIP(launch_absmax(v.dB.as<double>(), K, dSub.as<SigDesc>(),
+                              dTilesA.as<int64_t>(), n, pA[n], dLmax.as<unsigned long long>(),
+                              s));
+    }
     SRV_HIP(launch_apply_lambda(v.dSig.as<SigDesc>(), dSlots.as<int>(), dLamIn.as<double>(),
                                 dLmax.as<unsigned long long>(), n, s));
     SRV_HIP(hipMemcpyAsync(h_lmax, dLmax.p, n * sizeof(unsigned long long),
@@ -678,6 +741,8 @@ int Lane::check_jobs(const std::vector<Job*>& conv, std::vector<Job*>& resumed)
         const char* m;
     };
     std::vector<Done> finished;
+    if (beta_pending)  // beta0 of the requests admitted under MIXED
+        SRV_HIP(hipStreamWaitEvent(s, ev_b, 0));
     // state class of every request (bit 0: double now, bit 1: double in the
     // next round), decided before any request changes state
     std::vector<int> cls(conv.size());

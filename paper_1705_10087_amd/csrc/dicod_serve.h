@@ -25,6 +25,8 @@ struct DictView {
     const void* St64;                  // phase-kernel layout, double
     const double* Sc64;                // [l][k][2W] double, the check's copy
     const void *n2_32, *inv32, *n2_64, *inv64;
+    const unsigned short* Dsp;         // bf16 hi/lo split of D (split-bf16 correlation)
+    double dnorm_max;                  // max_k |D_k|
 };
 
 // accessors implemented in dicod_api.cpp

@@ -7,6 +7,7 @@
 // (Cauchy-Schwarz), so the host needs max_t |X[., t : t + W]|^2 per signal.
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstdint>
 
 #include "dicod_internal.h"
@@ -67,7 +68,42 @@ k_win_energy_max(const float* __restrict__ X, int P, int W, const SigDesc* __res
     }
 }
 
+// thr[i] = max(0, v_i - 2 coef sqrt(e_i)): v_i the largest split-bf16 |beta|
+// of signal i, e_i its largest window energy, coef = 1.05 c max_k |D_k| (the
+// per-entry error bound above with a 5% margin).  The maximiser's split value
+// is at least lambda_max - e >= v - 2 e, so every entry that can be the
+// maximum has a split value >= thr.
+__global__ void k_refine_threshold(const unsigned long long* __restrict__ vbits,
+                                   const unsigned long long* __restrict__ ebits, int n,
+                                   double coef, double* __restrict__ thr)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n)
+        return;
+    const double v = __longlong_as_double((long long)vbits[i]);
+    const double e = coef * sqrt(__longlong_as_double((long long)ebits[i]));
+    const double t = v - 2.0 * e;
+    thr[i] = t > 0.0 ? t : 0.0;
+}
+
 }  // namespace
+
+hipError_t launch_refine_threshold(const unsigned long long* vbits,
+                                   const unsigned long long* ebits, int n, double coef,
+                                   double* thr, hipStream_t s)
+{
+    if (n <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_refine_threshold, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                       vbits, ebits, n, coef, thr);
+    return hipGetLastError();
+}
+
+double refine_coef(int P, int W, double dnorm_max)
+{
+    const double c = 3.1 * std::ldexp(1.0, -16) + ((double)P * W + 1.0) * std::ldexp(1.0, -24);
+    return 1.05 * c * dnorm_max;
+}
 
 size_t win_energy_lds_bytes(int W) { return ((size_t)kEnergyTile + W - 1) * sizeof(double); }
 

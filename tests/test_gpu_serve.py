@@ -4,7 +4,8 @@ one-shot solver on the same device and against the FP64 oracle.
 A served request counts its coloured phases from its own admission, so the
 sequence of segment runs of a request, and its result, does not depend on the
 requests that share the device with it.  The tests therefore require the
-served Z to equal the one-shot Z element by element (FP32 and FP64 policies),
+served Z to equal the one-shot Z element by element (FP32, FP64 and MIXED
+policies; under MIXED both start from the split-bf16 correlation),
 and every served result of the mixed workload is also held to the oracle run
 to eps_ref = 1e-10: relative objective error <= 1e-6 and
 max |z - z_ref| <= 1e-4 max |z_ref|, and the oracle's from-scratch stop test
@@ -62,7 +63,7 @@ def solo(c, X, lam=-0.1, n_seg=0):
 LENGTHS = [1500, 400, 20_000, 5_000, 60_000, 2_345, 260]
 
 
-@pytest.mark.parametrize("precision", [1, 0])
+@pytest.mark.parametrize("precision", [1, 0, 2])
 def test_served_equals_one_shot(dicod, precision):
     print(f"\ncase: served mix of {len(LENGTHS)} precision={precision}", flush=True)
     D = paper_dict()
