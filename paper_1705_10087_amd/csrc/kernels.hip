@@ -2086,29 +2086,45 @@ k_grad_check(const float* __restrict__ X, const double* __restrict__ beta0,
                         }
                     }
                     const double* __restrict__ rows = sst + (size_t)cb * bstride + tid;
-                    for (int q = e; q < e1; ++q) {
-                        // lag of position t_a + tid + 256 j: d0 + tid + 256 j (32-bit:
-                        // positions are below 2^31); d0 is the same in every lane
-                        const int d0 = __builtin_amdgcn_readfirstlane(
-                            (int)(t_a - ls[q]) + (W - 1));
-                        const double z = lz[q];
+                    // up to 64 non-zeros of this atom at a time, one per lane:
+                    // lane c holds the lag base d0 (lag of position t_a + tid +
+                    // 256 j is d0 + tid + 256 j; 32-bit, positions are below
+                    // 2^31) and the value of non-zero c0 + c.  Per strip j a
+                    // ballot marks the non-zeros whose lags for this wave's 64
+                    // positions meet [0, nd); the wave then walks those bits in
+                    // increasing order (the order of the list, so every sum
+                    // keeps the order of (l, s)), reading d0 and z from their
+                    // lanes.
+                    for (int c0 = e; c0 < e1; c0 += 64) {
+                        const bool have = lane < e1 - c0;
+                        const int my_d0 = have ? (int)(t_a - ls[c0 + lane]) + (W - 1) : -(1 << 29);
+                        const double my_z = have ? lz[c0 + lane] : 0.0;
+                        const long long zbits = __double_as_longlong(my_z);
 #pragma unroll
                         for (int j = 0; j < J; ++j) {
-                            // this wave's 64 lags for j: a scalar test skips the
-                            // strips the window of the non-zero does not reach
-                            const int dw = d0 + wave * 64 + 256 * j;
-                            if (dw + 63 < 0 || dw >= nd)
-                                continue;
-                            const int d = d0 + tid + 256 * j;
-                            if ((unsigned)d < (unsigned)nd && tid + 256 * j < n_own) {
-                                const double* __restrict__ sr = rows + (d0 + 256 * j);
-                                double sv[KB];
+                            const int dw = my_d0 + wave * 64 + 256 * j;
+                            unsigned long long m = __ballot(have && dw + 63 >= 0 && dw < nd);
+                            while (m) {
+                                const int c = __builtin_ctzll(m);
+                                m &= ~(1ull << c);
+                                const int d0 = __builtin_amdgcn_readlane(my_d0, c);
+                                const unsigned zlo = (unsigned)__builtin_amdgcn_readlane(
+                                    (int)(unsigned)zbits, c);
+                                const unsigned zhi = (unsigned)__builtin_amdgcn_readlane(
+                                    (int)(zbits >> 32), c);
+                                const double z = __longlong_as_double(
+                                    (long long)(((unsigned long long)zhi << 32) | zlo));
+                                const int d = d0 + tid + 256 * j;
+                                if ((unsigned)d < (unsigned)nd && tid + 256 * j < n_own) {
+                                    const double* __restrict__ sr = rows + (d0 + 256 * j);
+                                    double sv[KB];
 #pragma unroll
-                                for (int kk = 0; kk < KB; ++kk)
-                                    sv[kk] = sr[rowoff[kk]];
+                                    for (int kk = 0; kk < KB; ++kk)
+                                        sv[kk] = sr[rowoff[kk]];
 #pragma unroll
-                                for (int kk = 0; kk < KB; ++kk)
-                                    acc[j][kk] -= sv[kk] * z;
+                                    for (int kk = 0; kk < KB; ++kk)
+                                        acc[j][kk] -= sv[kk] * z;
+                                }
                             }
                         }
                     }
