@@ -1763,8 +1763,8 @@ hipError_t launch_lgcd_phase_gm(const PhaseArgs& a, bool fp64, size_t* lds_bytes
 // Non-zero masks: word w of a signal is bit i = (Z_k[64 b + i] != 0), with
 // w = k * ceil(L / 64) + b.  A wave handles kMaskWords consecutive words:
 // their signal, atom and block indices are scalar arithmetic (the signal is
-// looked up once per wave), and all their loads are issued before the first
-// ballot.
+// looked up and (k, b) divided out once per wave, then stepped word by word),
+// and all their loads are issued before the first ballot.
 constexpr int kMaskWords = 16;
 
 __global__ void __launch_bounds__(256)
@@ -1778,8 +1778,11 @@ k_nz_mask(const double* __restrict__ Z, const SigDesc* __restrict__ sig,
     if (w0 >= n_words)
         return;
     int si = find_sig(mask_pref, n_sig, w0);
-    int64_t pref = mask_pref[si], pref_next = mask_pref[si + 1];
+    int64_t pref_next = mask_pref[si + 1];
     SigDesc sd = sig[si];
+    int64_t nb = (sd.L + 63) / 64;
+    int64_t k = (w0 - mask_pref[si]) / nb;   // word w0 = k nb + b of signal si
+    int64_t b = (w0 - mask_pref[si]) - k * nb;
     double z[kMaskWords];
 #pragma unroll
     for (int i = 0; i < kMaskWords; ++i) {
@@ -1787,19 +1790,22 @@ k_nz_mask(const double* __restrict__ Z, const SigDesc* __restrict__ sig,
         z[i] = 0.0;
         if (w >= n_words)
             continue;
-        while (w >= pref_next) {  // next signal (every signal has at least one word)
-            ++si;
-            pref = pref_next;
+        while (w >= pref_next) {  // next signal (every signal has at least one word),
+            ++si;                 // entered at its word 0
             pref_next = mask_pref[si + 1];
             sd = sig[si];
+            nb = (sd.L + 63) / 64;
+            k = 0;
+            b = 0;
         }
-        const int64_t nb = (sd.L + 63) / 64;
-        const int64_t loc = w - pref;
-        const int64_t k = loc / nb;
-        const int64_t t = (loc - k * nb) * 64 + lane;
+        const int64_t t = b * 64 + lane;
         const int64_t tc = t < sd.L ? t : sd.L - 1;  // a valid address, selected below
         const double v = Z[sd.z_off + (k < K ? k : K - 1) * sd.L + tc];
         z[i] = (k < K && t < sd.L) ? v : 0.0;
+        if (++b == nb) {
+            b = 0;
+            ++k;
+        }
     }
 #pragma unroll
     for (int i = 0; i < kMaskWords; ++i) {
@@ -2139,6 +2145,13 @@ k_grad_check(const float* __restrict__ X, const double* __restrict__ beta0,
     double mdz = 0.0, kon = 0.0, koff = 0.0, l1 = 0.0, mz = 0.0, nnz = 0.0, x2 = 0.0, bz = 0.0;
     double bx = 0.0, gm = 0.0;
     const double lam = sd.lam;
+    // 1 / |D_k|^2 once per atom: the per-coordinate quotients below become
+    // products (within an ulp of the quotient; a double division is some
+    // twenty instructions, and every zero coordinate needs one)
+    double inv[KB];
+#pragma unroll
+    for (int k = 0; k < KB; ++k)
+        inv[k] = 1.0 / n2v[kb + (k < kn ? k : kn - 1)];
 #pragma unroll
     for (int j = 0; j < J; ++j) {
         const int64_t t = t_a + tid + 256 * j;
@@ -2163,14 +2176,14 @@ k_grad_check(const float* __restrict__ X, const double* __restrict__ beta0,
             const double g = acc[j][k];
             const double bb = g + n2 * z;
             const double ab = fabs(bb) - lam;
-            const double zp = ab > 0.0 ? (bb > 0.0 ? ab : -ab) / n2 : 0.0;
+            const double zp = ab > 0.0 ? (bb > 0.0 ? ab : -ab) * inv[k] : 0.0;
             const double dz = fabs(zp - z);
             mdz = fmax(mdz, dz);
             gm = fmax(gm, fabs(g));
             if (dz >= flag_eps)
                 flag = true;
             if (z != 0.0) {
-                kon = fmax(kon, fabs(g - (z > 0.0 ? lam : -lam)) / n2);
+                kon = fmax(kon, fabs(g - (z > 0.0 ? lam : -lam)) * inv[k]);
                 l1 += fabs(z);
                 mz = fmax(mz, fabs(z));
                 nnz += 1.0;
@@ -2178,7 +2191,7 @@ k_grad_check(const float* __restrict__ X, const double* __restrict__ beta0,
                 bz += (b0 + g) * z;
                 bx += b0 * z;
             } else {
-                koff = fmax(koff, fmax(fabs(g) - lam, 0.0) / n2);
+                koff = fmax(koff, fmax(fabs(g) - lam, 0.0) * inv[k]);
             }
             if (g32 && !frozen)
                 g32[o] = (float)g;
