@@ -1506,7 +1506,7 @@ struct ChunkBest {
 // inside [wlo, whi] (none when the window is empty), then the best candidate
 // of the own positions.  Srow is always a valid row block of S; loads are at
 // clamped, valid indices and unconditional, their values selected afterwards.
-template <typename G, int KC>
+template <typename G>
 __device__ __forceinline__ void gm_chunk(int c, int K, int Kr, int W, int off, int Lm,
                                         int Lext, int ext_lo, int b, int64_t L,
                                         G* __restrict__ gs, const double* __restrict__ Zs,
@@ -1578,7 +1578,7 @@ __device__ __forceinline__ void gm_chunk(int c, int K, int Kr, int W, int off, i
     }
 }
 
-template <typename G, int KC>
+template <typename G>
 __global__ void __launch_bounds__(kPhaseThreads)
 k_lgcd_phase_gm(PhaseArgs a)
 {
@@ -1586,7 +1586,7 @@ k_lgcd_phase_gm(PhaseArgs a)
     typedef typename KO::T KeyT;
     constexpr int NT = kPhaseThreads;
     constexpr int NW = NT / 64;
-    const int K = KC ? KC : a.K;
+    const int K = a.K;
     const int W = a.W;
     const int tid = threadIdx.x;
     const int wave = tid >> 6;
@@ -1627,7 +1627,7 @@ k_lgcd_phase_gm(PhaseArgs a)
     __syncthreads();
 
     for (int c = wave; c < nch; c += NW)
-        gm_chunk<G, KC>(c, K, a.K, W, off, Lm, Lext, ext_lo, b, L, gs, Zs, S, (G)0, 0, 0,
+        gm_chunk<G>(c, K, a.K, W, off, Lm, Lext, ext_lo, b, L, gs, Zs, S, (G)0, 0, 0,
                         -1, n2l, invl, linvl, lam, cb);  // empty window: no update
     __syncthreads();
 
@@ -1697,7 +1697,7 @@ k_lgcd_phase_gm(PhaseArgs a)
             touch_r = true;
         const G* __restrict__ Srow = S + (size_t)k0 * K * nd;
         for (int c = wlo / 64 + ((wave - wlo / 64) % NW + NW) % NW; c <= whi / 64; c += NW)
-            gm_chunk<G, KC>(c, K, a.K, W, off, Lm, Lext, ext_lo, b, L, gs, Zs, Srow, delta,
+            gm_chunk<G>(c, K, a.K, W, off, Lm, Lext, ext_lo, b, L, gs, Zs, Srow, delta,
                             q0, wlo, whi, n2l, invl, linvl, lam, cb);
         __syncthreads();
         ++n;
@@ -1729,14 +1729,14 @@ size_t lgcd_gm_lds_bytes(int K, int lext_max, bool fp64)
     return cbs * ((size_t)lext_max / 64 + 1) + sls * 2 * (kPhaseThreads / 64) + 3 * e * (size_t)K;
 }
 
-template <typename G, int KC>
+template <typename G>
 static hipError_t launch_gm_k(const PhaseArgs& a, size_t lds, hipStream_t s)
 {
-    hipError_t e = hipFuncSetAttribute((const void*)k_lgcd_phase_gm<G, KC>,
+    hipError_t e = hipFuncSetAttribute((const void*)k_lgcd_phase_gm<G>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess)
         return e;
-    hipLaunchKernelGGL((k_lgcd_phase_gm<G, KC>), dim3((unsigned)a.n_list), dim3(kPhaseThreads),
+    hipLaunchKernelGGL((k_lgcd_phase_gm<G>), dim3((unsigned)a.n_list), dim3(kPhaseThreads),
                        lds, s, a);
     return hipGetLastError();
 }
@@ -1752,8 +1752,8 @@ hipError_t launch_lgcd_phase_gm(const PhaseArgs& a, bool fp64, size_t* lds_bytes
     if (lds > kLdsBytes)
         return hipErrorInvalidValue;
     if (fp64)
-        return a.K == 25 ? launch_gm_k<double, 25>(a, lds, s) : launch_gm_k<double, 0>(a, lds, s);
-    return a.K == 25 ? launch_gm_k<float, 25>(a, lds, s) : launch_gm_k<float, 0>(a, lds, s);
+        return launch_gm_k<double>(a, lds, s);
+    return launch_gm_k<float>(a, lds, s);
 }
 
 // ---------------------------------------------------------------------------
