@@ -119,6 +119,42 @@ def test_fp64_trajectory_matches_oracle(dicod, M, cap, lds, C, seed):
     assert abs(st["objective"] - Eo) <= 1e-10 * Eo
 
 
+@pytest.mark.parametrize("M,cap,lds,C", [(4, 8, 1, 2), (63, 16, 0, 2), (127, 4, 1, 3),
+                                         (1, 0, 1, 2)])
+@pytest.mark.parametrize("seed", [0, 1])
+def test_fp64_trajectory_matches_oracle_unequal_norms(dicod, M, cap, lds, C, seed):
+    """The same sequence equality with atoms of norms spread over [0.3, 3], so the
+    division by |D_k|^2 of eq. (pb_coord) acts: the GPU's g-form candidate
+    (g - lambda sign beta) / |D_k|^2 against the oracle's Sh(beta, lambda) /
+    |D_k|^2 - z, the Z it applies and the stop test."""
+    print(f"\ncase: FP64 trajectory unequal norms seed={seed} M={M} cap={cap} lds={lds} "
+          f"C={C}", flush=True)
+    X, D, _ = small(seed)
+    rng = np.random.default_rng(100 + seed)
+    Dn = f64(D) / np.sqrt(np.sum(f64(D) ** 2, axis=(1, 2), keepdims=True))
+    nrm = np.geomspace(0.3, 3.0, D.shape[0])[rng.permutation(D.shape[0])]
+    D = (Dn * nrm[:, None, None]).astype(np.float32)
+    n2 = oracle.norms(f64(D))
+    assert n2.min() < 0.1 and n2.max() > 8.9
+    lam = 0.1 * oracle.lambda_max(f64(X), f64(D))
+    Zo, so, tro = oracle.lgcd(f64(X), f64(D), lam, EPS, M, cap=cap, trace_cap=10**6, colors=C)
+    with ctx_of(dicod, precision=dicod.DICOD_PREC_FP64, update_cap=cap,
+                trace_capacity=10**6, state_in_lds=lds, colors=C) as c:
+        Z, st = c.solve(X, lam, EPS, n_seg=M, D=D)
+        tr = c.trace()
+    assert st["converged"] == 1 and so["converged"] == 1
+    assert st["n_updates"] == so["n_updates"] == len(tr)
+    assert st["n_phases"] == so["n_phases"]
+    a, b = _sorted_gpu_trace(tr), _sorted_oracle_trace(tro)
+    for f in ("phase", "seg", "k0", "t0"):
+        assert np.array_equal(a[f], b[f]), f
+    np.testing.assert_allclose(a["delta"], b["z_new"] - b["z_old"], rtol=1e-9, atol=1e-12)
+    np.testing.assert_allclose(Z, Zo, rtol=0, atol=1e-10 * max(1.0, np.abs(Zo).max()))
+    assert np.array_equal(Z != 0, Zo != 0)
+    Eo = oracle.objective(f64(X), f64(D), Zo, lam)
+    assert abs(st["objective"] - Eo) <= 1e-10 * Eo
+
+
 # ------------------------------------- MIXED: split-bf16 beta at Z = 0
 
 @pytest.mark.parametrize("K,P,W,T", [(5, 1, 32, 4096), (37, 3, 17, 1013), (25, 7, 200, 150_000),
